@@ -1,0 +1,299 @@
+"""Driver of the FP64 oracle: setup in numpy/scipy, per-step loop in C.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+State is kept in the E-form of eqs. (full_d_dfl)/(full_d_dal): E^n on
+edges, B^{n-1/2} on faces, particles with global (z, rho), their triangle
+and u = gamma v.  D^n = [*eps]_a E^n is carried beside it for the discrete
+Gauss law check of Sec. 3.4.2 ([*eps]_a = M^-1).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+import scipy.spatial
+
+from .topology import build_topology, AXIS
+from .hodge import hodge_eps, hodge_mu_inv, EPS0, C_LIGHT
+from .spai import spai
+from .cfl import cfl_dt
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_step.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle_pic.so")
+TWO_PI = 2.0 * np.pi
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile pic_step.c with gcc (plain -O2, FP64, single thread)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+                        "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build_oracle())
+        vp = C.c_void_p
+        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double] + [vp] * 8
+        _lib.oracle_step.restype = None
+        _lib.oracle_charge.argtypes = [vp, vp, vp, vp]
+        _lib.oracle_sample.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        _lib.oracle_walk_only.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double, vp, vp, vp]
+        _lib.oracle_walk_only.restype = C.c_int
+        _lib.oracle_boris.argtypes = [vp, vp, vp, C.c_double]
+        _lib.oracle_move.argtypes = [C.c_double, C.c_double, vp, C.c_double, vp, vp]
+    return _lib
+
+
+class _OMesh(C.Structure):
+    _fields_ = [("n0", C.c_int64), ("n1", C.c_int64), ("n2", C.c_int64)] + \
+               [(n, C.c_void_p) for n in ("nodes", "tris", "edges", "tri_edges", "tri_signs", "tri_nbr",
+                                          "edge_tag", "edge_free", "H", "m_ptr", "m_col", "m_val")]
+
+
+class _OParticles(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(n, C.c_void_p) for n in
+                                     ("z", "rho", "tri", "u", "alive", "species", "sp_qm", "sp_qw")]
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class OracleSim:
+    """Plain FP64 simulation of one meridian device."""
+
+    def __init__(self, nodes, tris, seg, tag, dt=None, bz=0.0, spai_level=3, drop_tol=1e-3,
+                 cfl_fraction=0.5, M=None):
+        t0 = time.perf_counter()
+        self.topo = build_topology(nodes, tris, seg, tag)
+        self.A = hodge_eps(self.topo)
+        self.H = hodge_mu_inv(self.topo)
+        self.M = M if M is not None else spai(self.A, self.topo.edge_free, spai_level, drop_tol)
+        self.M = sp.csr_matrix(self.M)
+        self.M.sort_indices()
+        self.dt_cfl, self.lam_max = cfl_dt(self.topo, self.H, self.M)
+        self.dt = float(dt) if dt is not None else cfl_fraction * self.dt_cfl
+        self.bz = float(bz)
+        self.setup_seconds = time.perf_counter() - t0
+        tp = self.topo
+        n0, n1, n2 = tp.n0, tp.n1, tp.n2
+        self.E = np.zeros(n1)
+        self.B = np.zeros(n2)
+        self.D = np.zeros(n1)
+        self.J = np.zeros(n1)
+        self.Qres = np.zeros(n0)
+        self._Bh = np.zeros(n2)
+        self._rhs = np.zeros(n1)
+        self.stats = np.zeros(3, dtype=np.int64)
+        self.n_step = 0
+        # contiguous arrays handed to C
+        self._arr = dict(
+            nodes=np.ascontiguousarray(tp.nodes, dtype=np.float64),
+            tris=np.ascontiguousarray(tp.tris, dtype=np.int64),
+            edges=np.ascontiguousarray(tp.edges, dtype=np.int64),
+            tri_edges=np.ascontiguousarray(tp.tri_edges, dtype=np.int64),
+            tri_signs=np.ascontiguousarray(tp.tri_signs, dtype=np.int64),
+            tri_nbr=np.ascontiguousarray(tp.tri_nbr, dtype=np.int64),
+            edge_tag=np.ascontiguousarray(tp.edge_tag, dtype=np.int64),
+            edge_free=np.ascontiguousarray(tp.edge_free, dtype=np.uint8),
+            H=np.ascontiguousarray(self.H, dtype=np.float64),
+            m_ptr=np.ascontiguousarray(self.M.indptr, dtype=np.int64),
+            m_col=np.ascontiguousarray(self.M.indices, dtype=np.int64),
+            m_val=np.ascontiguousarray(self.M.data, dtype=np.float64),
+        )
+        self._mesh = _OMesh(n0, n1, n2, *[_p(self._arr[k]) for k in (
+            "nodes", "tris", "edges", "tri_edges", "tri_signs", "tri_nbr", "edge_tag", "edge_free",
+            "H", "m_ptr", "m_col", "m_val")])
+        # particles
+        self.sp_qm = np.zeros(0)
+        self.sp_qw = np.zeros(0)
+        self.sp_m = np.zeros(0)
+        self.sp_w = np.zeros(0)
+        self.pz = np.zeros(0)
+        self.prho = np.zeros(0)
+        self.ptri = np.zeros(0, dtype=np.int64)
+        self.pu = np.zeros((0, 3))
+        self.palive = np.zeros(0, dtype=np.int8)
+        self.pspecies = np.zeros(0, dtype=np.int64)
+        self._tree = None
+        self._Msolve = None
+
+    # ---------------------------------------------------------------- fields
+    def set_fields(self, E0, B_mhalf):
+        free = self.topo.edge_free
+        self.E = np.where(free, np.asarray(E0, dtype=np.float64), 0.0)
+        self.B = np.asarray(B_mhalf, dtype=np.float64).copy()
+        self.D = self.eps_a(self.E)
+
+    def eps_a(self, E):
+        """[*eps]_a E = M^-1 E on free edges (sparse direct solve)."""
+        idx = np.flatnonzero(self.topo.edge_free)
+        if self._Msolve is None:
+            self._Msolve = spla.splu(self.M[idx][:, idx].tocsc())
+        D = np.zeros(self.topo.n1)
+        D[idx] = self._Msolve.solve(np.asarray(E)[idx])
+        return D
+
+    # ------------------------------------------------------------- particles
+    def add_species(self, q, m, weight):
+        self.sp_qm = np.append(self.sp_qm, q / m)
+        self.sp_qw = np.append(self.sp_qw, q * weight)
+        self.sp_m = np.append(self.sp_m, m)
+        self.sp_w = np.append(self.sp_w, float(weight))
+        return len(self.sp_qm) - 1
+
+    def locate(self, zr):
+        """Containing triangle of each point: the face among the nearest
+        centroids whose smallest barycentric coordinate is largest."""
+        tp = self.topo
+        if self._tree is None:
+            self._tree = scipy.spatial.cKDTree(tp.nodes[tp.tris].mean(axis=1))
+        zr = np.asarray(zr, dtype=np.float64).reshape(-1, 2)
+        k = min(24, tp.n2)
+        _, cand = self._tree.query(zr, k=k)
+        cand = np.asarray(cand).reshape(len(zr), -1)
+        minlam = _bary_many(tp.nodes[tp.tris[cand]], zr[:, None, :]).min(axis=-1)
+        out = cand[np.arange(len(zr)), np.argmax(minlam, axis=1)]
+        bad = np.flatnonzero(minlam.max(axis=1) < -1e-12)
+        for i in bad:                        # far from any centroid: scan all faces
+            ml = _bary_many(tp.nodes[tp.tris], zr[i][None, :]).min(axis=-1)
+            if ml.max() < -1e-9:
+                raise ValueError(f"point {zr[i]} is outside the mesh")
+            out[i] = int(np.argmax(ml))
+        return out.astype(np.int64)
+
+    def inject(self, species, zr, u):
+        zr = np.asarray(zr, dtype=np.float64).reshape(-1, 2)
+        u = np.asarray(u, dtype=np.float64).reshape(-1, 3)
+        tri = self.locate(zr)
+        n = len(zr)
+        self.pz = np.concatenate([self.pz, zr[:, 0]])
+        self.prho = np.concatenate([self.prho, zr[:, 1]])
+        self.ptri = np.concatenate([self.ptri, tri])
+        self.pu = np.concatenate([self.pu, u], axis=0)
+        self.palive = np.concatenate([self.palive, np.ones(n, dtype=np.int8)])
+        self.pspecies = np.concatenate([self.pspecies, np.full(n, species, dtype=np.int64)])
+
+    def _parts(self):
+        self.pz = np.ascontiguousarray(self.pz)
+        self.prho = np.ascontiguousarray(self.prho)
+        self.ptri = np.ascontiguousarray(self.ptri, dtype=np.int64)
+        self.pu = np.ascontiguousarray(self.pu)
+        self.palive = np.ascontiguousarray(self.palive)
+        self.pspecies = np.ascontiguousarray(self.pspecies)
+        self.sp_qm = np.ascontiguousarray(self.sp_qm)
+        self.sp_qw = np.ascontiguousarray(self.sp_qw)
+        return _OParticles(len(self.pz), _p(self.pz), _p(self.prho), _p(self.ptri), _p(self.pu),
+                           _p(self.palive), _p(self.pspecies), _p(self.sp_qm), _p(self.sp_qw))
+
+    # ------------------------------------------------------------------ step
+    def step(self, n=1):
+        lib = _load()
+        P = self._parts()
+        for _ in range(n):
+            lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz,
+                            _p(self.E), _p(self.B), _p(self.D), _p(self.J), _p(self.Qres),
+                            _p(self._Bh), _p(self._rhs), _p(self.stats))
+            self.n_step += 1
+
+    # ----------------------------------------------------------- diagnostics
+    def charge(self):
+        """Q^n per node, eq. (charge), including absorbed wall charge."""
+        lib = _load()
+        P = self._parts()
+        Q = np.zeros(self.topo.n0)
+        lib.oracle_charge(C.byref(self._mesh), C.byref(P), _p(self.Qres), _p(Q))
+        return Q
+
+    def gauss_residual(self, D=None):
+        """res^n = D~div [*eps]_a E^n - Q^n (Sec. 3.4.2), on every node."""
+        D = self.D if D is None else D
+        return self.topo.Ddiv @ D - self.charge()
+
+    def energies(self):
+        """(W_E, W_B, W_K) per radian: 1/2 E^T [*eps] E, 1/2 B^{n-1/2} H B^{n-1/2},
+        sum w (gamma - 1) m c^2 / (2 pi)."""
+        WE = 0.5 * self.E @ (self.A @ self.E)
+        WB = 0.5 * self.B @ (self.H * self.B)
+        a = self.palive.astype(bool)
+        g = np.sqrt(1.0 + (self.pu[a] ** 2).sum(axis=1) / C_LIGHT ** 2)
+        sp_ = self.pspecies[a]
+        WK = float(np.sum(self.sp_w[sp_] * self.sp_m[sp_] * (g - 1.0)) * C_LIGHT ** 2 / TWO_PI)
+        return float(WE), float(WB), WK
+
+    def sample(self, tri, z, rho):
+        lib = _load()
+        tri = np.ascontiguousarray(tri, dtype=np.int64)
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        out = np.zeros((len(tri), 3))
+        lib.oracle_sample(C.byref(self._mesh), len(tri), _p(tri), _p(z), _p(rho), _p(self.E), _p(self.B), _p(out))
+        return out
+
+    def walk_only(self, p, z_end, rho_end, J):
+        lib = _load()
+        P = self._parts()
+        return lib.oracle_walk_only(C.byref(self._mesh), C.byref(P), int(p), float(z_end), float(rho_end),
+                                    self.dt, _p(J), _p(self.Qres), _p(self.stats))
+
+    def particles(self):
+        a = self.palive.astype(bool)
+        return (np.stack([self.pz[a], self.prho[a]], axis=1), self.pu[a].copy(), self.pspecies[a].copy())
+
+
+def _bary_many(v, r):
+    """Barycentric coordinates of points r (..., 2) in triangles v (..., 3, 2)."""
+    A = 0.5 * ((v[..., 1, 0] - v[..., 0, 0]) * (v[..., 2, 1] - v[..., 0, 1])
+               - (v[..., 2, 0] - v[..., 0, 0]) * (v[..., 1, 1] - v[..., 0, 1]))
+    out = []
+    for i in range(3):
+        pj, pk = v[..., (i + 1) % 3, :], v[..., (i + 2) % 3, :]
+        out.append(0.5 * ((pj[..., 0] - r[..., 0]) * (pk[..., 1] - r[..., 1])
+                          - (pk[..., 0] - r[..., 0]) * (pj[..., 1] - r[..., 1])) / A)
+    return np.stack(out, axis=-1)
+
+
+def _bary_np(v, r):
+    """Barycentric coordinates of point r in triangle with vertices v (3, 2)."""
+    lam = np.empty(3)
+    A = 0.5 * ((v[1, 0] - v[0, 0]) * (v[2, 1] - v[0, 1]) - (v[2, 0] - v[0, 0]) * (v[1, 1] - v[0, 1]))
+    for i in range(3):
+        pj, pk = v[(i + 1) % 3], v[(i + 2) % 3]
+        lam[i] = 0.5 * ((pj[0] - r[0]) * (pk[1] - r[1]) - (pk[0] - r[0]) * (pj[1] - r[1])) / A
+    return lam
+
+
+def boris(u, E, B, k):
+    """Python handle on the oracle's Boris rotation (u is modified copy)."""
+    lib = _load()
+    u = np.ascontiguousarray(u, dtype=np.float64).copy()
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    lib.oracle_boris(_p(u), _p(E), _p(B), float(k))
+    return u
+
+
+def move(z, rho, u, dt):
+    lib = _load()
+    u = np.ascontiguousarray(u, dtype=np.float64).copy()
+    zn = C.c_double()
+    rn = C.c_double()
+    lib.oracle_move(float(z), float(rho), _p(u), float(dt), C.byref(zn), C.byref(rn))
+    return zn.value, rn.value, u
