@@ -1,0 +1,245 @@
+/*
+ * axpic — MI355X (gfx950) implementation of the per-time-step loop of the
+ * axisymmetric, charge-conserving electromagnetic particle-in-cell method of
+ * Na, Omelchenko, Moon, Borges and Teixeira, "Axisymmetric charge-conservative
+ * electromagnetic particle simulation algorithm on unstructured grids"
+ * (arXiv:1701.03784).
+ *
+ * The library keeps a meridian-plane (z, rho) triangle mesh, the field
+ * degrees of freedom (E on edges, B_phi flux on faces), macro-particles and
+ * the sparse approximate inverse (SPAI) of the permittivity Hodge matrix on
+ * one GPU, and advances them with hand-written HIP kernels:
+ *   Faraday update of face fluxes (Sec. 3.1, eq. full_d_dfl),
+ *   Whitney-form gather of E and B_phi (Sec. 3.2),
+ *   relativistic Boris push with an axisymmetric position update (Sec. 3.3),
+ *   charge-conserving edge-current scatter along each particle's path
+ *     across triangles (Sec. 3.4, eqs. current and DCE),
+ *   Ampere update made explicit by the SPAI matrix (eq. full_d_dal).
+ *
+ * Conventions (all calls):
+ *   - SI units.  Positions are (z, rho) pairs; momenta are u = gamma v in m/s
+ *     in the local cylindrical basis (u_rho, u_phi, u_z).
+ *   - Triangles must be counter-clockwise in the (z, rho) plane; face values
+ *     are fluxes of B_phi through them.
+ *   - Edge i of the mesh is the i-th pair (tail, head), tail < head, of the
+ *     lexicographically sorted edge set (the orientation of App. D); edge
+ *     values are line integrals of E from tail to head.  axp_get_edges
+ *     returns that list.
+ *   - Ring sources are per radian: a macro-particle of charge q deposits
+ *     q/(2 pi) of charge and current.
+ *   - Host pointers passed in are borrowed for the duration of the call only;
+ *     the library copies what it keeps.  All device memory is owned by the
+ *     context and released by axp_destroy.
+ *   - Every call returns an axp_status; no C++ exception crosses the ABI.
+ *     The message of the last failure is returned by axp_last_error.
+ *     Argument and mesh errors leave the context usable.  AXP_E_HIP,
+ *     AXP_E_NAN, AXP_E_WALK and AXP_E_FIXED_OVERFLOW are sticky: once
+ *     raised (at axp_sync/axp_diag, from device flags) every later call that
+ *     touches the device returns AXP_E_STATE.
+ *   - One context per host thread; distinct contexts are independent.
+ */
+#ifndef AXPIC_H
+#define AXPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct axp_ctx axp_ctx;
+typedef struct axp_batch axp_batch;
+typedef int32_t axp_status;
+
+enum {
+    AXP_OK = 0,
+    AXP_E_ARG = -1,            /* bad argument (null pointer, size, range) */
+    AXP_E_MESH = -2,           /* invalid mesh: orientation, untagged boundary, non-manifold */
+    AXP_E_SPAI = -3,           /* SPAI failed (singular least-squares block, not SPD) */
+    AXP_E_UNSTABLE = -4,       /* dt above the leapfrog stability limit */
+    AXP_E_OOM = -5,            /* device or host allocation failed */
+    AXP_E_HIP = -6,            /* HIP runtime error */
+    AXP_E_WALK = -7,           /* a particle path needed more than the segment cap */
+    AXP_E_FIXED_OVERFLOW = -8, /* 64-bit fixed-point current or charge out of range */
+    AXP_E_NAN = -9,            /* non-finite momentum or field */
+    AXP_E_STATE = -10          /* call out of order, or a sticky error was raised before */
+};
+
+/* Boundary tags of boundary segments (axp_set_boundary). */
+enum {
+    AXP_BC_PEC = 1,     /* conductor: tangential E = 0; particles absorbed, charge kept on the wall */
+    AXP_BC_AXIS = 2,    /* rho = 0: free (natural) edges; particles cannot cross */
+    AXP_BC_EMITTER = 3, /* conductor that emits particles (axp_set_injector) */
+    AXP_BC_OPEN = 4     /* free (natural, PMC-like) field boundary; particles absorbed */
+};
+
+/* Arithmetic of the time step. */
+enum {
+    AXP_PREC_PLAIN_FP64 = 0, /* FP64 gather/push/SpMV, FP64 barycentric positions, FP64 atomics */
+    AXP_PREC_MIXED = 1       /* FP32 gather/push/SpMV; element-local fixed-point positions;
+                                64-bit fixed-point current; FP64 D, B and diagnostics */
+};
+
+typedef void *(*axp_alloc_fn)(size_t bytes, void *user);
+typedef void (*axp_free_fn)(void *ptr, void *user);
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    void *hip_stream;        /* hipStream_t the steps are enqueued on (NULL = default stream) */
+    int32_t precision;       /* AXP_PREC_* */
+    double dt;               /* time step [s]; <= 0: cfl_fraction * stability limit */
+    double cfl_fraction;     /* used when dt <= 0 (default 0.5) */
+    int32_t spai_level;      /* SPAI a-priori pattern level L (pattern of A^L), default 3 */
+    double spai_drop_tol;    /* relative drop tolerance within each SPAI column, default 1e-3 */
+    int32_t sort_period;     /* re-sort particles by triangle every this many steps (>= 1) */
+    int32_t diag_every;      /* device diagnostics every this many steps (0 = only on axp_diag) */
+    int32_t max_walk;        /* cap on path pieces per particle and step (default 64) */
+    int32_t use_graph;       /* 1: capture axp_step's launches in a hipGraph and replay it */
+    axp_alloc_fn alloc;      /* optional device allocator (NULL: hipMalloc) */
+    axp_free_fn free;
+    void *alloc_user;
+} axp_config;
+
+typedef struct {
+    int64_t n_nodes, n_edges, n_faces;
+    int64_t n_free_edges, n_free_nodes;
+    int64_t spai_nnz;            /* non-zeros of M over free edges */
+    double spai_fro_residual;    /* ||I - A M||_F / sqrt(n) over free edges */
+    double spai_max_col_residual;
+    double dt, dt_cfl;           /* time step in use and the leapfrog limit */
+    double setup_seconds;        /* host time of axp_build */
+    int64_t particle_capacity;
+    int64_t n_particles;         /* live particles after the last sync */
+    int64_t step;                /* steps taken */
+    int32_t precision;
+    int32_t n_species;
+} axp_info;
+
+typedef struct {
+    int64_t step;
+    int64_t n_live;              /* live particles */
+    int64_t n_absorbed;          /* particles absorbed at walls (cumulative) */
+    int64_t walk_overflow;       /* paths cut at the segment cap (cumulative) */
+    int64_t nan_count;           /* non-finite momenta seen (cumulative) */
+    int64_t fixed_overflow;      /* fixed-point headroom violations (cumulative) */
+    int64_t dce_max_abs;         /* max over nodes |2^24 (Q^{n+1}-Q^n) + Ddiv J| in fixed point (mixed; 0 = exact) */
+    double dce_max_rel;          /* same, relative to max |Q| (plain FP64 mode) */
+    double gauss_max_drift;      /* max over free nodes |res^n - res^0| (Sec. 3.4.2) */
+    double gauss_max_abs;        /* max over free nodes |res^n| */
+    double gauss_scale;          /* max over free nodes of sum |D_e| at the node */
+    double W_E, W_B, W_K;        /* energies per radian [J/rad]: 1/2 E^T[*eps]E, 1/2 B^{n+1/2} H B^{n-1/2}, sum w(gamma-1)mc^2/2pi */
+    double Q_total;              /* total charge per radian incl. wall charge [C/rad] */
+} axp_diag;
+
+/* Fills cfg with defaults: device 0, default stream, mixed precision,
+ * dt = 0.5 x stability limit, SPAI level 3 / drop 1e-3, sort every 4 steps,
+ * no periodic diagnostics, walk cap 64, graphs on, hipMalloc. */
+void axp_config_default(axp_config *cfg);
+
+/* Creates an empty context on cfg->device.  *out receives the handle. */
+axp_status axp_create(const axp_config *cfg, axp_ctx **out);
+
+/* Meridian mesh (Sec. 2.2, Fig. 2b; App. D): n_nodes points zr[n][2] =
+ * (z, rho >= 0) and n_tris triangles tri[n][3] (node ids, counter-clockwise
+ * in (z, rho)).  Copied.  AXP_E_MESH on clockwise or degenerate triangles. */
+axp_status axp_set_mesh(axp_ctx *ctx, int32_t n_nodes, const double *zr, int32_t n_tris, const int32_t *tri);
+
+/* Boundary segments seg_nodes[n][2] with tags tag[n] (AXP_BC_*).  Every
+ * boundary edge of the mesh must be listed (AXP_E_MESH at axp_build if not). */
+axp_status axp_set_boundary(axp_ctx *ctx, int32_t n_seg, const int32_t *seg_nodes, const uint8_t *tag);
+
+/* Setup (host FP64 + uploads): topology and incidence (App. D), Hodge
+ * matrices by exact quadrature of their defining integrals (Sec. 3.1, App. B),
+ * SPAI of [*eps] (Sec. 3.1), the stability limit, locality renumbering,
+ * device layouts.  Must precede every call below. */
+axp_status axp_build(axp_ctx *ctx);
+
+axp_status axp_info_get(const axp_ctx *ctx, axp_info *out);
+
+/* Canonical edge list edges[n_edges][2] (tail, head), see Conventions. */
+axp_status axp_get_edges(const axp_ctx *ctx, int32_t *edges);
+
+/* The SPAI matrix M ~ [*eps]^-1 in CSR over canonical edge indices (zero rows
+ * and columns on conductor edges).  rowptr[n_edges+1]; col/val hold
+ * capacity entries; *nnz receives the count (AXP_E_ARG if it exceeds capacity,
+ * with *nnz still set). */
+axp_status axp_get_spai(const axp_ctx *ctx, int64_t capacity, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val);
+
+/* Fields at step 0: E0[n_edges] edge line integrals at t = 0 and
+ * B_mhalf[n_faces] face fluxes at t = -dt/2 (face order of axp_set_mesh).
+ * Conductor edge values are ignored (set to 0).  D^0 = [*eps]_a E^0 = M^-1 E^0
+ * is solved by conjugate gradients in FP64. */
+axp_status axp_set_fields(axp_ctx *ctx, const double *E0, const double *B_mhalf);
+
+/* Uniform static axial field B_z [T] added at the gather (beam focusing, Sec. 3.2). */
+axp_status axp_set_external_bz(axp_ctx *ctx, double bz);
+
+/* Particle species: q [C] and m [kg] of one physical particle, and the
+ * number of physical particles per macro-particle (weight >= 1).  In mixed
+ * precision every species' macro charge q*weight must be an integer multiple
+ * of the first species' macro charge (the fixed-point charge unit).
+ * *species_id receives the new id (at most 16 species). */
+axp_status axp_add_species(axp_ctx *ctx, double q, double m, int64_t weight, int32_t *species_id);
+
+/* Adds n macro-particles at zr[n][2] with momenta u[n][3]; each is located
+ * in the mesh (AXP_E_ARG if outside).  Enqueued on the stream. */
+axp_status axp_inject(axp_ctx *ctx, int32_t species, int64_t n, const double *zr, const double *u);
+
+/* Continuous injection from the AXP_BC_EMITTER boundary: per_step particles
+ * of `species` per step, uniform per unit area on the emitting surface, with
+ * momentum u_mean + u_spread * (uniform in [-1,1]^3) in the local frame where
+ * u_z points into the domain for an emitter at a z-face.  The charge of each
+ * injected particle is taken from the emitter nodes (charge conservation).
+ * seed selects the counter-based random stream. */
+axp_status axp_set_injector(axp_ctx *ctx, int32_t species, int64_t per_step, const double u_mean[3],
+                            double u_spread, uint64_t seed);
+
+/* Enqueues n_steps time steps on cfg.hip_stream and returns. */
+axp_status axp_step(axp_ctx *ctx, int32_t n_steps);
+
+/* Waits for the stream and raises sticky errors from device flags. */
+axp_status axp_sync(axp_ctx *ctx);
+
+/* Computes the diagnostics of the current state (syncs first). */
+axp_status axp_diag_get(axp_ctx *ctx, axp_diag *out);
+
+/* E^n[n_edges] (canonical edge order) and B^{n-1/2}[n_faces] (input face
+ * order); either pointer may be NULL. */
+axp_status axp_get_fields(axp_ctx *ctx, double *E, double *B_half);
+
+/* D^n = [*eps]_a E^n (canonical edges), the last step's edge current
+ * J^{n-1/2} times dt [C/rad] (canonical edges) and the nodal charge Q^n
+ * [C/rad] (input node order, incl. wall charge).  Pointers may be NULL. */
+axp_status axp_get_sources(axp_ctx *ctx, double *D, double *J_dt, double *Q);
+
+/* Live particles: positions zr[cap][2], momenta u[cap][3], species[cap];
+ * *n receives the live count (AXP_E_ARG if above cap, *n still set).  The
+ * order is the library's storage order (grouped by triangle). */
+axp_status axp_get_particles(axp_ctx *ctx, int64_t cap, int64_t *n, double *zr, double *u, int32_t *species);
+
+/* Checkpoint of the complete state to a file / restore into a context built
+ * from the same mesh and configuration. */
+axp_status axp_save(axp_ctx *ctx, const char *path);
+axp_status axp_load(axp_ctx *ctx, const char *path);
+
+const char *axp_last_error(const axp_ctx *ctx);
+void axp_destroy(axp_ctx *ctx);
+
+/* ---- batched sweep: many independent devices advanced together ---------
+ * axp_batch_create pools n built contexts (same precision, each with fields
+ * and particles set) into one set of device arrays; axp_batch_step advances
+ * all of them by n_steps with one launch per phase for the whole pool
+ * (captured in one hipGraph per step).  The contexts are borrowed and must
+ * outlive the batch; their state is read back with axp_batch_sync, after
+ * which the per-context getters return the batched state. */
+axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out);
+axp_status axp_batch_step(axp_batch *b, int32_t n_steps);
+axp_status axp_batch_sync(axp_batch *b);
+void axp_batch_destroy(axp_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AXPIC_H */

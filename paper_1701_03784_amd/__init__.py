@@ -1,0 +1,11 @@
+"""MI355X-native axisymmetric charge-conserving EM-PIC step (arXiv:1701.03784).
+
+The compute lives in the HIP library ``_lib/libaxpic.so`` (C ABI in
+``include/axpic.h``); :mod:`paper_1701_03784_amd.axpic` is its thin ctypes
+binding.  Build with :func:`paper_1701_03784_amd.build.build`.
+"""
+
+from .axpic import (  # noqa: F401
+    Ctx, AxpError, make_ctx, load_library, EXPORTS, LIB_PATH,
+    BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN, PREC_MIXED, PREC_PLAIN_FP64,
+)

@@ -1,0 +1,301 @@
+"""Thin Python binding of the axpic C ABI (include/axpic.h).
+
+Argument marshalling only: numpy arrays are handed to the library as host
+pointers; every step of the simulation runs in the library's HIP kernels.
+PyTorch, when present, supplies the HIP stream (and, optionally, device
+memory through the allocator callback).  The binding refuses to run
+without the built library: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libaxpic.so")
+
+AXP_OK = 0
+ERRORS = {-1: "AXP_E_ARG", -2: "AXP_E_MESH", -3: "AXP_E_SPAI", -4: "AXP_E_UNSTABLE", -5: "AXP_E_OOM",
+          -6: "AXP_E_HIP", -7: "AXP_E_WALK", -8: "AXP_E_FIXED_OVERFLOW", -9: "AXP_E_NAN", -10: "AXP_E_STATE"}
+BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN = 1, 2, 3, 4
+PREC_PLAIN_FP64, PREC_MIXED = 0, 1
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class AxpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("hip_stream", C.c_void_p), ("precision", C.c_int32),
+                ("dt", C.c_double), ("cfl_fraction", C.c_double), ("spai_level", C.c_int32),
+                ("spai_drop_tol", C.c_double), ("sort_period", C.c_int32), ("diag_every", C.c_int32),
+                ("max_walk", C.c_int32), ("use_graph", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_edges", C.c_int64), ("n_faces", C.c_int64),
+                ("n_free_edges", C.c_int64), ("n_free_nodes", C.c_int64), ("spai_nnz", C.c_int64),
+                ("spai_fro_residual", C.c_double), ("spai_max_col_residual", C.c_double),
+                ("dt", C.c_double), ("dt_cfl", C.c_double), ("setup_seconds", C.c_double),
+                ("particle_capacity", C.c_int64), ("n_particles", C.c_int64), ("step", C.c_int64),
+                ("precision", C.c_int32), ("n_species", C.c_int32)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_live", C.c_int64), ("n_absorbed", C.c_int64),
+                ("walk_overflow", C.c_int64), ("nan_count", C.c_int64), ("fixed_overflow", C.c_int64),
+                ("dce_max_abs", C.c_int64), ("dce_max_rel", C.c_double), ("gauss_max_drift", C.c_double),
+                ("gauss_max_abs", C.c_double), ("gauss_scale", C.c_double), ("W_E", C.c_double),
+                ("W_B", C.c_double), ("W_K", C.c_double), ("Q_total", C.c_double)]
+
+
+EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary", "axp_build",
+           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_external_bz",
+           "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
+           "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
+           "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
+           "axp_batch_destroy"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libaxpic.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1701_03784_amd.build.build()")
+    try:
+        # PyTorch carries its own HIP runtime; load it first so that the
+        # library binds to the same one (one HIP runtime per process)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "axp_config_default": (None, [C.POINTER(Config)]),
+        "axp_create": (i32, [C.POINTER(Config), C.POINTER(vp)]),
+        "axp_set_mesh": (i32, [vp, i32, vp, i32, vp]),
+        "axp_set_boundary": (i32, [vp, i32, vp, vp]),
+        "axp_build": (i32, [vp]),
+        "axp_info_get": (i32, [vp, C.POINTER(Info)]),
+        "axp_get_edges": (i32, [vp, vp]),
+        "axp_get_spai": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
+        "axp_set_fields": (i32, [vp, vp, vp]),
+        "axp_set_external_bz": (i32, [vp, dbl]),
+        "axp_add_species": (i32, [vp, dbl, dbl, i64, C.POINTER(i32)]),
+        "axp_inject": (i32, [vp, i32, i64, vp, vp]),
+        "axp_set_injector": (i32, [vp, i32, i64, vp, dbl, C.c_uint64]),
+        "axp_step": (i32, [vp, i32]),
+        "axp_sync": (i32, [vp]),
+        "axp_diag_get": (i32, [vp, C.POINTER(Diag)]),
+        "axp_get_fields": (i32, [vp, vp, vp]),
+        "axp_get_sources": (i32, [vp, vp, vp, vp]),
+        "axp_get_particles": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
+        "axp_save": (i32, [vp, C.c_char_p]),
+        "axp_load": (i32, [vp, C.c_char_p]),
+        "axp_last_error": (C.c_char_p, [vp]),
+        "axp_destroy": (None, [vp]),
+        "axp_batch_create": (i32, [vp, i32, C.POINTER(vp)]),
+        "axp_batch_step": (i32, [vp, i32]),
+        "axp_batch_sync": (i32, [vp]),
+        "axp_batch_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, ptr, user):
+        self.live.pop(int(ptr) if ptr else 0, None)
+
+
+def current_torch_stream(device=0):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream(device).cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Ctx:
+    """One simulated device (mesh + fields + particles) on one GPU."""
+
+    def __init__(self, precision=PREC_MIXED, dt=0.0, cfl_fraction=0.5, spai_level=3, spai_drop_tol=1e-3,
+                 sort_period=4, diag_every=0, max_walk=64, use_graph=1, device=0, stream=None,
+                 torch_memory=False):
+        self.lib = load_library()
+        cfg = Config()
+        self.lib.axp_config_default(C.byref(cfg))
+        cfg.device, cfg.precision, cfg.dt, cfg.cfl_fraction = device, precision, dt, cfl_fraction
+        cfg.spai_level, cfg.spai_drop_tol, cfg.sort_period = spai_level, spai_drop_tol, sort_period
+        cfg.diag_every, cfg.max_walk, cfg.use_graph = diag_every, max_walk, use_graph
+        cfg.hip_stream = stream if stream is not None else current_torch_stream(device)
+        self._allocator = None
+        if torch_memory:
+            self._allocator = TorchAllocator(device)
+            cfg.alloc, cfg.free = self._allocator.alloc_cb, self._allocator.free_cb
+        self.cfg = cfg
+        h = C.c_void_p()
+        self._check(self.lib.axp_create(C.byref(cfg), C.byref(h)), None)
+        self.h = h
+
+    def _check(self, st, h="self"):
+        if st != AXP_OK:
+            msg = ""
+            if h is not None and getattr(self, "h", None):
+                msg = (self.lib.axp_last_error(self.h) or b"").decode()
+            raise AxpError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.axp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- setup
+    def set_mesh(self, nodes, tris):
+        self._nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self._tris = np.ascontiguousarray(tris, dtype=np.int32)
+        self._check(self.lib.axp_set_mesh(self.h, len(self._nodes), _ptr(self._nodes), len(self._tris), _ptr(self._tris)))
+
+    def set_boundary(self, seg, tag):
+        seg = np.ascontiguousarray(seg, dtype=np.int32)
+        tag = np.ascontiguousarray(tag, dtype=np.uint8)
+        self._check(self.lib.axp_set_boundary(self.h, len(seg), _ptr(seg), _ptr(tag)))
+
+    def build(self):
+        self._check(self.lib.axp_build(self.h))
+
+    def info(self):
+        i = Info()
+        self._check(self.lib.axp_info_get(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}
+
+    def get_edges(self):
+        n = self.info()["n_edges"]
+        e = np.zeros((n, 2), dtype=np.int32)
+        self._check(self.lib.axp_get_edges(self.h, _ptr(e)))
+        return e
+
+    def get_spai(self):
+        import scipy.sparse as sp
+        n = self.info()["n_edges"]
+        nnz = C.c_int64()
+        rowptr = np.zeros(n + 1, dtype=np.int64)
+        self.lib.axp_get_spai(self.h, 0, C.byref(nnz), _ptr(rowptr), None, None)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        self._check(self.lib.axp_get_spai(self.h, nnz.value, C.byref(nnz), _ptr(rowptr), _ptr(col), _ptr(val)))
+        return sp.csr_matrix((val, col, rowptr), shape=(n, n))
+
+    def set_fields(self, E0, B_mhalf):
+        E0 = np.ascontiguousarray(E0, dtype=np.float64)
+        B = np.ascontiguousarray(B_mhalf, dtype=np.float64)
+        self._check(self.lib.axp_set_fields(self.h, _ptr(E0), _ptr(B)))
+
+    def set_external_bz(self, bz):
+        self._check(self.lib.axp_set_external_bz(self.h, float(bz)))
+
+    def add_species(self, q, m, weight):
+        sid = C.c_int32()
+        self._check(self.lib.axp_add_species(self.h, float(q), float(m), int(weight), C.byref(sid)))
+        return sid.value
+
+    def inject(self, species, zr, u):
+        zr = np.ascontiguousarray(zr, dtype=np.float64).reshape(-1, 2)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        self._check(self.lib.axp_inject(self.h, int(species), len(zr), _ptr(zr), _ptr(u)))
+
+    def set_injector(self, species, per_step, u_mean, u_spread, seed):
+        um = np.ascontiguousarray(u_mean, dtype=np.float64)
+        self._check(self.lib.axp_set_injector(self.h, int(species), int(per_step), _ptr(um), float(u_spread), int(seed)))
+
+    # ---- run
+    def step(self, n=1):
+        self._check(self.lib.axp_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.axp_sync(self.h))
+
+    def diag(self):
+        d = Diag()
+        self._check(self.lib.axp_diag_get(self.h, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    # ---- read-back
+    def get_fields(self):
+        i = self.info()
+        E = np.zeros(i["n_edges"])
+        B = np.zeros(i["n_faces"])
+        self._check(self.lib.axp_get_fields(self.h, _ptr(E), _ptr(B)))
+        return E, B
+
+    def get_sources(self):
+        i = self.info()
+        D = np.zeros(i["n_edges"])
+        J = np.zeros(i["n_edges"])
+        Q = np.zeros(i["n_nodes"])
+        self._check(self.lib.axp_get_sources(self.h, _ptr(D), _ptr(J), _ptr(Q)))
+        return D, J, Q
+
+    def get_particles(self):
+        n = C.c_int64()
+        self.lib.axp_get_particles(self.h, 0, C.byref(n), None, None, None)
+        cap = n.value
+        zr = np.zeros((cap, 2))
+        u = np.zeros((cap, 3))
+        sp = np.zeros(cap, dtype=np.int32)
+        self._check(self.lib.axp_get_particles(self.h, cap, C.byref(n), _ptr(zr), _ptr(u), _ptr(sp)))
+        return zr[:n.value], u[:n.value], sp[:n.value]
+
+
+def make_ctx(mesh, **kw):
+    """Context with mesh and boundary set and built (mesh: synth.Mesh-like)."""
+    c = Ctx(**kw)
+    c.set_mesh(mesh.nodes, mesh.tris)
+    c.set_boundary(mesh.seg, mesh.tag)
+    c.build()
+    return c

@@ -1,0 +1,112 @@
+// Device-side state of one (or a pool of) meridian devices and the host
+// launchers of the HIP kernels.  Plain pointers only; the host owns them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace axp {
+
+constexpr int kCellBits = 27;                       // face index bits of a particle cell word
+constexpr int32_t kCellMask = (1 << kCellBits) - 1; // species in bits 27..30, sign bit = dead
+constexpr int kMaxSpecies = 16;
+
+// Per-instance constants (one entry per device in a pooled batch).
+struct InstConst {
+    double dt;         // time step [s]
+    double jscale;     // charge unit / (2 pi 2^48): fixed-point current -> D increment [C/rad]
+    double qscale;     // charge unit / (2 pi 2^24): fixed-point charge -> C/rad
+    float cdt;         // c dt [m]
+    float bz;          // external B_z [T]
+    int32_t n_species;
+    int32_t pad;
+    // per species: q dt/(2 m c) [1/(V/m)], q dt/(2 m) [1/T], integer charge multiple
+    float qe[kMaxSpecies];
+    float qb[kMaxSpecies];
+    int32_t kq[kMaxSpecies];
+    double mw[kMaxSpecies];   // m * weight * c^2 / (2 pi) for the kinetic energy [J/rad]
+};
+
+struct DevMesh {
+    int32_t n0 = 0, n1 = 0, n2 = 0, n_inst = 1;
+    // faces (internal order)
+    const float4 *gS = nullptr;     // 2^24 grad lam0 (z, rho), 2^24 grad lam1 (z, rho)
+    const float4 *rho4 = nullptr;   // rho of local nodes 0..2, 1/(2 area)
+    const int4 *nbr = nullptr;      // face across side k (>= 0) or -tag; w: neighbour-local ids, 4 bits/side
+    const int4 *tedge = nullptr;    // edge of side k; w: bit k set -> incidence sign -1
+    const int4 *tnodes = nullptr;   // node ids of local nodes 0..2
+    const double *Hdt = nullptr;    // dt [*mu^-1]_T
+    const int32_t *tinst = nullptr; // instance of each face (pooled batches), or null
+    // edges
+    const int4 *etri = nullptr;     // left face, right face (-1), packed sides/signs/free, instance
+    // nodes: incident edges with divergence sign
+    const int32_t *nptr = nullptr, *nedge = nullptr;
+    const int8_t *nsign = nullptr;
+    const uint8_t *nfree = nullptr;
+    const int32_t *ninst = nullptr; // instance of each node, or null
+    // SPAI M in sliced-ELL (slices of 64 rows, column-major inside a slice)
+    const int64_t *m_sptr = nullptr;
+    const int32_t *m_slen = nullptr;
+    const float *m_val = nullptr;
+    const int32_t *m_col = nullptr;
+    // [*eps] in CSR (energy diagnostic)
+    const int64_t *a_ptr = nullptr;
+    const int32_t *a_col = nullptr;
+    const double *a_val = nullptr;
+    const InstConst *inst = nullptr;
+};
+
+struct DevCounters {
+    unsigned long long n_slots;       // particle slots in use (live + dead until the next sort)
+    unsigned long long n_absorbed;
+    unsigned long long walk_overflow;
+    unsigned long long nan_count;
+    unsigned long long fixed_overflow;
+    unsigned long long pad[3];
+};
+
+struct DevDiag {
+    unsigned long long gauss_drift_bits;  // max |res^n - res^0| (double bits, >= 0)
+    unsigned long long gauss_abs_bits;
+    unsigned long long gauss_scale_bits;
+    unsigned long long dce_max;           // max |2^24 dQ + Ddiv J| (fixed point)
+    double WE, WB, WK, Qtot;
+};
+
+struct DevState {
+    // fields
+    double *B = nullptr;        // face flux, B^{n-1/2} before a step, B^{n+1/2} after its first kernel
+    double *Bprev = nullptr;    // B^{n-1/2} of the last step
+    double *HBdt = nullptr;     // dt H B^{n+1/2}
+    float4 *f0 = nullptr, *f1 = nullptr;  // gather tile per face
+    unsigned long long *Jloc = nullptr;   // fixed-point current per face side (3 per face)
+    double *D = nullptr;        // [*eps]_a E on edges (FP64)
+    float *D32 = nullptr;       // FP32 copy read by the SpMV
+    float *E = nullptr;         // E on edges
+    long long *Jfx = nullptr;   // fixed-point edge current of the last step (diagnostic)
+    long long *Qres = nullptr;  // fixed-point wall/emitter charge per node (units 2^-24 charge unit)
+    long long *Qfx = nullptr;   // fixed-point nodal charge (diagnostic)
+    long long *Qprev = nullptr;
+    double *g0 = nullptr;       // Gauss residual at the first diagnostic
+    // particles (structure of arrays, two buffers for the sort)
+    int32_t *cell[2] = {nullptr, nullptr};
+    uint32_t *L0[2] = {nullptr, nullptr}, *L1[2] = {nullptr, nullptr};
+    float *ur[2] = {nullptr, nullptr}, *up[2] = {nullptr, nullptr}, *uz[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t capacity = 0;
+    // sort scratch
+    int32_t *cnt = nullptr;     // n2 + 1
+    int32_t *blk = nullptr;     // scan block sums
+    DevCounters *ctr = nullptr;
+    DevDiag *diag = nullptr;
+};
+
+// ---- launchers (kernels_mixed.hip) ----
+void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, hipStream_t st);
+void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st);
+void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);
+void launch_sort(const DevMesh &m, DevState &s, hipStream_t st);
+void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st);
+
+}  // namespace axp

@@ -1,0 +1,562 @@
+// Host-side FP64 setup: topology (App. D), Hodge matrices (Sec. 3.1, App. B),
+// plain SPAI of [*eps] (Sec. 3.1), leapfrog stability limit, CG, locator.
+#include "host_setup.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+
+#include "../../include/axpic.h"
+
+namespace axp {
+
+void Csr::spmv(const double *x, double *y) const {
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0;
+        for (int64_t j = ptr[i]; j < ptr[i + 1]; ++j) s += val[j] * x[col[j]];
+        y[i] = s;
+    }
+}
+
+static inline uint64_t edge_key(int32_t a, int32_t b) {
+    if (a > b) std::swap(a, b);
+    return (uint64_t(uint32_t(a)) << 32) | uint32_t(b);
+}
+
+// Position of (x, y) on a Hilbert curve over a 2^order grid (iterative
+// quadrant rotation of the classical construction).
+static uint64_t hilbert_index(uint32_t x, uint32_t y, int order) {
+    uint64_t d = 0;
+    for (uint32_t s = 1u << (order - 1); s > 0; s >>= 1) {
+        uint32_t rx = (x & s) ? 1 : 0;
+        uint32_t ry = (y & s) ? 1 : 0;
+        d += uint64_t(s) * uint64_t(s) * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = s - 1 - x;
+                y = s - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tris, const int32_t *tri,
+                    int32_t n_seg, const int32_t *seg, const uint8_t *tag) {
+    m.n0 = n_nodes;
+    m.n2 = n_tris;
+    m.z.resize(n_nodes);
+    m.r.resize(n_nodes);
+    for (int i = 0; i < n_nodes; ++i) {
+        m.z[i] = zr[2 * i];
+        m.r[i] = zr[2 * i + 1];
+        if (!(m.r[i] >= 0.0) || !std::isfinite(m.z[i])) throw SetupError{AXP_E_MESH, "node with rho < 0 or non-finite"};
+    }
+    // locality order of faces: Hilbert index of the centroid
+    double zmin = 1e300, zmax = -1e300, rmin = 1e300, rmax = -1e300;
+    for (int i = 0; i < n_nodes; ++i) {
+        zmin = std::min(zmin, m.z[i]); zmax = std::max(zmax, m.z[i]);
+        rmin = std::min(rmin, m.r[i]); rmax = std::max(rmax, m.r[i]);
+    }
+    double ext = std::max(zmax - zmin, rmax - rmin);
+    if (!(ext > 0)) throw SetupError{AXP_E_MESH, "degenerate node set"};
+    std::vector<std::pair<uint64_t, int32_t>> order(n_tris);
+    for (int t = 0; t < n_tris; ++t) {
+        const int32_t *v = tri + 3 * t;
+        for (int k = 0; k < 3; ++k)
+            if (v[k] < 0 || v[k] >= n_nodes) throw SetupError{AXP_E_MESH, "triangle node id out of range"};
+        double a2 = (m.z[v[1]] - m.z[v[0]]) * (m.r[v[2]] - m.r[v[0]]) - (m.z[v[2]] - m.z[v[0]]) * (m.r[v[1]] - m.r[v[0]]);
+        if (!(a2 > 0)) throw SetupError{AXP_E_MESH, "triangle " + std::to_string(t) + " is not counter-clockwise in (z, rho)"};
+        double cz = (m.z[v[0]] + m.z[v[1]] + m.z[v[2]]) / 3.0, cr = (m.r[v[0]] + m.r[v[1]] + m.r[v[2]]) / 3.0;
+        uint32_t qx = uint32_t(std::min(65535.0, std::floor((cz - zmin) / ext * 65536.0)));
+        uint32_t qy = uint32_t(std::min(65535.0, std::floor((cr - rmin) / ext * 65536.0)));
+        order[t] = {hilbert_index(qx, qy, 16), t};
+    }
+    std::sort(order.begin(), order.end());
+    m.tri_user.resize(n_tris);
+    m.tri_int.resize(n_tris);
+    m.tv.resize(n_tris);
+    for (int t = 0; t < n_tris; ++t) {
+        int u = order[t].second;
+        m.tri_user[t] = u;
+        m.tri_int[u] = t;
+        m.tv[t] = {tri[3 * u], tri[3 * u + 1], tri[3 * u + 2]};
+    }
+    // edges numbered by first appearance along the face order
+    std::unordered_map<uint64_t, int32_t> eid;
+    eid.reserve(size_t(n_tris) * 2);
+    m.tedge.resize(n_tris);
+    m.tsign.resize(n_tris);
+    m.ev.clear();
+    std::vector<std::array<int32_t, 2>> etri;
+    std::vector<std::array<int8_t, 2>> eside;
+    for (int t = 0; t < n_tris; ++t) {
+        for (int k = 0; k < 3; ++k) {
+            int32_t a = m.tv[t][(k + 1) % 3], b = m.tv[t][(k + 2) % 3];   // side k: a -> b (CCW)
+            uint64_t key = edge_key(a, b);
+            auto it = eid.find(key);
+            int32_t e;
+            if (it == eid.end()) {
+                e = int32_t(m.ev.size());
+                eid.emplace(key, e);
+                m.ev.push_back({std::min(a, b), std::max(a, b)});
+                etri.push_back({t, -1});
+                eside.push_back({int8_t(k), int8_t(-1)});
+            } else {
+                e = it->second;
+                if (etri[e][1] >= 0) throw SetupError{AXP_E_MESH, "edge shared by more than two triangles"};
+                etri[e][1] = t;
+                eside[e][1] = int8_t(k);
+            }
+            m.tedge[t][k] = e;
+            m.tsign[t][k] = (a < b) ? 1 : -1;
+        }
+    }
+    m.n1 = int32_t(m.ev.size());
+    m.etri = etri;
+    m.eside = eside;
+    // canonical (sorted) edge order for the interface
+    std::vector<int32_t> idx(m.n1);
+    for (int i = 0; i < m.n1; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return m.ev[x] < m.ev[y]; });
+    m.edge_int = idx;
+    m.edge_can.resize(m.n1);
+    for (int c = 0; c < m.n1; ++c) m.edge_can[idx[c]] = c;
+    // boundary tags
+    std::unordered_map<uint64_t, int> stag;
+    for (int s = 0; s < n_seg; ++s) stag[edge_key(seg[2 * s], seg[2 * s + 1])] = tag[s];
+    m.etag.assign(m.n1, TAG_NONE);
+    m.tnbr.resize(n_tris);
+    m.tnbr_map.assign(n_tris, 0u);
+    for (int e = 0; e < m.n1; ++e) {
+        if (m.etri[e][1] < 0) {
+            auto it = stag.find(edge_key(m.ev[e][0], m.ev[e][1]));
+            if (it == stag.end())
+                throw SetupError{AXP_E_MESH, "boundary edge (" + std::to_string(m.ev[e][0]) + "," +
+                                                 std::to_string(m.ev[e][1]) + ") has no boundary tag"};
+            if (it->second < TAG_PEC || it->second > TAG_OPEN) throw SetupError{AXP_E_MESH, "unknown boundary tag"};
+            m.etag[e] = it->second;
+        }
+    }
+    for (int t = 0; t < n_tris; ++t) {
+        for (int k = 0; k < 3; ++k) {
+            int e = m.tedge[t][k];
+            int other = (m.etri[e][0] == t) ? m.etri[e][1] : m.etri[e][0];
+            if (other < 0) {
+                m.tnbr[t][k] = -m.etag[e];
+            } else {
+                m.tnbr[t][k] = other;
+                int32_t a = m.tv[t][(k + 1) % 3], b = m.tv[t][(k + 2) % 3];
+                uint32_t pa = 3, pb = 3;
+                for (int j = 0; j < 3; ++j) {
+                    if (m.tv[other][j] == a) pa = j;
+                    if (m.tv[other][j] == b) pb = j;
+                }
+                m.tnbr_map[t] |= (pa | (pb << 2)) << (4 * k);
+            }
+        }
+    }
+    m.efree.resize(m.n1);
+    m.nfree.assign(m.n0, 1);
+    m.n_free_edges = 0;
+    for (int e = 0; e < m.n1; ++e) {
+        bool cond = (m.etag[e] == TAG_PEC || m.etag[e] == TAG_EMITTER);
+        m.efree[e] = cond ? 0 : 1;
+        m.n_free_edges += m.efree[e];
+        if (cond) m.nfree[m.ev[e][0]] = m.nfree[m.ev[e][1]] = 0;
+    }
+    m.n_free_nodes = 0;
+    for (int v = 0; v < m.n0; ++v) m.n_free_nodes += m.nfree[v];
+    // node -> edges with divergence sign (+1 at the tail, -1 at the head)
+    m.nptr.assign(m.n0 + 1, 0);
+    for (int e = 0; e < m.n1; ++e) { m.nptr[m.ev[e][0] + 1]++; m.nptr[m.ev[e][1] + 1]++; }
+    for (int v = 0; v < m.n0; ++v) m.nptr[v + 1] += m.nptr[v];
+    m.nedge.resize(m.nptr[m.n0]);
+    m.nsign.resize(m.nptr[m.n0]);
+    std::vector<int32_t> cur(m.nptr.begin(), m.nptr.end() - 1);
+    for (int e = 0; e < m.n1; ++e) {
+        int c0 = cur[m.ev[e][0]]++, c1 = cur[m.ev[e][1]]++;
+        m.nedge[c0] = e; m.nsign[c0] = 1;
+        m.nedge[c1] = e; m.nsign[c1] = -1;
+    }
+    // geometry
+    m.area.resize(n_tris);
+    m.grad.resize(n_tris);
+    for (int t = 0; t < n_tris; ++t) {
+        double zz[3], rr[3];
+        for (int k = 0; k < 3; ++k) { zz[k] = m.z[m.tv[t][k]]; rr[k] = m.r[m.tv[t][k]]; }
+        double a2 = (zz[1] - zz[0]) * (rr[2] - rr[0]) - (zz[2] - zz[0]) * (rr[1] - rr[0]);
+        m.area[t] = 0.5 * a2;
+        for (int k = 0; k < 3; ++k) {
+            int j = (k + 1) % 3, l = (k + 2) % 3;
+            m.grad[t][2 * k] = (rr[j] - rr[l]) / a2;       // d lambda_k / dz
+            m.grad[t][2 * k + 1] = (zz[l] - zz[j]) / a2;   // d lambda_k / drho
+        }
+    }
+}
+
+// int_T lambda_i lambda_j lambda_k dA = 2 Area (product of multiplicity factorials) / 5!
+static double moment3(int i, int j, int k, double area) {
+    int c[3] = {0, 0, 0};
+    c[i]++; c[j]++; c[k]++;
+    static const double fact[4] = {1, 1, 2, 6};
+    return 2.0 * area * fact[c[0]] * fact[c[1]] * fact[c[2]] / 120.0;
+}
+
+void assemble_hodge(HostMesh &m) {
+    // [*eps]_ij = eps0 int rho W_i . W_j, W_(a,b) = lam_a grad lam_b - lam_b grad lam_a
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(m.n1);
+    for (auto &r : rows) r.reserve(5);
+    m.H.resize(m.n2);
+    for (int t = 0; t < m.n2; ++t) {
+        const auto &g = m.grad[t];
+        double gg[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) gg[a][b] = g[2 * a] * g[2 * b] + g[2 * a + 1] * g[2 * b + 1];
+        double rho[3] = {m.r[m.tv[t][0]], m.r[m.tv[t][1]], m.r[m.tv[t][2]]};
+        int ta[3], hb[3];
+        for (int k = 0; k < 3; ++k) {
+            int32_t e = m.tedge[t][k];
+            int la = (k + 1) % 3, lb = (k + 2) % 3;   // CCW side from la to lb
+            if (m.tv[t][la] == m.ev[e][0]) { ta[k] = la; hb[k] = lb; } else { ta[k] = lb; hb[k] = la; }
+        }
+        for (int k = 0; k < 3; ++k) {
+            for (int l = 0; l < 3; ++l) {
+                int a = ta[k], b = hb[k], c = ta[l], d = hb[l];
+                double s = 0;
+                for (int q = 0; q < 3; ++q) {
+                    double A = m.area[t];
+                    s += rho[q] * (moment3(q, a, c, A) * gg[b][d] - moment3(q, a, d, A) * gg[b][c] -
+                                   moment3(q, b, c, A) * gg[a][d] + moment3(q, b, d, A) * gg[a][c]);
+                }
+                int32_t ek = m.tedge[t][k], el = m.tedge[t][l];
+                auto &row = rows[ek];
+                bool found = false;
+                for (auto &p : row)
+                    if (p.first == el) { p.second += kEps0 * s; found = true; break; }
+                if (!found) row.push_back({el, kEps0 * s});
+            }
+        }
+        // [*mu^-1]_T = (1/mu0) int_T rho (W2)^2, W2 = 1/Area
+        m.H[t] = (rho[0] + rho[1] + rho[2]) / (3.0 * kMu0 * m.area[t]);
+    }
+    m.A.n = m.n1;
+    m.A.ptr.assign(m.n1 + 1, 0);
+    for (int i = 0; i < m.n1; ++i) {
+        std::sort(rows[i].begin(), rows[i].end());
+        m.A.ptr[i + 1] = m.A.ptr[i] + int64_t(rows[i].size());
+    }
+    m.A.col.resize(m.A.ptr[m.n1]);
+    m.A.val.resize(m.A.ptr[m.n1]);
+    for (int i = 0; i < m.n1; ++i)
+        for (size_t j = 0; j < rows[i].size(); ++j) {
+            m.A.col[m.A.ptr[i] + j] = rows[i][j].first;
+            m.A.val[m.A.ptr[i] + j] = rows[i][j].second;
+        }
+}
+
+// Dense least squares min ||B x - b|| by Householder QR (B: rows x cols,
+// column-major, modified in place).  Returns false if a pivot vanishes.
+static bool householder_ls(int rows, int cols, double *B, double *b, double *x) {
+    for (int j = 0; j < cols; ++j) {
+        double *cj = B + size_t(j) * rows;
+        double norm = 0;
+        for (int i = j; i < rows; ++i) norm += cj[i] * cj[i];
+        norm = std::sqrt(norm);
+        if (norm == 0.0) return false;
+        double alpha = cj[j] > 0 ? -norm : norm;
+        double v0 = cj[j] - alpha;
+        // v = (v0, cj[j+1..]); H = I - 2 v v^T / (v^T v)
+        double vtv = v0 * v0;
+        for (int i = j + 1; i < rows; ++i) vtv += cj[i] * cj[i];
+        cj[j] = v0;
+        for (int c = j + 1; c < cols; ++c) {
+            double *cc = B + size_t(c) * rows;
+            double s = 0;
+            for (int i = j; i < rows; ++i) s += cj[i] * cc[i];
+            s = 2.0 * s / vtv;
+            for (int i = j; i < rows; ++i) cc[i] -= s * cj[i];
+        }
+        double s = 0;
+        for (int i = j; i < rows; ++i) s += cj[i] * b[i];
+        s = 2.0 * s / vtv;
+        for (int i = j; i < rows; ++i) b[i] -= s * cj[i];
+        cj[j] = alpha;   // R diagonal
+    }
+    for (int j = cols - 1; j >= 0; --j) {
+        double s = b[j];
+        for (int c = j + 1; c < cols; ++c) s -= B[size_t(c) * rows + j] * x[c];
+        double d = B[size_t(j) * rows + j];
+        if (d == 0.0) return false;
+        x[j] = s / d;
+    }
+    return true;
+}
+
+void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
+    // free-edge numbering and Jacobi scaling A^ = S^-1/2 A S^-1/2
+    std::vector<int32_t> fidx(m.n1, -1), fedge;
+    for (int e = 0; e < m.n1; ++e)
+        if (m.efree[e]) { fidx[e] = int32_t(fedge.size()); fedge.push_back(e); }
+    const int nf = int(fedge.size());
+    std::vector<double> s(nf);
+    std::vector<std::vector<std::pair<int32_t, double>>> adj(nf);   // scaled rows over free edges
+    for (int i = 0; i < nf; ++i) {
+        int e = fedge[i];
+        double d = 0;
+        for (int64_t j = m.A.ptr[e]; j < m.A.ptr[e + 1]; ++j)
+            if (m.A.col[j] == e) d = m.A.val[j];
+        if (!(d > 0)) throw SetupError{AXP_E_SPAI, "non-positive diagonal of [*eps]"};
+        s[i] = 1.0 / std::sqrt(d);
+    }
+    for (int i = 0; i < nf; ++i) {
+        int e = fedge[i];
+        for (int64_t j = m.A.ptr[e]; j < m.A.ptr[e + 1]; ++j) {
+            int c = fidx[m.A.col[j]];
+            if (c >= 0 && m.A.val[j] != 0.0) adj[i].push_back({c, s[i] * m.A.val[j] * s[c]});
+        }
+    }
+    // column k: pattern J_k = nodes within `level` hops, rows I_k = J_k plus one more hop
+    struct Entry { int32_t row, col; double v; };
+    std::vector<std::vector<Entry>> per_thread(std::max(1, n_threads));
+    std::atomic<int> next{0};
+    std::atomic<bool> failed{false};
+    auto work = [&](int tid) {
+        std::vector<int32_t> mark(nf, -1), rmark(nf, -1);
+        std::vector<int32_t> J, I, frontier, nxt;
+        std::vector<double> B, rhs, x;
+        auto &out = per_thread[tid];
+        for (;;) {
+            int k0 = next.fetch_add(64);
+            if (k0 >= nf || failed.load()) break;
+            for (int k = k0; k < std::min(nf, k0 + 64); ++k) {
+                J.clear(); frontier.clear();
+                J.push_back(k); frontier.push_back(k); mark[k] = k;
+                for (int l = 0; l < level; ++l) {   // structure of A^level: within `level` hops
+                    nxt.clear();
+                    for (int u : frontier)
+                        for (auto &p : adj[u])
+                            if (mark[p.first] != k) { mark[p.first] = k; nxt.push_back(p.first); J.push_back(p.first); }
+                    frontier.swap(nxt);
+                }
+                std::sort(J.begin(), J.end());
+                I.clear();
+                for (int j : J)
+                    for (auto &p : adj[j])
+                        if (rmark[p.first] != k) { rmark[p.first] = k; I.push_back(p.first); }
+                std::sort(I.begin(), I.end());
+                const int nr = int(I.size()), nc = int(J.size());
+                B.assign(size_t(nr) * nc, 0.0);
+                for (int c = 0; c < nc; ++c) {
+                    for (auto &p : adj[J[c]]) {
+                        int r = int(std::lower_bound(I.begin(), I.end(), p.first) - I.begin());
+                        B[size_t(c) * nr + r] = p.second;   // A^ symmetric: column J[c] = row J[c]
+                    }
+                }
+                rhs.assign(nr, 0.0);
+                rhs[std::lower_bound(I.begin(), I.end(), k) - I.begin()] = 1.0;
+                x.assign(nc, 0.0);
+                if (!householder_ls(nr, nc, B.data(), rhs.data(), x.data())) { failed = true; break; }
+                double mx = 0;
+                for (double v : x) mx = std::max(mx, std::fabs(v));
+                for (int c = 0; c < nc; ++c)
+                    if (std::fabs(x[c]) >= drop_tol * mx) out.push_back({J[c], k, x[c]});
+            }
+        }
+    };
+    int nt = std::max(1, n_threads);
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &t : th) t.join();
+    if (failed) throw SetupError{AXP_E_SPAI, "rank-deficient SPAI least-squares block"};
+    // symmetric average (M^ + M^T)/2 and unscaling, into CSR over internal edges
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
+    for (auto &v : per_thread)
+        for (auto &e : v) {
+            rows[e.row].push_back({e.col, 0.5 * e.v});
+            rows[e.col].push_back({e.row, 0.5 * e.v});
+        }
+    m.M.n = m.n1;
+    m.M.ptr.assign(m.n1 + 1, 0);
+    std::vector<std::vector<std::pair<int32_t, double>>> merged(nf);
+    for (int i = 0; i < nf; ++i) {
+        auto &r = rows[i];
+        std::sort(r.begin(), r.end());
+        for (auto &p : r) {
+            if (!merged[i].empty() && merged[i].back().first == p.first) merged[i].back().second += p.second;
+            else merged[i].push_back(p);
+        }
+        rows[i].clear();
+        rows[i].shrink_to_fit();
+    }
+    for (int e = 0; e < m.n1; ++e) {
+        int i = fidx[e];
+        m.M.ptr[e + 1] = m.M.ptr[e] + (i >= 0 ? int64_t(merged[i].size()) : 0);
+    }
+    m.M.col.resize(m.M.ptr[m.n1]);
+    m.M.val.resize(m.M.ptr[m.n1]);
+    for (int e = 0; e < m.n1; ++e) {
+        int i = fidx[e];
+        if (i < 0) continue;
+        int64_t o = m.M.ptr[e];
+        for (auto &p : merged[i]) {
+            m.M.col[o] = fedge[p.first];
+            m.M.val[o] = s[i] * p.second * s[p.first];
+            ++o;
+        }
+    }
+    m.spai_nnz = m.M.ptr[m.n1];
+    // residual of each column: A m_k - e_k (M symmetric: column k = row k)
+    double fro = 0, mxc = 0;
+    std::vector<double> acc(m.n1, 0.0);
+    std::vector<int32_t> touched;
+    for (int e = 0; e < m.n1; ++e) {
+        if (!m.efree[e]) continue;
+        touched.clear();
+        for (int64_t j = m.M.ptr[e]; j < m.M.ptr[e + 1]; ++j) {
+            int c = m.M.col[j];
+            for (int64_t q = m.A.ptr[c]; q < m.A.ptr[c + 1]; ++q) {
+                int r = m.A.col[q];
+                if (!m.efree[r]) continue;
+                if (acc[r] == 0.0) touched.push_back(r);
+                acc[r] += m.A.val[q] * m.M.val[j];
+            }
+        }
+        acc[e] -= 1.0;
+        if (std::find(touched.begin(), touched.end(), e) == touched.end()) touched.push_back(e);
+        double col2 = 0;
+        for (int r : touched) { col2 += acc[r] * acc[r]; acc[r] = 0.0; }
+        fro += col2;
+        mxc = std::max(mxc, std::sqrt(col2));
+    }
+    m.spai_fro = std::sqrt(fro / std::max(1, nf));
+    m.spai_max_col = mxc;
+}
+
+// y = K x with K = C^T diag(H) C restricted to free edges
+static void apply_K(const HostMesh &m, const double *x, double *y, std::vector<double> &tmp) {
+    tmp.assign(m.n2, 0.0);
+    for (int t = 0; t < m.n2; ++t) {
+        double c = 0;
+        for (int k = 0; k < 3; ++k) {
+            int e = m.tedge[t][k];
+            if (m.efree[e]) c += m.tsign[t][k] * x[e];
+        }
+        tmp[t] = m.H[t] * c;
+    }
+    for (int e = 0; e < m.n1; ++e) {
+        double s = 0;
+        if (m.efree[e])
+            for (int q = 0; q < 2; ++q) {
+                int t = m.etri[e][q];
+                if (t < 0) continue;
+                s += m.tsign[t][m.eside[e][q]] * tmp[t];
+            }
+        y[e] = s;
+    }
+}
+
+double cfl_dt(const HostMesh &m, int iters) {
+    std::vector<double> x(m.n1), y(m.n1), w(m.n1), tmp;
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (int e = 0; e < m.n1; ++e) {
+        st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+        x[e] = m.efree[e] ? (double(st >> 11) / 9007199254740992.0 - 0.5) : 0.0;
+    }
+    double lam = 0;
+    for (int it = 0; it < iters; ++it) {
+        apply_K(m, x.data(), w.data(), tmp);
+        m.M.spmv(w.data(), y.data());
+        double n2 = 0, nx = 0;
+        for (int e = 0; e < m.n1; ++e) { n2 += y[e] * y[e]; nx += x[e] * x[e]; }
+        lam = std::sqrt(n2 / nx);
+        double inv = 1.0 / std::sqrt(n2);
+        for (int e = 0; e < m.n1; ++e) x[e] = y[e] * inv;
+    }
+    return 2.0 / std::sqrt(lam);
+}
+
+int cg_solve_M(const HostMesh &m, const double *b, double *x, double rtol, int max_iter) {
+    const int n = m.n1;
+    std::vector<double> r(n), p(n), q(n);
+    for (int e = 0; e < n; ++e) x[e] = 0.0;
+    double bb = 0;
+    for (int e = 0; e < n; ++e) { r[e] = m.efree[e] ? b[e] : 0.0; p[e] = r[e]; bb += r[e] * r[e]; }
+    if (bb == 0.0) return 0;
+    double rr = bb;
+    int it = 0;
+    for (; it < max_iter && rr > rtol * rtol * bb; ++it) {
+        m.M.spmv(p.data(), q.data());
+        double pq = 0;
+        for (int e = 0; e < n; ++e) pq += p[e] * q[e];
+        double a = rr / pq;
+        double rn = 0;
+        for (int e = 0; e < n; ++e) { x[e] += a * p[e]; r[e] -= a * q[e]; rn += r[e] * r[e]; }
+        double beta = rn / rr;
+        rr = rn;
+        for (int e = 0; e < n; ++e) p[e] = r[e] + beta * p[e];
+    }
+    return it;
+}
+
+void build_locator(HostMesh &m) {
+    double zmin = 1e300, zmax = -1e300, rmin = 1e300, rmax = -1e300;
+    for (int i = 0; i < m.n0; ++i) {
+        zmin = std::min(zmin, m.z[i]); zmax = std::max(zmax, m.z[i]);
+        rmin = std::min(rmin, m.r[i]); rmax = std::max(rmax, m.r[i]);
+    }
+    double area = (zmax - zmin) * (rmax - rmin);
+    double cell = std::sqrt(std::max(area, 1e-300) / std::max(1, m.n2) * 2.0);
+    m.gnz = std::max(1, int((zmax - zmin) / cell) + 1);
+    m.gnr = std::max(1, int((rmax - rmin) / cell) + 1);
+    m.gz0 = zmin; m.gr0 = rmin;
+    m.ghz = (zmax - zmin) / m.gnz + 1e-300;
+    m.ghr = (rmax - rmin) / m.gnr + 1e-300;
+    std::vector<std::vector<int32_t>> cells(size_t(m.gnz) * m.gnr);
+    for (int t = 0; t < m.n2; ++t) {
+        double z0 = 1e300, z1 = -1e300, r0 = 1e300, r1 = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            z0 = std::min(z0, m.z[m.tv[t][k]]); z1 = std::max(z1, m.z[m.tv[t][k]]);
+            r0 = std::min(r0, m.r[m.tv[t][k]]); r1 = std::max(r1, m.r[m.tv[t][k]]);
+        }
+        int iz0 = std::max(0, int((z0 - m.gz0) / m.ghz)), iz1 = std::min(m.gnz - 1, int((z1 - m.gz0) / m.ghz));
+        int ir0 = std::max(0, int((r0 - m.gr0) / m.ghr)), ir1 = std::min(m.gnr - 1, int((r1 - m.gr0) / m.ghr));
+        for (int a = iz0; a <= iz1; ++a)
+            for (int b = ir0; b <= ir1; ++b) cells[size_t(a) * m.gnr + b].push_back(t);
+    }
+    m.gptr.assign(cells.size() + 1, 0);
+    for (size_t c = 0; c < cells.size(); ++c) m.gptr[c + 1] = m.gptr[c] + int32_t(cells[c].size());
+    m.gtri.resize(m.gptr.back());
+    for (size_t c = 0; c < cells.size(); ++c) std::copy(cells[c].begin(), cells[c].end(), m.gtri.begin() + m.gptr[c]);
+}
+
+int32_t locate_point(const HostMesh &m, double z, double rho, double lam[3]) {
+    int iz = int((z - m.gz0) / m.ghz), ir = int((rho - m.gr0) / m.ghr);
+    int best = -1;
+    double bestv = -1e300, bl[3] = {0, 0, 0};
+    for (int a = std::max(0, iz - 1); a <= std::min(m.gnz - 1, iz + 1); ++a)
+        for (int b = std::max(0, ir - 1); b <= std::min(m.gnr - 1, ir + 1); ++b) {
+            size_t c = size_t(a) * m.gnr + b;
+            for (int32_t q = m.gptr[c]; q < m.gptr[c + 1]; ++q) {
+                int t = m.gtri[q];
+                double l[3];
+                for (int k = 0; k < 3; ++k) {
+                    int j = (k + 1) % 3, n = (k + 2) % 3;
+                    double zj = m.z[m.tv[t][j]], rj = m.r[m.tv[t][j]], zn = m.z[m.tv[t][n]], rn = m.r[m.tv[t][n]];
+                    l[k] = 0.5 * ((zj - z) * (rn - rho) - (zn - z) * (rj - rho)) / m.area[t];
+                }
+                double mn = std::min(l[0], std::min(l[1], l[2]));
+                if (mn > bestv) { bestv = mn; best = t; bl[0] = l[0]; bl[1] = l[1]; bl[2] = l[2]; }
+            }
+        }
+    if (best < 0 || bestv < -1e-9) return -1;
+    for (int k = 0; k < 3; ++k) lam[k] = bl[k];
+    return best;
+}
+
+}  // namespace axp

@@ -1,0 +1,85 @@
+// Host-side (FP64) setup of the axisymmetric EM-PIC discretisation: mesh
+// topology and locality order, Hodge matrices, SPAI, stability limit, CG.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace axp {
+
+constexpr double kC = 299792458.0;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kMu0 = 1.0 / (kEps0 * kC * kC);
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr int kLamBits = 24;                       // element-local fixed point: lambda * 2^24
+constexpr int64_t kLamOne = int64_t(1) << kLamBits;
+
+enum Tag : int { TAG_NONE = 0, TAG_PEC = 1, TAG_AXIS = 2, TAG_EMITTER = 3, TAG_OPEN = 4 };
+
+struct Csr {
+    int64_t n = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    void spmv(const double *x, double *y) const;
+};
+
+struct SetupError {
+    int code;
+    std::string msg;
+};
+
+// Mesh in the library's internal numbering.  Local node k of a triangle is
+// opposite its side k; side k runs from local node k+1 to k+2 (counter-
+// clockwise), so its incidence sign is +1 when that direction agrees with
+// the edge orientation tail -> head (tail < head, global node ids).
+struct HostMesh {
+    int32_t n0 = 0, n1 = 0, n2 = 0;
+    std::vector<double> z, r;                      // node coordinates, user order
+    std::vector<int32_t> tri_user;                 // internal face -> user face
+    std::vector<int32_t> tri_int;                  // user face -> internal face
+    std::vector<std::array<int32_t, 3>> tv;        // internal face -> nodes (CCW)
+    std::vector<std::array<int32_t, 2>> ev;        // internal edge -> (tail, head)
+    std::vector<int32_t> edge_can;                 // internal edge -> canonical edge
+    std::vector<int32_t> edge_int;                 // canonical edge -> internal edge
+    std::vector<std::array<int32_t, 3>> tedge;     // face side k -> internal edge
+    std::vector<std::array<int8_t, 3>> tsign;      // face side k -> incidence sign
+    std::vector<std::array<int32_t, 3>> tnbr;      // face across side k, or -tag
+    std::vector<uint32_t> tnbr_map;                // 4 bits per side: local ids in the neighbour
+    std::vector<std::array<int32_t, 2>> etri;      // edge -> (left face, right face or -1)
+    std::vector<std::array<int8_t, 2>> eside;      // side index of the edge in those faces
+    std::vector<int32_t> etag;                     // 0 interior, else boundary tag
+    std::vector<uint8_t> efree;                    // E unknown on the edge
+    std::vector<uint8_t> nfree;                    // node touches no conductor edge
+    std::vector<double> area;                      // face areas (internal)
+    std::vector<std::array<double, 6>> grad;       // grad lambda_k (z, rho) per face
+    std::vector<double> H;                         // [*mu^-1] diagonal (internal faces)
+    Csr A;                                         // [*eps] over internal edges
+    Csr M;                                         // SPAI of [*eps] (free rows/cols)
+    double spai_fro = 0, spai_max_col = 0;
+    int64_t spai_nnz = 0;
+    int32_t n_free_edges = 0, n_free_nodes = 0;
+    // node -> incident edges with divergence sign (+1 tail, -1 head)
+    std::vector<int32_t> nptr, nedge;
+    std::vector<int8_t> nsign;
+    // point location grid
+    double gz0 = 0, gr0 = 0, ghz = 1, ghr = 1;
+    int32_t gnz = 0, gnr = 0;
+    std::vector<int32_t> gptr, gtri;
+};
+
+// Builds topology, locality order and incidence.  seg: boundary segments.
+void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tris, const int32_t *tri,
+                    int32_t n_seg, const int32_t *seg, const uint8_t *tag);
+void assemble_hodge(HostMesh &m);
+void build_spai(HostMesh &m, int level, double drop_tol, int n_threads);
+double cfl_dt(const HostMesh &m, int iters);
+// Solves M x = b on free edges (conjugate gradients, FP64); returns iterations.
+int cg_solve_M(const HostMesh &m, const double *b, double *x, double rtol, int max_iter);
+void build_locator(HostMesh &m);
+// Locates (z, rho); returns the internal face and barycentric coordinates, or -1.
+int32_t locate_point(const HostMesh &m, double z, double rho, double lam[3]);
+
+}  // namespace axp

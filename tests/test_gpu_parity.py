@@ -1,0 +1,166 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Cavity workload: ~2,000 faces, TM010 field, 10,000 electrons at 0.5 c.
+Tolerances: setup products (edge list, SPAI matrix) agree to FP64 rounding;
+fields after 1,000 steps agree to relative L2 <= 1e-5 (the mixed-precision
+path computes E in FP32: ~1e-7 per step, not accumulating in the D-form);
+one-step particle positions agree to 1e-8 m and momenta to 1e-5 relative
+(FP32 push, 2^-24 element-local coordinates); the continuity equation is
+exact in fixed point; the Gauss-law residual stays at its initial value to
+FP64 rounding of D.
+"""
+
+import numpy as np
+import pytest
+import scipy.spatial
+
+import synth
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+QE, ME = synth.ELECTRON_CHARGE, synth.ELECTRON_MASS
+
+
+@pytest.fixture(scope="module")
+def axp():
+    import paper_1701_03784_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def cavity():
+    from oracle.pic import OracleSim
+    m = configs.cavity_mesh()
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=configs.CAVITY_DT)
+    E0, B0, omega = synth.tm010_fields(m.nodes, m.tris, sim.topo.edges, configs.CAVITY_A, 1e6, sim.dt)
+    return m, sim, E0, B0
+
+
+def _ctx(axp, m, **kw):
+    print(f"[gpu] build ctx faces={m.n_tris} {kw}", flush=True)
+    kw.setdefault("dt", configs.CAVITY_DT)
+    return axp.make_ctx(m, **kw)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_setup_matches_oracle(axp, cavity):
+    m, sim, _, _ = cavity
+    c = _ctx(axp, m)
+    assert np.array_equal(c.get_edges(), synth.canonical_edges(m.tris))
+    M = c.get_spai()
+    assert M.nnz == sim.M.nnz
+    assert abs(M - sim.M).max() <= 1e-12 * abs(sim.M).max()
+    info = c.info()
+    assert info["dt_cfl"] == pytest.approx(sim.dt_cfl, rel=1e-6)
+    assert info["n_free_edges"] == int(sim.topo.edge_free.sum())
+
+
+def test_field_only_1000_steps(axp, cavity):
+    from oracle.pic import OracleSim
+    m, sim0, E0, B0 = cavity
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=sim0.dt, M=sim0.M)
+    sim.set_fields(E0, B0)
+    c = _ctx(axp, m)
+    c.set_fields(E0, B0)
+    for chunk in range(4):
+        c.step(250)
+        sim.step(250)
+        E, B = c.get_fields()
+        print(f"[gpu] field-only step {250 * (chunk + 1)}: relL2 E {_rel_l2(E, sim.E):.2e} B {_rel_l2(B, sim.B):.2e}",
+              flush=True)
+    assert _rel_l2(E, sim.E) <= 1e-5
+    assert _rel_l2(B, sim.B) <= 1e-5
+
+
+def _match(zr_a, u_a, zr_b, u_b):
+    """Pair particles of two sets by nearest neighbour in (z, rho, u) space."""
+    sa = np.concatenate([zr_a / 1e-6, u_a / 1e3], axis=1)
+    sb = np.concatenate([zr_b / 1e-6, u_b / 1e3], axis=1)
+    d, idx = scipy.spatial.cKDTree(sb).query(sa)
+    assert len(np.unique(idx)) == len(idx)
+    return idx
+
+
+def test_one_step_particles_and_current(axp, cavity):
+    from oracle.pic import OracleSim
+    m, sim0, E0, B0 = cavity
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=sim0.dt, M=sim0.M)
+    sim.set_fields(E0, B0)
+    sp_o = sim.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    zr, u = configs.cavity_beam()
+    sim.inject(sp_o, zr, u)
+    c = _ctx(axp, m)
+    c.set_fields(E0, B0)
+    sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    c.inject(sp, zr, u)
+    zr_g, u_g, _ = c.get_particles()
+    assert len(zr_g) == len(zr)
+    c.step(1)
+    sim.step(1)
+    zr_g, u_g, _ = c.get_particles()
+    zr_o, u_o, _ = sim.particles()
+    assert len(zr_g) == len(zr_o)
+    idx = _match(zr_g, u_g, zr_o, u_o)
+    assert np.abs(zr_g - zr_o[idx]).max() < 1e-8
+    assert np.abs(u_g - u_o[idx]).max() < 1e-5 * np.abs(u_o).max()
+    D, Jdt, Q = c.get_sources()
+    J_o = sim.J * sim.dt
+    assert np.abs(Jdt - J_o).max() <= 1e-5 * np.abs(J_o).max()
+    E, B = c.get_fields()
+    assert _rel_l2(E, sim.E) <= 1e-6
+    # B^{1/2} - B^{-1/2} is the circulation of the FP32 edge E (three nearly
+    # cancelling values), so one step already differs at ~1e-6
+    assert _rel_l2(B, sim.B) <= 1e-5
+
+
+def test_pic_1000_steps_parity_dce_gauss(axp, cavity):
+    from oracle.pic import OracleSim
+    m, sim0, E0, B0 = cavity
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=sim0.dt, M=sim0.M)
+    sim.set_fields(E0, B0)
+    sp_o = sim.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    zr, u = configs.cavity_beam()
+    sim.inject(sp_o, zr, u)
+    c = _ctx(axp, m, diag_every=1)
+    c.set_fields(E0, B0)
+    sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    c.inject(sp, zr, u)
+    d0 = c.diag()
+    for chunk in range(10):
+        c.step(100)
+        sim.step(100)
+        d = c.diag()
+        E, B = c.get_fields()
+        print(f"[gpu] pic step {d['step']}: live {d['n_live']} absorbed {d['n_absorbed']} dce {d['dce_max_abs']} "
+              f"gauss drift {d['gauss_max_drift']:.3e} / scale {d['gauss_scale']:.3e} "
+              f"relL2 E {_rel_l2(E, sim.E):.2e} B {_rel_l2(B, sim.B):.2e}", flush=True)
+        assert d["dce_max_abs"] == 0
+        assert d["gauss_max_drift"] <= 1e-13 * d["gauss_scale"]
+        assert d["walk_overflow"] == 0 and d["nan_count"] == 0
+    assert _rel_l2(E, sim.E) <= 1e-5
+    assert _rel_l2(B, sim.B) <= 1e-5
+    assert d["n_absorbed"] == int(sim.stats[1])
+
+
+def test_deterministic_rerun(axp, cavity):
+    m, sim0, E0, B0 = cavity
+    zr, u = configs.cavity_beam(3000, seed=5)
+    out = []
+    for rep in range(2):
+        c = _ctx(axp, m)
+        c.set_fields(E0, B0)
+        sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+        perm = np.random.default_rng(rep).permutation(len(zr))   # different injection order
+        c.inject(sp, zr[perm], u[perm])
+        c.step(200)
+        E, B = c.get_fields()
+        D, J, Q = c.get_sources()
+        out.append((E, B, D, J, Q))
+        c.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
