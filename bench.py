@@ -1,0 +1,197 @@
+"""Throughput benchmark of the axisymmetric EM-PIC step on one MI355X.
+
+Workload (default): rippled-wall BWO slow-wave tube, ~208k faces, 8M
+macro-electrons of a 500 keV annular beam, B_z = 1 T, mixed precision,
+dt = 0.5 x the leapfrog stability limit.  Inputs are seeded and synthetic.
+
+Prints one JSON line: particle-steps/s of the whole step (value), the field
+kernels' HBM rate, the dominant kernel's roofline (HIP-event time of the
+particle kernel on the library's stream) and the FP64 CPU oracle timed on a
+bounded slice of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def particle_bytes(n_live, n_faces):
+    """Algorithmic bytes of one particle-kernel launch: 24 B of particle state
+    read and written per particle, plus the per-face gather tile (32 B),
+    geometry (48 B) and current accumulators (24 B) once per face."""
+    return 48.0 * n_live + 104.0 * n_faces
+
+
+def field_bytes(n_edges, n_faces, spai_nnz_padded):
+    """Bytes the three field kernels must move once per step:
+    face pass 144 B/face + 4 B/edge; edge pass 44 B/edge + 32 B/face;
+    SpMV 8 B per stored matrix entry + 8 B/edge."""
+    return (144.0 * n_faces + 4.0 * n_edges) + (44.0 * n_edges + 32.0 * n_faces) + \
+        (8.0 * spai_nnz_padded + 8.0 * n_edges)
+
+
+def setup_bwo(n_particles, seed=3, sort_period=4):
+    import synth
+    from synth import configs
+    import paper_1701_03784_amd as axp
+    t0 = time.perf_counter()
+    m = configs.bwo_mesh(seed=seed)
+    L = m.meta["length"]
+    log(f"mesh: {m.n_nodes} nodes, {m.n_tris} faces ({time.perf_counter() - t0:.1f} s)")
+    c = axp.make_ctx(m, sort_period=sort_period)
+    info = c.info()
+    log(f"built: {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s "
+        f"(limit {info['dt_cfl']:.3e}), setup {info['setup_seconds']:.1f} s")
+    c.set_fields(np.zeros(info["n_edges"]), np.zeros(info["n_faces"]))
+    c.set_external_bz(configs.BWO_BZ)
+    w = configs.bwo_weight(n_particles, L)
+    sp = c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, w)
+    zr, u = configs.bwo_beam(n_particles, L, seed=seed)
+    t1 = time.perf_counter()
+    c.inject(sp, zr, u)
+    log(f"injected {n_particles} particles (weight {w}) in {time.perf_counter() - t1:.1f} s")
+    desc = (f"bwo: rippled-wall tube R=1.5+0.25 sin cm, 10 periods of 1.67 cm + drifts, {m.n_tris} faces, "
+            f"{info['n_edges']} edges; {n_particles} macro-electrons, 500 keV annular beam, B_z=1 T; "
+            f"SPAI level 3 ({info['spai_nnz']} nnz); dt=0.5 CFL")
+    return c, m, info, desc
+
+
+def cpu_baseline(target_seconds=15.0):
+    """FP64 oracle on a bounded slice of the BWO workload: one ripple period
+    of the same profile and mesh size, the same beam density."""
+    from synth import configs
+    import synth
+    from oracle.pic import OracleSim
+    m = configs.bwo_mesh(seed=3, n_periods=1, up=0.0, down=0.0)
+    full_area = 0.217 * 0.015
+    area = m.signed_areas().sum()
+    n = int(8_000_000 * area / full_area)
+    t0 = time.perf_counter()
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag)
+    setup = time.perf_counter() - t0
+    sim.bz = configs.BWO_BZ
+    L = m.meta["length"]
+    zr, u = configs.bwo_beam(n, L, seed=3)
+    sp = sim.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.bwo_weight(n, L))
+    sim.inject(sp, zr, u)
+    sim.step(1)
+    steps, el = 0, 0.0
+    while el < target_seconds and steps < 50:
+        t1 = time.perf_counter()
+        sim.step(1)
+        el += time.perf_counter() - t1
+        steps += 1
+    live = int(sim.palive.sum())
+    rate = live * steps / el
+    return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one ripple period of the bwo profile (1.67 cm, {m.n_tris} faces, h=0.19 mm) with "
+                      f"{live} particles at the full beam density, {steps} steps timed "
+                      f"({el:.1f} s) after {setup:.1f} s of oracle setup; single thread FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--particles", type=int, default=8_000_000)
+    ap.add_argument("--sort-period", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the workload is measured at N=1 and the multi-GPU path "
+              "is a design (z-slab decomposition), not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1701_03784_amd as axp
+    axp.load_library()
+    c, m, info, desc = setup_bwo(args.particles, sort_period=args.sort_period)
+    c.step(args.warmup)
+    c.sync()
+    log(f"warmup {args.warmup} steps done")
+    c.set_timing(True)
+    c.sync()
+    t0 = time.perf_counter()
+    c.step(args.steps)
+    c.sync()
+    el = time.perf_counter() - t0
+    tim = c.get_timing()
+    d = c.diag()
+    n_live = d["n_live"]
+    n1, n2 = info["n_edges"], info["n_faces"]
+    ms_step = el * 1e3 / args.steps
+    value = n_live * args.steps / el
+    part_ms, part_n = tim["particles"]
+    part_avg_s = part_ms / part_n / 1e3
+    pb = particle_bytes(n_live, n2)
+    achieved = pb / part_avg_s / 1e9
+    nnz_pad = info["spai_nnz"] * 1.15
+    fb = field_bytes(n1, n2, nnz_pad)
+    field_ms = sum(tim[k][0] for k in ("face", "edge", "spmv")) / args.steps
+    field_gbs = fb / (field_ms / 1e3) / 1e9
+    per_phase = {k: round(v[0] / max(1, v[1]) * 1e3, 2) for k, v in tim.items() if v[1]}
+    log(f"{args.steps} steps in {el:.3f} s: {ms_step:.3f} ms/step; per-launch us {per_phase}")
+    log(f"diag: live {n_live} absorbed {d['n_absorbed']} overflow {d['walk_overflow']} nan {d['nan_count']}")
+
+    if args.copy_probe_mib:
+        import torch
+        a = torch.empty(args.copy_probe_mib * 2 ** 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB x3")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.3e} particle-steps/s")
+
+    out = {
+        "metric": "particle-steps/s + field HBM GB/s at 1 GPU; batched-mixed vs plain at fixed error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+i64",
+        "data": "synthetic (seeded mesh, beam and fields)",
+        "config": {"workload": desc, "faces": n2, "edges": n1, "particles": int(n_live),
+                   "precision": "mixed", "sort_period": args.sort_period},
+        "field_dof_steps_per_s": (n1 + n2) * args.steps / el,
+        "field_hbm_gbs": field_gbs,
+        "phase_us_per_launch": per_phase,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_particles", "bytes_per_launch": pb,
+                     "avg_launch_us": part_avg_s * 1e6},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -123,7 +123,7 @@ typedef struct {
     int64_t walk_overflow;       /* paths cut at the segment cap (cumulative) */
     int64_t nan_count;           /* non-finite momenta seen (cumulative) */
     int64_t fixed_overflow;      /* fixed-point headroom violations (cumulative) */
-    int64_t dce_max_abs;         /* max over nodes |2^24 (Q^{n+1}-Q^n) + Ddiv J| in fixed point (mixed; 0 = exact) */
+    int64_t dce_max_abs;         /* max over nodes |2^23 (Q^{n+1}-Q^n) + Ddiv J| in fixed point (mixed; 0 = exact) */
     double dce_max_rel;          /* same, relative to max |Q| (plain FP64 mode) */
     double gauss_max_drift;      /* max over free nodes |res^n - res^0| (Sec. 3.4.2) */
     double gauss_max_abs;        /* max over free nodes |res^n| */
@@ -222,6 +222,23 @@ axp_status axp_get_particles(axp_ctx *ctx, int64_t cap, int64_t *n, double *zr, 
  * from the same mesh and configuration. */
 axp_status axp_save(axp_ctx *ctx, const char *path);
 axp_status axp_load(axp_ctx *ctx, const char *path);
+
+/* Per-phase kernel timing (observability).  While on, every phase of
+ * axp_step is bracketed by HIP events recorded on cfg.hip_stream; the
+ * accumulated device milliseconds and launch counts are returned (after a
+ * stream sync) and reset by axp_set_timing(ctx, 1). */
+enum {
+    AXP_PHASE_FACE = 0,      /* Faraday + gather tile (per face) */
+    AXP_PHASE_PARTICLES = 1, /* gather + push + walk + current (per particle) */
+    AXP_PHASE_EDGE = 2,      /* D update (per edge) */
+    AXP_PHASE_SPMV = 3,      /* E = M D (per edge row) */
+    AXP_PHASE_SORT = 4,      /* counting sort of particles by face */
+    AXP_PHASE_DIAG = 5,      /* diagnostics */
+    AXP_PHASE_INJECT = 6,    /* continuous injection */
+    AXP_N_PHASES = 7
+};
+axp_status axp_set_timing(axp_ctx *ctx, int32_t on);
+axp_status axp_get_timing(axp_ctx *ctx, double *ms /*[AXP_N_PHASES]*/, int64_t *launches /*[AXP_N_PHASES]*/);
 
 const char *axp_last_error(const axp_ctx *ctx);
 void axp_destroy(axp_ctx *ctx);

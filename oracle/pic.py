@@ -167,11 +167,15 @@ class OracleSim:
             self._tree = scipy.spatial.cKDTree(tp.nodes[tp.tris].mean(axis=1))
         zr = np.asarray(zr, dtype=np.float64).reshape(-1, 2)
         k = min(24, tp.n2)
-        _, cand = self._tree.query(zr, k=k)
-        cand = np.asarray(cand).reshape(len(zr), -1)
-        minlam = _bary_many(tp.nodes[tp.tris[cand]], zr[:, None, :]).min(axis=-1)
-        out = cand[np.arange(len(zr)), np.argmax(minlam, axis=1)]
-        bad = np.flatnonzero(minlam.max(axis=1) < -1e-12)
+        out = np.empty(len(zr), dtype=np.int64)
+        bad = []
+        for a in range(0, len(zr), 65536):           # bounded memory
+            z = zr[a:a + 65536]
+            _, cand = self._tree.query(z, k=k)
+            cand = np.asarray(cand).reshape(len(z), -1)
+            minlam = _bary_many(tp.nodes[tp.tris[cand]], z[:, None, :]).min(axis=-1)
+            out[a:a + len(z)] = cand[np.arange(len(z)), np.argmax(minlam, axis=1)]
+            bad.extend(a + np.flatnonzero(minlam.max(axis=1) < -1e-12))
         for i in bad:                        # far from any centroid: scan all faces
             ml = _bary_many(tp.nodes[tp.tris], zr[i][None, :]).min(axis=-1)
             if ml.max() < -1e-9:

@@ -63,7 +63,8 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
-           "axp_batch_destroy"]
+           "axp_batch_destroy", "axp_set_timing", "axp_get_timing"]
+PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject"]
 
 _lib = None
 
@@ -111,6 +112,8 @@ def load_library(path: str = LIB_PATH):
         "axp_batch_step": (i32, [vp, i32]),
         "axp_batch_sync": (i32, [vp]),
         "axp_batch_destroy": (None, [vp]),
+        "axp_set_timing": (i32, [vp, i32]),
+        "axp_get_timing": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -264,6 +267,16 @@ class Ctx:
         d = Diag()
         self._check(self.lib.axp_diag_get(self.h, C.byref(d)))
         return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    def set_timing(self, on=True):
+        self._check(self.lib.axp_set_timing(self.h, 1 if on else 0))
+
+    def get_timing(self):
+        """{phase: (total device ms, launches)} since set_timing(True)."""
+        ms = np.zeros(len(PHASES))
+        n = np.zeros(len(PHASES), dtype=np.int64)
+        self._check(self.lib.axp_get_timing(self.h, _ptr(ms), _ptr(n)))
+        return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(PHASES)}
 
     # ---- read-back
     def get_fields(self):

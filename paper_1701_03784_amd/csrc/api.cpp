@@ -47,6 +47,12 @@ struct axp_ctx {
     int64_t n_live_host = 0;
     // injector
     bool inj_on = false;
+    // per-phase timing
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;   // pending (phase, start, stop)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+    double phase_ms[AXP_N_PHASES] = {0};
+    int64_t phase_n[AXP_N_PHASES] = {0};
 };
 
 namespace {
@@ -156,12 +162,57 @@ void grow_particles(axp_ctx *c, int64_t need) {
         dfree(c, s.ur[b]); dfree(c, s.up[b]); dfree(c, s.uz[b]);
         s.cell[b] = cell; s.L0[b] = l0; s.L1[b] = l1; s.ur[b] = ur; s.up[b] = up; s.uz[b] = uz;
     }
+    dfree(c, s.mv_p); dfree(c, s.mv_c); dfree(c, s.mv_l0); dfree(c, s.mv_l1); dfree(c, s.mv_fz); dfree(c, s.mv_fr);
+    dfree(c, s.mv_n);
+    s.mv_n = zeros<int32_t>(c, cap / 1024 + 1);
+    s.mv_p = zeros<int32_t>(c, cap); s.mv_c = zeros<int32_t>(c, cap);
+    s.mv_l0 = zeros<int32_t>(c, cap); s.mv_l1 = zeros<int32_t>(c, cap);
+    s.mv_fz = zeros<float>(c, cap); s.mv_fr = zeros<float>(c, cap);
     s.capacity = cap;
+}
+
+struct PhaseScope {
+    axp_ctx *c;
+    int phase;
+    hipEvent_t b = nullptr, e = nullptr;
+    PhaseScope(axp_ctx *ctx, int ph) : c(ctx), phase(ph) {
+        if (!c->timing) return;
+        if (!c->ev_free.empty()) {
+            b = c->ev_free.back().first;
+            e = c->ev_free.back().second;
+            c->ev_free.pop_back();
+        } else {
+            hcheck(hipEventCreate(&b), "event");
+            hcheck(hipEventCreate(&e), "event");
+        }
+        hcheck(hipEventRecord(b, c->stream), "event record");
+    }
+    ~PhaseScope() {
+        if (!c->timing || !b) return;
+        (void)hipEventRecord(e, c->stream);
+        c->ev.push_back({phase, {b, e}});
+    }
+};
+
+void collect_timing(axp_ctx *c) {
+    if (c->ev.empty()) return;
+    hcheck(hipStreamSynchronize(c->stream), "sync");
+    for (auto &r : c->ev) {
+        float ms = 0.f;
+        hcheck(hipEventElapsedTime(&ms, r.second.first, r.second.second), "elapsed");
+        c->phase_ms[r.first] += ms;
+        c->phase_n[r.first] += 1;
+        c->ev_free.push_back(r.second);
+    }
+    c->ev.clear();
 }
 
 void run_diag(axp_ctx *c) {
     bool have_prev = (c->last_diag_step == c->step - 1) && c->step > 0;
-    launch_diag(c->dm, c->ds, have_prev, !c->g0_set, c->stream);
+    {
+        PhaseScope ps(c, AXP_PHASE_DIAG);
+        launch_diag(c->dm, c->ds, have_prev, !c->g0_set, c->stream);
+    }
     c->g0_set = true;
     c->last_diag_step = c->step;
 }
@@ -245,6 +296,7 @@ void build_device(axp_ctx *c) {
     s.blk = zeros<int32_t>(c, size_t(m.n2) / 1024 + 2);
     s.ctr = zeros<DevCounters>(c, 1);
     s.diag = zeros<DevDiag>(c, 1);
+    s.kin_part = zeros<double>(c, 1024);
     s.capacity = 0;
     s.cur = 0;
     hcheck(hipStreamSynchronize(c->stream), "build sync");
@@ -439,8 +491,8 @@ axp_status axp_add_species(axp_ctx *c, double q, double m, int64_t weight, int32
         ic.qb[sp] = float(q * c->dt / (2.0 * m));
         ic.kq[sp] = int32_t(std::nearbyint(k));
         ic.mw[sp] = m * double(weight) * kC * kC / kTwoPi;
-        ic.jscale = c->q_unit / (kTwoPi * 281474976710656.0);   // / 2^48
-        ic.qscale = c->q_unit / (kTwoPi * 16777216.0);          // / 2^24
+        ic.jscale = c->q_unit / (kTwoPi * double(kLamOne) * double(kLamOne));   // current unit 2^-46
+        ic.qscale = c->q_unit / (kTwoPi * double(kLamOne));                    // charge unit 2^-23
         upload_inst(c);
         *id = sp;
         return AXP_OK;
@@ -501,7 +553,7 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
         hcheck(hipMemcpyAsync(s.uz[b] + used, uz.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
         unsigned long long ns = (unsigned long long)(used + n);
         hcheck(hipMemcpyAsync(&s.ctr->n_slots, &ns, 8, hipMemcpyHostToDevice, c->stream), "slots");
-        launch_sort(c->dm, s, c->stream);
+        launch_sort(c->dm, s, false, c->stream);
         hcheck(hipGetLastError(), "sort launch");
         hcheck(hipStreamSynchronize(c->stream), "inject sync");
         c->n_live_host = int64_t(read_counters(c).n_slots);
@@ -520,13 +572,23 @@ axp_status axp_step(axp_ctx *c, int32_t n_steps) {
     return guarded(c, [&]() -> axp_status {
         require_built(c);
         for (int i = 0; i < n_steps; ++i) {
-            launch_tri_pass(c->dm, c->ds, c->stream);
-            launch_particles(c->dm, c->ds, c->cfg.max_walk, c->stream);
-            launch_edge_pass(c->dm, c->ds, true, c->stream);
-            launch_spmv(c->dm, c->ds, c->stream);
+            const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
+            { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(c->dm, c->ds, c->stream); }
+            if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(c->dm, c->ds, c->stream); }
+            {
+                PhaseScope ps(c, AXP_PHASE_PARTICLES);
+                const bool single = c->dm.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
+                launch_particles(c->dm, c->ds, c->cfg.max_walk, sort_now, single ? &c->ic : nullptr, c->stream);
+            }
+            { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass(c->dm, c->ds, true, c->stream); }
+            { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv(c->dm, c->ds, c->stream); }
             ++c->step;
-            if (c->step % c->cfg.sort_period == 0) launch_sort(c->dm, c->ds, c->stream);
+            if (sort_now) {
+                PhaseScope ps(c, AXP_PHASE_SORT);
+                launch_sort(c->dm, c->ds, true, c->stream);
+            }
             if (c->cfg.diag_every > 0 && c->step % c->cfg.diag_every == 0) run_diag(c);
+            if (c->ev.size() > 4096) collect_timing(c);
         }
         hcheck(hipGetLastError(), "step launch");
         return AXP_OK;
@@ -668,11 +730,32 @@ axp_status axp_get_particles(axp_ctx *c, int64_t cap, int64_t *n, double *zr, do
 axp_status axp_save(axp_ctx *c, const char *) { return c ? fail(c, AXP_E_STATE, "checkpoints not available in this build") : AXP_E_ARG; }
 axp_status axp_load(axp_ctx *c, const char *) { return c ? fail(c, AXP_E_STATE, "checkpoints not available in this build") : AXP_E_ARG; }
 
+axp_status axp_set_timing(axp_ctx *c, int32_t on) {
+    if (!c) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        collect_timing(c);
+        c->timing = on != 0;
+        for (int k = 0; k < AXP_N_PHASES; ++k) { c->phase_ms[k] = 0; c->phase_n[k] = 0; }
+        return AXP_OK;
+    });
+}
+
+axp_status axp_get_timing(axp_ctx *c, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        collect_timing(c);
+        for (int k = 0; k < AXP_N_PHASES; ++k) { ms[k] = c->phase_ms[k]; launches[k] = c->phase_n[k]; }
+        return AXP_OK;
+    });
+}
+
 const char *axp_last_error(const axp_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 void axp_destroy(axp_ctx *c) {
     if (!c) return;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &r : c->ev) { (void)hipEventDestroy(r.second.first); (void)hipEventDestroy(r.second.second); }
+    for (auto &r : c->ev_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
     for (void *p : std::vector<void *>(c->allocs)) dfree(c, p);
     delete c;
 }

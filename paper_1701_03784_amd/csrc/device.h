@@ -14,8 +14,8 @@ constexpr int kMaxSpecies = 16;
 // Per-instance constants (one entry per device in a pooled batch).
 struct InstConst {
     double dt;         // time step [s]
-    double jscale;     // charge unit / (2 pi 2^48): fixed-point current -> D increment [C/rad]
-    double qscale;     // charge unit / (2 pi 2^24): fixed-point charge -> C/rad
+    double jscale;     // charge unit / (2 pi 2^46): fixed-point current -> D increment [C/rad]
+    double qscale;     // charge unit / (2 pi 2^23): fixed-point charge -> C/rad
     float cdt;         // c dt [m]
     float bz;          // external B_z [T]
     int32_t n_species;
@@ -30,7 +30,7 @@ struct InstConst {
 struct DevMesh {
     int32_t n0 = 0, n1 = 0, n2 = 0, n_inst = 1;
     // faces (internal order)
-    const float4 *gS = nullptr;     // 2^24 grad lam0 (z, rho), 2^24 grad lam1 (z, rho)
+    const float4 *gS = nullptr;     // 2^23 grad lam0 (z, rho), 2^23 grad lam1 (z, rho)
     const float4 *rho4 = nullptr;   // rho of local nodes 0..2, 1/(2 area)
     const int4 *nbr = nullptr;      // face across side k (>= 0) or -tag; w: neighbour-local ids, 4 bits/side
     const int4 *tedge = nullptr;    // edge of side k; w: bit k set -> incidence sign -1
@@ -69,7 +69,7 @@ struct DevDiag {
     unsigned long long gauss_drift_bits;  // max |res^n - res^0| (double bits, >= 0)
     unsigned long long gauss_abs_bits;
     unsigned long long gauss_scale_bits;
-    unsigned long long dce_max;           // max |2^24 dQ + Ddiv J| (fixed point)
+    unsigned long long dce_max;           // max |2^23 dQ + Ddiv J| (fixed point)
     double WE, WB, WK, Qtot;
 };
 
@@ -84,7 +84,7 @@ struct DevState {
     float *D32 = nullptr;       // FP32 copy read by the SpMV
     float *E = nullptr;         // E on edges
     long long *Jfx = nullptr;   // fixed-point edge current of the last step (diagnostic)
-    long long *Qres = nullptr;  // fixed-point wall/emitter charge per node (units 2^-24 charge unit)
+    long long *Qres = nullptr;  // fixed-point wall/emitter charge per node (units 2^-23 charge unit)
     long long *Qfx = nullptr;   // fixed-point nodal charge (diagnostic)
     long long *Qprev = nullptr;
     double *g0 = nullptr;       // Gauss residual at the first diagnostic
@@ -94,19 +94,26 @@ struct DevState {
     float *ur[2] = {nullptr, nullptr}, *up[2] = {nullptr, nullptr}, *uz[2] = {nullptr, nullptr};
     int cur = 0;
     int64_t capacity = 0;
+    // mover list (particles leaving their face this step), capacity entries
+    int32_t *mv_p = nullptr, *mv_c = nullptr, *mv_l0 = nullptr, *mv_l1 = nullptr;
+    float *mv_fz = nullptr, *mv_fr = nullptr;
+    int32_t *mv_n = nullptr;    // movers per particle block (capacity / 1024 blocks)
     // sort scratch
     int32_t *cnt = nullptr;     // n2 + 1
     int32_t *blk = nullptr;     // scan block sums
     DevCounters *ctr = nullptr;
     DevDiag *diag = nullptr;
+    double *kin_part = nullptr;  // 1024 partial sums of the kinetic energy
 };
 
 // ---- launchers (kernels_mixed.hip) ----
 void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
-void launch_particles(const DevMesh &m, DevState &s, int max_walk, hipStream_t st);
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single,
+                      hipStream_t st);
+void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);
-void launch_sort(const DevMesh &m, DevState &s, hipStream_t st);
+void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st);
 void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st);
 
 }  // namespace axp

@@ -13,7 +13,7 @@ constexpr double kC = 299792458.0;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kMu0 = 1.0 / (kEps0 * kC * kC);
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr int kLamBits = 24;                       // element-local fixed point: lambda * 2^24
+constexpr int kLamBits = 23;                       // element-local fixed point: lambda * 2^23
 constexpr int64_t kLamOne = int64_t(1) << kLamBits;
 
 enum Tag : int { TAG_NONE = 0, TAG_PEC = 1, TAG_AXIS = 2, TAG_EMITTER = 3, TAG_OPEN = 4 };

@@ -13,11 +13,11 @@
 //                 residual (eq. DGL_RSD_REL), energies.
 //
 // Element-local positions: a particle is (face T, Lambda_0, Lambda_1) with
-// Lambda_k = lambda_k 2^24 exactly (Lambda_2 = 2^24 - Lambda_0 - Lambda_1).
+// Lambda_k = lambda_k 2^23 exactly (Lambda_2 = 2^23 - Lambda_0 - Lambda_1).
 // A straight piece of path from Lambda^s to Lambda^e inside T contributes
-// Lambda^s_{k+1} Lambda^e_{k+2} - Lambda^s_{k+2} Lambda^e_{k+1} (units 2^-48)
+// Lambda^s_{k+1} Lambda^e_{k+2} - Lambda^s_{k+2} Lambda^e_{k+1} (units 2^-46)
 // to the current of side k (oriented from local node k+1 to k+2); the
-// sum of these over a node's sides is exactly 2^24 times the change of the
+// sum of these over a node's sides is exactly 2^23 times the change of the
 // node's Lambda, so the continuity equation holds bit-exactly.
 #include <hip/hip_runtime.h>
 
@@ -25,8 +25,8 @@
 
 namespace axp {
 
-constexpr int kS = 1 << 24;
-constexpr float kInvS = 1.0f / 16777216.0f;
+constexpr int kS = 1 << 23;                  // element-local fixed point: lambda * 2^23
+constexpr float kInvS = 1.0f / 8388608.0f;
 constexpr int kTagAxis = 2;
 
 __device__ __forceinline__ int xcd_block(int bid, int nb) {
@@ -75,35 +75,128 @@ __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s) {
 }
 
 // -------------------------------------------------------------- particles
+// Two kernels per step:
+//   k_push   one pass over the particle array (4 consecutive particles per
+//            thread): gather, Boris, position update; a particle whose path
+//            ends in its own face deposits the single piece's current into the
+//            thread's register accumulator (consecutive particles share faces),
+//            which is reduced per face across the wave before one lane adds it
+//            to the face's fixed-point current; a particle that leaves its face
+//            is appended to the mover list.
+//   k_walk   grid-stride pass over the mover list: walk face by face, with the
+//            per-piece currents reduced per face across the wave at each piece.
 constexpr int kPPT = 4;          // particles per thread (consecutive in storage)
 constexpr int kWG = 256;
-constexpr int kWin = 512;        // faces in the LDS current window
 
-struct WinAcc {
-    unsigned long long *lds;
-    int base;
-    unsigned long long *glob;
-};
-
-__device__ __forceinline__ void dep3(const WinAcc &w, int t, long long c0, long long c1, long long c2) {
-    const int rel = t - w.base;
-    if (rel >= 0 && rel < kWin) {
-        if (c0) atomicAdd(&w.lds[3 * rel], (unsigned long long)c0);
-        if (c1) atomicAdd(&w.lds[3 * rel + 1], (unsigned long long)c1);
-        if (c2) atomicAdd(&w.lds[3 * rel + 2], (unsigned long long)c2);
-    } else {
-        if (c0) atomicAdd(&w.glob[3 * t], (unsigned long long)c0);
-        if (c1) atomicAdd(&w.glob[3 * t + 1], (unsigned long long)c1);
-        if (c2) atomicAdd(&w.glob[3 * t + 2], (unsigned long long)c2);
-    }
+// exact 48-bit product of two coordinates in [0, 2^23] (full-rate 24-bit multiplies)
+__device__ __forceinline__ long long m24(int a, int b) {
+    return (long long)((unsigned long long)((unsigned)a & 0xFFFFFFu) * ((unsigned)b & 0xFFFFFFu));
 }
 
 // current of the straight piece s -> e inside one face, per side k
 __device__ __forceinline__ void piece_current(int s0, int s1, int s2, int e0, int e1, int e2, int kq,
                                               long long &c0, long long &c1, long long &c2) {
-    c0 = ((long long)s1 * e2 - (long long)s2 * e1) * kq;
-    c1 = ((long long)s2 * e0 - (long long)s0 * e2) * kq;
-    c2 = ((long long)s0 * e1 - (long long)s1 * e0) * kq;
+    c0 = m24(s1, e2) - m24(s2, e1);
+    c1 = m24(s2, e0) - m24(s0, e2);
+    c2 = m24(s0, e1) - m24(s1, e0);
+    if (kq != 1) { c0 *= kq; c1 *= kq; c2 *= kq; }
+}
+
+// Sum of a 64-bit value over the lanes of the wave (butterfly of shuffles).
+__device__ __forceinline__ long long wave_sum64(long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Per-block accumulation window: the fixed-point currents and sort counts of
+// kWin consecutive faces live in LDS; faces outside the window go straight to
+// global memory.  A block's particles are sorted by face, so nearly all of
+// its deposits land in the window, and the window is added to global memory
+// once per face at the end of the block.
+constexpr int kWin = 256;
+constexpr int kWinLead = 64;     // window starts this many faces before the block's first face
+
+struct Win {
+    unsigned long long *jl;      // LDS, 3 * kWin
+    int *cl;                     // LDS, kWin
+    int base;
+};
+
+__device__ __forceinline__ void win_add_j(const Win &w, unsigned long long *J, int t, long long a0, long long a1,
+                                          long long a2) {
+    const int rel = t - w.base;
+    if (rel >= 0 && rel < kWin) {
+        if (a0) atomicAdd(&w.jl[3 * rel], (unsigned long long)a0);
+        if (a1) atomicAdd(&w.jl[3 * rel + 1], (unsigned long long)a1);
+        if (a2) atomicAdd(&w.jl[3 * rel + 2], (unsigned long long)a2);
+    } else {
+        if (a0) atomicAdd(&J[3 * t], (unsigned long long)a0);
+        if (a1) atomicAdd(&J[3 * t + 1], (unsigned long long)a1);
+        if (a2) atomicAdd(&J[3 * t + 2], (unsigned long long)a2);
+    }
+}
+
+__device__ __forceinline__ void win_add_c(const Win &w, int *cnt, int t, int v) {
+    const int rel = t - w.base;
+    if (rel >= 0 && rel < kWin) atomicAdd(&w.cl[rel], v);
+    else atomicAdd(&cnt[t], v);
+}
+
+// Deposit every lane's (face t, 3 side currents): lanes holding the same face
+// are summed across the wave and one lane adds the total.  Lanes with t < 0
+// hold nothing.  All lanes of the wave must call this together.
+__device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0,
+                                             long long a1, long long a2) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const unsigned long long pending = __ballot(t >= 0);
+        if (pending == 0ull) break;
+        const int leader = __ffsll((long long)pending) - 1;
+        const int t0 = __shfl(t, leader, 64);
+        const bool mine = (t == t0);
+        const long long s0 = wave_sum64(mine ? a0 : 0ll);
+        const long long s1 = wave_sum64(mine ? a1 : 0ll);
+        const long long s2 = wave_sum64(mine ? a2 : 0ll);
+        if (lane == leader) win_add_j(w, J, t0, s0, s1, s2);
+        if (mine) t = -1;
+    }
+}
+
+// Same for a count per face (histogram of the counting sort).
+__device__ __forceinline__ void wave_count(const Win &w, int *cnt, int t, int c) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const unsigned long long pending = __ballot(t >= 0);
+        if (pending == 0ull) break;
+        const int leader = __ffsll((long long)pending) - 1;
+        const int t0 = __shfl(t, leader, 64);
+        const bool mine = (t == t0);
+        int v = mine ? c : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == leader && v) win_add_c(w, cnt, t0, v);
+        if (mine) t = -1;
+    }
+}
+
+__device__ __forceinline__ void win_zero(const Win &w) {
+    for (int i = threadIdx.x; i < 3 * kWin; i += blockDim.x) w.jl[i] = 0ull;
+    for (int i = threadIdx.x; i < kWin; i += blockDim.x) w.cl[i] = 0;
+}
+
+// after a barrier: add the window to the global arrays
+__device__ __forceinline__ void win_flush(const Win &w, unsigned long long *J, int *cnt, int n2, bool counts) {
+    for (int i = threadIdx.x; i < 3 * kWin; i += blockDim.x) {
+        const unsigned long long v = w.jl[i];
+        const long long gi = 3ll * w.base + i;
+        if (v != 0ull && gi >= 0 && gi < 3ll * n2) atomicAdd(&J[gi], v);
+    }
+    if (counts)
+        for (int i = threadIdx.x; i < kWin; i += blockDim.x) {
+            const int v = w.cl[i], t = w.base + i;
+            if (v != 0 && t >= 0 && t < n2) atomicAdd(&cnt[t], v);
+        }
 }
 
 struct Particle {
@@ -112,21 +205,25 @@ struct Particle {
     float ur, up, uz;
 };
 
-// Push one particle and walk it; first-piece current goes to the register
-// accumulator (acc_t, a0..a2), the rest to the window / global arrays.
-__device__ __forceinline__ void push_walk(const DevMesh &m, const DevState &s, Particle &P, const WinAcc &w,
-                                          int &acc_t, long long &a0, long long &a1, long long &a2, int max_walk) {
-    if (P.cell < 0) return;
-    const int T = P.cell & kCellMask;
-    const int sp = (P.cell >> kCellBits) & 15;
-    const int inst = m.tinst ? m.tinst[T] : 0;
-    const InstConst &ic = m.inst[inst];
-    const float qe = ic.qe[sp], qb = ic.qb[sp];
-    const int kq = ic.kq[sp];
-    int L0 = (int)P.L0, L1 = (int)P.L1, L2 = kS - L0 - L1;
+struct PushConst {
+    float qe, qb, cdt, bz;
+    int kq;
+};
+
+template <bool SINGLE>
+__device__ __forceinline__ PushConst push_const(const DevMesh &m, const PushConst &k0, int T, int sp) {
+    if (SINGLE) return k0;
+    const InstConst &ic = m.inst[m.tinst ? m.tinst[T] : 0];
+    return PushConst{ic.qe[sp], ic.qb[sp], ic.cdt, ic.bz, ic.kq[sp]};
+}
+
+// Gather, relativistic Boris and the axisymmetric position update of one
+// particle: returns the meridian displacement (dz, drho) and updates u.
+__device__ __forceinline__ void push(const DevState &s, Particle &P, const PushConst &ic, const float4 f0,
+                                     const float4 f1, const float4 r4, int L0, int L1, int L2, float &fz, float &fr) {
+    const float qe = ic.qe, qb = ic.qb;
     const float l0 = L0 * kInvS, l1 = L1 * kInvS, l2 = L2 * kInvS;
-    // gather (Whitney 1-form E, face-constant B_phi, external B_z)
-    const float4 f0 = s.f0[T], f1 = s.f1[T];
+    // Whitney 1-form E, face-constant B_phi, external B_z
     const float Ez = l0 * f0.x + l1 * f0.z + l2 * f1.x;
     const float Er = l0 * f0.y + l1 * f0.w + l2 * f1.y;
     const float Bp = f1.z, Bz = ic.bz;
@@ -134,7 +231,7 @@ __device__ __forceinline__ void push_walk(const DevMesh &m, const DevState &s, P
     const float umr = P.ur + qe * Er, ump = P.up, umz = P.uz + qe * Ez;
     const float igm = __builtin_amdgcn_rsqf(1.0f + umr * umr + ump * ump + umz * umz);
     const float tp = qb * Bp * igm, tz = qb * Bz * igm;
-    const float f = 2.0f / (1.0f + tp * tp + tz * tz);
+    const float f = 2.0f * __builtin_amdgcn_rcpf(1.0f + tp * tp + tz * tz);
     const float sp_ = f * tp, sz = f * tz;
     const float vr = umr + (ump * tz - umz * tp);
     const float vp = ump - umr * tz;
@@ -142,137 +239,75 @@ __device__ __forceinline__ void push_walk(const DevMesh &m, const DevState &s, P
     float ur = umr + (vp * sz - vz * sp_) + qe * Er;
     float up = ump - vr * sz;
     float uz = umz + vr * sp_ + qe * Ez;
-    const float u2 = ur * ur + up * up + uz * uz;
-    if (!(u2 < 3.0e38f)) {     // non-finite or absurd momentum: count, stop the particle
+    if (!(ur * ur + up * up + uz * uz < 3.0e38f)) {   // non-finite or absurd momentum: count, stop
         atomicAdd(&s.ctr->nan_count, 1ull);
         ur = up = uz = 0.0f;
     }
-    const float ig = __builtin_amdgcn_rsqf(1.0f + ur * ur + up * up + uz * uz);
     // move in the local Cartesian frame, rotate back to the meridian plane
-    const float4 r4 = m.rho4[T];
+    const float ig = __builtin_amdgcn_rsqf(1.0f + ur * ur + up * up + uz * uz) * ic.cdt;
     const float rho = l0 * r4.x + l1 * r4.y + l2 * r4.z;
-    const float dr = ur * ig * ic.cdt, dp = up * ig * ic.cdt, dz = uz * ig * ic.cdt;
+    const float dr = ur * ig, dp = up * ig;
+    fz = uz * ig;
     const float X = rho + dr;
-    const float r1 = __builtin_sqrtf(X * X + dp * dp);
-    if (r1 > 0.0f) {
-        const float ir = 1.0f / r1;
+    const float r2 = X * X + dp * dp;
+    const float ir = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    if (r2 > 0.0f) {
         const float cs = X * ir, sn = dp * ir;
         const float nr = cs * ur + sn * up;
         up = -sn * ur + cs * up;
         ur = nr;
     }
-    const float den = r1 + rho;
-    float fr = den > 0.0f ? (2.0f * rho * dr + dr * dr + dp * dp) / den : 0.0f;
-    float fz = dz;
+    const float den = r2 * ir + rho;              // rho' + rho
+    fr = den > 0.0f ? (2.0f * rho * dr + dr * dr + dp * dp) * __builtin_amdgcn_rcpf(den) : 0.0f;
     P.ur = ur; P.up = up; P.uz = uz;
-
-    // walk across faces; element-local integer coordinates
-    int t = T, entry = -1;
-    bool first = true;
-    for (int seg = 0;; ++seg) {
-        const float4 g = m.gS[t];
-        const float d0f = fminf(fmaxf(g.x * fz + g.y * fr, -1.0e9f), 1.0e9f);
-        const float d1f = fminf(fmaxf(g.z * fz + g.w * fr, -1.0e9f), 1.0e9f);
-        int d0 = (int)__builtin_rintf(d0f), d1 = (int)__builtin_rintf(d1f), d2 = -d0 - d1;
-        // never leave through the side just entered (rounding); slide along it instead
-        if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
-        if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
-        if (entry == 2 && d2 < 0) { d2 = 0; d1 = -d0; }
-        const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
-        long long c0, c1, c2;
-        if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
-            piece_current(L0, L1, L2, e0, e1, e2, kq, c0, c1, c2);
-            if (first && t == acc_t) { a0 += c0; a1 += c1; a2 += c2; }
-            else if (first) { dep3(w, acc_t, a0, a1, a2); acc_t = t; a0 = c0; a1 = c1; a2 = c2; }
-            else dep3(w, t, c0, c1, c2);
-            L0 = e0; L1 = e1; L2 = e2;
-            break;
-        }
-        // exit side: smallest Lambda_k / (-d_k) among the coordinates going negative (ties: lower k)
-        int kx = -1;
-        long long num = 0, dd = 1;
-        if (e0 < 0) { kx = 0; num = L0; dd = -(long long)d0; }
-        if (e1 < 0 && (kx < 0 || (long long)L1 * dd < num * (-(long long)d1))) { kx = 1; num = L1; dd = -(long long)d1; }
-        if (e2 < 0 && (kx < 0 || (long long)L2 * dd < num * (-(long long)d2))) { kx = 2; num = L2; dd = -(long long)d2; }
-        const float sx = (float)num / (float)dd;
-        // crossing point: Lambda_kx = 0, the other two keep their sum
-        const int ka = kx == 2 ? 0 : kx + 1;
-        const int kb = kx == 0 ? 2 : kx - 1;
-        const int La = sel3(ka, L0, L1, L2), da = sel3(ka, d0, d1, d2);
-        int xa = La + (int)__builtin_rintf(sx * (float)da);
-        xa = xa < 0 ? 0 : (xa > kS ? kS : xa);
-        const int xb = kS - xa;
-        const int x0 = ka == 0 ? xa : (kb == 0 ? xb : 0);
-        const int x1 = ka == 1 ? xa : (kb == 1 ? xb : 0);
-        const int x2 = ka == 2 ? xa : (kb == 2 ? xb : 0);
-        piece_current(L0, L1, L2, x0, x1, x2, kq, c0, c1, c2);
-        if (first && t == acc_t) { a0 += c0; a1 += c1; a2 += c2; }
-        else if (first) { dep3(w, acc_t, a0, a1, a2); acc_t = t; a0 = c0; a1 = c1; a2 = c2; }
-        else dep3(w, t, c0, c1, c2);
-        first = false;
-        const float rem = 1.0f - sx;
-        fz *= rem;
-        fr *= rem;
-        const int4 nb = m.nbr[t];
-        const int n = sel3(kx, nb.x, nb.y, nb.z);
-        if (n < 0) {
-            if (-n == kTagAxis) {           // rho = 0 cannot be crossed: stay on it
-                L0 = x0; L1 = x1; L2 = x2;
-                break;
-            }
-            // conductor / open boundary: absorbed; its charge stays on the wall nodes
-            const int4 tn = m.tnodes[t];
-            const int na = sel3(ka, tn.x, tn.y, tn.z), nbn = sel3(kb, tn.x, tn.y, tn.z);
-            atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
-            atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
-            atomicAdd(&s.ctr->n_absorbed, 1ull);
-            P.cell = -1;
-            return;
-        }
-        const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
-        const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
-        L0 = pa == 0 ? xa : (pb == 0 ? xb : 0);
-        L1 = pa == 1 ? xa : (pb == 1 ? xb : 0);
-        L2 = pa == 2 ? xa : (pb == 2 ? xb : 0);
-        entry = q;
-        t = n;
-        if (seg + 1 >= max_walk) {          // cut: the particle stops at the crossing
-            atomicAdd(&s.ctr->walk_overflow, 1ull);
-            break;
-        }
-    }
-    P.cell = t | (sp << kCellBits);
-    P.L0 = (uint32_t)L0;
-    P.L1 = (uint32_t)L1;
 }
 
-__global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int max_walk) {
-    __shared__ unsigned long long lacc[3 * kWin];
-    __shared__ int s_base;
+// integer change of the barycentric coordinates for a displacement in face t
+__device__ __forceinline__ void lam_change(const float4 g, float fz, float fr, int &d0, int &d1, int &d2) {
+    const float d0f = fminf(fmaxf(g.x * fz + g.y * fr, -1.0e9f), 1.0e9f);
+    const float d1f = fminf(fmaxf(g.z * fz + g.w * fr, -1.0e9f), 1.0e9f);
+    d0 = (int)__builtin_rintf(d0f);
+    d1 = (int)__builtin_rintf(d1f);
+    d2 = -d0 - d1;
+}
+
+constexpr int kChunk = kWG * kPPT;   // particles per k_push block = mover slots per block
+
+template <bool SINGLE>
+__global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_count, PushConst k0) {
+    __shared__ int s_nmv;
     const int chunk = xcd_block(blockIdx.x, gridDim.x);
     const long long n = (long long)s.ctr->n_slots;
-    const long long pb = (long long)chunk * kWG * kPPT;
-    if (pb >= n) return;
+    const long long p0 = ((long long)chunk * kWG + threadIdx.x) * kPPT;
+    if ((long long)chunk * kChunk >= n) {                    // whole block past the end
+        if (threadIdx.x == 0) s.mv_n[chunk] = 0;
+        return;
+    }
+    __shared__ unsigned long long s_jl[3 * kWin];
+    __shared__ int s_cl[kWin];
+    __shared__ int s_base;
+    if (threadIdx.x == 0) {
+        s_nmv = 0;
+        const int c0 = s.cell[s.cur][(long long)chunk * kChunk];
+        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kWinLead;
+    }
+    Win w{s_jl, s_cl, 0};
+    win_zero(w);
+    __syncthreads();
+    w.base = s_base;
     const int c = s.cur;
     int32_t *cell = s.cell[c];
-    uint32_t *L0 = s.L0[c], *L1 = s.L1[c];
-    float *ur = s.ur[c], *up = s.up[c], *uz = s.uz[c];
-    if (threadIdx.x == 0) {
-        const int c0 = cell[pb];
-        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kWin / 8;
-    }
-    for (int i = threadIdx.x; i < 3 * kWin; i += kWG) lacc[i] = 0ull;
-    __syncthreads();
-    WinAcc w{lacc, s_base, s.Jloc};
-    const long long p0 = pb + (long long)threadIdx.x * kPPT;
+    uint32_t *L0a = s.L0[c], *L1a = s.L1[c];
+    float *ura = s.ur[c], *upa = s.up[c], *uza = s.uz[c];
+    const bool full = p0 + kPPT <= n;
     Particle P[kPPT];
-    if (p0 + kPPT <= n) {
+    if (full) {
         const int4 cc = *reinterpret_cast<const int4 *>(cell + p0);
-        const uint4 a = *reinterpret_cast<const uint4 *>(L0 + p0);
-        const uint4 b = *reinterpret_cast<const uint4 *>(L1 + p0);
-        const float4 x = *reinterpret_cast<const float4 *>(ur + p0);
-        const float4 y = *reinterpret_cast<const float4 *>(up + p0);
-        const float4 z = *reinterpret_cast<const float4 *>(uz + p0);
+        const uint4 a = *reinterpret_cast<const uint4 *>(L0a + p0);
+        const uint4 b = *reinterpret_cast<const uint4 *>(L1a + p0);
+        const float4 x = *reinterpret_cast<const float4 *>(ura + p0);
+        const float4 y = *reinterpret_cast<const float4 *>(upa + p0);
+        const float4 z = *reinterpret_cast<const float4 *>(uza + p0);
         P[0] = {cc.x, a.x, b.x, x.x, y.x, z.x};
         P[1] = {cc.y, a.y, b.y, x.y, y.y, z.y};
         P[2] = {cc.z, a.z, b.z, x.z, y.z, z.z};
@@ -281,38 +316,222 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const long long p = p0 + j;
-            if (p < n) P[j] = {cell[p], L0[p], L1[p], ur[p], up[p], uz[p]};
+            if (p < n) P[j] = {cell[p], L0a[p], L1a[p], ura[p], upa[p], uza[p]};
             else P[j] = {-1, 0u, 0u, 0.f, 0.f, 0.f};
         }
     }
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
+    int ct = -1, cc = 0;             // run-length count of the new faces (stayers only)
+    bool mover[kPPT];
+    float mfz[kPPT], mfr[kPPT];
+    // face data cached across the thread's particles (consecutive particles share faces)
+    int Tc = -1;
+    float4 cf0 = make_float4(0.f, 0.f, 0.f, 0.f), cf1 = cf0, cr4 = cf0, cg = cf0;
 #pragma unroll
-    for (int j = 0; j < kPPT; ++j) push_walk(m, s, P[j], w, acc_t, a0, a1, a2, max_walk);
-    if (acc_t >= 0) dep3(w, acc_t, a0, a1, a2);
-    if (p0 + kPPT <= n) {
+    for (int j = 0; j < kPPT; ++j) {
+        mover[j] = false;
+        mfz[j] = mfr[j] = 0.0f;
+        if (P[j].cell < 0) continue;
+        const int T = P[j].cell & kCellMask;
+        const int sp = (P[j].cell >> kCellBits) & 15;
+        if (T != Tc) {
+            Tc = T;
+            cf0 = s.f0[T]; cf1 = s.f1[T]; cr4 = m.rho4[T]; cg = m.gS[T];
+        }
+        const PushConst ic = push_const<SINGLE>(m, k0, T, sp);
+        const int L0 = (int)P[j].L0, L1 = (int)P[j].L1, L2 = kS - L0 - L1;
+        float fz, fr;
+        push(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
+        int d0, d1, d2;
+        lam_change(cg, fz, fr, d0, d1, d2);
+        const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
+        if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
+            long long c0, c1, c2;
+            piece_current(L0, L1, L2, e0, e1, e2, SINGLE ? 1 : ic.kq, c0, c1, c2);
+            if (T != acc_t) {
+                if (acc_t >= 0) win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
+                acc_t = T; a0 = a1 = a2 = 0;
+            }
+            a0 += c0; a1 += c1; a2 += c2;
+            P[j].L0 = (uint32_t)e0;
+            P[j].L1 = (uint32_t)e1;
+            if (do_count) {
+                if (T == ct) ++cc;
+                else {
+                    if (ct >= 0) win_add_c(w, s.cnt, ct, cc);
+                    ct = T; cc = 1;
+                }
+            }
+        } else {
+            mover[j] = true;
+            mfz[j] = fz;
+            mfr[j] = fr;
+        }
+    }
+    wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
+    if (do_count) wave_count(w, s.cnt, ct, cc);
+    // append the movers to this block's region of the mover list (LDS counter)
+    const int lane = threadIdx.x & 63;
+    const long long region = (long long)chunk * kChunk;
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j) {
+        const unsigned long long mask = __ballot(mover[j]);
+        if (mask == 0ull) continue;
+        int base = 0;
+        if (lane == __ffsll((long long)mask) - 1) base = atomicAdd(&s_nmv, __popcll(mask));
+        base = __shfl(base, __ffsll((long long)mask) - 1, 64);
+        if (mover[j]) {
+            const long long q = region + base + __popcll(mask & ((1ull << lane) - 1ull));
+            s.mv_p[q] = (int)(p0 + j);
+            s.mv_c[q] = P[j].cell;
+            s.mv_l0[q] = (int)P[j].L0;
+            s.mv_l1[q] = (int)P[j].L1;
+            s.mv_fz[q] = mfz[j];
+            s.mv_fr[q] = mfr[j];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.mv_n[chunk] = s_nmv;
+    win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
+    if (full) {
         *reinterpret_cast<int4 *>(cell + p0) = make_int4(P[0].cell, P[1].cell, P[2].cell, P[3].cell);
-        *reinterpret_cast<uint4 *>(L0 + p0) = make_uint4(P[0].L0, P[1].L0, P[2].L0, P[3].L0);
-        *reinterpret_cast<uint4 *>(L1 + p0) = make_uint4(P[0].L1, P[1].L1, P[2].L1, P[3].L1);
-        *reinterpret_cast<float4 *>(ur + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
-        *reinterpret_cast<float4 *>(up + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
-        *reinterpret_cast<float4 *>(uz + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
+        *reinterpret_cast<uint4 *>(L0a + p0) = make_uint4(P[0].L0, P[1].L0, P[2].L0, P[3].L0);
+        *reinterpret_cast<uint4 *>(L1a + p0) = make_uint4(P[0].L1, P[1].L1, P[2].L1, P[3].L1);
+        *reinterpret_cast<float4 *>(ura + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
+        *reinterpret_cast<float4 *>(upa + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
+        *reinterpret_cast<float4 *>(uza + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
     } else {
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const long long p = p0 + j;
             if (p < n) {
-                cell[p] = P[j].cell; L0[p] = P[j].L0; L1[p] = P[j].L1;
-                ur[p] = P[j].ur; up[p] = P[j].up; uz[p] = P[j].uz;
+                cell[p] = P[j].cell; L0a[p] = P[j].L0; L1a[p] = P[j].L1;
+                ura[p] = P[j].ur; upa[p] = P[j].up; uza[p] = P[j].uz;
             }
         }
     }
+}
+
+// Walk of the particles that leave their face: straight pieces face by
+// face, each piece's current deposited (reduced per face across the wave),
+// until the path ends inside a face, is absorbed by a conductor or open
+// boundary (its charge kept on the wall nodes), stops on the axis, or hits
+// the piece cap.  Writes the particle's new cell and coordinates.
+// Block b walks the movers k_push block b appended (same faces: locality).
+template <bool SINGLE>
+__global__ __launch_bounds__(kWG) void k_walk(DevMesh m, DevState s, int max_walk, int do_count, PushConst k0) {
+    __shared__ unsigned long long s_jl[3 * kWin];
+    __shared__ int s_cl[kWin];
+    const int b = blockIdx.x;
+    const int nmv = s.mv_n[b];
+    if (nmv == 0) return;
+    const long long region = (long long)b * kChunk;
+    Win w{s_jl, s_cl, (s.mv_c[region] & kCellMask) - kWinLead};
+    win_zero(w);
     __syncthreads();
-    for (int i = threadIdx.x; i < 3 * kWin; i += kWG) {
-        const unsigned long long v = lacc[i];
-        const long long gi = 3ll * w.base + i;
-        if (v != 0ull && gi >= 0 && gi < 3ll * m.n2) atomicAdd(&s.Jloc[gi], v);
+    // uniform trip count across the block so the per-piece reductions see all lanes
+    const int rounds = (nmv + kWG - 1) / kWG;
+    const int c = s.cur;
+    for (int r = 0; r < rounds; ++r) {
+        const int ii = r * kWG + threadIdx.x;
+        const long long i = region + ii;
+        bool active = ii < nmv;
+        int t = 0, sp = 0, kq = 1, L0 = 0, L1 = 0, L2 = 0, entry = -1;
+        float fz = 0.f, fr = 0.f;
+        long long p = 0;
+        if (active) {
+            p = s.mv_p[i];
+            const int cw = s.mv_c[i];
+            t = cw & kCellMask;
+            sp = (cw >> kCellBits) & 15;
+            kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
+            L0 = s.mv_l0[i]; L1 = s.mv_l1[i]; L2 = kS - L0 - L1;
+            fz = s.mv_fz[i]; fr = s.mv_fr[i];
+        }
+        int newcell = -2;                   // -2: still walking
+        for (int seg = 0; active; ++seg) {
+            int dt_face = -1;
+            long long c0 = 0, c1 = 0, c2 = 0;
+            if (active) {
+                int d0, d1, d2;
+                lam_change(m.gS[t], fz, fr, d0, d1, d2);
+                // never leave through the side just entered (rounding); slide along it instead
+                if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
+                if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
+                if (entry == 2 && d2 < 0) { d2 = 0; d1 = -d0; }
+                const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
+                dt_face = t;
+                if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
+                    piece_current(L0, L1, L2, e0, e1, e2, kq, c0, c1, c2);
+                    L0 = e0; L1 = e1; L2 = e2;
+                    newcell = t | (sp << kCellBits);
+                    active = false;
+                } else {
+                    // exit side: smallest Lambda_k / (-d_k) among the coordinates going negative
+                    // (float comparison: any valid choice keeps the walk charge-conserving)
+                    int kx = -1;
+                    float best = 3.0e38f;
+                    if (e0 < 0) { kx = 0; best = (float)L0 * __builtin_amdgcn_rcpf((float)(-d0)); }
+                    if (e1 < 0) { const float v = (float)L1 * __builtin_amdgcn_rcpf((float)(-d1)); if (v < best) { kx = 1; best = v; } }
+                    if (e2 < 0) { const float v = (float)L2 * __builtin_amdgcn_rcpf((float)(-d2)); if (v < best) { kx = 2; best = v; } }
+                    const float sx = fminf(best, 1.0f);
+                    // crossing point: Lambda_kx = 0, the other two keep their sum
+                    const int ka = kx == 2 ? 0 : kx + 1;
+                    const int kb = kx == 0 ? 2 : kx - 1;
+                    const int La = sel3(ka, L0, L1, L2), da = sel3(ka, d0, d1, d2);
+                    int xa = La + (int)__builtin_rintf(sx * (float)da);
+                    xa = xa < 0 ? 0 : (xa > kS ? kS : xa);
+                    const int xb = kS - xa;
+                    const int x0 = ka == 0 ? xa : (kb == 0 ? xb : 0);
+                    const int x1 = ka == 1 ? xa : (kb == 1 ? xb : 0);
+                    const int x2 = ka == 2 ? xa : (kb == 2 ? xb : 0);
+                    piece_current(L0, L1, L2, x0, x1, x2, kq, c0, c1, c2);
+                    const float rem = 1.0f - sx;
+                    fz *= rem;
+                    fr *= rem;
+                    const int4 nb = m.nbr[t];
+                    const int nn = sel3(kx, nb.x, nb.y, nb.z);
+                    if (nn < 0) {
+                        if (-nn == kTagAxis) {          // rho = 0 cannot be crossed: stay on it
+                            L0 = x0; L1 = x1; L2 = x2;
+                            newcell = t | (sp << kCellBits);
+                        } else {                        // absorbed; its charge stays on the wall nodes
+                            const int4 tn = m.tnodes[t];
+                            const int na = sel3(ka, tn.x, tn.y, tn.z), nbn = sel3(kb, tn.x, tn.y, tn.z);
+                            atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
+                            atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
+                            atomicAdd(&s.ctr->n_absorbed, 1ull);
+                            newcell = -1;
+                        }
+                        active = false;
+                    } else {
+                        const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
+                        const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
+                        L0 = pa == 0 ? xa : (pb == 0 ? xb : 0);
+                        L1 = pa == 1 ? xa : (pb == 1 ? xb : 0);
+                        L2 = pa == 2 ? xa : (pb == 2 ? xb : 0);
+                        entry = q;
+                        t = nn;
+                        if (seg + 1 >= max_walk) {      // cut: the particle stops at the crossing
+                            atomicAdd(&s.ctr->walk_overflow, 1ull);
+                            newcell = t | (sp << kCellBits);
+                            active = false;
+                        }
+                    }
+                }
+            }
+            if (dt_face >= 0) win_add_j(w, s.Jloc, dt_face, c0, c1, c2);
+        }
+        if (ii < nmv) {
+            s.cell[c][p] = newcell;
+            s.L0[c][p] = (uint32_t)L0;
+            s.L1[c][p] = (uint32_t)L1;
+        }
+        if (do_count && ii < nmv && newcell >= 0) win_add_c(w, s.cnt, newcell & kCellMask, 1);
     }
+    __syncthreads();
+    win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
 }
 
 // ------------------------------------------------------------------ edges
@@ -363,12 +582,48 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t *p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_count(DevState s) {
+// Counting-sort passes over blocks of kSortChunk consecutive particles.  A
+// block's particles usually lie in few consecutive faces (the array is kept
+// sorted), so counts and slot reservations go through an LDS window of faces
+// and only one global atomic per (block, face) is needed.
+constexpr int kSortChunk = 1024;
+constexpr int kSortWin = 1024;
+
+__global__ __launch_bounds__(256) void k_count(DevState s, int n2) {
+    __shared__ int lcnt[kSortWin];
+    __shared__ int s_base;
     const long long n = (long long)s.ctr->n_slots;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int c = s.cell[s.cur][p];
-    if (c >= 0) atomicAdd(&s.cnt[c & kCellMask], 1);
+    const long long pb = (long long)blockIdx.x * kSortChunk;
+    if (pb >= n) return;
+    const int32_t *__restrict__ cell = s.cell[s.cur];
+    if (threadIdx.x == 0) {
+        const int c0 = cell[pb];
+        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kSortWin / 8;
+    }
+    for (int i = threadIdx.x; i < kSortWin; i += 256) lcnt[i] = 0;
+    __syncthreads();
+    const int base = s_base;
+    const int lane = threadIdx.x & 63;
+    for (int j = threadIdx.x; j < kSortChunk; j += 256) {
+        const long long p = pb + j;
+        const int c = p < n ? cell[p] : -1;
+        const int t = c & kCellMask, rel = t - base;
+        const bool inwin = c >= 0 && rel >= 0 && rel < kSortWin;
+        if (c >= 0 && !inwin) atomicAdd(&s.cnt[t], 1);
+        unsigned long long todo = __ballot(inwin);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int k0 = __shfl(t, leader, 64);
+            const unsigned long long same = __ballot(inwin && t == k0);
+            if (lane == leader) atomicAdd(&lcnt[rel], __popcll(same));
+            todo &= ~same;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kSortWin; i += 256) {
+        const int v = lcnt[i], t = base + i;
+        if (v != 0 && t >= 0 && t < n2) atomicAdd(&s.cnt[t], v);
+    }
 }
 
 // exclusive scan of cnt[0..n) in blocks of 1024; block totals to blk
@@ -424,20 +679,91 @@ __global__ __launch_bounds__(256) void k_scan_add(int32_t *cnt, const int32_t *b
         if (i + j < n) cnt[i + j] += blk[blockIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_scatter(DevState s) {
+__global__ __launch_bounds__(256) void k_scatter(DevState s, int n2) {
+    __shared__ int lcnt[kSortWin];
+    __shared__ int s_base;
+    constexpr int K = kSortChunk / 256;
     const long long n = (long long)s.ctr->n_slots;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    const long long pb = (long long)blockIdx.x * kSortChunk;
+    if (pb >= n) return;
     const int a = s.cur, b = 1 - s.cur;
-    const int c = s.cell[a][p];
-    if (c < 0) return;
-    const int q = atomicAdd(&s.cnt[c & kCellMask], 1);
-    s.cell[b][q] = c;
-    s.L0[b][q] = s.L0[a][p];
-    s.L1[b][q] = s.L1[a][p];
-    s.ur[b][q] = s.ur[a][p];
-    s.up[b][q] = s.up[a][p];
-    s.uz[b][q] = s.uz[a][p];
+    const int32_t *__restrict__ cell_a = s.cell[a];
+    const uint32_t *__restrict__ l0_a = s.L0[a];
+    const uint32_t *__restrict__ l1_a = s.L1[a];
+    const float *__restrict__ ur_a = s.ur[a];
+    const float *__restrict__ up_a = s.up[a];
+    const float *__restrict__ uz_a = s.uz[a];
+    int32_t *__restrict__ cell_b = s.cell[b];
+    uint32_t *__restrict__ l0_b = s.L0[b];
+    uint32_t *__restrict__ l1_b = s.L1[b];
+    float *__restrict__ ur_b = s.ur[b];
+    float *__restrict__ up_b = s.up[b];
+    float *__restrict__ uz_b = s.uz[b];
+    if (threadIdx.x == 0) {
+        const int c0 = cell_a[pb];
+        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kSortWin / 8;
+    }
+    for (int i = threadIdx.x; i < kSortWin; i += 256) lcnt[i] = 0;
+    int cv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const long long p = pb + threadIdx.x + 256 * k;
+        cv[k] = p < n ? cell_a[p] : -1;
+    }
+    __syncthreads();
+    const int base = s_base;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int rank[K];
+    // 1. rank of each particle among the block's particles of the same face:
+    //    lanes of a wave holding the same face are ranked by ballot, and the
+    //    wave takes its range of the block's count with one LDS atomic
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = cv[k];
+        const int t = c & kCellMask, rel = t - base;
+        const bool inwin = c >= 0 && rel >= 0 && rel < kSortWin;
+        rank[k] = -1;
+        if (c >= 0 && !inwin) rank[k] = -2 - atomicAdd(&s.cnt[t], 1);   // outside the window: global slot
+        unsigned long long todo = __ballot(inwin);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int k0 = __shfl(t, leader, 64);
+            const unsigned long long same = __ballot(inwin && t == k0);
+            int off = 0;
+            if (lane == leader) off = atomicAdd(&lcnt[rel], __popcll(same));
+            off = __shfl(off, leader, 64);
+            if (inwin && t == k0) rank[k] = off + __popcll(same & lt);
+            todo &= ~same;
+        }
+    }
+    __syncthreads();
+    // 2. one global reservation per face of the window
+    for (int i = threadIdx.x; i < kSortWin; i += 256) {
+        const int v = lcnt[i], t = base + i;
+        if (v != 0) lcnt[i] = atomicAdd(&s.cnt[t], v);
+    }
+    __syncthreads();
+    // 3. move: all loads first, then all stores
+    uint32_t v0[K], v1[K];
+    float v2[K], v3[K], v4[K];
+    int q[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const long long p = pb + threadIdx.x + 256 * k;
+        q[k] = -1;
+        if (rank[k] == -1) continue;
+        v0[k] = l0_a[p]; v1[k] = l1_a[p]; v2[k] = ur_a[p]; v3[k] = up_a[p]; v4[k] = uz_a[p];
+        q[k] = rank[k] >= 0 ? lcnt[(cv[k] & kCellMask) - base] + rank[k] : -2 - rank[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (q[k] < 0) continue;
+        const int qq = q[k];
+        cell_b[qq] = cv[k];
+        l0_b[qq] = v0[k]; l1_b[qq] = v1[k];
+        ur_b[qq] = v2[k]; up_b[qq] = v3[k]; uz_b[qq] = v4[k];
+    }
 }
 
 __global__ void k_set_slots(DevState s, const int32_t *total) { s.ctr->n_slots = (unsigned long long)(*total); }
@@ -449,19 +775,37 @@ __global__ __launch_bounds__(256) void k_charge_init(DevMesh m, DevState s) {
 }
 
 __global__ __launch_bounds__(256) void k_charge(DevMesh m, DevState s) {
+    // each thread sums 8 consecutive particles, one atomic per run of equal faces
     const long long n = (long long)s.ctr->n_slots;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int c = s.cell[s.cur][p];
-    if (c < 0) return;
-    const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
-    const int inst = m.tinst ? m.tinst[T] : 0;
-    const long long kq = m.inst[inst].kq[sp];
-    const long long L0 = s.L0[s.cur][p], L1 = s.L1[s.cur][p], L2 = kS - L0 - L1;
-    const int4 tn = m.tnodes[T];
-    atomicAdd((unsigned long long *)&s.Qfx[tn.x], (unsigned long long)(kq * L0));
-    atomicAdd((unsigned long long *)&s.Qfx[tn.y], (unsigned long long)(kq * L1));
-    atomicAdd((unsigned long long *)&s.Qfx[tn.z], (unsigned long long)(kq * L2));
+    const long long p0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+    int run_t = -1;
+    long long q0 = 0, q1 = 0, q2 = 0;
+    for (int j = 0; j < 8; ++j) {
+        const long long p = p0 + j;
+        if (p >= n) break;
+        const int c = s.cell[s.cur][p];
+        if (c < 0) continue;
+        const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
+        const int inst = m.tinst ? m.tinst[T] : 0;
+        const long long kq = m.inst[inst].kq[sp];
+        const long long L0 = s.L0[s.cur][p], L1 = s.L1[s.cur][p], L2 = kS - L0 - L1;
+        if (T != run_t) {
+            if (run_t >= 0) {
+                const int4 tn = m.tnodes[run_t];
+                atomicAdd((unsigned long long *)&s.Qfx[tn.x], (unsigned long long)q0);
+                atomicAdd((unsigned long long *)&s.Qfx[tn.y], (unsigned long long)q1);
+                atomicAdd((unsigned long long *)&s.Qfx[tn.z], (unsigned long long)q2);
+            }
+            run_t = T; q0 = q1 = q2 = 0;
+        }
+        q0 += kq * L0; q1 += kq * L1; q2 += kq * L2;
+    }
+    if (run_t >= 0) {
+        const int4 tn = m.tnodes[run_t];
+        atomicAdd((unsigned long long *)&s.Qfx[tn.x], (unsigned long long)q0);
+        atomicAdd((unsigned long long *)&s.Qfx[tn.y], (unsigned long long)q1);
+        atomicAdd((unsigned long long *)&s.Qfx[tn.z], (unsigned long long)q2);
+    }
 }
 
 __device__ __forceinline__ void atomic_max_pos(unsigned long long *a, double v) {
@@ -469,7 +813,7 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long *a, double v) 
 }
 
 // Gauss residual res_v = (Ddiv D)_v - Q_v, its drift from res^0, and the
-// continuity residual 2^24 (Q^{n+1} - Q^n) + (Ddiv J)_v in fixed point.
+// continuity residual 2^23 (Q^{n+1} - Q^n) + (Ddiv J)_v in fixed point.
 __global__ __launch_bounds__(256) void k_node_diag(DevMesh m, DevState s, int have_prev, int first) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= m.n0) return;
@@ -532,22 +876,27 @@ __global__ __launch_bounds__(256) void k_energy_fields(DevMesh m, DevState s) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_energy_kin(DevMesh m, DevState s) {
+__global__ __launch_bounds__(256) void k_energy_kin(DevMesh m, DevState s, double *part) {
     const long long n = (long long)s.ctr->n_slots;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double wk = 0.0;
-    if (p < n) {
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
         const int c = s.cell[s.cur][p];
-        if (c >= 0) {
-            const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
-            const int inst = m.tinst ? m.tinst[T] : 0;
-            const double a = s.ur[s.cur][p], b = s.up[s.cur][p], z = s.uz[s.cur][p];
-            const double u2 = a * a + b * b + z * z;
-            wk = m.inst[inst].mw[sp] * (u2 / (sqrt(1.0 + u2) + 1.0));   // (gamma - 1) without cancellation
-        }
+        if (c < 0) continue;
+        const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
+        const int inst = m.tinst ? m.tinst[T] : 0;
+        const double a = s.ur[s.cur][p], b = s.up[s.cur][p], z = s.uz[s.cur][p];
+        const double u2 = a * a + b * b + z * z;
+        wk += m.inst[inst].mw[sp] * (u2 / (sqrt(1.0 + u2) + 1.0));   // (gamma - 1) without cancellation
     }
     wk = block_sum(wk);
-    if (threadIdx.x == 0) atomicAdd(&s.diag->WK, wk);
+    if (threadIdx.x == 0) part[blockIdx.x] = wk;
+}
+
+__global__ __launch_bounds__(256) void k_energy_kin_final(DevState s, const double *part, int np) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) v += part[i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) s.diag->WK = v;
 }
 
 // --------------------------------------------------------------- launchers
@@ -558,9 +907,27 @@ void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st) {
     hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s);
 }
 
-void launch_particles(const DevMesh &m, DevState &s, int max_walk, hipStream_t st) {
+// single: one instance with one species whose charge multiple is 1; its
+// constants travel as kernel arguments (scalar registers) instead of a
+// per-particle table lookup.
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single,
+                      hipStream_t st) {
     if (s.capacity == 0) return;
-    hipLaunchKernelGGL(k_particles, dim3(nblk(s.capacity, kWG * kPPT)), dim3(kWG), 0, st, m, s, max_walk);
+    const dim3 grid(nblk(s.capacity, kChunk));
+    const dim3 wgrid = grid;
+    if (single) {
+        const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1};
+        hipLaunchKernelGGL(k_push<true>, grid, dim3(kWG), 0, st, m, s, count ? 1 : 0, k0);
+        hipLaunchKernelGGL(k_walk<true>, wgrid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
+    } else {
+        const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
+        hipLaunchKernelGGL(k_push<false>, grid, dim3(kWG), 0, st, m, s, count ? 1 : 0, k0);
+        hipLaunchKernelGGL(k_walk<false>, wgrid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
+    }
+}
+
+void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(nblk(m.n2 + 1, 256)), dim3(256), 0, st, s.cnt, (int64_t)m.n2 + 1);
 }
 
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st) {
@@ -571,16 +938,19 @@ void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st) {
     hipLaunchKernelGGL(k_spmv, dim3(nblk(m.n1, 256)), dim3(256), 0, st, m, s);
 }
 
-void launch_sort(const DevMesh &m, DevState &s, hipStream_t st) {
+// counted: the particle kernel of this step already histogrammed the faces
+void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st) {
     if (s.capacity == 0) return;
     const int n = m.n2;
     const int nb = (int)nblk(n, 1024);
-    hipLaunchKernelGGL(k_zero_i32, dim3(nblk(n + 1, 256)), dim3(256), 0, st, s.cnt, (int64_t)n + 1);
-    hipLaunchKernelGGL(k_count, dim3(nblk(s.capacity, 256)), dim3(256), 0, st, s);
+    if (!counted) {
+        launch_sort_zero(m, s, st);
+        hipLaunchKernelGGL(k_count, dim3(nblk(s.capacity, kSortChunk)), dim3(256), 0, st, s, n);
+    }
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, st, s.cnt, s.blk, n);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, st, s.blk, nb, s.cnt + n, s);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, st, s.cnt, s.blk, n);
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(s.capacity, 256)), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(s.capacity, kSortChunk)), dim3(256), 0, st, s, n);
     hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, st, s, s.cnt + n);
     s.cur = 1 - s.cur;
 }
@@ -588,11 +958,15 @@ void launch_sort(const DevMesh &m, DevState &s, hipStream_t st) {
 void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st) {
     (void)hipMemsetAsync(s.diag, 0, sizeof(DevDiag), st);
     hipLaunchKernelGGL(k_charge_init, dim3(nblk(m.n0, 256)), dim3(256), 0, st, m, s);
-    if (s.capacity) hipLaunchKernelGGL(k_charge, dim3(nblk(s.capacity, 256)), dim3(256), 0, st, m, s);
+    if (s.capacity) hipLaunchKernelGGL(k_charge, dim3(nblk(s.capacity, 256 * 8)), dim3(256), 0, st, m, s);
     hipLaunchKernelGGL(k_node_diag, dim3(nblk(m.n0, 256)), dim3(256), 0, st, m, s, have_prev_q ? 1 : 0, first ? 1 : 0);
     const int64_t ne = m.n1 > m.n2 ? m.n1 : m.n2;
     hipLaunchKernelGGL(k_energy_fields, dim3(nblk(ne, 256)), dim3(256), 0, st, m, s);
-    if (s.capacity) hipLaunchKernelGGL(k_energy_kin, dim3(nblk(s.capacity, 256)), dim3(256), 0, st, m, s);
+    if (s.capacity) {
+        const int np = 1024;   // partial sums (s.blk-sized scratch is int; use the Jfx-free diag buffer)
+        hipLaunchKernelGGL(k_energy_kin, dim3(np), dim3(256), 0, st, m, s, s.kin_part);
+        hipLaunchKernelGGL(k_energy_kin_final, dim3(1), dim3(256), 0, st, s, s.kin_part, np);
+    }
 }
 
 }  // namespace axp
