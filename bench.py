@@ -30,11 +30,39 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1701_03784_amd", "csrc", "kernels_mixed.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_bwo_traffic.txt")
+
+
 def particle_bytes(n_live, n_faces):
-    """Algorithmic bytes of one particle-kernel launch: 24 B of particle state
-    read and written per particle, plus the per-face gather tile (32 B),
-    geometry (48 B) and current accumulators (24 B) once per face."""
-    return 48.0 * n_live + 104.0 * n_faces
+    """Algorithmic bytes of one k_push launch: 24 B of particle state read and
+    written per particle (48 B), plus once per face the gather tile (32 B),
+    the geometry used by the push (rho of the nodes and the scaled barycentric
+    gradients, 32 B) and the three fixed-point side currents (24 B)."""
+    return 48.0 * n_live + 88.0 * n_faces
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_push launch from the committed counter summary, if it
+    was taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def field_bytes(n_edges, n_faces, spai_nnz_padded):
@@ -146,6 +174,7 @@ def main():
     nnz_pad = info["spai_nnz"] * 1.15
     fb = field_bytes(n1, n2, nnz_pad)
     field_ms = sum(tim[k][0] for k in ("face", "edge", "spmv")) / args.steps
+    walk_ms, walk_n = tim["walk"]
     field_gbs = fb / (field_ms / 1e3) / 1e9
     per_phase = {k: round(v[0] / max(1, v[1]) * 1e3, 2) for k, v in tim.items() if v[1]}
     log(f"{args.steps} steps in {el:.3f} s: {ms_step:.3f} ms/step; per-launch us {per_phase}")
@@ -184,10 +213,12 @@ def main():
         "field_dof_steps_per_s": (n1 + n2) * args.steps / el,
         "field_hbm_gbs": field_gbs,
         "phase_us_per_launch": per_phase,
+        "phase_us_per_step": {k: round(v[0] / args.steps * 1e3, 2) for k, v in tim.items() if v[1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_particles", "bytes_per_launch": pb,
-                     "avg_launch_us": part_avg_s * 1e6},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_push", "bytes_per_launch": pb,
+                     "avg_launch_us": part_avg_s * 1e6,
+                     "kernel_source_sha256_16": kernel_source_hash()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

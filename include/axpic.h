@@ -229,13 +229,14 @@ axp_status axp_load(axp_ctx *ctx, const char *path);
  * stream sync) and reset by axp_set_timing(ctx, 1). */
 enum {
     AXP_PHASE_FACE = 0,      /* Faraday + gather tile (per face) */
-    AXP_PHASE_PARTICLES = 1, /* gather + push + walk + current (per particle) */
+    AXP_PHASE_PARTICLES = 1, /* gather + push + in-face current (per particle) */
     AXP_PHASE_EDGE = 2,      /* D update (per edge) */
     AXP_PHASE_SPMV = 3,      /* E = M D (per edge row) */
     AXP_PHASE_SORT = 4,      /* counting sort of particles by face */
     AXP_PHASE_DIAG = 5,      /* diagnostics */
     AXP_PHASE_INJECT = 6,    /* continuous injection */
-    AXP_N_PHASES = 7
+    AXP_PHASE_WALK = 7,      /* walk of the particles that leave their face (per mover) */
+    AXP_N_PHASES = 8
 };
 axp_status axp_set_timing(axp_ctx *ctx, int32_t on);
 axp_status axp_get_timing(axp_ctx *ctx, double *ms /*[AXP_N_PHASES]*/, int64_t *launches /*[AXP_N_PHASES]*/);

@@ -64,7 +64,7 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
            "axp_batch_destroy", "axp_set_timing", "axp_get_timing"]
-PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject"]
+PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject", "walk"]
 
 _lib = None
 

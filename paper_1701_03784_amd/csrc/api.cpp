@@ -575,10 +575,14 @@ axp_status axp_step(axp_ctx *c, int32_t n_steps) {
             const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
             { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(c->dm, c->ds, c->stream); }
             if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(c->dm, c->ds, c->stream); }
+            const bool single = c->dm.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
             {
                 PhaseScope ps(c, AXP_PHASE_PARTICLES);
-                const bool single = c->dm.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
-                launch_particles(c->dm, c->ds, c->cfg.max_walk, sort_now, single ? &c->ic : nullptr, c->stream);
+                launch_push(c->dm, c->ds, sort_now, single ? &c->ic : nullptr, c->stream);
+            }
+            {
+                PhaseScope ps(c, AXP_PHASE_WALK);
+                launch_walk(c->dm, c->ds, c->cfg.max_walk, sort_now, single ? &c->ic : nullptr, c->stream);
             }
             { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass(c->dm, c->ds, true, c->stream); }
             { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv(c->dm, c->ds, c->stream); }

@@ -108,8 +108,8 @@ struct DevState {
 
 // ---- launchers (kernels_mixed.hip) ----
 void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
-void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single,
-                      hipStream_t st);
+void launch_push(const DevMesh &m, DevState &s, bool count, const InstConst *single, hipStream_t st);
+void launch_walk(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st);
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);

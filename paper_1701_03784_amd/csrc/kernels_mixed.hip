@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t *p, int64_t n) {
 // sorted), so counts and slot reservations go through an LDS window of faces
 // and only one global atomic per (block, face) is needed.
 constexpr int kSortChunk = 1024;
-constexpr int kSortWin = 1024;
+constexpr int kSortWin = 4096;
 
 __global__ __launch_bounds__(256) void k_count(DevState s, int n2) {
     __shared__ int lcnt[kSortWin];
@@ -910,20 +910,24 @@ void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st) {
 // single: one instance with one species whose charge multiple is 1; its
 // constants travel as kernel arguments (scalar registers) instead of a
 // per-particle table lookup.
-void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single,
-                      hipStream_t st) {
+void launch_push(const DevMesh &m, DevState &s, bool count, const InstConst *single, hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nblk(s.capacity, kChunk));
-    const dim3 wgrid = grid;
     if (single) {
         const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1};
         hipLaunchKernelGGL(k_push<true>, grid, dim3(kWG), 0, st, m, s, count ? 1 : 0, k0);
-        hipLaunchKernelGGL(k_walk<true>, wgrid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
     } else {
         const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
         hipLaunchKernelGGL(k_push<false>, grid, dim3(kWG), 0, st, m, s, count ? 1 : 0, k0);
-        hipLaunchKernelGGL(k_walk<false>, wgrid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
     }
+}
+
+void launch_walk(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st) {
+    if (s.capacity == 0) return;
+    const dim3 grid(nblk(s.capacity, kChunk));
+    const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
+    if (single) hipLaunchKernelGGL(k_walk<true>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
+    else hipLaunchKernelGGL(k_walk<false>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
 }
 
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st) {
