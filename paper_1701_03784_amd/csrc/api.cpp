@@ -38,6 +38,9 @@ struct axp_ctx {
     DevMesh dm{};
     DevState ds{};
     InstConst ic{};
+    bool plain = false;   // FP64 step (AXP_PREC_PLAIN_FP64)
+    DevPlain dp{};
+    PlainConst pc{};
     std::vector<void *> allocs;
     std::vector<Species> species;
     double q_unit = 0;
@@ -145,6 +148,32 @@ void grow_particles(axp_ctx *c, int64_t need) {
     cap = (cap + 1023) / 1024 * 1024;
     DevCounters h = read_counters(c);
     int64_t used = (int64_t)h.n_slots;
+    if (c->plain) {
+        DevPlain &p = c->dp;
+        for (int b = 0; b < 2; ++b) {
+            int32_t *cell = zeros<int32_t>(c, cap);
+            double *f[5];
+            double **old[5] = {&p.l0[b], &p.l1[b], &p.ur[b], &p.up[b], &p.uz[b]};
+            for (int k = 0; k < 5; ++k) f[k] = zeros<double>(c, cap);
+            if (b == s.cur && used > 0) {
+                hcheck(hipMemcpyAsync(cell, s.cell[b], used * 4, hipMemcpyDeviceToDevice, c->stream), "copy");
+                for (int k = 0; k < 5; ++k)
+                    hcheck(hipMemcpyAsync(f[k], *old[k], used * 8, hipMemcpyDeviceToDevice, c->stream), "copy");
+            }
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+            dfree(c, s.cell[b]);
+            s.cell[b] = cell;
+            for (int k = 0; k < 5; ++k) { dfree(c, *old[k]); *old[k] = f[k]; }
+        }
+        dfree(c, p.mv_p); dfree(c, p.mv_c); dfree(c, p.mv_l0); dfree(c, p.mv_l1); dfree(c, p.mv_fz); dfree(c, p.mv_fr);
+        dfree(c, s.mv_n);
+        s.mv_n = zeros<int32_t>(c, cap / 1024 + 1);
+        p.mv_p = zeros<int32_t>(c, cap); p.mv_c = zeros<int32_t>(c, cap);
+        p.mv_l0 = zeros<double>(c, cap); p.mv_l1 = zeros<double>(c, cap);
+        p.mv_fz = zeros<double>(c, cap); p.mv_fr = zeros<double>(c, cap);
+        s.capacity = cap;
+        return;
+    }
     for (int b = 0; b < 2; ++b) {
         int32_t *cell = zeros<int32_t>(c, cap);
         uint32_t *l0 = zeros<uint32_t>(c, cap), *l1 = zeros<uint32_t>(c, cap);
@@ -211,7 +240,8 @@ void run_diag(axp_ctx *c) {
     bool have_prev = (c->last_diag_step == c->step - 1) && c->step > 0;
     {
         PhaseScope ps(c, AXP_PHASE_DIAG);
-        launch_diag(c->dm, c->ds, have_prev, !c->g0_set, c->stream);
+        if (c->plain) launch_diag_plain(c->dm, c->ds, c->dp, c->pc, have_prev, !c->g0_set, c->stream);
+        else launch_diag(c->dm, c->ds, have_prev, !c->g0_set, c->stream);
     }
     c->g0_set = true;
     c->last_diag_step = c->step;
@@ -258,6 +288,7 @@ void build_device(axp_ctx *c) {
         sptr[sl + 1] = sptr[sl] + int64_t(mx) * 64;
     }
     std::vector<float> mval(sptr[ns], 0.0f);
+    std::vector<double> mvald(c->plain ? sptr[ns] : 0, 0.0);
     std::vector<int32_t> mcol(sptr[ns], 0);
     for (int sl = 0; sl < ns; ++sl)
         for (int lane = 0; lane < 64; ++lane) {
@@ -267,6 +298,7 @@ void build_device(axp_ctx *c) {
             if (i < m.n1)
                 for (int64_t q = m.M.ptr[i]; q < m.M.ptr[i + 1]; ++q, ++j) {
                     mval[o + 64 * j] = float(m.M.val[q]);
+                    if (c->plain) mvald[o + 64 * j] = m.M.val[q];
                     mcol[o + 64 * j] = m.M.col[q];
                 }
             for (; j < slen[sl]; ++j) mcol[o + 64 * j] = i < m.n1 ? i : 0;
@@ -277,7 +309,8 @@ void build_device(axp_ctx *c) {
     d.etri = upload(c, etri);
     d.nptr = upload(c, m.nptr); d.nedge = upload(c, m.nedge); d.nsign = upload(c, m.nsign);
     d.nfree = upload(c, m.nfree); d.ninst = nullptr;
-    d.m_sptr = upload(c, sptr); d.m_slen = upload(c, slen); d.m_val = upload(c, mval); d.m_col = upload(c, mcol);
+    d.m_sptr = upload(c, sptr); d.m_slen = upload(c, slen); d.m_col = upload(c, mcol);
+    d.m_val = c->plain ? nullptr : upload(c, mval);
     d.a_ptr = upload(c, m.A.ptr); d.a_col = upload(c, m.A.col); d.a_val = upload(c, m.A.val);
     std::memset(&c->ic, 0, sizeof(InstConst));
     c->ic.dt = c->dt;
@@ -286,12 +319,31 @@ void build_device(axp_ctx *c) {
     upload_inst(c);
     DevState &s = c->ds;
     s.B = zeros<double>(c, m.n2); s.Bprev = zeros<double>(c, m.n2); s.HBdt = zeros<double>(c, m.n2);
-    s.f0 = zeros<float4>(c, m.n2); s.f1 = zeros<float4>(c, m.n2);
-    s.Jloc = zeros<unsigned long long>(c, size_t(3) * m.n2);
-    s.D = zeros<double>(c, m.n1); s.D32 = zeros<float>(c, m.n1); s.E = zeros<float>(c, m.n1);
-    s.Jfx = zeros<long long>(c, m.n1);
-    s.Qres = zeros<long long>(c, m.n0); s.Qfx = zeros<long long>(c, m.n0); s.Qprev = zeros<long long>(c, m.n0);
+    s.D = zeros<double>(c, m.n1);
     s.g0 = zeros<double>(c, m.n0);
+    if (c->plain) {
+        DevPlain &p = c->dp;
+        std::vector<double4> grad(m.n2), rho(m.n2);
+        for (int t = 0; t < m.n2; ++t) {
+            const auto &g = m.grad[t];
+            grad[t] = make_double4(g[0], g[1], g[2], g[3]);
+            rho[t] = make_double4(m.r[m.tv[t][0]], m.r[m.tv[t][1]], m.r[m.tv[t][2]], 1.0 / (2.0 * m.area[t]));
+        }
+        p.grad = upload(c, grad); p.rho = upload(c, rho); p.m_val = upload(c, mvald);
+        p.E = zeros<double>(c, m.n1);
+        p.f0 = zeros<double4>(c, m.n2); p.f1 = zeros<double4>(c, m.n2);
+        p.Jloc = zeros<double>(c, size_t(3) * m.n2); p.Jfx = zeros<double>(c, m.n1);
+        p.Qres = zeros<double>(c, m.n0); p.Q = zeros<double>(c, m.n0); p.Qprev = zeros<double>(c, m.n0);
+        std::memset(&c->pc, 0, sizeof(PlainConst));
+        c->pc.dt = c->dt;
+        c->pc.cdt = kC * c->dt;
+    } else {
+        s.f0 = zeros<float4>(c, m.n2); s.f1 = zeros<float4>(c, m.n2);
+        s.Jloc = zeros<unsigned long long>(c, size_t(3) * m.n2);
+        s.D32 = zeros<float>(c, m.n1); s.E = zeros<float>(c, m.n1);
+        s.Jfx = zeros<long long>(c, m.n1);
+        s.Qres = zeros<long long>(c, m.n0); s.Qfx = zeros<long long>(c, m.n0); s.Qprev = zeros<long long>(c, m.n0);
+    }
     s.cnt = zeros<int32_t>(c, size_t(m.n2) + 1);
     s.blk = zeros<int32_t>(c, size_t(m.n2) / 1024 + 2);
     s.ctr = zeros<DevCounters>(c, 1);
@@ -329,12 +381,12 @@ axp_status axp_create(const axp_config *cfg, axp_ctx **out) {
     if (cfg->spai_level < 1 || cfg->spai_level > 6 || cfg->spai_drop_tol < 0 || cfg->sort_period < 1 ||
         cfg->max_walk < 1 || cfg->diag_every < 0)
         return AXP_E_ARG;
-    if (cfg->precision == AXP_PREC_PLAIN_FP64) return AXP_E_ARG;   // FP64 step: see axp_plain.cpp
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return AXP_E_HIP;
     auto *c = new (std::nothrow) axp_ctx();
     if (!c) return AXP_E_OOM;
     c->cfg = *cfg;
+    c->plain = cfg->precision == AXP_PREC_PLAIN_FP64;
     if (hipSetDevice(cfg->device) != hipSuccess) { delete c; return AXP_E_HIP; }
     c->stream = (hipStream_t)cfg->hip_stream;
     *out = c;
@@ -454,8 +506,12 @@ axp_status axp_set_fields(axp_ctx *c, const double *E0, const double *B_mhalf) {
         DevState &s = c->ds;
         hcheck(hipMemcpyAsync(s.B, B.data(), m.n2 * 8, hipMemcpyHostToDevice, c->stream), "B");
         hcheck(hipMemcpyAsync(s.D, D.data(), m.n1 * 8, hipMemcpyHostToDevice, c->stream), "D");
-        hcheck(hipMemcpyAsync(s.D32, D32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "D32");
-        hcheck(hipMemcpyAsync(s.E, E32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "E");
+        if (c->plain) {
+            hcheck(hipMemcpyAsync(c->dp.E, E.data(), m.n1 * 8, hipMemcpyHostToDevice, c->stream), "E");
+        } else {
+            hcheck(hipMemcpyAsync(s.D32, D32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "D32");
+            hcheck(hipMemcpyAsync(s.E, E32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "E");
+        }
         hcheck(hipStreamSynchronize(c->stream), "sync");
         c->g0_set = false;
         c->last_diag_step = -1;
@@ -468,6 +524,7 @@ axp_status axp_set_external_bz(axp_ctx *c, double bz) {
     return guarded(c, [&]() -> axp_status {
         require_built(c);
         c->ic.bz = float(bz);
+        c->pc.bz = bz;
         upload_inst(c);
         return AXP_OK;
     });
@@ -493,6 +550,13 @@ axp_status axp_add_species(axp_ctx *c, double q, double m, int64_t weight, int32
         ic.mw[sp] = m * double(weight) * kC * kC / kTwoPi;
         ic.jscale = c->q_unit / (kTwoPi * double(kLamOne) * double(kLamOne));   // current unit 2^-46
         ic.qscale = c->q_unit / (kTwoPi * double(kLamOne));                    // charge unit 2^-23
+        PlainConst &pc = c->pc;
+        pc.n_species = ic.n_species;
+        pc.qe[sp] = q * c->dt / (2.0 * m * kC);
+        pc.qb[sp] = q * c->dt / (2.0 * m);
+        pc.kq[sp] = std::nearbyint(k);
+        pc.mw[sp] = ic.mw[sp];
+        pc.qunit = c->q_unit / kTwoPi;
         upload_inst(c);
         *id = sp;
         return AXP_OK;
@@ -509,6 +573,9 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
         std::vector<int32_t> cell(n);
         std::vector<uint32_t> l0(n), l1(n);
         std::vector<float> ur(n), up(n), uz(n);
+        const bool plain = c->plain;
+        std::vector<double> dl0(plain ? n : 0), dl1(plain ? n : 0), dur(plain ? n : 0), dup(plain ? n : 0),
+            duz(plain ? n : 0);
         std::vector<int> bad(1, -1);
         int nt = int(std::min<int64_t>(16, std::max<int64_t>(1, n / 4096)));
         std::vector<std::thread> th;
@@ -523,11 +590,19 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
                 }
                 double s = 0;
                 for (int k = 0; k < 3; ++k) { lam[k] = std::max(0.0, lam[k]); s += lam[k]; }
+                cell[i] = t | (species << kCellBits);
+                if (plain) {
+                    dl0[i] = lam[0] / s;
+                    dl1[i] = lam[1] / s;
+                    dur[i] = u[3 * i] / kC;
+                    dup[i] = u[3 * i + 1] / kC;
+                    duz[i] = u[3 * i + 2] / kC;
+                    continue;
+                }
                 int64_t a = std::llround(lam[0] / s * double(kLamOne));
                 int64_t b = std::llround(lam[1] / s * double(kLamOne));
                 a = std::min<int64_t>(std::max<int64_t>(a, 0), kLamOne);
                 b = std::min<int64_t>(std::max<int64_t>(b, 0), kLamOne - a);
-                cell[i] = t | (species << kCellBits);
                 l0[i] = uint32_t(a);
                 l1[i] = uint32_t(b);
                 ur[i] = float(u[3 * i] / kC);
@@ -546,14 +621,24 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
         DevState &s = c->ds;
         int b = s.cur;
         hcheck(hipMemcpyAsync(s.cell[b] + used, cell.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
+        if (plain) {
+            DevPlain &p = c->dp;
+            hcheck(hipMemcpyAsync(p.l0[b] + used, dl0.data(), n * 8, hipMemcpyHostToDevice, c->stream), "inject");
+            hcheck(hipMemcpyAsync(p.l1[b] + used, dl1.data(), n * 8, hipMemcpyHostToDevice, c->stream), "inject");
+            hcheck(hipMemcpyAsync(p.ur[b] + used, dur.data(), n * 8, hipMemcpyHostToDevice, c->stream), "inject");
+            hcheck(hipMemcpyAsync(p.up[b] + used, dup.data(), n * 8, hipMemcpyHostToDevice, c->stream), "inject");
+            hcheck(hipMemcpyAsync(p.uz[b] + used, duz.data(), n * 8, hipMemcpyHostToDevice, c->stream), "inject");
+        } else {
         hcheck(hipMemcpyAsync(s.L0[b] + used, l0.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
         hcheck(hipMemcpyAsync(s.L1[b] + used, l1.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
         hcheck(hipMemcpyAsync(s.ur[b] + used, ur.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
         hcheck(hipMemcpyAsync(s.up[b] + used, up.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
         hcheck(hipMemcpyAsync(s.uz[b] + used, uz.data(), n * 4, hipMemcpyHostToDevice, c->stream), "inject");
+        }
         unsigned long long ns = (unsigned long long)(used + n);
         hcheck(hipMemcpyAsync(&s.ctr->n_slots, &ns, 8, hipMemcpyHostToDevice, c->stream), "slots");
-        launch_sort(c->dm, s, false, c->stream);
+        if (plain) launch_sort_plain(c->dm, s, c->dp, false, c->stream);
+        else launch_sort(c->dm, s, false, c->stream);
         hcheck(hipGetLastError(), "sort launch");
         hcheck(hipStreamSynchronize(c->stream), "inject sync");
         c->n_live_host = int64_t(read_counters(c).n_slots);
@@ -571,7 +656,23 @@ axp_status axp_step(axp_ctx *c, int32_t n_steps) {
     if (!c || n_steps < 0) return AXP_E_ARG;
     return guarded(c, [&]() -> axp_status {
         require_built(c);
-        for (int i = 0; i < n_steps; ++i) {
+        for (int i = 0; i < n_steps && c->plain; ++i) {
+            const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
+            { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass_plain(c->dm, c->ds, c->dp, c->pc, c->stream); }
+            if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(c->dm, c->ds, c->stream); }
+            { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_push_plain(c->dm, c->ds, c->dp, c->pc, sort_now, c->stream); }
+            {
+                PhaseScope ps(c, AXP_PHASE_WALK);
+                launch_walk_plain(c->dm, c->ds, c->dp, c->pc, c->cfg.max_walk, sort_now, c->stream);
+            }
+            { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass_plain(c->dm, c->ds, c->dp, c->pc, c->stream); }
+            { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv_plain(c->dm, c->ds, c->dp, c->stream); }
+            ++c->step;
+            if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_plain(c->dm, c->ds, c->dp, true, c->stream); }
+            if (c->cfg.diag_every > 0 && c->step % c->cfg.diag_every == 0) run_diag(c);
+            if (c->ev.size() > 4096) collect_timing(c);
+        }
+        for (int i = 0; i < n_steps && !c->plain; ++i) {
             const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
             { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(c->dm, c->ds, c->stream); }
             if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(c->dm, c->ds, c->stream); }
@@ -634,6 +735,13 @@ axp_status axp_diag_get(axp_ctx *c, axp_diag *out) {
         std::memcpy(&v, &d.gauss_abs_bits, 8); out->gauss_max_abs = v;
         std::memcpy(&v, &d.gauss_scale_bits, 8); out->gauss_scale = v;
         out->W_E = d.WE; out->W_B = d.WB; out->W_K = d.WK; out->Q_total = d.Qtot;
+        if (c->plain) {
+            double da, qm;
+            std::memcpy(&da, &d.dce_abs_bits, 8);
+            std::memcpy(&qm, &d.qmax_bits, 8);
+            out->dce_max_abs = 0;
+            out->dce_max_rel = qm > 0 ? da / qm : da;
+        }
         return axp_sync(c);
     });
 }
@@ -643,7 +751,12 @@ axp_status axp_get_fields(axp_ctx *c, double *E, double *B) {
     return guarded(c, [&]() -> axp_status {
         require_built(c);
         const HostMesh &m = c->hm;
-        if (E) {
+        if (E && c->plain) {
+            std::vector<double> e(m.n1);
+            hcheck(hipMemcpyAsync(e.data(), c->dp.E, m.n1 * 8, hipMemcpyDeviceToHost, c->stream), "E");
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+            for (int k = 0; k < m.n1; ++k) E[k] = e[m.edge_int[k]];
+        } else if (E) {
             std::vector<float> e(m.n1);
             hcheck(hipMemcpyAsync(e.data(), c->ds.E, m.n1 * 4, hipMemcpyDeviceToHost, c->stream), "E");
             hcheck(hipStreamSynchronize(c->stream), "sync");
@@ -670,13 +783,24 @@ axp_status axp_get_sources(axp_ctx *c, double *D, double *J_dt, double *Q) {
             hcheck(hipStreamSynchronize(c->stream), "sync");
             for (int k = 0; k < m.n1; ++k) D[k] = d[m.edge_int[k]];
         }
-        if (J_dt) {
+        if (J_dt && c->plain) {
+            std::vector<double> j(m.n1);
+            hcheck(hipMemcpyAsync(j.data(), c->dp.Jfx, m.n1 * 8, hipMemcpyDeviceToHost, c->stream), "J");
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+            for (int k = 0; k < m.n1; ++k) J_dt[k] = j[m.edge_int[k]] * c->pc.qunit;
+        } else if (J_dt) {
             std::vector<long long> j(m.n1);
             hcheck(hipMemcpyAsync(j.data(), c->ds.Jfx, m.n1 * 8, hipMemcpyDeviceToHost, c->stream), "J");
             hcheck(hipStreamSynchronize(c->stream), "sync");
             for (int k = 0; k < m.n1; ++k) J_dt[k] = double(j[m.edge_int[k]]) * c->ic.jscale;
         }
-        if (Q) {
+        if (Q && c->plain) {
+            if (c->last_diag_step != c->step) run_diag(c);
+            std::vector<double> q(m.n0);
+            hcheck(hipMemcpyAsync(q.data(), c->dp.Q, m.n0 * 8, hipMemcpyDeviceToHost, c->stream), "Q");
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+            for (int v = 0; v < m.n0; ++v) Q[v] = q[v] * c->pc.qunit;
+        } else if (Q) {
             if (c->last_diag_step != c->step) run_diag(c);
             std::vector<long long> q(m.n0);
             hcheck(hipMemcpyAsync(q.data(), c->ds.Qfx, m.n0 * 8, hipMemcpyDeviceToHost, c->stream), "Q");
@@ -697,8 +821,19 @@ axp_status axp_get_particles(axp_ctx *c, int64_t cap, int64_t *n, double *zr, do
         std::vector<int32_t> cell(ns);
         std::vector<uint32_t> l0(ns), l1(ns);
         std::vector<float> a(ns), b(ns), z(ns);
+        std::vector<double> pl0, pl1, pa, pb, pz;
         int cb = s.cur;
-        if (ns) {
+        if (ns && c->plain) {
+            const DevPlain &p = c->dp;
+            pl0.resize(ns); pl1.resize(ns); pa.resize(ns); pb.resize(ns); pz.resize(ns);
+            hcheck(hipMemcpyAsync(cell.data(), s.cell[cb], ns * 4, hipMemcpyDeviceToHost, c->stream), "p");
+            hcheck(hipMemcpyAsync(pl0.data(), p.l0[cb], ns * 8, hipMemcpyDeviceToHost, c->stream), "p");
+            hcheck(hipMemcpyAsync(pl1.data(), p.l1[cb], ns * 8, hipMemcpyDeviceToHost, c->stream), "p");
+            hcheck(hipMemcpyAsync(pa.data(), p.ur[cb], ns * 8, hipMemcpyDeviceToHost, c->stream), "p");
+            hcheck(hipMemcpyAsync(pb.data(), p.up[cb], ns * 8, hipMemcpyDeviceToHost, c->stream), "p");
+            hcheck(hipMemcpyAsync(pz.data(), p.uz[cb], ns * 8, hipMemcpyDeviceToHost, c->stream), "p");
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+        } else if (ns) {
             hcheck(hipMemcpyAsync(cell.data(), s.cell[cb], ns * 4, hipMemcpyDeviceToHost, c->stream), "p");
             hcheck(hipMemcpyAsync(l0.data(), s.L0[cb], ns * 4, hipMemcpyDeviceToHost, c->stream), "p");
             hcheck(hipMemcpyAsync(l1.data(), s.L1[cb], ns * 4, hipMemcpyDeviceToHost, c->stream), "p");
@@ -716,14 +851,22 @@ axp_status axp_get_particles(axp_ctx *c, int64_t cap, int64_t *n, double *zr, do
         for (int64_t i = 0; i < ns; ++i) {
             if (cell[i] < 0) continue;
             int t = cell[i] & kCellMask;
-            double L[3] = {double(l0[i]), double(l1[i]), double(kLamOne - int64_t(l0[i]) - int64_t(l1[i]))};
+            double L[3];
+            if (c->plain) {
+                L[0] = pl0[i]; L[1] = pl1[i]; L[2] = 1.0 - pl0[i] - pl1[i];
+            } else {
+                L[0] = double(l0[i]) / double(kLamOne);
+                L[1] = double(l1[i]) / double(kLamOne);
+                L[2] = double(kLamOne - int64_t(l0[i]) - int64_t(l1[i])) / double(kLamOne);
+            }
             double zz = 0, rr = 0;
             for (int k = 0; k < 3; ++k) {
-                zz += L[k] / double(kLamOne) * m.z[m.tv[t][k]];
-                rr += L[k] / double(kLamOne) * m.r[m.tv[t][k]];
+                zz += L[k] * m.z[m.tv[t][k]];
+                rr += L[k] * m.r[m.tv[t][k]];
             }
             if (zr) { zr[2 * o] = zz; zr[2 * o + 1] = rr; }
-            if (u) { u[3 * o] = double(a[i]) * kC; u[3 * o + 1] = double(b[i]) * kC; u[3 * o + 2] = double(z[i]) * kC; }
+            if (u && c->plain) { u[3 * o] = pa[i] * kC; u[3 * o + 1] = pb[i] * kC; u[3 * o + 2] = pz[i] * kC; }
+            else if (u) { u[3 * o] = double(a[i]) * kC; u[3 * o + 1] = double(b[i]) * kC; u[3 * o + 2] = double(z[i]) * kC; }
             if (species) species[o] = (cell[i] >> kCellBits) & 15;
             ++o;
         }

@@ -71,6 +71,8 @@ struct DevDiag {
     unsigned long long gauss_scale_bits;
     unsigned long long dce_max;           // max |2^23 dQ + Ddiv J| (fixed point)
     double WE, WB, WK, Qtot;
+    unsigned long long dce_abs_bits;      // FP64 step: max |dQ + Ddiv J| (charge units)
+    unsigned long long qmax_bits;         // FP64 step: max |Q|
 };
 
 struct DevState {
@@ -106,6 +108,36 @@ struct DevState {
     double *kin_part = nullptr;  // 1024 partial sums of the kinetic energy
 };
 
+// FP64 step (one instance): constants, geometry and state that differ from
+// the mixed step.  B, Bprev, HBdt, D, g0, the sort scratch, counters and the
+// particle cell words are shared with DevMesh / DevState.
+struct PlainConst {
+    double dt, cdt, bz;
+    double qunit;            // charge unit / (2 pi) [C/rad]
+    int32_t n_species, pad;
+    double qe[kMaxSpecies];  // q dt / (2 m c)
+    double qb[kMaxSpecies];  // q dt / (2 m)
+    double kq[kMaxSpecies];  // macro charge / charge unit
+    double mw[kMaxSpecies];  // m * weight * c^2 / (2 pi)
+};
+
+struct DevPlain {
+    const double4 *grad = nullptr;   // grad lam0 (z, rho), grad lam1 (z, rho)
+    const double4 *rho = nullptr;    // rho of local nodes 0..2, 1/(2 area)
+    const double *m_val = nullptr;   // SPAI values in the same sliced ELL as DevMesh
+    double *E = nullptr;             // E on edges
+    double4 *f0 = nullptr, *f1 = nullptr;   // gather tile (f1.z = B_phi)
+    double *Jloc = nullptr;          // current per face side, charge-unit * lambda products
+    double *Jfx = nullptr;           // edge current of the last step (same units)
+    double *Qres = nullptr;          // wall charge per node (charge units)
+    double *Q = nullptr, *Qprev = nullptr;
+    double *l0[2] = {nullptr, nullptr}, *l1[2] = {nullptr, nullptr};
+    double *ur[2] = {nullptr, nullptr}, *up[2] = {nullptr, nullptr}, *uz[2] = {nullptr, nullptr};
+    // mover list
+    int32_t *mv_p = nullptr, *mv_c = nullptr;
+    double *mv_l0 = nullptr, *mv_l1 = nullptr, *mv_fz = nullptr, *mv_fr = nullptr;
+};
+
 // ---- launchers (kernels_mixed.hip) ----
 void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_push(const DevMesh &m, DevState &s, bool count, const InstConst *single, hipStream_t st);
@@ -115,5 +147,21 @@ void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st);
 void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st);
+// Counting sort of the particle arrays by face: cell words in s.cell plus
+// n_fields payload arrays of `width` bytes (4 or 8) per particle, src[f] ->
+// dst[f].  counted: s.cnt already holds the face histogram.
+void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width, int n_fields, void *const *src,
+                         void *const *dst, hipStream_t st);
+
+// ---- launchers (kernels_plain.hip) ----
+void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
+void launch_push_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool count, hipStream_t st);
+void launch_walk_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk, bool count,
+                       hipStream_t st);
+void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
+void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st);
+void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted, hipStream_t st);
+void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool have_prev_q,
+                       bool first, hipStream_t st);
 
 }  // namespace axp

@@ -679,7 +679,15 @@ __global__ __launch_bounds__(256) void k_scan_add(int32_t *cnt, const int32_t *b
         if (i + j < n) cnt[i + j] += blk[blockIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_scatter(DevState s, int n2) {
+// Payload of the particle move: NF arrays of W (4- or 8-byte words).
+template <class W, int NF>
+struct Payload {
+    const W *src[NF];
+    W *dst[NF];
+};
+
+template <class W, int NF>
+__global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, NF> pl) {
     __shared__ int lcnt[kSortWin];
     __shared__ int s_base;
     constexpr int K = kSortChunk / 256;
@@ -688,17 +696,7 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2) {
     if (pb >= n) return;
     const int a = s.cur, b = 1 - s.cur;
     const int32_t *__restrict__ cell_a = s.cell[a];
-    const uint32_t *__restrict__ l0_a = s.L0[a];
-    const uint32_t *__restrict__ l1_a = s.L1[a];
-    const float *__restrict__ ur_a = s.ur[a];
-    const float *__restrict__ up_a = s.up[a];
-    const float *__restrict__ uz_a = s.uz[a];
     int32_t *__restrict__ cell_b = s.cell[b];
-    uint32_t *__restrict__ l0_b = s.L0[b];
-    uint32_t *__restrict__ l1_b = s.L1[b];
-    float *__restrict__ ur_b = s.ur[b];
-    float *__restrict__ up_b = s.up[b];
-    float *__restrict__ uz_b = s.uz[b];
     if (threadIdx.x == 0) {
         const int c0 = cell_a[pb];
         s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kSortWin / 8;
@@ -745,15 +743,15 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2) {
     }
     __syncthreads();
     // 3. move: all loads first, then all stores
-    uint32_t v0[K], v1[K];
-    float v2[K], v3[K], v4[K];
+    W v[NF][K];
     int q[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const long long p = pb + threadIdx.x + 256 * k;
         q[k] = -1;
         if (rank[k] == -1) continue;
-        v0[k] = l0_a[p]; v1[k] = l1_a[p]; v2[k] = ur_a[p]; v3[k] = up_a[p]; v4[k] = uz_a[p];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[f][k] = pl.src[f][p];
         q[k] = rank[k] >= 0 ? lcnt[(cv[k] & kCellMask) - base] + rank[k] : -2 - rank[k];
     }
 #pragma unroll
@@ -761,8 +759,8 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2) {
         if (q[k] < 0) continue;
         const int qq = q[k];
         cell_b[qq] = cv[k];
-        l0_b[qq] = v0[k]; l1_b[qq] = v1[k];
-        ur_b[qq] = v2[k]; up_b[qq] = v3[k]; uz_b[qq] = v4[k];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) pl.dst[f][qq] = v[f][k];
     }
 }
 
@@ -943,7 +941,8 @@ void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st) {
 }
 
 // counted: the particle kernel of this step already histogrammed the faces
-void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st) {
+void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width, int n_fields, void *const *src,
+                         void *const *dst, hipStream_t st) {
     if (s.capacity == 0) return;
     const int n = m.n2;
     const int nb = (int)nblk(n, 1024);
@@ -954,9 +953,28 @@ void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, st, s.cnt, s.blk, n);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, st, s.blk, nb, s.cnt + n, s);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, st, s.cnt, s.blk, n);
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(s.capacity, kSortChunk)), dim3(256), 0, st, s, n);
+    const dim3 grid(nblk(s.capacity, kSortChunk));
+    if (width == 4 && n_fields == 5) {
+        Payload<uint32_t, 5> pl;
+        for (int f = 0; f < 5; ++f) { pl.src[f] = (const uint32_t *)src[f]; pl.dst[f] = (uint32_t *)dst[f]; }
+        hipLaunchKernelGGL((k_scatter<uint32_t, 5>), grid, dim3(256), 0, st, s, n, pl);
+    } else if (width == 8 && n_fields == 5) {
+        Payload<unsigned long long, 5> pl;
+        for (int f = 0; f < 5; ++f) {
+            pl.src[f] = (const unsigned long long *)src[f];
+            pl.dst[f] = (unsigned long long *)dst[f];
+        }
+        hipLaunchKernelGGL((k_scatter<unsigned long long, 5>), grid, dim3(256), 0, st, s, n, pl);
+    }
     hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, st, s, s.cnt + n);
     s.cur = 1 - s.cur;
+}
+
+void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st) {
+    const int a = s.cur, b = 1 - s.cur;
+    void *const src[5] = {s.L0[a], s.L1[a], s.ur[a], s.up[a], s.uz[a]};
+    void *const dst[5] = {s.L0[b], s.L1[b], s.ur[b], s.up[b], s.uz[b]};
+    launch_sort_payload(m, s, counted, 4, 5, src, dst, st);
 }
 
 void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st) {

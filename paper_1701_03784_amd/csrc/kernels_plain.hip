@@ -1,0 +1,481 @@
+// FP64 variant of the time step: the reference point of the mixed step.
+// Same kernels and data flow (face pass, push + walk with a mover list,
+// edge pass, sliced-ELL SpMV, counting sort by face), but every quantity is
+// FP64: barycentric positions, momenta, the gather tile, the SPAI values,
+// E, and the currents, which are summed with FP64 atomics (so their order,
+// and the last bits, vary from run to run).
+//
+//   k_tri_pass_d   eq. (full_d_dfl) and the Whitney gather tile (Sec. 3.2)
+//   k_push_d       gather, relativistic Boris (eqs. DNE, DLE), axisymmetric
+//                  position update; current of a path that stays in its face
+//   k_walk_d       walk of the particles that leave their face, eq. (current)
+//   k_edge_pass_d  D += dt C^T H B^{n+1/2} - dt J (eq. full_d_dal, D-form)
+//   k_spmv_d       E = M D
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace axp {
+
+namespace {
+
+constexpr int kTagAxisD = 2;
+constexpr int kWGd = 256;
+constexpr int kChunkD = 1024;          // particles per push block = mover slots per block (as the mixed step)
+constexpr int kPPTd = kChunkD / kWGd;
+
+__device__ __forceinline__ double sel3d(int k, double a, double b, double c) { return k == 0 ? a : (k == 1 ? b : c); }
+__device__ __forceinline__ int sel3i(int k, int a, int b, int c) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ __forceinline__ void fadd(double *a, double v) {
+    if (v != 0.0) unsafeAtomicAdd(a, v);       // hardware FP64 atomic add
+}
+
+__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.n2) return;
+    const int4 e = m.tedge[t];
+    double E0 = p.E[e.x], E1 = p.E[e.y], E2 = p.E[e.z];
+    if (e.w & 1) E0 = -E0;
+    if (e.w & 2) E1 = -E1;
+    if (e.w & 4) E2 = -E2;
+    const double bo = s.B[t];
+    const double bn = bo - dt * (E0 + E1 + E2);
+    s.B[t] = bn;
+    s.Bprev[t] = bo;
+    s.HBdt[t] = m.Hdt[t] * bn;
+    const double4 g = p.grad[t];
+    const double g0z = g.x, g0r = g.y, g1z = g.z, g1r = g.w;
+    const double g2z = -(g0z + g1z), g2r = -(g0r + g1r);
+    // E(lambda) = sum_j lambda_j a_j,  a_j = E_{j-1} grad lam_{j+1} - E_{j+1} grad lam_{j-1}
+    double4 f0, f1;
+    f0.x = E2 * g1z - E1 * g2z;
+    f0.y = E2 * g1r - E1 * g2r;
+    f0.z = E0 * g2z - E2 * g0z;
+    f0.w = E0 * g2r - E2 * g0r;
+    f1.x = E1 * g0z - E0 * g1z;
+    f1.y = E1 * g0r - E0 * g1r;
+    f1.z = (bn + bo) * p.rho[t].w;          // B_phi = (B^{n+1/2} + B^{n-1/2}) / (2 area)
+    f1.w = 0.0;
+    p.f0[t] = f0;
+    p.f1[t] = f1;
+    p.Jloc[3 * t] = 0.0;
+    p.Jloc[3 * t + 1] = 0.0;
+    p.Jloc[3 * t + 2] = 0.0;
+}
+
+// current of the straight piece s -> e inside one face, per side k
+// (side k runs from local node k+1 to k+2), times the charge multiple
+__device__ __forceinline__ void piece_d(double s0, double s1, double s2, double e0, double e1, double e2, double kq,
+                                        double &c0, double &c1, double &c2) {
+    c0 = kq * (s1 * e2 - s2 * e1);
+    c1 = kq * (s2 * e0 - s0 * e2);
+    c2 = kq * (s0 * e1 - s1 * e0);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kWGd) void k_push_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int do_count) {
+    __shared__ int s_nmv;
+    const int chunk = blockIdx.x;
+    const long long n = (long long)s.ctr->n_slots;
+    if ((long long)chunk * kChunkD >= n) {
+        if (threadIdx.x == 0) s.mv_n[chunk] = 0;
+        return;
+    }
+    if (threadIdx.x == 0) s_nmv = 0;
+    __syncthreads();
+    const int c = s.cur;
+    const int lane = threadIdx.x & 63;
+    const long long region = (long long)chunk * kChunkD;
+    for (int j = 0; j < kPPTd; ++j) {
+        const long long i = region + j * kWGd + threadIdx.x;     // consecutive lanes, consecutive particles
+        const int cw = i < n ? s.cell[c][i] : -1;
+        int T = -1;
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+        bool mover = false;
+        double l0 = 0.0, l1 = 0.0, fz = 0.0, fr = 0.0;
+        if (cw >= 0) {
+            T = cw & kCellMask;
+            const int sp = (cw >> kCellBits) & 15;
+            l0 = p.l0[c][i];
+            l1 = p.l1[c][i];
+            const double l2 = 1.0 - l0 - l1;
+            const double4 f0 = p.f0[T], f1 = p.f1[T], r4 = p.rho[T];
+            const double Ez = l0 * f0.x + l1 * f0.z + l2 * f1.x;
+            const double Er = l0 * f0.y + l1 * f0.w + l2 * f1.y;
+            const double Bp = f1.z, Bz = k.bz;
+            const double qe = k.qe[sp], qb = k.qb[sp];
+            // relativistic Boris with u normalised by c; basis (rho, phi, z)
+            const double umr = p.ur[c][i] + qe * Er, ump = p.up[c][i], umz = p.uz[c][i] + qe * Ez;
+            const double igm = 1.0 / sqrt(1.0 + umr * umr + ump * ump + umz * umz);
+            const double tp = qb * Bp * igm, tz = qb * Bz * igm;
+            const double f = 2.0 / (1.0 + tp * tp + tz * tz);
+            const double sp_ = f * tp, sz = f * tz;
+            const double vr = umr + (ump * tz - umz * tp);
+            const double vp = ump - umr * tz;
+            const double vz = umz + umr * tp;
+            double ur = umr + (vp * sz - vz * sp_) + qe * Er;
+            double up = ump - vr * sz;
+            double uz = umz + vr * sp_ + qe * Ez;
+            if (!(ur * ur + up * up + uz * uz < 1.0e300)) {
+                atomicAdd(&s.ctr->nan_count, 1ull);
+                ur = up = uz = 0.0;
+            }
+            // move in the local Cartesian frame, rotate back to the meridian plane
+            const double ig = k.cdt / sqrt(1.0 + ur * ur + up * up + uz * uz);
+            const double rho = l0 * r4.x + l1 * r4.y + l2 * r4.z;
+            const double dr = ur * ig, dp = up * ig;
+            fz = uz * ig;
+            const double X = rho + dr;
+            const double r1 = sqrt(X * X + dp * dp);
+            if (r1 > 0.0) {
+                const double cs = X / r1, sn = dp / r1;
+                const double nr = cs * ur + sn * up;
+                up = -sn * ur + cs * up;
+                ur = nr;
+            }
+            const double den = r1 + rho;
+            fr = den > 0.0 ? (2.0 * rho * dr + dr * dr + dp * dp) / den : 0.0;
+            p.ur[c][i] = ur;
+            p.up[c][i] = up;
+            p.uz[c][i] = uz;
+            const double4 g = p.grad[T];
+            const double d0 = g.x * fz + g.y * fr, d1 = g.z * fz + g.w * fr, d2 = -d0 - d1;
+            const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
+            if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
+                piece_d(l0, l1, l2, e0, e1, e2, k.kq[sp], c0, c1, c2);
+                p.l0[c][i] = e0;
+                p.l1[c][i] = e1;
+                if (do_count) atomicAdd(&s.cnt[T], 1);
+            } else {
+                mover = true;
+                T = -1;
+            }
+        }
+        // lanes holding the same face are summed across the wave, one atomic per face and side
+        int t = T;
+        for (;;) {
+            const unsigned long long pending = __ballot(t >= 0);
+            if (pending == 0ull) break;
+            const int leader = __ffsll((long long)pending) - 1;
+            const int t0 = __shfl(t, leader, 64);
+            const bool mine = (t == t0);
+            const double a0 = wave_sum_d(mine ? c0 : 0.0);
+            const double a1 = wave_sum_d(mine ? c1 : 0.0);
+            const double a2 = wave_sum_d(mine ? c2 : 0.0);
+            if (lane == leader) {
+                fadd(&p.Jloc[3 * t0], a0);
+                fadd(&p.Jloc[3 * t0 + 1], a1);
+                fadd(&p.Jloc[3 * t0 + 2], a2);
+            }
+            if (mine) t = -1;
+        }
+        const unsigned long long mask = __ballot(mover);
+        if (mask != 0ull) {
+            const int first = __ffsll((long long)mask) - 1;
+            int base = 0;
+            if (lane == first) base = atomicAdd(&s_nmv, __popcll(mask));
+            base = __shfl(base, first, 64);
+            if (mover) {
+                const long long q = region + base + __popcll(mask & ((1ull << lane) - 1ull));
+                p.mv_p[q] = (int)i;
+                p.mv_c[q] = cw;
+                p.mv_l0[q] = l0;
+                p.mv_l1[q] = l1;
+                p.mv_fz[q] = fz;
+                p.mv_fr[q] = fr;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s.mv_n[chunk] = s_nmv;
+}
+
+// Walk of the movers of push block b, face by face, with FP64 atomics for
+// each piece's current.
+__global__ __launch_bounds__(kWGd) void k_walk_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int max_walk,
+                                                 int do_count) {
+    const int b = blockIdx.x;
+    const int nmv = s.mv_n[b];
+    const int c = s.cur;
+    for (int ii = threadIdx.x; ii < nmv; ii += kWGd) {
+        const long long i = (long long)b * kChunkD + ii;
+        const long long pi = p.mv_p[i];
+        const int cw = p.mv_c[i];
+        int t = cw & kCellMask;
+        const int sp = (cw >> kCellBits) & 15;
+        const double kq = k.kq[sp];
+        double l0 = p.mv_l0[i], l1 = p.mv_l1[i], l2 = 1.0 - l0 - l1;
+        double fz = p.mv_fz[i], fr = p.mv_fr[i];
+        int entry = -1;
+        int newcell = -2;
+        for (int seg = 0; newcell == -2; ++seg) {
+            const double4 g = p.grad[t];
+            double d0 = g.x * fz + g.y * fr, d1 = g.z * fz + g.w * fr, d2 = -d0 - d1;
+            // never leave through the side just entered (rounding): slide along it
+            if (entry == 0 && d0 < 0.0) { d0 = 0.0; d2 = -d1; }
+            if (entry == 1 && d1 < 0.0) { d1 = 0.0; d2 = -d0; }
+            if (entry == 2 && d2 < 0.0) { d2 = 0.0; d1 = -d0; }
+            const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
+            double c0, c1, c2;
+            if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
+                piece_d(l0, l1, l2, e0, e1, e2, kq, c0, c1, c2);
+                fadd(&p.Jloc[3 * t], c0);
+                fadd(&p.Jloc[3 * t + 1], c1);
+                fadd(&p.Jloc[3 * t + 2], c2);
+                l0 = e0; l1 = e1; l2 = e2;
+                newcell = t | (sp << kCellBits);
+                break;
+            }
+            // exit side: smallest lambda_k / (-d_k) among the coordinates going negative
+            int kx = -1;
+            double best = 3.0;
+            if (e0 < 0.0) { kx = 0; best = l0 / (-d0); }
+            if (e1 < 0.0) { const double v = l1 / (-d1); if (v < best) { kx = 1; best = v; } }
+            if (e2 < 0.0) { const double v = l2 / (-d2); if (v < best) { kx = 2; best = v; } }
+            if (kx < 0) {                               // non-finite displacement: stop here
+                atomicAdd(&s.ctr->nan_count, 1ull);
+                newcell = t | (sp << kCellBits);
+                break;
+            }
+            const double sx = fmin(fmax(best, 0.0), 1.0);
+            const int ka = kx == 2 ? 0 : kx + 1, kb = kx == 0 ? 2 : kx - 1;
+            double xa = sel3d(ka, l0, l1, l2) + sx * sel3d(ka, d0, d1, d2);
+            xa = fmin(fmax(xa, 0.0), 1.0);
+            const double xb = 1.0 - xa;
+            const double x0 = ka == 0 ? xa : (kb == 0 ? xb : 0.0);
+            const double x1 = ka == 1 ? xa : (kb == 1 ? xb : 0.0);
+            const double x2 = ka == 2 ? xa : (kb == 2 ? xb : 0.0);
+            piece_d(l0, l1, l2, x0, x1, x2, kq, c0, c1, c2);
+            fadd(&p.Jloc[3 * t], c0);
+            fadd(&p.Jloc[3 * t + 1], c1);
+            fadd(&p.Jloc[3 * t + 2], c2);
+            fz *= (1.0 - sx);
+            fr *= (1.0 - sx);
+            const int4 nb = m.nbr[t];
+            const int nn = sel3i(kx, nb.x, nb.y, nb.z);
+            if (nn < 0) {
+                if (-nn == kTagAxisD) {                 // rho = 0 cannot be crossed: stay on it
+                    l0 = x0; l1 = x1; l2 = x2;
+                    newcell = t | (sp << kCellBits);
+                } else {                                // absorbed; its charge stays on the wall nodes
+                    const int4 tn = m.tnodes[t];
+                    fadd(&p.Qres[sel3i(ka, tn.x, tn.y, tn.z)], kq * xa);
+                    fadd(&p.Qres[sel3i(kb, tn.x, tn.y, tn.z)], kq * xb);
+                    atomicAdd(&s.ctr->n_absorbed, 1ull);
+                    newcell = -1;
+                }
+                break;
+            }
+            const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
+            const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
+            l0 = pa == 0 ? xa : (pb == 0 ? xb : 0.0);
+            l1 = pa == 1 ? xa : (pb == 1 ? xb : 0.0);
+            l2 = pa == 2 ? xa : (pb == 2 ? xb : 0.0);
+            entry = q;
+            t = nn;
+            if (seg + 1 >= max_walk) {                  // cut: the particle stops at the crossing
+                atomicAdd(&s.ctr->walk_overflow, 1ull);
+                newcell = t | (sp << kCellBits);
+            }
+        }
+        s.cell[c][pi] = newcell;
+        p.l0[c][pi] = l0;
+        p.l1[c][pi] = l1;
+        if (do_count && newcell >= 0) atomicAdd(&s.cnt[newcell & kCellMask], 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_edge_pass_d(DevMesh m, DevState s, DevPlain p, double qunit) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m.n1) return;
+    const int4 et = m.etri[e];
+    const int kl = et.z & 3, kr = (et.z >> 2) & 3;
+    const double jl = p.Jloc[3 * et.x + kl];
+    const double sl = (et.z & 16) ? -1.0 : 1.0;
+    double acc = sl * (s.HBdt[et.x] - qunit * jl);
+    double jfx = sl * jl;
+    if (et.y >= 0) {
+        const double jr = p.Jloc[3 * et.y + kr];
+        const double sr = (et.z & 32) ? -1.0 : 1.0;
+        acc += sr * (s.HBdt[et.y] - qunit * jr);
+        jfx += sr * jr;
+    }
+    p.Jfx[e] = jfx;                    // every edge: conductor edges carry current too (continuity check)
+    if (!(et.z & 64)) return;          // conductor edge: tangential E stays 0
+    s.D[e] += acc;
+}
+
+__global__ __launch_bounds__(256) void k_spmv_d(DevMesh m, DevState s, DevPlain p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n1) return;
+    const int sl = i >> 6, lane = i & 63;
+    const int64_t beg = m.m_sptr[sl];
+    const int len = m.m_slen[sl];
+    const double *v = p.m_val + beg + lane;
+    const int32_t *cc = m.m_col + beg + lane;
+    double acc = 0.0;
+    for (int j = 0; j < len; ++j) acc = fma(v[64 * j], s.D[cc[64 * j]], acc);
+    p.E[i] = acc;
+}
+
+// ------------------------------------------------------------ diagnostics
+__global__ __launch_bounds__(256) void k_charge_init_d(DevMesh m, DevPlain p) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < m.n0) p.Q[v] = p.Qres[v];
+}
+
+__global__ __launch_bounds__(256) void k_charge_d(DevMesh m, DevState s, DevPlain p, PlainConst k) {
+    const long long n = (long long)s.ctr->n_slots;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = s.cell[s.cur][i];
+    if (c < 0) return;
+    const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
+    const double kq = k.kq[sp];
+    const double l0 = p.l0[s.cur][i], l1 = p.l1[s.cur][i];
+    const int4 tn = m.tnodes[T];
+    fadd(&p.Q[tn.x], kq * l0);
+    fadd(&p.Q[tn.y], kq * l1);
+    fadd(&p.Q[tn.z], kq * (1.0 - l0 - l1));
+}
+
+__device__ __forceinline__ void amax_pos(unsigned long long *a, double v) {
+    atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(256) void k_node_diag_d(DevMesh m, DevState s, DevPlain p, double qunit, int have_prev,
+                                                     int first) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m.n0) return;
+    double div = 0.0, mag = 0.0, divj = 0.0;
+    for (int q = m.nptr[v]; q < m.nptr[v + 1]; ++q) {
+        const int e = m.nedge[q];
+        const double d = s.D[e];
+        div += m.nsign[q] > 0 ? d : -d;
+        mag += fabs(d);
+        if (have_prev) divj += m.nsign[q] > 0 ? p.Jfx[e] : -p.Jfx[e];
+    }
+    const double Qv = p.Q[v];
+    const double g = div - Qv * qunit;
+    if (have_prev) amax_pos(&s.diag->dce_abs_bits, fabs((Qv - p.Qprev[v]) + divj));
+    amax_pos(&s.diag->qmax_bits, fabs(Qv));
+    p.Qprev[v] = Qv;
+    if (m.nfree[v]) {
+        if (first) s.g0[v] = g;
+        amax_pos(&s.diag->gauss_drift_bits, fabs(g - s.g0[v]));
+        amax_pos(&s.diag->gauss_abs_bits, fabs(g));
+        amax_pos(&s.diag->gauss_scale_bits, mag);
+    }
+    unsafeAtomicAdd(&s.diag->Qtot, Qv * qunit);
+}
+
+__device__ __forceinline__ double block_sum_d(double v) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_energy_fields_d(DevMesh m, DevState s, DevPlain p, double dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double we = 0.0, wb = 0.0;
+    if (i < m.n1) {
+        double ae = 0.0;
+        for (int64_t q = m.a_ptr[i]; q < m.a_ptr[i + 1]; ++q) ae += m.a_val[q] * p.E[m.a_col[q]];
+        we = 0.5 * p.E[i] * ae;
+    }
+    if (i < m.n2) wb = 0.5 * (m.Hdt[i] / dt) * s.B[i] * s.Bprev[i];
+    we = block_sum_d(we);
+    wb = block_sum_d(wb);
+    if (threadIdx.x == 0) {
+        atomicAdd(&s.diag->WE, we);
+        atomicAdd(&s.diag->WB, wb);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_energy_kin_d(DevState s, DevPlain p, PlainConst k, double *part) {
+    const long long n = (long long)s.ctr->n_slots;
+    double wk = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int c = s.cell[s.cur][i];
+        if (c < 0) continue;
+        const int sp = (c >> kCellBits) & 15;
+        const double a = p.ur[s.cur][i], b = p.up[s.cur][i], z = p.uz[s.cur][i];
+        const double u2 = a * a + b * b + z * z;
+        wk += k.mw[sp] * (u2 / (sqrt(1.0 + u2) + 1.0));
+    }
+    wk = block_sum_d(wk);
+    if (threadIdx.x == 0) part[blockIdx.x] = wk;
+}
+
+__global__ __launch_bounds__(256) void k_energy_kin_final_d(DevState s, const double *part, int np) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) v += part[i];
+    v = block_sum_d(v);
+    if (threadIdx.x == 0) s.diag->WK = v;
+}
+
+inline unsigned nb_(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {
+    if (m.n2 == 0) return;
+    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt);
+}
+
+void launch_push_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool count, hipStream_t st) {
+    if (s.capacity == 0) return;
+    hipLaunchKernelGGL(k_push_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k, count ? 1 : 0);
+}
+
+void launch_walk_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk, bool count,
+                       hipStream_t st) {
+    if (s.capacity == 0) return;
+    hipLaunchKernelGGL(k_walk_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k, max_walk, count ? 1 : 0);
+}
+
+void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {
+    hipLaunchKernelGGL(k_edge_pass_d, dim3(nb_(m.n1, 256)), dim3(256), 0, st, m, s, p, k.qunit);
+}
+
+void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st) {
+    hipLaunchKernelGGL(k_spmv_d, dim3(nb_(m.n1, 256)), dim3(256), 0, st, m, s, p);
+}
+
+void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted, hipStream_t st) {
+    const int a = s.cur, b = 1 - s.cur;
+    void *const src[5] = {p.l0[a], p.l1[a], p.ur[a], p.up[a], p.uz[a]};
+    void *const dst[5] = {p.l0[b], p.l1[b], p.ur[b], p.up[b], p.uz[b]};
+    launch_sort_payload(m, s, counted, 8, 5, src, dst, st);
+}
+
+void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool have_prev_q,
+                       bool first, hipStream_t st) {
+    (void)hipMemsetAsync(s.diag, 0, sizeof(DevDiag), st);
+    hipLaunchKernelGGL(k_charge_init_d, dim3(nb_(m.n0, 256)), dim3(256), 0, st, m, p);
+    if (s.capacity) hipLaunchKernelGGL(k_charge_d, dim3(nb_(s.capacity, 256)), dim3(256), 0, st, m, s, p, k);
+    hipLaunchKernelGGL(k_node_diag_d, dim3(nb_(m.n0, 256)), dim3(256), 0, st, m, s, p, k.qunit, have_prev_q ? 1 : 0,
+                       first ? 1 : 0);
+    const int64_t ne = m.n1 > m.n2 ? m.n1 : m.n2;
+    hipLaunchKernelGGL(k_energy_fields_d, dim3(nb_(ne, 256)), dim3(256), 0, st, m, s, p, k.dt);
+    if (s.capacity) {
+        const int np = 1024;
+        hipLaunchKernelGGL(k_energy_kin_d, dim3(np), dim3(256), 0, st, s, p, k, s.kin_part);
+        hipLaunchKernelGGL(k_energy_kin_final_d, dim3(1), dim3(256), 0, st, s, s.kin_part, np);
+    }
+}
+
+}  // namespace axp

@@ -1,0 +1,143 @@
+"""Parity of the FP64 GPU step (AXP_PREC_PLAIN_FP64) with the FP64 oracle.
+
+Same cavity workload as the mixed-precision parity tests.  Every quantity
+of this step is FP64, so the bounds are those of FP64 rounding: the GPU
+keeps D = [*eps]_a E and recomputes E = M D each step while the oracle
+updates E directly (equal in exact arithmetic), and the currents are summed
+by FP64 atomics in varying order.  Bounds: fields rel-L2 <= 1e-9 after
+1,000 steps; particles 1e-12 m / 1e-10 relative after one step; the
+continuity residual <= 1e-12 of max |Q| (eq. DCE in FP64); the Gauss
+residual stays at its initial value to 1e-13 of the D scale.
+"""
+
+import numpy as np
+import pytest
+import scipy.spatial
+
+import synth
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+QE, ME = synth.ELECTRON_CHARGE, synth.ELECTRON_MASS
+
+
+@pytest.fixture(scope="module")
+def axp():
+    import paper_1701_03784_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def cavity():
+    from oracle.pic import OracleSim
+    m = configs.cavity_mesh()
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=configs.CAVITY_DT)
+    E0, B0, omega = synth.tm010_fields(m.nodes, m.tris, sim.topo.edges, configs.CAVITY_A, 1e6, sim.dt)
+    return m, sim, E0, B0
+
+
+def _ctx(axp, m, **kw):
+    print(f"[gpu] build plain ctx faces={m.n_tris} {kw}", flush=True)
+    kw.setdefault("dt", configs.CAVITY_DT)
+    return axp.make_ctx(m, precision=axp.PREC_PLAIN_FP64, **kw)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_plain_field_only_1000_steps(axp, cavity):
+    from oracle.pic import OracleSim
+    m, sim0, E0, B0 = cavity
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=sim0.dt, M=sim0.M)
+    sim.set_fields(E0, B0)
+    c = _ctx(axp, m)
+    assert c.info()["precision"] == axp.PREC_PLAIN_FP64
+    c.set_fields(E0, B0)
+    c.step(1000)
+    sim.step(1000)
+    E, B = c.get_fields()
+    print(f"[gpu] plain field-only: relL2 E {_rel_l2(E, sim.E):.2e} B {_rel_l2(B, sim.B):.2e}", flush=True)
+    assert _rel_l2(E, sim.E) <= 1e-9
+    assert _rel_l2(B, sim.B) <= 1e-9
+
+
+def test_plain_one_step_particles(axp, cavity):
+    from oracle.pic import OracleSim
+    m, sim0, E0, B0 = cavity
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=sim0.dt, M=sim0.M)
+    sim.set_fields(E0, B0)
+    sp_o = sim.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    zr, u = configs.cavity_beam()
+    sim.inject(sp_o, zr, u)
+    c = _ctx(axp, m)
+    c.set_fields(E0, B0)
+    sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    c.inject(sp, zr, u)
+    c.step(1)
+    sim.step(1)
+    zr_g, u_g, _ = c.get_particles()
+    zr_o, u_o, _ = sim.particles()
+    assert len(zr_g) == len(zr_o)
+    d, idx = scipy.spatial.cKDTree(np.concatenate([zr_o / 1e-6, u_o / 1e3], 1)).query(
+        np.concatenate([zr_g / 1e-6, u_g / 1e3], 1))
+    assert len(np.unique(idx)) == len(idx)
+    assert np.abs(zr_g - zr_o[idx]).max() < 1e-12
+    assert np.abs(u_g - u_o[idx]).max() < 1e-10 * np.abs(u_o).max()
+    D, Jdt, Q = c.get_sources()
+    J_o = sim.J * sim.dt
+    assert np.abs(Jdt - J_o).max() <= 1e-10 * np.abs(J_o).max()
+    E, B = c.get_fields()
+    assert _rel_l2(E, sim.E) <= 1e-10
+    assert _rel_l2(B, sim.B) <= 1e-10
+
+
+def test_plain_pic_1000_steps(axp, cavity):
+    from oracle.pic import OracleSim
+    m, sim0, E0, B0 = cavity
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=sim0.dt, M=sim0.M)
+    sim.set_fields(E0, B0)
+    sp_o = sim.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    zr, u = configs.cavity_beam()
+    sim.inject(sp_o, zr, u)
+    c = _ctx(axp, m, diag_every=1)
+    c.set_fields(E0, B0)
+    sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+    c.inject(sp, zr, u)
+    c.diag()
+    for chunk in range(10):
+        c.step(100)
+        sim.step(100)
+        d = c.diag()
+        E, B = c.get_fields()
+        print(f"[gpu] plain pic step {d['step']}: live {d['n_live']} absorbed {d['n_absorbed']} "
+              f"dce rel {d['dce_max_rel']:.2e} gauss drift {d['gauss_max_drift']:.3e} / {d['gauss_scale']:.3e} "
+              f"relL2 E {_rel_l2(E, sim.E):.2e} B {_rel_l2(B, sim.B):.2e}", flush=True)
+        assert d["dce_max_rel"] <= 1e-12
+        assert d["gauss_max_drift"] <= 1e-13 * d["gauss_scale"]
+        assert d["walk_overflow"] == 0 and d["nan_count"] == 0
+    assert _rel_l2(E, sim.E) <= 1e-9
+    assert _rel_l2(B, sim.B) <= 1e-9
+    assert d["n_absorbed"] == int(sim.stats[1])
+
+
+def test_plain_and_mixed_agree_on_energy(axp, cavity):
+    """Both precisions advance the same scheme: after 200 steps their field
+    and kinetic energies agree to the mixed step's FP32 level."""
+    m, _, E0, B0 = cavity
+    zr, u = configs.cavity_beam(4000, seed=9)
+    out = {}
+    for prec in (axp.PREC_PLAIN_FP64, axp.PREC_MIXED):
+        c = axp.make_ctx(m, precision=prec, dt=configs.CAVITY_DT)
+        c.set_fields(E0, B0)
+        sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+        c.inject(sp, zr, u)
+        c.step(200)
+        out[prec] = c.diag()
+        c.close()
+    a, b = out[axp.PREC_PLAIN_FP64], out[axp.PREC_MIXED]
+    for k in ("W_E", "W_B", "W_K"):
+        assert b[k] == pytest.approx(a[k], rel=1e-4), k
+    assert a["n_absorbed"] == b["n_absorbed"]
