@@ -244,16 +244,37 @@ axp_status axp_get_timing(axp_ctx *ctx, double *ms /*[AXP_N_PHASES]*/, int64_t *
 const char *axp_last_error(const axp_ctx *ctx);
 void axp_destroy(axp_ctx *ctx);
 
+/* Sort schedule autotuner: runs about trial_steps real steps under each of
+ * the sort periods 1, 2, 4, 8, 16 (plus one settling window each), times
+ * them with HIP events and keeps the fastest in the context's configuration
+ * (*sort_period receives it; may be NULL).  The state advances by those
+ * steps; since the current is summed in fixed point, the fields and
+ * particles after them do not depend on the schedule (bit for bit; only the
+ * storage order of the particles does). */
+axp_status axp_autotune(axp_ctx *ctx, int32_t trial_steps, int32_t *sort_period);
+
 /* ---- batched sweep: many independent devices advanced together ---------
- * axp_batch_create pools n built contexts (same precision, each with fields
- * and particles set) into one set of device arrays; axp_batch_step advances
- * all of them by n_steps with one launch per phase for the whole pool
- * (captured in one hipGraph per step).  The contexts are borrowed and must
- * outlive the batch; their state is read back with axp_batch_sync, after
- * which the per-context getters return the batched state. */
+ * axp_batch_create pools n built mixed-precision contexts (each with fields,
+ * a species and particles set) into one set of device arrays: faces, edges
+ * and nodes of the members are concatenated, and every face, edge and node
+ * carries its member's index for the per-member constants (dt, B_z, species).
+ * axp_batch_step advances all members together with one launch per phase
+ * for the whole pool; with cfg.use_graph of the first member the launches
+ * of 2 x sort_period steps are captured in one hipGraph and replayed.  The
+ * contexts are borrowed and must outlive the batch; their own state is
+ * stale until axp_batch_sync copies the pooled state back (after which the
+ * per-context getters and axp_diag_get see it).  Every member's result is
+ * the same, bit for bit, as stepping that context alone. */
 axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out);
 axp_status axp_batch_step(axp_batch *b, int32_t n_steps);
 axp_status axp_batch_sync(axp_batch *b);
+/* Autotuner and timing of the pool (as axp_autotune / axp_set_timing). */
+axp_status axp_batch_autotune(axp_batch *b, int32_t trial_steps, int32_t *sort_period);
+axp_status axp_batch_set_timing(axp_batch *b, int32_t on);
+axp_status axp_batch_get_timing(axp_batch *b, double *ms /*[AXP_N_PHASES]*/, int64_t *launches /*[AXP_N_PHASES]*/);
+/* Pool sizes, particle slots in use and steps taken; pointers may be NULL. */
+axp_status axp_batch_info(axp_batch *b, int64_t *n_faces, int64_t *n_edges, int64_t *n_particles, int64_t *step);
+const char *axp_batch_last_error(const axp_batch *b);
 void axp_batch_destroy(axp_batch *b);
 
 #ifdef __cplusplus

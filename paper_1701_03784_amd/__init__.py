@@ -6,6 +6,6 @@ binding.  Build with :func:`paper_1701_03784_amd.build.build`.
 """
 
 from .axpic import (  # noqa: F401
-    Ctx, AxpError, make_ctx, load_library, EXPORTS, LIB_PATH,
+    Ctx, Batch, AxpError, make_ctx, load_library, EXPORTS, LIB_PATH,
     BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN, PREC_MIXED, PREC_PLAIN_FP64,
 )

@@ -63,7 +63,8 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
-           "axp_batch_destroy", "axp_set_timing", "axp_get_timing"]
+           "axp_batch_destroy", "axp_set_timing", "axp_get_timing", "axp_autotune", "axp_batch_autotune",
+           "axp_batch_set_timing", "axp_batch_get_timing", "axp_batch_info", "axp_batch_last_error"]
 PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject", "walk"]
 
 _lib = None
@@ -114,6 +115,12 @@ def load_library(path: str = LIB_PATH):
         "axp_batch_destroy": (None, [vp]),
         "axp_set_timing": (i32, [vp, i32]),
         "axp_get_timing": (i32, [vp, vp, vp]),
+        "axp_autotune": (i32, [vp, i32, C.POINTER(i32)]),
+        "axp_batch_autotune": (i32, [vp, i32, C.POINTER(i32)]),
+        "axp_batch_set_timing": (i32, [vp, i32]),
+        "axp_batch_get_timing": (i32, [vp, vp, vp]),
+        "axp_batch_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
+        "axp_batch_last_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -271,6 +278,12 @@ class Ctx:
     def set_timing(self, on=True):
         self._check(self.lib.axp_set_timing(self.h, 1 if on else 0))
 
+    def autotune(self, trial_steps=16):
+        """Chooses the sort period by timing real steps; returns it."""
+        sp = C.c_int32()
+        self._check(self.lib.axp_autotune(self.h, int(trial_steps), C.byref(sp)))
+        return sp.value
+
     def get_timing(self):
         """{phase: (total device ms, launches)} since set_timing(True)."""
         ms = np.zeros(len(PHASES))
@@ -312,3 +325,59 @@ def make_ctx(mesh, **kw):
     c.set_boundary(mesh.seg, mesh.tag)
     c.build()
     return c
+
+
+class Batch:
+    """Pool of built contexts advanced together (axp_batch_*).  The member
+    contexts must stay alive while the batch exists; their state is read
+    back by sync()."""
+
+    def __init__(self, ctxs):
+        self.lib = load_library()
+        self.ctxs = list(ctxs)
+        arr = (C.c_void_p * len(self.ctxs))(*[c.h for c in self.ctxs])
+        h = C.c_void_p()
+        st = self.lib.axp_batch_create(arr, len(self.ctxs), C.byref(h))
+        if st != AXP_OK:
+            raise AxpError(st, (self.lib.axp_last_error(self.ctxs[0].h) or b"").decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != AXP_OK:
+            raise AxpError(st, (self.lib.axp_batch_last_error(self.h) or b"").decode())
+
+    def step(self, n=1):
+        self._check(self.lib.axp_batch_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.axp_batch_sync(self.h))
+
+    def autotune(self, trial_steps=16):
+        sp = C.c_int32()
+        self._check(self.lib.axp_batch_autotune(self.h, int(trial_steps), C.byref(sp)))
+        return sp.value
+
+    def set_timing(self, on=True):
+        self._check(self.lib.axp_batch_set_timing(self.h, 1 if on else 0))
+
+    def get_timing(self):
+        ms = np.zeros(len(PHASES))
+        n = np.zeros(len(PHASES), dtype=np.int64)
+        self._check(self.lib.axp_batch_get_timing(self.h, _ptr(ms), _ptr(n)))
+        return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(PHASES)}
+
+    def info(self):
+        v = [C.c_int64() for _ in range(4)]
+        self._check(self.lib.axp_batch_info(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(["n_faces", "n_edges", "n_particles", "step"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.axp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -56,6 +56,10 @@ struct axp_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
     double phase_ms[AXP_N_PHASES] = {0};
     int64_t phase_n[AXP_N_PHASES] = {0};
+    // step graphs (one per particle buffer), replayed on stream
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_window = 0;
 };
 
 namespace {
@@ -141,9 +145,12 @@ DevCounters read_counters(axp_ctx *c) {
     return h;
 }
 
+void drop_graphs(axp_ctx *c);
+
 void grow_particles(axp_ctx *c, int64_t need) {
     DevState &s = c->ds;
     if (need <= s.capacity) return;
+    drop_graphs(c);   // kernel arguments change
     int64_t cap = std::max<int64_t>(need, s.capacity + s.capacity / 2);
     cap = (cap + 1023) / 1024 * 1024;
     DevCounters h = read_counters(c);
@@ -247,27 +254,38 @@ void run_diag(axp_ctx *c) {
     c->last_diag_step = c->step;
 }
 
-void build_device(axp_ctx *c) {
-    HostMesh &m = c->hm;
-    DevMesh &d = c->dm;
-    d.n0 = m.n0; d.n1 = m.n1; d.n2 = m.n2; d.n_inst = 1;
+// Host images of the device tables of one instance or of a pool of them.
+struct HostTables {
+    std::vector<float4> gS, rho4;
+    std::vector<int4> nbr, tedge, tnodes, etri;
+    std::vector<double> Hdt;
+    std::vector<int32_t> tinst, ninst;
+    std::vector<int32_t> nptr{0}, nedge;
+    std::vector<int8_t> nsign;
+    std::vector<uint8_t> nfree;
+    Csr M, A;   // pooled rows, column indices offset per instance
+    int32_t n0 = 0, n1 = 0, n2 = 0;
+};
+
+// Appends one instance (faces, edges and nodes offset by the current sizes).
+void append_instance(HostTables &h, const HostMesh &m, double dt, int inst) {
+    const int32_t fo = h.n2, eo = h.n1, no = h.n0;
     const double S = double(kLamOne);
-    std::vector<float4> gS(m.n2), rho4(m.n2);
-    std::vector<int4> nbr(m.n2), tedge(m.n2), tnodes(m.n2);
-    std::vector<double> Hdt(m.n2);
     for (int t = 0; t < m.n2; ++t) {
         const auto &g = m.grad[t];
-        gS[t] = make_float4(float(S * g[0]), float(S * g[1]), float(S * g[2]), float(S * g[3]));
-        rho4[t] = make_float4(float(m.r[m.tv[t][0]]), float(m.r[m.tv[t][1]]), float(m.r[m.tv[t][2]]),
-                              float(1.0 / (2.0 * m.area[t])));
-        nbr[t] = make_int4(m.tnbr[t][0], m.tnbr[t][1], m.tnbr[t][2], int(m.tnbr_map[t]));
+        h.gS.push_back(make_float4(float(S * g[0]), float(S * g[1]), float(S * g[2]), float(S * g[3])));
+        h.rho4.push_back(make_float4(float(m.r[m.tv[t][0]]), float(m.r[m.tv[t][1]]), float(m.r[m.tv[t][2]]),
+                                     float(1.0 / (2.0 * m.area[t]))));
+        int nb[3];
+        for (int k = 0; k < 3; ++k) nb[k] = m.tnbr[t][k] >= 0 ? m.tnbr[t][k] + fo : m.tnbr[t][k];
+        h.nbr.push_back(make_int4(nb[0], nb[1], nb[2], int(m.tnbr_map[t])));
         int sb = 0;
         for (int k = 0; k < 3; ++k) if (m.tsign[t][k] < 0) sb |= 1 << k;
-        tedge[t] = make_int4(m.tedge[t][0], m.tedge[t][1], m.tedge[t][2], sb);
-        tnodes[t] = make_int4(m.tv[t][0], m.tv[t][1], m.tv[t][2], 0);
-        Hdt[t] = c->dt * m.H[t];
+        h.tedge.push_back(make_int4(m.tedge[t][0] + eo, m.tedge[t][1] + eo, m.tedge[t][2] + eo, sb));
+        h.tnodes.push_back(make_int4(m.tv[t][0] + no, m.tv[t][1] + no, m.tv[t][2] + no, 0));
+        h.Hdt.push_back(dt * m.H[t]);
+        h.tinst.push_back(inst);
     }
-    std::vector<int4> etri(m.n1);
     for (int e = 0; e < m.n1; ++e) {
         int L = m.etri[e][0], R = m.etri[e][1];
         int kl = m.eside[e][0], kr = R >= 0 ? m.eside[e][1] : 0;
@@ -275,52 +293,116 @@ void build_device(axp_ctx *c) {
         if (m.tsign[L][kl] < 0) packed |= 16;
         if (R >= 0 && m.tsign[R][kr] < 0) packed |= 32;
         if (m.efree[e]) packed |= 64;
-        etri[e] = make_int4(L, R, packed, 0);
+        h.etri.push_back(make_int4(L + fo, R >= 0 ? R + fo : -1, packed, inst));
     }
-    // SPAI in sliced ELL, 64 rows per slice, column-major within a slice
-    const int ns = (m.n1 + 63) / 64;
-    std::vector<int64_t> sptr(ns + 1, 0);
-    std::vector<int32_t> slen(ns, 0);
+    for (int v = 0; v < m.n0; ++v) {
+        for (int q = m.nptr[v]; q < m.nptr[v + 1]; ++q) {
+            h.nedge.push_back(m.nedge[q] + eo);
+            h.nsign.push_back(m.nsign[q]);
+        }
+        h.nptr.push_back(int32_t(h.nedge.size()));
+        h.nfree.push_back(m.nfree[v]);
+        h.ninst.push_back(inst);
+    }
+    auto app = [&](Csr &dst, const Csr &src) {
+        if (dst.ptr.empty()) dst.ptr.push_back(0);
+        for (int64_t i = 0; i < src.n; ++i) {
+            for (int64_t q = src.ptr[i]; q < src.ptr[i + 1]; ++q) {
+                dst.col.push_back(src.col[q] + eo);
+                dst.val.push_back(src.val[q]);
+            }
+            dst.ptr.push_back(int64_t(dst.col.size()));
+        }
+        dst.n += src.n;
+    };
+    app(h.M, m.M);
+    app(h.A, m.A);
+    h.n0 += m.n0; h.n1 += m.n1; h.n2 += m.n2;
+}
+
+// Sliced ELL of a CSR matrix: slices of 64 rows, column-major in a slice,
+// padded with zero values on the row's own column.
+void build_sell(const Csr &M, int32_t n1, std::vector<int64_t> &sptr, std::vector<int32_t> &slen,
+                std::vector<float> &mval, std::vector<double> *mvald, std::vector<int32_t> &mcol) {
+    const int ns = (n1 + 63) / 64;
+    sptr.assign(ns + 1, 0);
+    slen.assign(ns, 0);
     for (int sl = 0; sl < ns; ++sl) {
         int mx = 0;
-        for (int i = sl * 64; i < std::min(m.n1, sl * 64 + 64); ++i) mx = std::max<int>(mx, int(m.M.ptr[i + 1] - m.M.ptr[i]));
+        for (int i = sl * 64; i < std::min(n1, sl * 64 + 64); ++i) mx = std::max<int>(mx, int(M.ptr[i + 1] - M.ptr[i]));
         slen[sl] = mx;
         sptr[sl + 1] = sptr[sl] + int64_t(mx) * 64;
     }
-    std::vector<float> mval(sptr[ns], 0.0f);
-    std::vector<double> mvald(c->plain ? sptr[ns] : 0, 0.0);
-    std::vector<int32_t> mcol(sptr[ns], 0);
+    mval.assign(sptr[ns], 0.0f);
+    if (mvald) mvald->assign(sptr[ns], 0.0);
+    mcol.assign(sptr[ns], 0);
     for (int sl = 0; sl < ns; ++sl)
         for (int lane = 0; lane < 64; ++lane) {
             int i = sl * 64 + lane;
             int64_t o = sptr[sl] + lane;
             int j = 0;
-            if (i < m.n1)
-                for (int64_t q = m.M.ptr[i]; q < m.M.ptr[i + 1]; ++q, ++j) {
-                    mval[o + 64 * j] = float(m.M.val[q]);
-                    if (c->plain) mvald[o + 64 * j] = m.M.val[q];
-                    mcol[o + 64 * j] = m.M.col[q];
+            if (i < n1)
+                for (int64_t q = M.ptr[i]; q < M.ptr[i + 1]; ++q, ++j) {
+                    mval[o + 64 * j] = float(M.val[q]);
+                    if (mvald) (*mvald)[o + 64 * j] = M.val[q];
+                    mcol[o + 64 * j] = M.col[q];
                 }
-            for (; j < slen[sl]; ++j) mcol[o + 64 * j] = i < m.n1 ? i : 0;
+            for (; j < slen[sl]; ++j) mcol[o + 64 * j] = i < n1 ? i : 0;
         }
-    d.gS = upload(c, gS); d.rho4 = upload(c, rho4); d.nbr = upload(c, nbr);
-    d.tedge = upload(c, tedge); d.tnodes = upload(c, tnodes); d.Hdt = upload(c, Hdt);
-    d.tinst = nullptr;
-    d.etri = upload(c, etri);
-    d.nptr = upload(c, m.nptr); d.nedge = upload(c, m.nedge); d.nsign = upload(c, m.nsign);
-    d.nfree = upload(c, m.nfree); d.ninst = nullptr;
+}
+
+// Uploads the tables and allocates the field state of a context (one
+// instance: pooled = false; a batch pool: per-face / per-node instance ids).
+void upload_tables(axp_ctx *c, const HostTables &h, bool pooled, int n_inst) {
+    DevMesh &d = c->dm;
+    d.n0 = h.n0; d.n1 = h.n1; d.n2 = h.n2; d.n_inst = n_inst;
+    std::vector<int64_t> sptr;
+    std::vector<int32_t> slen, mcol;
+    std::vector<float> mval;
+    std::vector<double> mvald;
+    build_sell(h.M, h.n1, sptr, slen, mval, c->plain ? &mvald : nullptr, mcol);
+    d.gS = upload(c, h.gS); d.rho4 = upload(c, h.rho4); d.nbr = upload(c, h.nbr);
+    d.tedge = upload(c, h.tedge); d.tnodes = upload(c, h.tnodes); d.Hdt = upload(c, h.Hdt);
+    d.tinst = pooled ? upload(c, h.tinst) : nullptr;
+    d.etri = upload(c, h.etri);
+    d.nptr = upload(c, h.nptr); d.nedge = upload(c, h.nedge); d.nsign = upload(c, h.nsign);
+    d.nfree = upload(c, h.nfree); d.ninst = pooled ? upload(c, h.ninst) : nullptr;
     d.m_sptr = upload(c, sptr); d.m_slen = upload(c, slen); d.m_col = upload(c, mcol);
     d.m_val = c->plain ? nullptr : upload(c, mval);
-    d.a_ptr = upload(c, m.A.ptr); d.a_col = upload(c, m.A.col); d.a_val = upload(c, m.A.val);
-    std::memset(&c->ic, 0, sizeof(InstConst));
-    c->ic.dt = c->dt;
-    c->ic.cdt = float(kC * c->dt);
-    d.inst = (InstConst *)dalloc(c, sizeof(InstConst));
-    upload_inst(c);
+    d.a_ptr = upload(c, h.A.ptr); d.a_col = upload(c, h.A.col); d.a_val = upload(c, h.A.val);
+    d.inst = (InstConst *)dalloc(c, sizeof(InstConst) * size_t(n_inst));
     DevState &s = c->ds;
-    s.B = zeros<double>(c, m.n2); s.Bprev = zeros<double>(c, m.n2); s.HBdt = zeros<double>(c, m.n2);
-    s.D = zeros<double>(c, m.n1);
-    s.g0 = zeros<double>(c, m.n0);
+    s.B = zeros<double>(c, h.n2); s.Bprev = zeros<double>(c, h.n2); s.HBdt = zeros<double>(c, h.n2);
+    s.D = zeros<double>(c, h.n1);
+    s.g0 = zeros<double>(c, h.n0);
+    if (c->plain) {
+        DevPlain &p = c->dp;
+        p.m_val = upload(c, mvald);
+        p.E = zeros<double>(c, h.n1);
+        p.f0 = zeros<double4>(c, h.n2); p.f1 = zeros<double4>(c, h.n2);
+        p.Jloc = zeros<double>(c, size_t(3) * h.n2); p.Jfx = zeros<double>(c, h.n1);
+        p.Qres = zeros<double>(c, h.n0); p.Q = zeros<double>(c, h.n0); p.Qprev = zeros<double>(c, h.n0);
+    } else {
+        s.f0 = zeros<float4>(c, h.n2); s.f1 = zeros<float4>(c, h.n2);
+        s.Jloc = zeros<unsigned long long>(c, size_t(3) * h.n2);
+        s.D32 = zeros<float>(c, h.n1); s.E = zeros<float>(c, h.n1);
+        s.Jfx = zeros<long long>(c, h.n1);
+        s.Qres = zeros<long long>(c, h.n0); s.Qfx = zeros<long long>(c, h.n0); s.Qprev = zeros<long long>(c, h.n0);
+    }
+    s.cnt = zeros<int32_t>(c, size_t(h.n2) + 1);
+    s.blk = zeros<int32_t>(c, size_t(h.n2) / 1024 + 2);
+    s.ctr = zeros<DevCounters>(c, 1);
+    s.diag = zeros<DevDiag>(c, 1);
+    s.kin_part = zeros<double>(c, 1024);
+    s.capacity = 0;
+    s.cur = 0;
+}
+
+void build_device(axp_ctx *c) {
+    const HostMesh &m = c->hm;
+    HostTables h;
+    append_instance(h, m, c->dt, 0);
+    upload_tables(c, h, false, 1);
     if (c->plain) {
         DevPlain &p = c->dp;
         std::vector<double4> grad(m.n2), rho(m.n2);
@@ -329,29 +411,100 @@ void build_device(axp_ctx *c) {
             grad[t] = make_double4(g[0], g[1], g[2], g[3]);
             rho[t] = make_double4(m.r[m.tv[t][0]], m.r[m.tv[t][1]], m.r[m.tv[t][2]], 1.0 / (2.0 * m.area[t]));
         }
-        p.grad = upload(c, grad); p.rho = upload(c, rho); p.m_val = upload(c, mvald);
-        p.E = zeros<double>(c, m.n1);
-        p.f0 = zeros<double4>(c, m.n2); p.f1 = zeros<double4>(c, m.n2);
-        p.Jloc = zeros<double>(c, size_t(3) * m.n2); p.Jfx = zeros<double>(c, m.n1);
-        p.Qres = zeros<double>(c, m.n0); p.Q = zeros<double>(c, m.n0); p.Qprev = zeros<double>(c, m.n0);
+        p.grad = upload(c, grad); p.rho = upload(c, rho);
         std::memset(&c->pc, 0, sizeof(PlainConst));
         c->pc.dt = c->dt;
         c->pc.cdt = kC * c->dt;
-    } else {
-        s.f0 = zeros<float4>(c, m.n2); s.f1 = zeros<float4>(c, m.n2);
-        s.Jloc = zeros<unsigned long long>(c, size_t(3) * m.n2);
-        s.D32 = zeros<float>(c, m.n1); s.E = zeros<float>(c, m.n1);
-        s.Jfx = zeros<long long>(c, m.n1);
-        s.Qres = zeros<long long>(c, m.n0); s.Qfx = zeros<long long>(c, m.n0); s.Qprev = zeros<long long>(c, m.n0);
     }
-    s.cnt = zeros<int32_t>(c, size_t(m.n2) + 1);
-    s.blk = zeros<int32_t>(c, size_t(m.n2) / 1024 + 2);
-    s.ctr = zeros<DevCounters>(c, 1);
-    s.diag = zeros<DevDiag>(c, 1);
-    s.kin_part = zeros<double>(c, 1024);
-    s.capacity = 0;
-    s.cur = 0;
+    std::memset(&c->ic, 0, sizeof(InstConst));
+    c->ic.dt = c->dt;
+    c->ic.cdt = float(kC * c->dt);
+    upload_inst(c);
     hcheck(hipStreamSynchronize(c->stream), "build sync");
+}
+
+
+// One time step enqueued on st (c->stream unless a graph is being captured).
+void enqueue_step(axp_ctx *c, hipStream_t st) {
+    const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
+    DevMesh &m = c->dm;
+    DevState &s = c->ds;
+    if (c->plain) {
+        { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass_plain(m, s, c->dp, c->pc, st); }
+        if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(m, s, st); }
+        { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_push_plain(m, s, c->dp, c->pc, sort_now, st); }
+        { PhaseScope ps(c, AXP_PHASE_WALK); launch_walk_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, st); }
+        { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
+        { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv_plain(m, s, c->dp, st); }
+        ++c->step;
+        if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_plain(m, s, c->dp, true, st); }
+        return;
+    }
+    const bool single = m.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
+    const InstConst *k0 = single ? &c->ic : nullptr;
+    { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(m, s, st); }
+    if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(m, s, st); }
+    { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_push(m, s, sort_now, k0, st); }
+    { PhaseScope ps(c, AXP_PHASE_WALK); launch_walk(m, s, c->cfg.max_walk, sort_now, k0, st); }
+    { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass(m, s, true, st); }
+    { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv(m, s, st); }
+    ++c->step;
+    if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort(m, s, true, st); }
+}
+
+void drop_graphs(axp_ctx *c) {
+    for (auto &g : c->gexec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+// Graph of 2 * sort_period steps starting at a step that is a multiple of
+// the sort period: it holds exactly two sorts, so the particle buffer in use
+// is the same before and after it, and one graph per buffer suffices.
+void launch_graph(axp_ctx *c, int W) {
+    const int cur0 = c->ds.cur;
+    if (!c->gexec[cur0]) {
+        if (!c->cap_stream) hcheck(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
+        const DevState saved = c->ds;
+        const int64_t saved_step = c->step;
+        hcheck(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        for (int k = 0; k < W; ++k) enqueue_step(c, c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
+        c->ds = saved;              // the captured launches have not run
+        c->step = saved_step;
+        hcheck(e1, "end capture");
+        const hipError_t e2 = hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hcheck(e2, "graph instantiate");
+        c->graph_window = W;
+    }
+    hcheck(hipGraphLaunch(c->gexec[cur0], c->stream), "graph launch");
+    c->step += W;
+}
+
+void run_steps(axp_ctx *c, int n_steps) {
+    const int sp = c->cfg.sort_period;
+    const int W = 2 * sp;
+    for (int i = 0; i < n_steps;) {
+        const int de = c->cfg.diag_every;
+        bool graph = c->cfg.use_graph && !c->plain && !c->timing && c->step % sp == 0 && n_steps - i >= W;
+        if (graph && de > 0) {
+            // a diagnostic falls inside the window: run eagerly
+            const int64_t next = (c->step / de + 1) * de;
+            if (next <= c->step + W) graph = false;
+        }
+        if (graph && c->graph_window != 0 && c->graph_window != W) drop_graphs(c);
+        if (graph) {
+            launch_graph(c, W);
+            i += W;
+            continue;
+        }
+        enqueue_step(c, c->stream);
+        ++i;
+        if (de > 0 && c->step % de == 0) run_diag(c);
+        if (c->ev.size() > 4096) collect_timing(c);
+    }
+    hcheck(hipGetLastError(), "step launch");
 }
 
 }  // namespace
@@ -526,6 +679,7 @@ axp_status axp_set_external_bz(axp_ctx *c, double bz) {
         c->ic.bz = float(bz);
         c->pc.bz = bz;
         upload_inst(c);
+        drop_graphs(c);
         return AXP_OK;
     });
 }
@@ -558,6 +712,7 @@ axp_status axp_add_species(axp_ctx *c, double q, double m, int64_t weight, int32
         pc.mw[sp] = ic.mw[sp];
         pc.qunit = c->q_unit / kTwoPi;
         upload_inst(c);
+        drop_graphs(c);
         *id = sp;
         return AXP_OK;
     });
@@ -656,46 +811,7 @@ axp_status axp_step(axp_ctx *c, int32_t n_steps) {
     if (!c || n_steps < 0) return AXP_E_ARG;
     return guarded(c, [&]() -> axp_status {
         require_built(c);
-        for (int i = 0; i < n_steps && c->plain; ++i) {
-            const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
-            { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass_plain(c->dm, c->ds, c->dp, c->pc, c->stream); }
-            if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(c->dm, c->ds, c->stream); }
-            { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_push_plain(c->dm, c->ds, c->dp, c->pc, sort_now, c->stream); }
-            {
-                PhaseScope ps(c, AXP_PHASE_WALK);
-                launch_walk_plain(c->dm, c->ds, c->dp, c->pc, c->cfg.max_walk, sort_now, c->stream);
-            }
-            { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass_plain(c->dm, c->ds, c->dp, c->pc, c->stream); }
-            { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv_plain(c->dm, c->ds, c->dp, c->stream); }
-            ++c->step;
-            if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_plain(c->dm, c->ds, c->dp, true, c->stream); }
-            if (c->cfg.diag_every > 0 && c->step % c->cfg.diag_every == 0) run_diag(c);
-            if (c->ev.size() > 4096) collect_timing(c);
-        }
-        for (int i = 0; i < n_steps && !c->plain; ++i) {
-            const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
-            { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(c->dm, c->ds, c->stream); }
-            if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(c->dm, c->ds, c->stream); }
-            const bool single = c->dm.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
-            {
-                PhaseScope ps(c, AXP_PHASE_PARTICLES);
-                launch_push(c->dm, c->ds, sort_now, single ? &c->ic : nullptr, c->stream);
-            }
-            {
-                PhaseScope ps(c, AXP_PHASE_WALK);
-                launch_walk(c->dm, c->ds, c->cfg.max_walk, sort_now, single ? &c->ic : nullptr, c->stream);
-            }
-            { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass(c->dm, c->ds, true, c->stream); }
-            { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv(c->dm, c->ds, c->stream); }
-            ++c->step;
-            if (sort_now) {
-                PhaseScope ps(c, AXP_PHASE_SORT);
-                launch_sort(c->dm, c->ds, true, c->stream);
-            }
-            if (c->cfg.diag_every > 0 && c->step % c->cfg.diag_every == 0) run_diag(c);
-            if (c->ev.size() > 4096) collect_timing(c);
-        }
-        hcheck(hipGetLastError(), "step launch");
+        run_steps(c, n_steps);
         return AXP_OK;
     });
 }
@@ -901,18 +1017,268 @@ const char *axp_last_error(const axp_ctx *c) { return c ? c->err.c_str() : "null
 void axp_destroy(axp_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &r : c->ev) { (void)hipEventDestroy(r.second.first); (void)hipEventDestroy(r.second.second); }
     for (auto &r : c->ev_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
     for (void *p : std::vector<void *>(c->allocs)) dfree(c, p);
     delete c;
 }
 
-axp_status axp_batch_create(axp_ctx *const *, int32_t, axp_batch **out) {
-    if (out) *out = nullptr;
-    return AXP_E_STATE;
+axp_status axp_autotune(axp_ctx *c, int32_t trial_steps, int32_t *sort_period) {
+    if (!c || trial_steps < 1) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        if (c->timing) throw ApiError{AXP_E_STATE, "turn timing off before autotuning"};
+        const int cand[] = {1, 2, 4, 8, 16};
+        hipEvent_t e0, e1;
+        hcheck(hipEventCreate(&e0), "event");
+        hcheck(hipEventCreate(&e1), "event");
+        double best = 1e300;
+        int best_sp = c->cfg.sort_period;
+        for (int sp : cand) {
+            c->cfg.sort_period = sp;
+            drop_graphs(c);
+            // align to the sort period, then one window to build the graph and settle the order
+            const int align = int((sp - c->step % sp) % sp);
+            run_steps(c, align + 2 * sp);
+            const int n = (trial_steps + 2 * sp - 1) / (2 * sp) * (2 * sp);
+            hcheck(hipEventRecord(e0, c->stream), "event record");
+            run_steps(c, n);
+            hcheck(hipEventRecord(e1, c->stream), "event record");
+            hcheck(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            hcheck(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            const double per = double(ms) / n;
+            if (per < best) { best = per; best_sp = sp; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->cfg.sort_period = best_sp;
+        drop_graphs(c);
+        if (sort_period) *sort_period = best_sp;
+        return AXP_OK;
+    });
 }
-axp_status axp_batch_step(axp_batch *, int32_t) { return AXP_E_STATE; }
-axp_status axp_batch_sync(axp_batch *) { return AXP_E_STATE; }
-void axp_batch_destroy(axp_batch *) {}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch
+struct axp_batch {
+    axp_ctx *pool = nullptr;
+    std::vector<axp_ctx *> ctxs;
+    std::vector<int32_t> fo, eo, no;       // face / edge / node offsets of the instances (n + 1)
+    std::vector<int64_t> live;             // live particles per instance at the last sync
+    int64_t synced_step = 0;               // pool step at the last sync
+};
+
+namespace {
+
+// Sorts the pool (compacting absorbed particles) and returns the particle
+// range of each instance: after the sort the particles of instance k are
+// those of faces [fo[k], fo[k+1]), which are contiguous.
+std::vector<int64_t> pool_ranges(axp_batch *b) {
+    axp_ctx *p = b->pool;
+    const size_t n = b->ctxs.size();
+    std::vector<int64_t> start(n + 1, 0);
+    if (p->ds.capacity == 0) return start;
+    launch_sort(p->dm, p->ds, false, p->stream);
+    hcheck(hipGetLastError(), "sort launch");
+    // after the scatter cnt[t] holds the end of face t
+    for (size_t k = 1; k <= n; ++k) {
+        int32_t v = 0;
+        const int32_t f = b->fo[k] - 1;
+        hcheck(hipMemcpyAsync(&v, p->ds.cnt + f, 4, hipMemcpyDeviceToHost, p->stream), "ranges");
+        hcheck(hipStreamSynchronize(p->stream), "sync");
+        start[k] = v;
+    }
+    return start;
+}
+
+template <class T>
+void d2d(axp_ctx *p, T *dst, const T *src, size_t n) {
+    if (n) hcheck(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, p->stream), "copy");
+}
+
+}  // namespace
+
+extern "C" {
+
+axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
+    if (!out || !ctxs || n < 1) return AXP_E_ARG;
+    *out = nullptr;
+    for (int k = 0; k < n; ++k) {
+        axp_ctx *c = ctxs[k];
+        if (!c) return AXP_E_ARG;
+        if (!c->built || c->sticky) return fail(c, AXP_E_STATE, "batch members must be built and error-free");
+        if (c->plain) return fail(c, AXP_E_ARG, "batches advance the mixed-precision step only");
+        if (c->cfg.device != ctxs[0]->cfg.device) return fail(c, AXP_E_ARG, "batch members must share a device");
+        if (c->species.empty()) return fail(c, AXP_E_STATE, "batch members need a species");
+    }
+    auto *b = new (std::nothrow) axp_batch();
+    if (!b) return AXP_E_OOM;
+    auto *p = new (std::nothrow) axp_ctx();
+    if (!p) { delete b; return AXP_E_OOM; }
+    b->pool = p;
+    b->ctxs.assign(ctxs, ctxs + n);
+    p->cfg = ctxs[0]->cfg;
+    p->cfg.diag_every = 0;
+    p->stream = ctxs[0]->stream;
+    const axp_status st = guarded(p, [&]() -> axp_status {
+        hcheck(hipSetDevice(p->cfg.device), "hipSetDevice");
+        for (auto *c : b->ctxs) hcheck(hipStreamSynchronize(c->stream), "member sync");
+        HostTables h;
+        for (int k = 0; k < n; ++k) {
+            b->fo.push_back(h.n2); b->eo.push_back(h.n1); b->no.push_back(h.n0);
+            if (int64_t(h.n2) + ctxs[k]->hm.n2 >= (int64_t(1) << kCellBits))
+                throw ApiError{AXP_E_ARG, "too many faces in the batch"};
+            append_instance(h, ctxs[k]->hm, ctxs[k]->dt, k);
+        }
+        b->fo.push_back(h.n2); b->eo.push_back(h.n1); b->no.push_back(h.n0);
+        upload_tables(p, h, true, n);
+        std::vector<InstConst> ics(n);
+        for (int k = 0; k < n; ++k) ics[k] = ctxs[k]->ic;
+        hcheck(hipMemcpyAsync((void *)p->dm.inst, ics.data(), sizeof(InstConst) * n, hipMemcpyHostToDevice, p->stream),
+               "inst");
+        p->ic = ics[0];
+        p->dt = ctxs[0]->dt;
+        DevState &ps = p->ds;
+        int64_t total = 0;
+        std::vector<int64_t> slots(n);
+        for (int k = 0; k < n; ++k) {
+            slots[k] = int64_t(read_counters(ctxs[k]).n_slots);
+            total += slots[k];
+        }
+        if (total >= (int64_t(1) << 31) - 4096) throw ApiError{AXP_E_ARG, "too many particles in the batch"};
+        for (int k = 0; k < n; ++k) {
+            const DevState &cs = ctxs[k]->ds;
+            const HostMesh &m = ctxs[k]->hm;
+            d2d(p, ps.B + b->fo[k], cs.B, m.n2);
+            d2d(p, ps.Bprev + b->fo[k], cs.Bprev, m.n2);
+            d2d(p, ps.D + b->eo[k], cs.D, m.n1);
+            d2d(p, ps.D32 + b->eo[k], cs.D32, m.n1);
+            d2d(p, ps.E + b->eo[k], cs.E, m.n1);
+            d2d(p, ps.Jfx + b->eo[k], cs.Jfx, m.n1);
+            d2d(p, ps.Qres + b->no[k], cs.Qres, m.n0);
+        }
+        grow_particles(p, std::max<int64_t>(total, 1));
+        int64_t o = 0;
+        for (int k = 0; k < n; ++k) {
+            const DevState &cs = ctxs[k]->ds;
+            const int a = cs.cur, q = ps.cur;
+            d2d(p, ps.cell[q] + o, cs.cell[a], slots[k]);
+            d2d(p, ps.L0[q] + o, cs.L0[a], slots[k]);
+            d2d(p, ps.L1[q] + o, cs.L1[a], slots[k]);
+            d2d(p, ps.ur[q] + o, cs.ur[a], slots[k]);
+            d2d(p, ps.up[q] + o, cs.up[a], slots[k]);
+            d2d(p, ps.uz[q] + o, cs.uz[a], slots[k]);
+            launch_offset_cells(ps.cell[q] + o, slots[k], b->fo[k], p->stream);
+            o += slots[k];
+        }
+        unsigned long long ns = (unsigned long long)total;
+        hcheck(hipMemcpyAsync(&ps.ctr->n_slots, &ns, 8, hipMemcpyHostToDevice, p->stream), "slots");
+        std::vector<int64_t> start = pool_ranges(b);
+        b->live.resize(n);
+        for (int k = 0; k < n; ++k) b->live[k] = start[k + 1] - start[k];
+        hcheck(hipStreamSynchronize(p->stream), "batch sync");
+        p->built = true;
+        return AXP_OK;
+    });
+    if (st != AXP_OK) {
+        for (auto *c : b->ctxs) c->err = "axp_batch_create: " + p->err;
+        axp_destroy(p);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return AXP_OK;
+}
+
+axp_status axp_batch_step(axp_batch *b, int32_t n_steps) {
+    if (!b || n_steps < 0) return AXP_E_ARG;
+    return axp_step(b->pool, n_steps);
+}
+
+axp_status axp_batch_sync(axp_batch *b) {
+    if (!b) return AXP_E_ARG;
+    axp_ctx *p = b->pool;
+    axp_status st = axp_sync(p);
+    if (st != AXP_OK) {
+        for (auto *c : b->ctxs) { c->sticky = st; c->err = "batch: " + p->err; }
+        return st;
+    }
+    return guarded(p, [&]() -> axp_status {
+        std::vector<int64_t> start = pool_ranges(b);
+        DevState &ps = p->ds;
+        for (size_t k = 0; k < b->ctxs.size(); ++k) {
+            axp_ctx *c = b->ctxs[k];
+            const HostMesh &m = c->hm;
+            DevState &cs = c->ds;
+            const int64_t nk = start[k + 1] - start[k];
+            DevCounters h = read_counters(c);
+            h.n_slots = 0;
+            hcheck(hipMemcpyAsync(cs.ctr, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+            grow_particles(c, nk);
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+            const int a = ps.cur, q = cs.cur;
+            const int64_t o = start[k];
+            d2d(p, cs.cell[q], ps.cell[a] + o, nk);
+            d2d(p, cs.L0[q], ps.L0[a] + o, nk);
+            d2d(p, cs.L1[q], ps.L1[a] + o, nk);
+            d2d(p, cs.ur[q], ps.ur[a] + o, nk);
+            d2d(p, cs.up[q], ps.up[a] + o, nk);
+            d2d(p, cs.uz[q], ps.uz[a] + o, nk);
+            launch_offset_cells(cs.cell[q], nk, -b->fo[k], p->stream);
+            d2d(p, cs.B, ps.B + b->fo[k], m.n2);
+            d2d(p, cs.Bprev, ps.Bprev + b->fo[k], m.n2);
+            d2d(p, cs.D, ps.D + b->eo[k], m.n1);
+            d2d(p, cs.D32, ps.D32 + b->eo[k], m.n1);
+            d2d(p, cs.E, ps.E + b->eo[k], m.n1);
+            d2d(p, cs.Jfx, ps.Jfx + b->eo[k], m.n1);
+            d2d(p, cs.Qres, ps.Qres + b->no[k], m.n0);
+            h.n_slots = (unsigned long long)nk;
+            h.n_absorbed += (unsigned long long)std::max<int64_t>(0, b->live[k] - nk);
+            hcheck(hipMemcpyAsync(cs.ctr, &h, sizeof(h), hipMemcpyHostToDevice, p->stream), "counters");
+            hcheck(hipStreamSynchronize(p->stream), "sync");
+            c->step += p->step - b->synced_step;
+            c->last_diag_step = -1;
+            c->n_live_host = nk;
+            b->live[k] = nk;
+        }
+        b->synced_step = p->step;
+        return AXP_OK;
+    });
+}
+
+axp_status axp_batch_autotune(axp_batch *b, int32_t trial_steps, int32_t *sort_period) {
+    if (!b) return AXP_E_ARG;
+    return axp_autotune(b->pool, trial_steps, sort_period);
+}
+
+axp_status axp_batch_set_timing(axp_batch *b, int32_t on) { return b ? axp_set_timing(b->pool, on) : AXP_E_ARG; }
+
+axp_status axp_batch_get_timing(axp_batch *b, double *ms, int64_t *launches) {
+    return b ? axp_get_timing(b->pool, ms, launches) : AXP_E_ARG;
+}
+
+axp_status axp_batch_info(axp_batch *b, int64_t *n_faces, int64_t *n_edges, int64_t *n_particles, int64_t *step) {
+    if (!b) return AXP_E_ARG;
+    axp_ctx *p = b->pool;
+    return guarded(p, [&]() -> axp_status {
+        if (n_faces) *n_faces = p->dm.n2;
+        if (n_edges) *n_edges = p->dm.n1;
+        if (n_particles) *n_particles = int64_t(read_counters(p).n_slots);
+        if (step) *step = p->step;
+        return AXP_OK;
+    });
+}
+
+const char *axp_batch_last_error(const axp_batch *b) { return b ? b->pool->err.c_str() : "null batch"; }
+
+void axp_batch_destroy(axp_batch *b) {
+    if (!b) return;
+    axp_destroy(b->pool);
+    delete b;
+}
 
 }  // extern "C"

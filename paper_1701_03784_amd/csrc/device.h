@@ -150,6 +150,7 @@ void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hi
 // Counting sort of the particle arrays by face: cell words in s.cell plus
 // n_fields payload arrays of `width` bytes (4 or 8) per particle, src[f] ->
 // dst[f].  counted: s.cnt already holds the face histogram.
+void launch_offset_cells(int32_t *cell, int64_t n, int32_t delta, hipStream_t st);
 void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width, int n_fields, void *const *src,
                          void *const *dst, hipStream_t st);
 

@@ -328,6 +328,8 @@ __global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_coun
     // face data cached across the thread's particles (consecutive particles share faces)
     int Tc = -1;
     float4 cf0 = make_float4(0.f, 0.f, 0.f, 0.f), cf1 = cf0, cr4 = cf0, cg = cf0;
+    int ic_key = -1;                 // cell word (face, species) the constants below belong to
+    PushConst ic = k0;
 #pragma unroll
     for (int j = 0; j < kPPT; ++j) {
         mover[j] = false;
@@ -339,7 +341,10 @@ __global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_coun
             Tc = T;
             cf0 = s.f0[T]; cf1 = s.f1[T]; cr4 = m.rho4[T]; cg = m.gS[T];
         }
-        const PushConst ic = push_const<SINGLE>(m, k0, T, sp);
+        if (!SINGLE && P[j].cell != ic_key) {
+            ic_key = P[j].cell;
+            ic = push_const<SINGLE>(m, k0, T, sp);
+        }
         const int L0 = (int)P[j].L0, L1 = (int)P[j].L1, L2 = kS - L0 - L1;
         float fz, fr;
         push(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
@@ -766,6 +771,12 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, 
 
 __global__ void k_set_slots(DevState s, const int32_t *total) { s.ctr->n_slots = (unsigned long long)(*total); }
 
+// adds delta to the face index of every live cell word (pooling of instances)
+__global__ __launch_bounds__(256) void k_offset_cells(int32_t *cell, int64_t n, int32_t delta) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cell[i] >= 0) cell[i] += delta;
+}
+
 // ------------------------------------------------------------ diagnostics
 __global__ __launch_bounds__(256) void k_charge_init(DevMesh m, DevState s) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -968,6 +979,10 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
     }
     hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, st, s, s.cnt + n);
     s.cur = 1 - s.cur;
+}
+
+void launch_offset_cells(int32_t *cell, int64_t n, int32_t delta, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_offset_cells, dim3(nblk(n, 256)), dim3(256), 0, st, cell, n, delta);
 }
 
 void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st) {
