@@ -73,7 +73,7 @@ def field_bytes(n_edges, n_faces, spai_nnz_padded):
         (8.0 * spai_nnz_padded + 8.0 * n_edges)
 
 
-def setup_bwo(n_particles, seed=3, sort_period=4):
+def setup_bwo(n_particles, seed=3, sort_period=4, precision=None):
     import synth
     from synth import configs
     import paper_1701_03784_amd as axp
@@ -81,7 +81,8 @@ def setup_bwo(n_particles, seed=3, sort_period=4):
     m = configs.bwo_mesh(seed=seed)
     L = m.meta["length"]
     log(f"mesh: {m.n_nodes} nodes, {m.n_tris} faces ({time.perf_counter() - t0:.1f} s)")
-    c = axp.make_ctx(m, sort_period=sort_period)
+    kw = {} if precision is None else {"precision": precision}
+    c = axp.make_ctx(m, sort_period=sort_period, **kw)
     info = c.info()
     log(f"built: {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s "
         f"(limit {info['dt_cfl']:.3e}), setup {info['setup_seconds']:.1f} s")
@@ -97,6 +98,71 @@ def setup_bwo(n_particles, seed=3, sort_period=4):
             f"{info['n_edges']} edges; {n_particles} macro-electrons, 500 keV annular beam, B_z=1 T; "
             f"SPAI level 3 ({info['spai_nnz']} nnz); dt=0.5 CFL")
     return c, m, info, desc
+
+
+def plain_leg(n_particles, steps, warmup):
+    """The same workload on the FP64 GPU step (no graph, one instance)."""
+    import paper_1701_03784_amd as axp
+    c, m, info, _ = setup_bwo(n_particles, precision=axp.PREC_PLAIN_FP64)
+    c.step(warmup)
+    c.sync()
+    t0 = time.perf_counter()
+    c.step(steps)
+    c.sync()
+    el = time.perf_counter() - t0
+    d = c.diag()
+    c.close()
+    return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
+            "steps": steps, "precision": "plain fp64", "particles": int(d["n_live"])}
+
+
+def batched_leg(n_variants, steps, per_face=25, seed_note=""):
+    """Batched sweep: members 0..n-1 of the seeded BWO variant family (ripple
+    amplitude, period, taper, beam voltage; 20k-300k faces), ~25 particles
+    per face each, pooled into one batch, sort schedule autotuned, steps
+    replayed from graphs."""
+    import synth
+    from synth import configs
+    import paper_1701_03784_amd as axp
+    t0 = time.perf_counter()
+    ctxs = []
+    n_faces = n_part = 0
+    for i in range(n_variants):
+        m, p = configs.variant_mesh(i)
+        c = axp.make_ctx(m, sort_period=4)
+        info = c.info()
+        c.set_fields(np.zeros(info["n_edges"]), np.zeros(info["n_faces"]))
+        c.set_external_bz(configs.BWO_BZ)
+        L = m.meta["length"]
+        n = per_face * m.n_tris
+        sp = c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.bwo_weight(n, L, kev=p["kev"]))
+        r_out = min(0.011, 0.015 - p["amp"] - 0.001)       # keep the beam 1 mm inside the ripple minimum
+        zr, u = configs.bwo_beam(n, L, kev=p["kev"], seed=p["seed"], r_in=r_out - 0.002, r_out=r_out)
+        c.inject(sp, zr, u)
+        n_faces += m.n_tris
+        n_part += n
+        ctxs.append(c)
+        log(f"batch member {i}: {m.n_tris} faces, {n} particles, {p['kev']:.0f} keV")
+    b = axp.Batch(ctxs)
+    log(f"batch of {n_variants}: {n_faces} faces, {n_part} particles, setup {time.perf_counter() - t0:.1f} s")
+    sp_best = b.autotune(trial_steps=16)
+    log(f"autotuned sort period {sp_best}")
+    b.step(2 * sp_best)
+    b.sync()
+    steps = max(2 * sp_best, steps // (2 * sp_best) * (2 * sp_best))
+    t1 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    el = time.perf_counter() - t1
+    live = sum(c.info()["n_particles"] for c in ctxs)
+    n_edges = b.info()["n_edges"]
+    b.close()
+    for c in ctxs:
+        c.close()
+    return {"value": live * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
+            "steps": steps, "variants": n_variants, "faces": n_faces, "particles": int(live),
+            "sort_period": sp_best, "graphs": True,
+            "field_dof_steps_per_s": (n_faces + n_edges) * steps / el}
 
 
 def cpu_baseline(target_seconds=15.0):
@@ -119,7 +185,7 @@ def cpu_baseline(target_seconds=15.0):
     sim.inject(sp, zr, u)
     sim.step(1)
     steps, el = 0, 0.0
-    while el < target_seconds and steps < 50:
+    while el < target_seconds and steps < 400:
         t1 = time.perf_counter()
         sim.step(1)
         el += time.perf_counter() - t1
@@ -141,6 +207,9 @@ def main():
     ap.add_argument("--sort-period", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--plain-steps", type=int, default=20, help="timed steps of the FP64 leg (0: skip)")
+    ap.add_argument("--batch-variants", type=int, default=8, help="members of the batched sweep (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=48)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -189,6 +258,17 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB x3")
 
+    c.close()
+    plain = batched = None
+    if args.plain_steps > 0:
+        log("plain FP64 leg ...")
+        plain = plain_leg(args.particles, args.plain_steps, 4)
+        log(f"plain: {plain['value']:.3e} particle-steps/s ({plain['ms_per_step']:.3f} ms/step)")
+    if args.batch_variants > 0:
+        log("batched leg ...")
+        batched = batched_leg(args.batch_variants, args.batch_steps)
+        log(f"batched: {batched['value']:.3e} particle-steps/s ({batched['ms_per_step']:.3f} ms/step)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -220,6 +300,10 @@ def main():
                      "avg_launch_us": part_avg_s * 1e6,
                      "kernel_source_sha256_16": kernel_source_hash()},
         "cpu_baseline": cpu,
+        "plain_fp64": plain,
+        "batched_mixed": batched,
+        "speedup_mixed_vs_plain": (value / plain["value"]) if plain else None,
+        "speedup_batched_mixed_vs_plain": (batched["value"] / plain["value"]) if (plain and batched) else None,
     }
     print(json.dumps(out), flush=True)
 

@@ -83,6 +83,7 @@ def _hex_lattice(z0, z1, h, ny, jitter, rng):
         s = j / ny
         if j % 2 == 0:
             z = z0 + dx * np.arange(nx + 1)
+            z[-1] = z1                      # exact end point: it must stay on the side z = z1
         else:
             z = np.concatenate([[z0], z0 + dx * (np.arange(nx) + 0.5), [z1]])
         row = np.stack([z, np.full_like(z, s)], axis=1)
