@@ -81,6 +81,15 @@ enum {
                                 64-bit fixed-point current; FP64 D, B and diagnostics */
 };
 
+/* How the SPAI matrix was built (axp_info.spai_mode). */
+enum {
+    AXP_SPAI_PLAIN = 0,            /* least squares per column (Sec. 3.1) */
+    AXP_SPAI_LEARNED = 1,          /* network guess + refinement, least-squares fallback per column */
+    AXP_SPAI_LEARNED_REJECTED = 2  /* learned matrix failed the energy guard: plain SPAI used */
+};
+
+typedef struct axp_mlp axp_mlp;
+
 typedef void *(*axp_alloc_fn)(size_t bytes, void *user);
 typedef void (*axp_free_fn)(void *ptr, void *user);
 
@@ -114,6 +123,13 @@ typedef struct {
     int64_t step;                /* steps taken */
     int32_t precision;
     int32_t n_species;
+    int32_t spai_mode;               /* AXP_SPAI_* actually used */
+    int32_t pad_;
+    int64_t spai_fallback_columns;   /* learned SPAI: columns replaced by least squares */
+    double spai_pred_resid_mean;     /* learned SPAI: mean ||e_k - A^ m_k|| of the network's columns */
+    double spai_kept_resid_mean;     /* same after refinement, over the columns kept */
+    double spai_energy_drift;        /* learned SPAI: relative energy drift of the guard run */
+    double spai_seconds;             /* host time of the SPAI construction */
 } axp_info;
 
 typedef struct {
@@ -243,6 +259,66 @@ axp_status axp_get_timing(axp_ctx *ctx, double *ms /*[AXP_N_PHASES]*/, int64_t *
 
 const char *axp_last_error(const axp_ctx *ctx);
 void axp_destroy(axp_ctx *ctx);
+
+/* ---- learned SPAI ------------------------------------------------------
+ * A small network predicts the entries M^_kj of the Jacobi-scaled SPAI
+ * matrix (A^ = S^-1/2 [*eps] S^-1/2 on the free edges, S = diag) for every
+ * pair (k, j) of the level-L pattern, from 16 features of the pair, all
+ * symmetric in (k, j):
+ *   0-3  one-hot hop distance d(k, j) = 0..3 in the graph of A^
+ *   4-6  (A^)_kj, (A^^2)_kj, (A^^3)_kj
+ *   7    min/max of the two edge lengths (meridian plane)
+ *   8    midpoint distance / (l_k + l_j)
+ *   9    |cos| of the angle between the edges
+ *   10   min/max of the midpoint radii rho (1 if both are 0)
+ *   11   (l_k + l_j) / (rho_k + rho_j + l_k + l_j)
+ *   12   (n_k + n_j)/20 and 13 |n_k - n_j|/10, n = entries in the row of A^
+ *   14   mean over k, j of sum_i |A^_ki|, minus 1
+ *   15   d / 3
+ * Network: 16 -> H (tanh) -> ... -> H (tanh) -> 1 (linear), H = 32 or 64,
+ * 1-4 hidden layers.  Parameter vector (FP32): per layer W[n_out][n_in]
+ * row-major, then b[n_out].  Loss: sum_i w_i (p_i - y_i)^2 / sum_i w_i.
+ * The training kernels (forward, backward, weight gradients on the matrix
+ * cores, Adam) run on the network's device and stream. */
+axp_status axp_mlp_create(int32_t device, void *hip_stream, int32_t n_in, int32_t n_hidden, int32_t n_layers,
+                          int32_t spai_level, uint64_t seed, axp_mlp **out);
+int64_t axp_mlp_n_params(const axp_mlp *net);
+/* Host parameter vectors; set_params also clears the Adam state. */
+axp_status axp_mlp_set_params(axp_mlp *net, const float *params);
+axp_status axp_mlp_get_params(const axp_mlp *net, float *params);
+/* X[n][16], y[n] and w[n] are DEVICE pointers (FP32). forward: y = net(X). */
+axp_status axp_mlp_forward(axp_mlp *net, const float *X, int64_t n, float *y);
+/* Loss and gradient over the n samples (device inputs); *loss and grad[n_params]
+ * are host outputs and may be NULL (then nothing is synchronised). */
+axp_status axp_mlp_loss_grad(axp_mlp *net, const float *X, const float *y, const float *w, int64_t n, double *loss,
+                             float *grad);
+/* One Adam step (bias-corrected) with the gradient of the last loss_grad call. */
+axp_status axp_mlp_adam_step(axp_mlp *net, double lr, double beta1, double beta2, double eps);
+axp_status axp_mlp_info(const axp_mlp *net, int32_t *n_in, int32_t *n_hidden, int32_t *n_layers, int32_t *spai_level,
+                        int64_t *adam_steps);
+axp_status axp_mlp_save(const axp_mlp *net, const char *path);
+axp_status axp_mlp_load(int32_t device, void *hip_stream, const char *path, axp_mlp **out);
+const char *axp_mlp_last_error(const axp_mlp *net);
+void axp_mlp_destroy(axp_mlp *net);
+
+/* Use the network for this context's SPAI (call before axp_build; NULL
+ * restores the plain SPAI).  At axp_build the network's column m_k on the
+ * level-L pattern J_k starts `iters` conjugate-gradient steps on the normal
+ * equations of min ||e_k - A^(:, J_k) m||_2 (whose limit is the plain SPAI's
+ * least-squares column); a column whose residual ||e_k - A^ m_k||_2 then
+ * exceeds row_tol is replaced by its exact least-squares column; drop rule
+ * and symmetric average as in the plain SPAI.  The result must then conserve
+ * the discrete energy of a 64-step source-free leapfrog run to
+ * energy_drift_tol (relative), else the plain SPAI is used
+ * (AXP_SPAI_LEARNED_REJECTED).  The network is borrowed during axp_build. */
+axp_status axp_set_spai_model(axp_ctx *ctx, axp_mlp *net, double row_tol, double energy_drift_tol, int32_t iters);
+
+/* Training data of a built context: features X[n][16] of every pattern pair,
+ * the scaled entry y[n] = M^_kj of the context's SPAI (0 where dropped) and
+ * the canonical edge indices kj[n][2].  *n receives the pair count; with
+ * all outputs NULL only the count is returned (AXP_E_ARG if it exceeds
+ * capacity). */
+axp_status axp_spai_pairs(axp_ctx *ctx, int64_t capacity, int64_t *n, float *X, float *y, int32_t *kj);
 
 /* Sort schedule autotuner: runs about trial_steps real steps under each of
  * the sort periods 1, 2, 4, 8, 16 (plus one settling window each), times

@@ -22,6 +22,8 @@ ERRORS = {-1: "AXP_E_ARG", -2: "AXP_E_MESH", -3: "AXP_E_SPAI", -4: "AXP_E_UNSTAB
           -6: "AXP_E_HIP", -7: "AXP_E_WALK", -8: "AXP_E_FIXED_OVERFLOW", -9: "AXP_E_NAN", -10: "AXP_E_STATE"}
 BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN = 1, 2, 3, 4
 PREC_PLAIN_FP64, PREC_MIXED = 0, 1
+SPAI_PLAIN, SPAI_LEARNED, SPAI_LEARNED_REJECTED = 0, 1, 2
+SPAI_FEATURES = 16
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -47,7 +49,9 @@ class Info(C.Structure):
                 ("spai_fro_residual", C.c_double), ("spai_max_col_residual", C.c_double),
                 ("dt", C.c_double), ("dt_cfl", C.c_double), ("setup_seconds", C.c_double),
                 ("particle_capacity", C.c_int64), ("n_particles", C.c_int64), ("step", C.c_int64),
-                ("precision", C.c_int32), ("n_species", C.c_int32)]
+                ("precision", C.c_int32), ("n_species", C.c_int32), ("spai_mode", C.c_int32), ("pad_", C.c_int32),
+                ("spai_fallback_columns", C.c_int64), ("spai_pred_resid_mean", C.c_double),
+                ("spai_kept_resid_mean", C.c_double), ("spai_energy_drift", C.c_double), ("spai_seconds", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -64,7 +68,10 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
            "axp_batch_destroy", "axp_set_timing", "axp_get_timing", "axp_autotune", "axp_batch_autotune",
-           "axp_batch_set_timing", "axp_batch_get_timing", "axp_batch_info", "axp_batch_last_error"]
+           "axp_batch_set_timing", "axp_batch_get_timing", "axp_batch_info", "axp_batch_last_error",
+           "axp_mlp_create", "axp_mlp_n_params", "axp_mlp_set_params", "axp_mlp_get_params", "axp_mlp_forward",
+           "axp_mlp_loss_grad", "axp_mlp_adam_step", "axp_mlp_info", "axp_mlp_save", "axp_mlp_load",
+           "axp_mlp_last_error", "axp_mlp_destroy", "axp_set_spai_model", "axp_spai_pairs"]
 PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject", "walk"]
 
 _lib = None
@@ -121,6 +128,20 @@ def load_library(path: str = LIB_PATH):
         "axp_batch_get_timing": (i32, [vp, vp, vp]),
         "axp_batch_info": (i32, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
         "axp_batch_last_error": (C.c_char_p, [vp]),
+        "axp_mlp_create": (i32, [i32, vp, i32, i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
+        "axp_mlp_n_params": (i64, [vp]),
+        "axp_mlp_set_params": (i32, [vp, vp]),
+        "axp_mlp_get_params": (i32, [vp, vp]),
+        "axp_mlp_forward": (i32, [vp, vp, i64, vp]),
+        "axp_mlp_loss_grad": (i32, [vp, vp, vp, vp, i64, C.POINTER(dbl), vp]),
+        "axp_mlp_adam_step": (i32, [vp, dbl, dbl, dbl, dbl]),
+        "axp_mlp_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]),
+        "axp_mlp_save": (i32, [vp, C.c_char_p]),
+        "axp_mlp_load": (i32, [i32, vp, C.c_char_p, C.POINTER(vp)]),
+        "axp_mlp_last_error": (C.c_char_p, [vp]),
+        "axp_mlp_destroy": (None, [vp]),
+        "axp_set_spai_model": (i32, [vp, vp, dbl, dbl, i32]),
+        "axp_spai_pairs": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -278,6 +299,22 @@ class Ctx:
     def set_timing(self, on=True):
         self._check(self.lib.axp_set_timing(self.h, 1 if on else 0))
 
+    def set_spai_model(self, net, row_tol=0.01, energy_drift_tol=1e-6, iters=3):
+        """Learned SPAI for the next build (net: Mlp or None)."""
+        self._spai_model = net
+        self._check(self.lib.axp_set_spai_model(self.h, net.h if net is not None else None, float(row_tol),
+                                                float(energy_drift_tol), int(iters)))
+
+    def spai_pairs(self):
+        """(X[n][16] float32, y[n] float32, kj[n][2] int32) of the built context."""
+        n = C.c_int64()
+        self._check(self.lib.axp_spai_pairs(self.h, 0, C.byref(n), None, None, None))
+        X = np.zeros((n.value, SPAI_FEATURES), dtype=np.float32)
+        y = np.zeros(n.value, dtype=np.float32)
+        kj = np.zeros((n.value, 2), dtype=np.int32)
+        self._check(self.lib.axp_spai_pairs(self.h, n.value, C.byref(n), _ptr(X), _ptr(y), _ptr(kj)))
+        return X, y, kj
+
     def autotune(self, trial_steps=16):
         """Chooses the sort period by timing real steps; returns it."""
         sp = C.c_int32()
@@ -318,13 +355,96 @@ class Ctx:
         return zr[:n.value], u[:n.value], sp[:n.value]
 
 
-def make_ctx(mesh, **kw):
+def make_ctx(mesh, spai_model=None, spai_row_tol=0.01, spai_energy_tol=1e-6, spai_iters=3, **kw):
     """Context with mesh and boundary set and built (mesh: synth.Mesh-like)."""
     c = Ctx(**kw)
     c.set_mesh(mesh.nodes, mesh.tris)
     c.set_boundary(mesh.seg, mesh.tag)
+    if spai_model is not None:
+        c.set_spai_model(spai_model, spai_row_tol, spai_energy_tol, spai_iters)
     c.build()
     return c
+
+
+def _dptr(t):
+    """Device address of a contiguous torch tensor (device memory plumbing)."""
+    return C.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """The learned-SPAI network (axp_mlp_*): its kernels run on the device."""
+
+    def __init__(self, n_hidden=64, n_layers=2, spai_level=3, seed=0, device=0, stream=None, _handle=None):
+        self.lib = load_library()
+        if _handle is not None:
+            self.h = _handle
+        else:
+            h = C.c_void_p()
+            st = self.lib.axp_mlp_create(device, stream if stream is not None else current_torch_stream(device),
+                                         SPAI_FEATURES, n_hidden, n_layers, spai_level, int(seed), C.byref(h))
+            if st != AXP_OK:
+                raise AxpError(st, "axp_mlp_create")
+            self.h = h
+
+    @classmethod
+    def load(cls, path, device=0, stream=None):
+        lib = load_library()
+        h = C.c_void_p()
+        st = lib.axp_mlp_load(device, stream if stream is not None else current_torch_stream(device),
+                              str(path).encode(), C.byref(h))
+        if st != AXP_OK:
+            raise AxpError(st, f"axp_mlp_load {path}")
+        return cls(_handle=h)
+
+    def _check(self, st):
+        if st != AXP_OK:
+            raise AxpError(st, (self.lib.axp_mlp_last_error(self.h) or b"").decode())
+
+    def n_params(self):
+        return int(self.lib.axp_mlp_n_params(self.h))
+
+    def info(self):
+        v = [C.c_int32() for _ in range(4)] + [C.c_int64()]
+        self._check(self.lib.axp_mlp_info(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(["n_in", "n_hidden", "n_layers", "spai_level", "adam_steps"], [x.value for x in v]))
+
+    def get_params(self):
+        p = np.zeros(self.n_params(), dtype=np.float32)
+        self._check(self.lib.axp_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.n_params()
+        self._check(self.lib.axp_mlp_set_params(self.h, _ptr(p)))
+
+    def forward(self, X, y_out):
+        """X, y_out: contiguous float32 torch tensors on the device."""
+        self._check(self.lib.axp_mlp_forward(self.h, _dptr(X), int(X.shape[0]), _dptr(y_out)))
+
+    def loss_grad(self, X, y, w, want_grad=False):
+        loss = C.c_double()
+        g = np.zeros(self.n_params(), dtype=np.float32) if want_grad else None
+        self._check(self.lib.axp_mlp_loss_grad(self.h, _dptr(X), _dptr(y), _dptr(w), int(X.shape[0]), C.byref(loss),
+                                               _ptr(g)))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.axp_mlp_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def save(self, path):
+        self._check(self.lib.axp_mlp_save(self.h, str(path).encode()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.axp_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

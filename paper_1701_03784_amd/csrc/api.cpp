@@ -19,6 +19,12 @@
 
 using namespace axp;
 
+namespace axp {
+int mlp_predict_host(axp_mlp *net, const float *X, int64_t n, float *y, std::string &err);
+int mlp_level(const axp_mlp *net);
+int mlp_n_in(const axp_mlp *net);
+}  // namespace axp
+
 struct Species {
     double q, m;
     int64_t w;
@@ -56,6 +62,13 @@ struct axp_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
     double phase_ms[AXP_N_PHASES] = {0};
     int64_t phase_n[AXP_N_PHASES] = {0};
+    // learned SPAI
+    axp_mlp *spai_model = nullptr;      // borrowed
+    double spai_row_tol = 0.01, spai_energy_tol = 1e-6;
+    int spai_iters = 3;
+    int spai_mode_used = AXP_SPAI_PLAIN;
+    LearnedSpaiStats spai_stats;
+    double spai_energy_drift = 0, spai_seconds = 0;
     // step graphs (one per particle buffer), replayed on stream
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -578,9 +591,41 @@ axp_status axp_build(axp_ctx *c) {
                        c->in_tri.data(), int32_t(c->in_seg.size() / 2), c->in_seg.data(), c->in_tag.data());
         assemble_hodge(m);
         int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
-        build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+        auto ts = std::chrono::steady_clock::now();
+        c->spai_mode_used = AXP_SPAI_PLAIN;
+        if (c->spai_model) {
+            // network guess, refinement, least-squares fallback per column
+            ScaledHodge h;
+            scaled_hodge(m, h);
+            PairSet ps;
+            spai_pair_features(m, h, c->cfg.spai_level, nt, ps);
+            std::vector<float> pred(ps.j.size());
+            std::string err;
+            const int st = mlp_predict_host(c->spai_model, ps.X.data(), int64_t(ps.j.size()), pred.data(), err);
+            if (st != AXP_OK) throw ApiError{st, err};
+            ps.X.clear();
+            ps.X.shrink_to_fit();
+            learned_spai(m, h, ps, pred.data(), c->cfg.spai_level, c->cfg.spai_drop_tol, c->spai_iters, c->spai_row_tol,
+                         nt, c->spai_stats);
+            c->spai_mode_used = AXP_SPAI_LEARNED;
+        } else {
+            build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+        }
+        c->spai_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
         c->dt_cfl = cfl_dt(m, 400);
         c->dt = c->cfg.dt > 0 ? c->cfg.dt : c->cfg.cfl_fraction * c->dt_cfl;
+        if (c->spai_model) {
+            // run-level guard: the source-free leapfrog energy must be conserved
+            c->spai_energy_drift = std::isfinite(c->dt_cfl) && c->dt <= c->dt_cfl
+                                       ? leapfrog_energy_drift(m, c->dt, 64, 12345)
+                                       : INFINITY;
+            if (!(c->spai_energy_drift <= c->spai_energy_tol)) {
+                build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+                c->spai_mode_used = AXP_SPAI_LEARNED_REJECTED;
+                c->dt_cfl = cfl_dt(m, 400);
+                c->dt = c->cfg.dt > 0 ? c->cfg.dt : c->cfg.cfl_fraction * c->dt_cfl;
+            }
+        }
         if (!(c->dt > 0) || c->dt > c->dt_cfl * (1.0 + 1e-9))
             throw ApiError{AXP_E_UNSTABLE, "dt " + std::to_string(c->dt) + " exceeds the stability limit " +
                                                std::to_string(c->dt_cfl)};
@@ -604,6 +649,12 @@ axp_status axp_info_get(const axp_ctx *c, axp_info *out) {
     out->dt = c->dt; out->dt_cfl = c->dt_cfl; out->setup_seconds = c->setup_s;
     out->particle_capacity = c->ds.capacity; out->n_particles = c->n_live_host;
     out->step = c->step; out->precision = c->cfg.precision; out->n_species = int32_t(c->species.size());
+    out->spai_mode = c->spai_mode_used;
+    out->spai_fallback_columns = c->spai_stats.n_fallback;
+    out->spai_pred_resid_mean = c->spai_stats.pred_resid_mean;
+    out->spai_kept_resid_mean = c->spai_stats.kept_resid_mean;
+    out->spai_energy_drift = c->spai_energy_drift;
+    out->spai_seconds = c->spai_seconds;
     return c->built ? AXP_OK : AXP_E_STATE;
 }
 
@@ -1023,6 +1074,54 @@ void axp_destroy(axp_ctx *c) {
     for (auto &r : c->ev_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
     for (void *p : std::vector<void *>(c->allocs)) dfree(c, p);
     delete c;
+}
+
+axp_status axp_set_spai_model(axp_ctx *c, axp_mlp *net, double row_tol, double energy_drift_tol, int32_t iters) {
+    if (!c) return AXP_E_ARG;
+    if (c->built) return fail(c, AXP_E_STATE, "set the SPAI model before axp_build");
+    if (net && (!(row_tol > 0) || !(energy_drift_tol > 0) || iters < 0 || iters > 64))
+        return fail(c, AXP_E_ARG, "bad learned-SPAI tolerances");
+    if (net && (mlp_level(net) != c->cfg.spai_level || mlp_n_in(net) != kSpaiFeatures))
+        return fail(c, AXP_E_ARG, "the network was trained for another SPAI level or feature set");
+    c->spai_model = net;
+    c->spai_row_tol = row_tol;
+    c->spai_energy_tol = energy_drift_tol;
+    c->spai_iters = iters;
+    return AXP_OK;
+}
+
+axp_status axp_spai_pairs(axp_ctx *c, int64_t capacity, int64_t *n, float *X, float *y, int32_t *kj) {
+    if (!c || !n) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        const HostMesh &m = c->hm;
+        ScaledHodge h;
+        scaled_hodge(m, h);
+        PairSet ps;
+        const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+        spai_pair_features(m, h, c->cfg.spai_level, nt, ps);
+        const int64_t np = int64_t(ps.j.size());
+        *n = np;
+        if (!X && !y && !kj) return AXP_OK;
+        if (np > capacity) return fail(c, AXP_E_ARG, "capacity too small");
+        const int nf = int(h.fedge.size());
+        for (int k = 0; k < nf; ++k) {
+            const int ek = h.fedge[k];
+            for (int64_t q = ps.ptr[k]; q < ps.ptr[k + 1]; ++q) {
+                const int ej = h.fedge[ps.j[q]];
+                if (X) std::memcpy(X + q * kSpaiFeatures, &ps.X[size_t(q) * kSpaiFeatures], sizeof(float) * kSpaiFeatures);
+                if (y) {
+                    // scaled entry M^_kj = M_kj / (s_k s_j) of the context's SPAI (0 where dropped)
+                    const int32_t *b = m.M.col.data() + m.M.ptr[ek], *e = m.M.col.data() + m.M.ptr[ek + 1];
+                    const int32_t *it = std::lower_bound(b, e, ej);
+                    const double v = (it != e && *it == ej) ? m.M.val[it - m.M.col.data()] : 0.0;
+                    y[q] = float(v / (h.s[k] * h.s[ps.j[q]]));
+                }
+                if (kj) { kj[2 * q] = m.edge_can[ek]; kj[2 * q + 1] = m.edge_can[ej]; }
+            }
+        }
+        return AXP_OK;
+    });
 }
 
 axp_status axp_autotune(axp_ctx *c, int32_t trial_steps, int32_t *sort_period) {

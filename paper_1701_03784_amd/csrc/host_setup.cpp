@@ -297,62 +297,95 @@ static bool householder_ls(int rows, int cols, double *B, double *b, double *x) 
     return true;
 }
 
-void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
+void scaled_hodge(const HostMesh &m, ScaledHodge &h) {
     // free-edge numbering and Jacobi scaling A^ = S^-1/2 A S^-1/2
-    std::vector<int32_t> fidx(m.n1, -1), fedge;
+    h.fidx.assign(m.n1, -1);
+    h.fedge.clear();
     for (int e = 0; e < m.n1; ++e)
-        if (m.efree[e]) { fidx[e] = int32_t(fedge.size()); fedge.push_back(e); }
-    const int nf = int(fedge.size());
-    std::vector<double> s(nf);
-    std::vector<std::vector<std::pair<int32_t, double>>> adj(nf);   // scaled rows over free edges
+        if (m.efree[e]) { h.fidx[e] = int32_t(h.fedge.size()); h.fedge.push_back(e); }
+    const int nf = int(h.fedge.size());
+    h.s.assign(nf, 0.0);
+    h.adj.assign(nf, {});
     for (int i = 0; i < nf; ++i) {
-        int e = fedge[i];
+        int e = h.fedge[i];
         double d = 0;
         for (int64_t j = m.A.ptr[e]; j < m.A.ptr[e + 1]; ++j)
             if (m.A.col[j] == e) d = m.A.val[j];
         if (!(d > 0)) throw SetupError{AXP_E_SPAI, "non-positive diagonal of [*eps]"};
-        s[i] = 1.0 / std::sqrt(d);
+        h.s[i] = 1.0 / std::sqrt(d);
     }
     for (int i = 0; i < nf; ++i) {
-        int e = fedge[i];
+        int e = h.fedge[i];
         for (int64_t j = m.A.ptr[e]; j < m.A.ptr[e + 1]; ++j) {
-            int c = fidx[m.A.col[j]];
-            if (c >= 0 && m.A.val[j] != 0.0) adj[i].push_back({c, s[i] * m.A.val[j] * s[c]});
+            int c = h.fidx[m.A.col[j]];
+            if (c >= 0 && m.A.val[j] != 0.0) h.adj[i].push_back({c, h.s[i] * m.A.val[j] * h.s[c]});
         }
     }
+}
+
+// Runs body(tid) on n_threads threads.
+template <class F>
+static void parallel(int n_threads, F &&body) {
+    const int nt = std::max(1, n_threads);
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(body, t);
+    body(0);
+    for (auto &t : th) t.join();
+}
+
+// Columns J_k (free edges within `level` hops of k, sorted) with their hop
+// distance; work arrays are per thread.
+struct PatternWork {
+    std::vector<int32_t> mark, dist, J, frontier, nxt;
+    explicit PatternWork(int nf) : mark(nf, -1), dist(nf, 0) {}
+    void column(const ScaledHodge &h, int k, int level) {
+        J.clear(); frontier.clear();
+        J.push_back(k); frontier.push_back(k); mark[k] = k; dist[k] = 0;
+        for (int l = 0; l < level; ++l) {   // structure of A^level: within `level` hops
+            nxt.clear();
+            for (int u : frontier)
+                for (auto &p : h.adj[u])
+                    if (mark[p.first] != k) {
+                        mark[p.first] = k;
+                        dist[p.first] = l + 1;
+                        nxt.push_back(p.first);
+                        J.push_back(p.first);
+                    }
+            frontier.swap(nxt);
+        }
+        std::sort(J.begin(), J.end());
+    }
+};
+
+void spai_ls_columns(const ScaledHodge &h, int level, double drop_tol, const std::vector<int32_t> *cols, int n_threads,
+                     std::vector<SpaiEntry> &out) {
+    const int nf = int(h.fedge.size());
+    const int ncols = cols ? int(cols->size()) : nf;
     // column k: pattern J_k = nodes within `level` hops, rows I_k = J_k plus one more hop
-    struct Entry { int32_t row, col; double v; };
-    std::vector<std::vector<Entry>> per_thread(std::max(1, n_threads));
+    std::vector<std::vector<SpaiEntry>> per_thread(std::max(1, n_threads));
     std::atomic<int> next{0};
     std::atomic<bool> failed{false};
-    auto work = [&](int tid) {
-        std::vector<int32_t> mark(nf, -1), rmark(nf, -1);
-        std::vector<int32_t> J, I, frontier, nxt;
+    parallel(n_threads, [&](int tid) {
+        PatternWork pw(nf);
+        std::vector<int32_t> rmark(nf, -1), I;
         std::vector<double> B, rhs, x;
-        auto &out = per_thread[tid];
+        auto &o = per_thread[tid];
         for (;;) {
-            int k0 = next.fetch_add(64);
-            if (k0 >= nf || failed.load()) break;
-            for (int k = k0; k < std::min(nf, k0 + 64); ++k) {
-                J.clear(); frontier.clear();
-                J.push_back(k); frontier.push_back(k); mark[k] = k;
-                for (int l = 0; l < level; ++l) {   // structure of A^level: within `level` hops
-                    nxt.clear();
-                    for (int u : frontier)
-                        for (auto &p : adj[u])
-                            if (mark[p.first] != k) { mark[p.first] = k; nxt.push_back(p.first); J.push_back(p.first); }
-                    frontier.swap(nxt);
-                }
-                std::sort(J.begin(), J.end());
+            int q0 = next.fetch_add(64);
+            if (q0 >= ncols || failed.load()) break;
+            for (int q = q0; q < std::min(ncols, q0 + 64); ++q) {
+                const int k = cols ? (*cols)[q] : q;
+                pw.column(h, k, level);
+                const auto &J = pw.J;
                 I.clear();
                 for (int j : J)
-                    for (auto &p : adj[j])
+                    for (auto &p : h.adj[j])
                         if (rmark[p.first] != k) { rmark[p.first] = k; I.push_back(p.first); }
                 std::sort(I.begin(), I.end());
                 const int nr = int(I.size()), nc = int(J.size());
                 B.assign(size_t(nr) * nc, 0.0);
                 for (int c = 0; c < nc; ++c) {
-                    for (auto &p : adj[J[c]]) {
+                    for (auto &p : h.adj[J[c]]) {
                         int r = int(std::lower_bound(I.begin(), I.end(), p.first) - I.begin());
                         B[size_t(c) * nr + r] = p.second;   // A^ symmetric: column J[c] = row J[c]
                     }
@@ -364,23 +397,25 @@ void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
                 double mx = 0;
                 for (double v : x) mx = std::max(mx, std::fabs(v));
                 for (int c = 0; c < nc; ++c)
-                    if (std::fabs(x[c]) >= drop_tol * mx) out.push_back({J[c], k, x[c]});
+                    if (std::fabs(x[c]) >= drop_tol * mx) o.push_back({J[c], k, x[c]});
             }
         }
-    };
-    int nt = std::max(1, n_threads);
-    std::vector<std::thread> th;
-    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
-    work(0);
-    for (auto &t : th) t.join();
+    });
     if (failed) throw SetupError{AXP_E_SPAI, "rank-deficient SPAI least-squares block"};
+    for (auto &v : per_thread) out.insert(out.end(), v.begin(), v.end());
+}
+
+void finish_spai(HostMesh &m, const ScaledHodge &h, std::vector<SpaiEntry> &entries) {
+    const int nf = int(h.fedge.size());
     // symmetric average (M^ + M^T)/2 and unscaling, into CSR over internal edges
     std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
-    for (auto &v : per_thread)
-        for (auto &e : v) {
-            rows[e.row].push_back({e.col, 0.5 * e.v});
-            rows[e.col].push_back({e.row, 0.5 * e.v});
-        }
+    for (auto &e : entries) {
+        rows[e.row].push_back({e.col, 0.5 * e.v});
+        rows[e.col].push_back({e.row, 0.5 * e.v});
+    }
+    entries.clear();
+    entries.shrink_to_fit();
+    m.M = Csr{};
     m.M.n = m.n1;
     m.M.ptr.assign(m.n1 + 1, 0);
     std::vector<std::vector<std::pair<int32_t, double>>> merged(nf);
@@ -395,18 +430,18 @@ void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
         rows[i].shrink_to_fit();
     }
     for (int e = 0; e < m.n1; ++e) {
-        int i = fidx[e];
+        int i = h.fidx[e];
         m.M.ptr[e + 1] = m.M.ptr[e] + (i >= 0 ? int64_t(merged[i].size()) : 0);
     }
     m.M.col.resize(m.M.ptr[m.n1]);
     m.M.val.resize(m.M.ptr[m.n1]);
     for (int e = 0; e < m.n1; ++e) {
-        int i = fidx[e];
+        int i = h.fidx[e];
         if (i < 0) continue;
         int64_t o = m.M.ptr[e];
         for (auto &p : merged[i]) {
-            m.M.col[o] = fedge[p.first];
-            m.M.val[o] = s[i] * p.second * s[p.first];
+            m.M.col[o] = h.fedge[p.first];
+            m.M.val[o] = h.s[i] * p.second * h.s[p.first];
             ++o;
         }
     }
@@ -436,6 +471,260 @@ void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
     }
     m.spai_fro = std::sqrt(fro / std::max(1, nf));
     m.spai_max_col = mxc;
+}
+
+void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
+    ScaledHodge h;
+    scaled_hodge(m, h);
+    std::vector<SpaiEntry> entries;
+    spai_ls_columns(h, level, drop_tol, nullptr, n_threads, entries);
+    finish_spai(m, h, entries);
+}
+
+// ------------------------------------------------------- learned SPAI
+// Features of the pairs (k, j), j in J_k, of every free column k; the list
+// and its meaning are those of the network's training data.
+void spai_pair_features(const HostMesh &m, const ScaledHodge &h, int level, int n_threads, PairSet &ps) {
+    const int nf = int(h.fedge.size());
+    // per free edge: length, midpoint, unit direction in the meridian plane; row count and |row| sum of A^
+    std::vector<double> len(nf), mz(nf), mr(nf), dz(nf), dr(nf), rsum(nf);
+    std::vector<int32_t> nrow(nf);
+    for (int i = 0; i < nf; ++i) {
+        const auto &ev = m.ev[h.fedge[i]];
+        const double z0 = m.z[ev[0]], r0 = m.r[ev[0]], z1 = m.z[ev[1]], r1 = m.r[ev[1]];
+        const double L = std::sqrt((z1 - z0) * (z1 - z0) + (r1 - r0) * (r1 - r0));
+        len[i] = L; mz[i] = 0.5 * (z0 + z1); mr[i] = 0.5 * (r0 + r1);
+        dz[i] = (z1 - z0) / L; dr[i] = (r1 - r0) / L;
+        nrow[i] = int32_t(h.adj[i].size());
+        double a = 0;
+        for (auto &p : h.adj[i]) a += std::fabs(p.second);
+        rsum[i] = a;
+    }
+    // pass 1: pattern sizes
+    std::vector<int64_t> cnt(nf + 1, 0);
+    std::atomic<int> next{0};
+    parallel(n_threads, [&](int) {
+        PatternWork pw(nf);
+        for (;;) {
+            int k0 = next.fetch_add(256);
+            if (k0 >= nf) break;
+            for (int k = k0; k < std::min(nf, k0 + 256); ++k) {
+                pw.column(h, k, level);
+                cnt[k + 1] = int64_t(pw.J.size());
+            }
+        }
+    });
+    ps.ptr.assign(nf + 1, 0);
+    for (int k = 0; k < nf; ++k) ps.ptr[k + 1] = ps.ptr[k] + cnt[k + 1];
+    const int64_t np = ps.ptr[nf];
+    ps.j.assign(np, 0);
+    ps.X.assign(size_t(np) * kSpaiFeatures, 0.0f);
+    // pass 2: features; (A^^p)_jk by sparse products of column k
+    next = 0;
+    parallel(n_threads, [&](int) {
+        PatternWork pw(nf);
+        std::vector<double> v1(nf, 0.0), v2(nf, 0.0), v3(nf, 0.0);
+        std::vector<int32_t> t1, t2, t3;
+        std::vector<uint8_t> in1(nf, 0), in2(nf, 0), in3(nf, 0);
+        auto spread = [&](const std::vector<int32_t> &src, const std::vector<double> &vs, std::vector<int32_t> &dst,
+                          std::vector<double> &vd, std::vector<uint8_t> &in) {
+            for (int c : src)
+                for (auto &p : h.adj[c]) {
+                    if (!in[p.first]) { in[p.first] = 1; dst.push_back(p.first); }
+                    vd[p.first] += p.second * vs[c];
+                }
+        };
+        for (;;) {
+            int k0 = next.fetch_add(256);
+            if (k0 >= nf) break;
+            for (int k = k0; k < std::min(nf, k0 + 256); ++k) {
+                pw.column(h, k, level);
+                t1.clear(); t2.clear(); t3.clear();
+                for (auto &p : h.adj[k]) { v1[p.first] = p.second; in1[p.first] = 1; t1.push_back(p.first); }
+                spread(t1, v1, t2, v2, in2);
+                spread(t2, v2, t3, v3, in3);
+                int64_t o = ps.ptr[k];
+                for (int j : pw.J) {
+                    float *f = &ps.X[size_t(o) * kSpaiFeatures];
+                    const int d = pw.dist[j];
+                    if (d <= 3) f[d] = 1.0f;
+                    f[4] = float(v1[j]);
+                    f[5] = float(v2[j]);
+                    f[6] = float(v3[j]);
+                    f[7] = float(std::min(len[k], len[j]) / std::max(len[k], len[j]));
+                    const double ddz = mz[k] - mz[j], ddr = mr[k] - mr[j];
+                    f[8] = float(std::sqrt(ddz * ddz + ddr * ddr) / (len[k] + len[j]));
+                    f[9] = float(std::fabs(dz[k] * dz[j] + dr[k] * dr[j]));
+                    const double rmx = std::max(mr[k], mr[j]);
+                    f[10] = float(rmx > 0 ? std::min(mr[k], mr[j]) / rmx : 1.0);
+                    f[11] = float((len[k] + len[j]) / (mr[k] + mr[j] + len[k] + len[j]));
+                    f[12] = float(double(nrow[k] + nrow[j]) / 20.0);
+                    f[13] = float(std::fabs(double(nrow[k] - nrow[j])) / 10.0);
+                    f[14] = float(0.5 * (rsum[k] + rsum[j]) - 1.0);
+                    f[15] = float(double(d) / 3.0);
+                    ps.j[o] = j;
+                    ++o;
+                }
+                for (int c : t1) { v1[c] = 0.0; in1[c] = 0; }
+                for (int c : t2) { v2[c] = 0.0; in2[c] = 0; }
+                for (int c : t3) { v3[c] = 0.0; in3[c] = 0; }
+            }
+        }
+    });
+}
+
+// Learned SPAI: the predicted Jacobi-scaled column m_k on the level-L
+// pattern J_k is the starting point of `iters` conjugate-gradient steps on
+// the normal equations of min ||e_k - A^(:, J_k) m||_2 (CGNR), whose limit is
+// the plain SPAI's least-squares column; a column whose residual still
+// exceeds row_tol is replaced by the exact least-squares column.  Drop rule,
+// symmetric average and unscaling as for the plain SPAI.
+void learned_spai(HostMesh &m, const ScaledHodge &h, const PairSet &ps, const float *pred, int level, double drop_tol,
+                  int iters, double row_tol, int n_threads, LearnedSpaiStats &st) {
+    const int nf = int(h.fedge.size());
+    const int nt = std::max(1, n_threads);
+    std::vector<std::vector<SpaiEntry>> per_thread(nt);
+    std::vector<std::vector<int32_t>> fb_thread(nt);
+    std::vector<double> res0_t(nt, 0.0), res_t(nt, 0.0);
+    std::atomic<int> next{0};
+    parallel(n_threads, [&](int tid) {
+        // dense work vectors over free edges, with touched lists
+        std::vector<double> r(nf, 0.0), ap(nf, 0.0);
+        std::vector<uint8_t> inr(nf, 0), inap(nf, 0);
+        std::vector<int32_t> tr, tap;
+        std::vector<double> mv, g, pv;
+        for (;;) {
+            int k0 = next.fetch_add(128);
+            if (k0 >= nf) break;
+            for (int k = k0; k < std::min(nf, k0 + 128); ++k) {
+                const int64_t b = ps.ptr[k], e = ps.ptr[k + 1];
+                const int nc = int(e - b);
+                const int32_t *J = ps.j.data() + b;
+                mv.assign(nc, 0.0);
+                for (int c = 0; c < nc; ++c) mv[c] = double(pred[b + c]);
+                // r = e_k - A^ m
+                for (int q : tr) { r[q] = 0.0; inr[q] = 0; }
+                tr.clear();
+                for (int c = 0; c < nc; ++c)
+                    for (auto &p : h.adj[J[c]]) {
+                        if (!inr[p.first]) { inr[p.first] = 1; tr.push_back(p.first); }
+                        r[p.first] -= p.second * mv[c];
+                    }
+                if (!inr[k]) { inr[k] = 1; tr.push_back(k); }
+                r[k] += 1.0;
+                auto rnorm = [&]() {
+                    double s2 = 0;
+                    for (int q : tr) s2 += r[q] * r[q];
+                    return std::sqrt(s2);
+                };
+                res0_t[tid] += rnorm();
+                // g = (A^ r) on the pattern (A^ symmetric)
+                auto grad = [&](std::vector<double> &out) {
+                    out.assign(nc, 0.0);
+                    for (int c = 0; c < nc; ++c) {
+                        double v = 0;
+                        for (auto &p : h.adj[J[c]]) v += p.second * r[p.first];
+                        out[c] = v;
+                    }
+                };
+                grad(g);
+                pv = g;
+                double gg = 0;
+                for (double v : g) gg += v * v;
+                const double floor = 1e-26 * gg;   // the column has converged below this
+                for (int it = 0; it < iters && gg > floor; ++it) {
+                    for (int q : tap) { ap[q] = 0.0; inap[q] = 0; }
+                    tap.clear();
+                    for (int c = 0; c < nc; ++c) {
+                        if (pv[c] == 0.0) continue;
+                        for (auto &p : h.adj[J[c]]) {
+                            if (!inap[p.first]) { inap[p.first] = 1; tap.push_back(p.first); }
+                            ap[p.first] += p.second * pv[c];
+                        }
+                    }
+                    double den = 0;
+                    for (int q : tap) den += ap[q] * ap[q];
+                    if (!(den > 0)) break;
+                    const double alpha = gg / den;
+                    for (int c = 0; c < nc; ++c) mv[c] += alpha * pv[c];
+                    for (int q : tap) {            // r -= alpha A^ p (support of A^ p lies in that of r)
+                        if (!inr[q]) { inr[q] = 1; tr.push_back(q); }
+                        r[q] -= alpha * ap[q];
+                    }
+                    grad(g);
+                    double gn = 0;
+                    for (double v : g) gn += v * v;
+                    const double beta = gn / gg;
+                    for (int c = 0; c < nc; ++c) pv[c] = g[c] + beta * pv[c];
+                    gg = gn;
+                }
+                const double rn = rnorm();
+                if (!(rn <= row_tol)) {           // also catches a non-finite prediction
+                    fb_thread[tid].push_back(k);
+                    continue;
+                }
+                res_t[tid] += rn;
+                double mx = 0;
+                for (double v : mv) mx = std::max(mx, std::fabs(v));
+                for (int c = 0; c < nc; ++c)
+                    if (std::fabs(mv[c]) >= drop_tol * mx) per_thread[tid].push_back({J[c], k, mv[c]});
+            }
+        }
+    });
+    std::vector<int32_t> fb;
+    for (auto &v : fb_thread) fb.insert(fb.end(), v.begin(), v.end());
+    std::sort(fb.begin(), fb.end());
+    std::vector<SpaiEntry> entries;
+    for (auto &v : per_thread) entries.insert(entries.end(), v.begin(), v.end());
+    st.n_fallback = int64_t(fb.size());
+    double r0 = 0, r1 = 0;
+    for (double v : res0_t) r0 += v;
+    for (double v : res_t) r1 += v;
+    st.pred_resid_mean = nf ? r0 / nf : 0.0;
+    st.kept_resid_mean = (nf - st.n_fallback) > 0 ? r1 / double(nf - st.n_fallback) : 0.0;
+    if (!fb.empty()) spai_ls_columns(h, level, drop_tol, &fb, n_threads, entries);
+    finish_spai(m, h, entries);
+}
+
+// Source-free leapfrog in the D-form with the current M from a seeded random
+// D^0 (B^{-1/2} = 0): returns max_n |W^n - W^0| / W^0 of the discrete energy
+// W^n = 1/2 E^n . D^n + 1/2 B^{n+1/2} . H B^{n-1/2}, conserved by the
+// scheme when M is symmetric positive definite and dt is below the limit.
+double leapfrog_energy_drift(const HostMesh &m, double dt, int steps, uint64_t seed) {
+    std::vector<double> D(m.n1, 0.0), E(m.n1, 0.0), B(m.n2, 0.0), Bo(m.n2, 0.0);
+    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+    for (int e = 0; e < m.n1; ++e) {
+        x ^= x << 13; x ^= x >> 7; x ^= x << 17;           // xorshift64
+        D[e] = m.efree[e] ? double(x >> 11) * (1.0 / 9007199254740992.0) - 0.5 : 0.0;
+    }
+    // scale D so that E ~ 1 (keeps the energy O(1))
+    m.M.spmv(D.data(), E.data());
+    double w0 = -1, drift = 0;
+    for (int n = 0; n <= steps; ++n) {
+        // B^{n+1/2} = B^{n-1/2} - dt C E^n
+        for (int t = 0; t < m.n2; ++t) {
+            double c = 0;
+            for (int k = 0; k < 3; ++k) c += m.tsign[t][k] * E[m.tedge[t][k]];
+            Bo[t] = B[t];
+            B[t] -= dt * c;
+        }
+        double w = 0;
+        for (int e = 0; e < m.n1; ++e) w += 0.5 * E[e] * D[e];
+        for (int t = 0; t < m.n2; ++t) w += 0.5 * B[t] * m.H[t] * Bo[t];
+        if (!std::isfinite(w)) return INFINITY;
+        if (w0 < 0) w0 = w;
+        else drift = std::max(drift, std::fabs(w - w0) / w0);
+        // D^{n+1} = D^n + dt C^T H B^{n+1/2}; E^{n+1} = M D^{n+1}
+        for (int t = 0; t < m.n2; ++t) {
+            const double hb = dt * m.H[t] * B[t];
+            for (int k = 0; k < 3; ++k) {
+                const int e = m.tedge[t][k];
+                if (m.efree[e]) D[e] += m.tsign[t][k] * hb;
+            }
+        }
+        m.M.spmv(D.data(), E.data());
+    }
+    return w0 > 0 ? drift : INFINITY;
 }
 
 // y = K x with K = C^T diag(H) C restricted to free edges

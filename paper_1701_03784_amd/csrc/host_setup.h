@@ -70,11 +70,50 @@ struct HostMesh {
     std::vector<int32_t> gptr, gtri;
 };
 
+// Jacobi-scaled [*eps] over the free edges: A^ = S^-1/2 A S^-1/2.
+struct ScaledHodge {
+    std::vector<int32_t> fidx;     // internal edge -> free index (-1: conductor edge)
+    std::vector<int32_t> fedge;    // free index -> internal edge
+    std::vector<double> s;         // diag(A)^-1/2
+    std::vector<std::vector<std::pair<int32_t, double>>> adj;   // rows of A^ (free indices)
+};
+
+struct SpaiEntry {
+    int32_t row, col;
+    double v;
+};
+
+constexpr int kSpaiFeatures = 16;
+
+// Pairs (k, j), j in the level-L pattern of free column k (sorted), and
+// their network features X[pair][kSpaiFeatures].
+struct PairSet {
+    std::vector<int64_t> ptr;      // per free column
+    std::vector<int32_t> j;
+    std::vector<float> X;
+};
+
+struct LearnedSpaiStats {
+    int64_t n_fallback = 0;        // columns replaced by least squares
+    double pred_resid_mean = 0;    // mean ||e_k - A^ m_k|| of the network's columns
+    double kept_resid_mean = 0;    // same after the refinement, over the kept columns
+};
+
 // Builds topology, locality order and incidence.  seg: boundary segments.
 void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tris, const int32_t *tri,
                     int32_t n_seg, const int32_t *seg, const uint8_t *tag);
 void assemble_hodge(HostMesh &m);
 void build_spai(HostMesh &m, int level, double drop_tol, int n_threads);
+void scaled_hodge(const HostMesh &m, ScaledHodge &h);
+// least-squares columns (all free columns if cols is null), after the drop rule
+void spai_ls_columns(const ScaledHodge &h, int level, double drop_tol, const std::vector<int32_t> *cols, int n_threads,
+                     std::vector<SpaiEntry> &out);
+// symmetric average, unscaling into m.M, residual statistics
+void finish_spai(HostMesh &m, const ScaledHodge &h, std::vector<SpaiEntry> &entries);
+void spai_pair_features(const HostMesh &m, const ScaledHodge &h, int level, int n_threads, PairSet &ps);
+void learned_spai(HostMesh &m, const ScaledHodge &h, const PairSet &ps, const float *pred, int level, double drop_tol,
+                  int iters, double row_tol, int n_threads, LearnedSpaiStats &st);
+double leapfrog_energy_drift(const HostMesh &m, double dt, int steps, uint64_t seed);
 double cfl_dt(const HostMesh &m, int iters);
 // Solves M x = b on free edges (conjugate gradients, FP64); returns iterations.
 int cg_solve_M(const HostMesh &m, const double *b, double *x, double rtol, int max_iter);

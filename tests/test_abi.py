@@ -47,10 +47,52 @@ def test_enum_values_match_binding():
         assert val[v] == k
 
 
-def test_struct_sizes_match_header_layout():
+def _c_layout():
+    """sizeof/offsetof of the ABI structs as a C compiler lays them out."""
+    import subprocess
+    import tempfile
+    fields = {"axp_config": ["device", "hip_stream", "precision", "dt", "cfl_fraction", "spai_level", "spai_drop_tol",
+                             "sort_period", "diag_every", "max_walk", "use_graph", "alloc", "free", "alloc_user"],
+              "axp_info": ["n_nodes", "n_edges", "n_faces", "n_free_edges", "n_free_nodes", "spai_nnz",
+                           "spai_fro_residual", "spai_max_col_residual", "dt", "dt_cfl", "setup_seconds",
+                           "particle_capacity", "n_particles", "step", "precision", "n_species", "spai_mode",
+                           "spai_fallback_columns", "spai_pred_resid_mean", "spai_kept_resid_mean",
+                           "spai_energy_drift", "spai_seconds"],
+              "axp_diag": ["step", "n_live", "n_absorbed", "walk_overflow", "nan_count", "fixed_overflow",
+                           "dce_max_abs", "dce_max_rel", "gauss_max_drift", "gauss_max_abs", "gauss_scale", "W_E",
+                           "W_B", "W_K", "Q_total"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "probe.c"), os.path.join(d, "probe")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-o", exe, src], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    res = {}
+    for line in out.splitlines():
+        st, f, v = line.split()
+        res[(st, f)] = int(v)
+    return res, fields
+
+
+def test_struct_layout_matches_c_compiler():
     import ctypes as C
     import paper_1701_03784_amd.axpic as ax
-    # axp_config: 4 int + pointer, see include/axpic.h (natural alignment)
-    assert C.sizeof(ax.Config) == 96
-    assert C.sizeof(ax.Diag) == 7 * 8 + 8 * 8
-    assert C.sizeof(ax.Info) == 6 * 8 + 5 * 8 + 3 * 8 + 2 * 4
+    lay, fields = _c_layout()
+    for st, cls in (("axp_config", ax.Config), ("axp_info", ax.Info), ("axp_diag", ax.Diag)):
+        assert C.sizeof(cls) == lay[(st, "sizeof")], st
+        for f in fields[st]:
+            assert getattr(cls, f).offset == lay[(st, f)], (st, f)
+
+
+def test_spai_enum_values():
+    import paper_1701_03784_amd.axpic as ax
+    src = open(HEADER).read()
+    val = dict((k, int(v)) for k, v in re.findall(r"(AXP_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
+    assert val["AXP_SPAI_PLAIN"] == ax.SPAI_PLAIN
+    assert val["AXP_SPAI_LEARNED"] == ax.SPAI_LEARNED
+    assert val["AXP_SPAI_LEARNED_REJECTED"] == ax.SPAI_LEARNED_REJECTED
