@@ -202,12 +202,23 @@ axp_status axp_add_species(axp_ctx *ctx, double q, double m, int64_t weight, int
  * in the mesh (AXP_E_ARG if outside).  Enqueued on the stream. */
 axp_status axp_inject(axp_ctx *ctx, int32_t species, int64_t n, const double *zr, const double *u);
 
-/* Continuous injection from the AXP_BC_EMITTER boundary: per_step particles
- * of `species` per step, uniform per unit area on the emitting surface, with
- * momentum u_mean + u_spread * (uniform in [-1,1]^3) in the local frame where
- * u_z points into the domain for an emitter at a z-face.  The charge of each
- * injected particle is taken from the emitter nodes (charge conservation).
- * seed selects the counter-based random stream. */
+/* Continuous injection from the AXP_BC_EMITTER boundary (the emission of
+ * the diode and gun configurations, Sec. 4): at the start of every step,
+ * per_step macro-particles of `species` are placed on emitter edges,
+ * uniformly per unit area of the emitting surface of revolution (edge
+ * chosen with probability proportional to its length times its mean rho,
+ * position along it with density proportional to rho), in the face next to
+ * the edge.  Momentum [kg m/s per kg, i.e. gamma v]: u_mean + u_spread *
+ * (uniform in [-1, 1]^3), given in the edge frame (tangent tail -> head,
+ * phi, inward normal); for an emitter on a z = const wall, u_mean[2] is the
+ * momentum into the domain.  Each particle's charge is taken from the wall
+ * charge of the edge's two nodes in proportion to its barycentric
+ * coordinates, so the nodal charge, and the continuity equation, are
+ * unchanged by the emission.  Random numbers: draw d (0..4: edge, position,
+ * three momentum components) of particle i at step n is output
+ * c = 2^32 n + 8 i + d + 1 of the SplitMix64 generator seeded with `seed`
+ * (Steele, Lea and Flood 2014), as (out >> 11) * 2^-53.  per_step = 0
+ * switches the injector off.  Not available to batch members. */
 axp_status axp_set_injector(axp_ctx *ctx, int32_t species, int64_t per_step, const double u_mean[3],
                             double u_spread, uint64_t seed);
 

@@ -134,6 +134,7 @@ class OracleSim:
         self.pspecies = np.zeros(0, dtype=np.int64)
         self._tree = None
         self._Msolve = None
+        self._emit = None          # (Emitter, species, per_step, seed, u_mean, u_spread)
 
     # ---------------------------------------------------------------- fields
     def set_fields(self, E0, B_mhalf):
@@ -207,11 +208,36 @@ class OracleSim:
         return _OParticles(len(self.pz), _p(self.pz), _p(self.prho), _p(self.ptri), _p(self.pu),
                            _p(self.palive), _p(self.pspecies), _p(self.sp_qm), _p(self.sp_qw))
 
+    def set_injector(self, species, per_step, u_mean, u_spread, seed):
+        """Continuous emission at the start of every step (see oracle.inject)."""
+        from .inject import Emitter
+        if per_step == 0:
+            self._emit = None
+            return
+        self._emit = (Emitter(self.topo), int(species), int(per_step), int(seed),
+                      np.asarray(u_mean, dtype=np.float64), float(u_spread))
+
+    def _inject_step(self):
+        em, sp_, k, seed, um, us = self._emit
+        z, rho, face, u, ta, hb, wa = em.emit(self.n_step, k, seed, um, us)
+        q_ring = self.sp_qw[sp_] / (2.0 * np.pi)
+        np.subtract.at(self.Qres, ta, q_ring * wa)
+        np.subtract.at(self.Qres, hb, q_ring * (1.0 - wa))
+        self.pz = np.concatenate([self.pz, z])
+        self.prho = np.concatenate([self.prho, rho])
+        self.ptri = np.concatenate([self.ptri, face])
+        self.pu = np.concatenate([self.pu, u], axis=0)
+        self.palive = np.concatenate([self.palive, np.ones(k, dtype=np.int8)])
+        self.pspecies = np.concatenate([self.pspecies, np.full(k, sp_, dtype=np.int64)])
+
     # ------------------------------------------------------------------ step
     def step(self, n=1):
         lib = _load()
         P = self._parts()
         for _ in range(n):
+            if self._emit is not None:
+                self._inject_step()
+                P = self._parts()
             lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz,
                             _p(self.E), _p(self.B), _p(self.D), _p(self.J), _p(self.Qres),
                             _p(self._Bh), _p(self._rhs), _p(self.stats))

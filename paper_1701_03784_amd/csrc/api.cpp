@@ -54,8 +54,10 @@ struct axp_ctx {
     int64_t last_diag_step = -1;  // step at which Qprev was computed
     bool g0_set = false;
     int64_t n_live_host = 0;
-    // injector
+    // continuous injector
     bool inj_on = false;
+    InjParams inj{};
+    EmitEdge *inj_edges = nullptr;
     // per-phase timing
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;   // pending (phase, start, stop)
@@ -442,6 +444,11 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
     DevMesh &m = c->dm;
     DevState &s = c->ds;
+    if (c->inj_on) {
+        PhaseScope ps(c, AXP_PHASE_INJECT);
+        if (c->plain) launch_inject_plain(m, s, c->dp, c->inj_edges, c->inj, st);
+        else launch_inject(m, s, c->inj_edges, c->inj, st);
+    }
     if (c->plain) {
         { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass_plain(m, s, c->dp, c->pc, st); }
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(m, s, st); }
@@ -496,6 +503,10 @@ void launch_graph(axp_ctx *c, int W) {
 }
 
 void run_steps(axp_ctx *c, int n_steps) {
+    if (c->inj_on && n_steps > 0) {
+        const DevCounters h = read_counters(c);
+        grow_particles(c, int64_t(h.n_slots) + int64_t(n_steps) * c->inj.per_step);
+    }
     const int sp = c->cfg.sort_period;
     const int W = 2 * sp;
     for (int i = 0; i < n_steps;) {
@@ -853,9 +864,67 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
     });
 }
 
-axp_status axp_set_injector(axp_ctx *c, int32_t, int64_t, const double *, double, uint64_t) {
-    if (!c) return AXP_E_ARG;
-    return fail(c, AXP_E_STATE, "continuous injection is not available in this build");
+axp_status axp_set_injector(axp_ctx *c, int32_t species, int64_t per_step, const double *u_mean, double u_spread,
+                            uint64_t seed) {
+    if (!c || per_step < 0 || per_step > (int64_t(1) << 24) || (per_step > 0 && !u_mean) || !(u_spread >= 0))
+        return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        drop_graphs(c);
+        if (per_step == 0) { c->inj_on = false; return AXP_OK; }
+        if (species < 0 || species >= int(c->species.size())) throw ApiError{AXP_E_ARG, "unknown species"};
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(u_mean[k])) throw ApiError{AXP_E_ARG, "non-finite mean momentum"};
+        const HostMesh &m = c->hm;
+        std::vector<EmitEdge> ee;
+        double cum = 0;
+        for (int k = 0; k < m.n1; ++k) {            // canonical order
+            const int e = m.edge_int[k];
+            if (m.etag[e] != TAG_EMITTER) continue;
+            const int f = m.etri[e][0], side = m.eside[e][0];
+            const int ta = m.ev[e][0], hb = m.ev[e][1];
+            EmitEdge E{};
+            E.face = f;
+            E.ka = E.kb = -1;
+            for (int q = 0; q < 3; ++q) {
+                if (m.tv[f][q] == ta) E.ka = q;
+                if (m.tv[f][q] == hb) E.kb = q;
+            }
+            if (E.ka < 0 || E.kb < 0 || E.ka == side || E.kb == side) throw ApiError{AXP_E_MESH, "emitter edge topology"};
+            const int opp = 3 - E.ka - E.kb;
+            const double za = m.z[ta], ra = m.r[ta], zb = m.z[hb], rb = m.r[hb];
+            const double dz = zb - za, dr = rb - ra;
+            const double len = std::sqrt(dz * dz + dr * dr);
+            cum += len * (ra + rb) * 0.5;
+            E.cdf = cum;
+            E.ra = ra; E.rb = rb;
+            E.tz = dz / len; E.tr = dr / len;
+            // inward normal: towards the face's third node
+            double nz = -E.tr, nr = E.tz;
+            const double oz = m.z[m.tv[f][opp]] - za, orr = m.r[m.tv[f][opp]] - ra;
+            if (nz * oz + nr * orr < 0) { nz = -nz; nr = -nr; }
+            E.nz = nz; E.nr = nr;
+            E.na = ta; E.nb = hb;
+            ee.push_back(E);
+        }
+        if (ee.empty() || !(cum > 0)) throw ApiError{AXP_E_ARG, "no emitter edge off the axis (AXP_BC_EMITTER)"};
+        if (c->inj_edges) dfree(c, c->inj_edges);
+        c->inj_edges = upload(c, ee);
+        InjParams &p = c->inj;
+        p.seed = seed;
+        p.per_step = int32_t(per_step);
+        p.n_edges = int32_t(ee.size());
+        p.species = species;
+        p.kq = c->plain ? int32_t(c->pc.kq[species]) : c->ic.kq[species];
+        for (int k = 0; k < 3; ++k) p.um[k] = u_mean[k] / kC;
+        p.spread = u_spread / kC;
+        p.total = cum;
+        const unsigned long long st = (unsigned long long)c->step;
+        hcheck(hipMemcpyAsync(&c->ds.ctr->inj_step, &st, 8, hipMemcpyHostToDevice, c->stream), "injector step");
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        c->inj_on = true;
+        return AXP_OK;
+    });
 }
 
 axp_status axp_step(axp_ctx *c, int32_t n_steps) {
@@ -1213,6 +1282,7 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
         if (c->plain) return fail(c, AXP_E_ARG, "batches advance the mixed-precision step only");
         if (c->cfg.device != ctxs[0]->cfg.device) return fail(c, AXP_E_ARG, "batch members must share a device");
         if (c->species.empty()) return fail(c, AXP_E_STATE, "batch members need a species");
+        if (c->inj_on) return fail(c, AXP_E_ARG, "batch members cannot carry a continuous injector");
     }
     auto *b = new (std::nothrow) axp_batch();
     if (!b) return AXP_E_OOM;

@@ -62,7 +62,8 @@ struct DevCounters {
     unsigned long long walk_overflow;
     unsigned long long nan_count;
     unsigned long long fixed_overflow;
-    unsigned long long pad[3];
+    unsigned long long inj_step;      // step index of the next emission (random-stream counter)
+    unsigned long long pad[2];
 };
 
 struct DevDiag {
@@ -108,6 +109,24 @@ struct DevState {
     double *kin_part = nullptr;  // 1024 partial sums of the kinetic energy
 };
 
+// Emitter edge of the continuous injector (canonical edge order).
+struct EmitEdge {
+    double cdf;                // inclusive cumulative emission weight  l (rho_t + rho_h) / 2
+    double ra, rb;             // rho at tail and head
+    double tz, tr, nz, nr;     // unit tangent tail -> head and inward unit normal, (z, rho)
+    int32_t face, ka, kb;      // adjacent face and the local indices of tail and head in it
+    int32_t na, nb;            // node ids of tail and head
+    int32_t pad;
+};
+
+struct InjParams {
+    unsigned long long seed;
+    int32_t per_step, n_edges, species, kq;
+    double um[3];              // mean momentum / c in the (tangent, phi, inward normal) frame
+    double spread;             // half-width of the uniform spread, / c
+    double total;              // total emission weight
+};
+
 // FP64 step (one instance): constants, geometry and state that differ from
 // the mixed step.  B, Bprev, HBdt, D, g0, the sort scratch, counters and the
 // particle cell words are shared with DevMesh / DevState.
@@ -151,6 +170,9 @@ void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hi
 // n_fields payload arrays of `width` bytes (4 or 8) per particle, src[f] ->
 // dst[f].  counted: s.cnt already holds the face histogram.
 void launch_offset_cells(int32_t *cell, int64_t n, int32_t delta, hipStream_t st);
+// Continuous emission: appends per_step particles before the step's push and
+// takes their charge from the emitter nodes' wall charge.
+void launch_inject(const DevMesh &m, DevState &s, const EmitEdge *ee, const InjParams &p, hipStream_t st);
 void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width, int n_fields, void *const *src,
                          void *const *dst, hipStream_t st);
 
@@ -162,6 +184,8 @@ void launch_walk_plain(const DevMesh &m, DevState &s, const DevPlain &p, const P
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
 void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st);
 void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted, hipStream_t st);
+void launch_inject_plain(const DevMesh &m, DevState &s, const DevPlain &p, const EmitEdge *ee, const InjParams &ip,
+                         hipStream_t st);
 void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool have_prev_q,
                        bool first, hipStream_t st);
 

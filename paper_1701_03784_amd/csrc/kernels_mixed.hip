@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "inject.h"
 
 namespace axp {
 
@@ -979,6 +980,45 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
     }
     hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, st, s, s.cnt + n);
     s.cur = 1 - s.cur;
+}
+
+// ------------------------------------------------------------- emission
+// Appends particle n_slots + i at its emission point on an emitter edge (the
+// coordinate of the face's third node is 0) and takes its charge from the
+// tail and head nodes' wall charge in fixed point, so the nodal charge is
+// unchanged.
+__global__ __launch_bounds__(256) void k_inject(DevMesh m, DevState s, const EmitEdge *ee, InjParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.per_step) return;
+    const unsigned long long step = s.ctr->inj_step;
+    const long long q = (long long)s.ctr->n_slots + i;
+    const Emission em = sample_emission(ee, p, step, i);
+    const EmitEdge E = ee[em.e];
+    int La = (int)rint((1.0 - em.s) * (double)kS);
+    La = La < 0 ? 0 : (La > kS ? kS : La);
+    const int Lb = kS - La;
+    const int L0 = E.ka == 0 ? La : (E.kb == 0 ? Lb : 0);
+    const int L1 = E.ka == 1 ? La : (E.kb == 1 ? Lb : 0);
+    const int c = s.cur;
+    s.cell[c][q] = E.face | (p.species << kCellBits);
+    s.L0[c][q] = (uint32_t)L0;
+    s.L1[c][q] = (uint32_t)L1;
+    s.ur[c][q] = (float)em.ur;
+    s.up[c][q] = (float)em.up;
+    s.uz[c][q] = (float)em.uz;
+    atomicAdd((unsigned long long *)&s.Qres[E.na], (unsigned long long)(-(long long)La * p.kq));
+    atomicAdd((unsigned long long *)&s.Qres[E.nb], (unsigned long long)(-(long long)Lb * p.kq));
+}
+
+__global__ void k_inject_commit(DevState s, int per_step) {
+    s.ctr->n_slots += (unsigned long long)per_step;
+    s.ctr->inj_step += 1ull;
+}
+
+void launch_inject(const DevMesh &m, DevState &s, const EmitEdge *ee, const InjParams &p, hipStream_t st) {
+    if (p.per_step <= 0) return;
+    hipLaunchKernelGGL(k_inject, dim3(nblk(p.per_step, 256)), dim3(256), 0, st, m, s, ee, p);
+    hipLaunchKernelGGL(k_inject_commit, dim3(1), dim3(1), 0, st, s, p.per_step);
 }
 
 void launch_offset_cells(int32_t *cell, int64_t n, int32_t delta, hipStream_t st) {

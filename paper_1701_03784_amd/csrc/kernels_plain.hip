@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "inject.h"
 
 namespace axp {
 
@@ -427,6 +428,31 @@ __global__ __launch_bounds__(256) void k_energy_kin_final_d(DevState s, const do
     if (threadIdx.x == 0) s.diag->WK = v;
 }
 
+// emission: as the mixed step, with FP64 coordinates and wall charge
+__global__ __launch_bounds__(256) void k_inject_d(DevMesh m, DevState s, DevPlain pl, const EmitEdge *ee, InjParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.per_step) return;
+    const unsigned long long step = s.ctr->inj_step;
+    const long long q = (long long)s.ctr->n_slots + i;
+    const Emission em = sample_emission(ee, p, step, i);
+    const EmitEdge E = ee[em.e];
+    const double la = 1.0 - em.s, lb = em.s;
+    const int c = s.cur;
+    s.cell[c][q] = E.face | (p.species << kCellBits);
+    pl.l0[c][q] = E.ka == 0 ? la : (E.kb == 0 ? lb : 0.0);
+    pl.l1[c][q] = E.ka == 1 ? la : (E.kb == 1 ? lb : 0.0);
+    pl.ur[c][q] = em.ur;
+    pl.up[c][q] = em.up;
+    pl.uz[c][q] = em.uz;
+    unsafeAtomicAdd(&pl.Qres[E.na], -(double)p.kq * la);
+    unsafeAtomicAdd(&pl.Qres[E.nb], -(double)p.kq * lb);
+}
+
+__global__ void k_inject_commit_d(DevState s, int per_step) {
+    s.ctr->n_slots += (unsigned long long)per_step;
+    s.ctr->inj_step += 1ull;
+}
+
 inline unsigned nb_(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -460,6 +486,13 @@ void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted,
     void *const src[5] = {p.l0[a], p.l1[a], p.ur[a], p.up[a], p.uz[a]};
     void *const dst[5] = {p.l0[b], p.l1[b], p.ur[b], p.up[b], p.uz[b]};
     launch_sort_payload(m, s, counted, 8, 5, src, dst, st);
+}
+
+void launch_inject_plain(const DevMesh &m, DevState &s, const DevPlain &p, const EmitEdge *ee, const InjParams &ip,
+                         hipStream_t st) {
+    if (ip.per_step <= 0) return;
+    hipLaunchKernelGGL(k_inject_d, dim3(nb_(ip.per_step, 256)), dim3(256), 0, st, m, s, p, ee, ip);
+    hipLaunchKernelGGL(k_inject_commit_d, dim3(1), dim3(1), 0, st, s, ip.per_step);
 }
 
 void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool have_prev_q,
