@@ -245,8 +245,12 @@ axp_status axp_get_sources(axp_ctx *ctx, double *D, double *J_dt, double *Q);
  * order is the library's storage order (grouped by triangle). */
 axp_status axp_get_particles(axp_ctx *ctx, int64_t cap, int64_t *n, double *zr, double *u, int32_t *species);
 
-/* Checkpoint of the complete state to a file / restore into a context built
- * from the same mesh and configuration. */
+/* Checkpoint of the complete state (fields, wall charge, particles, species,
+ * B_z, injector, counters, step) to a file, and its restore into a context
+ * built from the same mesh, boundary, precision and time step that has no
+ * species yet (AXP_E_ARG on a mismatch).  A restored run continues exactly
+ * as the saved one would have (bit for bit in mixed precision).  The file
+ * layout is the library's own (native byte order). */
 axp_status axp_save(axp_ctx *ctx, const char *path);
 axp_status axp_load(axp_ctx *ctx, const char *path);
 

@@ -299,6 +299,12 @@ class Ctx:
     def set_timing(self, on=True):
         self._check(self.lib.axp_set_timing(self.h, 1 if on else 0))
 
+    def save(self, path):
+        self._check(self.lib.axp_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(self.lib.axp_load(self.h, str(path).encode()))
+
     def set_spai_model(self, net, row_tol=0.01, energy_drift_tol=1e-6, iters=3):
         """Learned SPAI for the next build (net: Mlp or None)."""
         self._spai_model = net

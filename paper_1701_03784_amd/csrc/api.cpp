@@ -1110,8 +1110,174 @@ axp_status axp_get_particles(axp_ctx *c, int64_t cap, int64_t *n, double *zr, do
     });
 }
 
-axp_status axp_save(axp_ctx *c, const char *) { return c ? fail(c, AXP_E_STATE, "checkpoints not available in this build") : AXP_E_ARG; }
-axp_status axp_load(axp_ctx *c, const char *) { return c ? fail(c, AXP_E_STATE, "checkpoints not available in this build") : AXP_E_ARG; }
+}  // extern "C"
+
+// ------------------------------------------------------------- checkpoints
+namespace {
+
+const char kCkptMagic[8] = {'A', 'X', 'P', 'C', 'K', 'P', 'T', '1'};
+
+// FNV-1a over the input mesh and boundary: a checkpoint is restored only
+// into a context built from the same inputs.
+uint64_t mesh_hash(const axp_ctx *c) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    };
+    mix(c->in_zr.data(), c->in_zr.size() * sizeof(double));
+    mix(c->in_tri.data(), c->in_tri.size() * sizeof(int32_t));
+    mix(c->in_seg.data(), c->in_seg.size() * sizeof(int32_t));
+    mix(c->in_tag.data(), c->in_tag.size());
+    return h;
+}
+
+struct CkptHeader {
+    char magic[8];
+    uint64_t mesh;
+    int32_t precision, n0, n1, n2;
+    double dt;
+    int64_t step, last_diag_step, n_slots;
+    int32_t g0_set, n_species, inj_on, pad;
+    double q_unit, bz;
+    DevCounters ctr;
+    InjParams inj;
+};
+
+struct Blob {
+    std::vector<char> bytes;
+    template <class T>
+    void dev(axp_ctx *c, const T *p, size_t n) {   // device array -> blob
+        const size_t o = bytes.size();
+        bytes.resize(o + n * sizeof(T));
+        if (n) hcheck(hipMemcpyAsync(bytes.data() + o, p, n * sizeof(T), hipMemcpyDeviceToHost, c->stream), "save");
+    }
+};
+
+template <class T>
+void restore(axp_ctx *c, FILE *f, T *p, size_t n) {
+    std::vector<T> tmp(n);
+    if (n && std::fread(tmp.data(), sizeof(T), n, f) != n) throw ApiError{AXP_E_ARG, "truncated checkpoint"};
+    if (n) hcheck(hipMemcpyAsync(p, tmp.data(), n * sizeof(T), hipMemcpyHostToDevice, c->stream), "load");
+    hcheck(hipStreamSynchronize(c->stream), "sync");
+}
+
+}  // namespace
+
+extern "C" {
+
+axp_status axp_save(axp_ctx *c, const char *path) {
+    if (!c || !path) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        const DevCounters h = read_counters(c);
+        CkptHeader H{};
+        std::memcpy(H.magic, kCkptMagic, 8);
+        H.mesh = mesh_hash(c);
+        H.precision = c->cfg.precision;
+        H.n0 = c->hm.n0; H.n1 = c->hm.n1; H.n2 = c->hm.n2;
+        H.dt = c->dt;
+        H.step = c->step;
+        H.last_diag_step = c->last_diag_step;
+        H.n_slots = int64_t(h.n_slots);
+        H.g0_set = c->g0_set;
+        H.n_species = int32_t(c->species.size());
+        H.inj_on = c->inj_on;
+        H.q_unit = c->q_unit;
+        H.bz = c->plain ? c->pc.bz : double(c->ic.bz);
+        H.ctr = h;
+        H.inj = c->inj;
+        const DevState &s = c->ds;
+        const size_t n0 = c->hm.n0, n1 = c->hm.n1, n2 = c->hm.n2, np = size_t(h.n_slots);
+        const int b = s.cur;
+        Blob blob;
+        blob.dev(c, s.B, n2); blob.dev(c, s.Bprev, n2); blob.dev(c, s.D, n1); blob.dev(c, s.g0, n0);
+        blob.dev(c, s.cell[b], np);
+        if (c->plain) {
+            const DevPlain &p = c->dp;
+            blob.dev(c, p.E, n1); blob.dev(c, p.Jfx, n1); blob.dev(c, p.Qres, n0); blob.dev(c, p.Qprev, n0);
+            blob.dev(c, p.l0[b], np); blob.dev(c, p.l1[b], np);
+            blob.dev(c, p.ur[b], np); blob.dev(c, p.up[b], np); blob.dev(c, p.uz[b], np);
+        } else {
+            blob.dev(c, s.E, n1); blob.dev(c, s.D32, n1); blob.dev(c, s.Jfx, n1);
+            blob.dev(c, s.Qres, n0); blob.dev(c, s.Qprev, n0);
+            blob.dev(c, s.L0[b], np); blob.dev(c, s.L1[b], np);
+            blob.dev(c, s.ur[b], np); blob.dev(c, s.up[b], np); blob.dev(c, s.uz[b], np);
+        }
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        FILE *f = std::fopen(path, "wb");
+        if (!f) throw ApiError{AXP_E_ARG, std::string("cannot open ") + path};
+        bool ok = std::fwrite(&H, sizeof(H), 1, f) == 1;
+        for (const auto &sp : c->species) ok = ok && std::fwrite(&sp, sizeof(sp), 1, f) == 1;
+        ok = ok && std::fwrite(blob.bytes.data(), 1, blob.bytes.size(), f) == blob.bytes.size();
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok) throw ApiError{AXP_E_ARG, std::string("write failed: ") + path};
+        return AXP_OK;
+    });
+}
+
+axp_status axp_load(axp_ctx *c, const char *path) {
+    if (!c || !path) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        FILE *f = std::fopen(path, "rb");
+        if (!f) throw ApiError{AXP_E_ARG, std::string("cannot open ") + path};
+        struct Closer { FILE *f; ~Closer() { std::fclose(f); } } closer{f};
+        CkptHeader H{};
+        if (std::fread(&H, sizeof(H), 1, f) != 1 || std::memcmp(H.magic, kCkptMagic, 8) != 0)
+            throw ApiError{AXP_E_ARG, "not a checkpoint"};
+        if (H.mesh != mesh_hash(c) || H.n0 != c->hm.n0 || H.n1 != c->hm.n1 || H.n2 != c->hm.n2)
+            throw ApiError{AXP_E_ARG, "checkpoint of another mesh"};
+        if (H.precision != c->cfg.precision || H.dt != c->dt)
+            throw ApiError{AXP_E_ARG, "checkpoint of another precision or time step"};
+        if (!c->species.empty()) throw ApiError{AXP_E_STATE, "load into a context without species"};
+        if (H.n_species < 0 || H.n_species > kMaxSpecies || H.n_slots < 0) throw ApiError{AXP_E_ARG, "corrupt checkpoint"};
+        std::vector<Species> sps(H.n_species);
+        for (auto &sp : sps)
+            if (std::fread(&sp, sizeof(sp), 1, f) != 1) throw ApiError{AXP_E_ARG, "truncated checkpoint"};
+        for (const auto &sp : sps) {
+            int32_t id = 0;
+            const axp_status st = axp_add_species(c, sp.q, sp.m, sp.w, &id);
+            if (st != AXP_OK) return st;
+        }
+        const axp_status st = axp_set_external_bz(c, H.bz);
+        if (st != AXP_OK) return st;
+        grow_particles(c, std::max<int64_t>(H.n_slots, 1));
+        DevState &s = c->ds;
+        const size_t n0 = H.n0, n1 = H.n1, n2 = H.n2, np = size_t(H.n_slots);
+        const int b = s.cur;
+        restore(c, f, s.B, n2); restore(c, f, s.Bprev, n2); restore(c, f, s.D, n1); restore(c, f, s.g0, n0);
+        restore(c, f, s.cell[b], np);
+        if (c->plain) {
+            DevPlain &p = c->dp;
+            restore(c, f, p.E, n1); restore(c, f, p.Jfx, n1); restore(c, f, p.Qres, n0); restore(c, f, p.Qprev, n0);
+            restore(c, f, p.l0[b], np); restore(c, f, p.l1[b], np);
+            restore(c, f, p.ur[b], np); restore(c, f, p.up[b], np); restore(c, f, p.uz[b], np);
+        } else {
+            restore(c, f, s.E, n1); restore(c, f, s.D32, n1); restore(c, f, s.Jfx, n1);
+            restore(c, f, s.Qres, n0); restore(c, f, s.Qprev, n0);
+            restore(c, f, s.L0[b], np); restore(c, f, s.L1[b], np);
+            restore(c, f, s.ur[b], np); restore(c, f, s.up[b], np); restore(c, f, s.uz[b], np);
+        }
+        hcheck(hipMemcpyAsync(s.ctr, &H.ctr, sizeof(DevCounters), hipMemcpyHostToDevice, c->stream), "counters");
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        c->step = H.step;
+        c->last_diag_step = H.last_diag_step;
+        c->g0_set = H.g0_set != 0;
+        c->n_live_host = H.n_slots;
+        if (H.inj_on) {
+            c->inj_on = false;
+            double um[3];
+            for (int k = 0; k < 3; ++k) um[k] = H.inj.um[k] * kC;
+            const axp_status si = axp_set_injector(c, H.inj.species, H.inj.per_step, um, H.inj.spread * kC, H.inj.seed);
+            if (si != AXP_OK) return si;
+            hcheck(hipMemcpyAsync(&s.ctr->inj_step, &H.ctr.inj_step, 8, hipMemcpyHostToDevice, c->stream), "counters");
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+        }
+        drop_graphs(c);
+        return AXP_OK;
+    });
+}
 
 axp_status axp_set_timing(axp_ctx *c, int32_t on) {
     if (!c) return AXP_E_ARG;
