@@ -31,14 +31,15 @@ def log(msg):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1701_03784_amd", "csrc", "kernels_mixed.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_bwo_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particles_bwo_traffic.txt")
 
 
 def particle_bytes(n_live, n_faces):
-    """Algorithmic bytes of one k_push launch: 24 B of particle state read and
-    written per particle (48 B), plus once per face the gather tile (32 B),
-    the geometry used by the push (rho of the nodes and the scaled barycentric
-    gradients, 32 B) and the three fixed-point side currents (24 B)."""
+    """Algorithmic bytes of one k_particles launch (gather, push, walk and
+    current): 24 B of particle state read and written per particle (48 B),
+    plus once per face the gather tile (32 B), the geometry used by the push
+    (rho of the nodes and the scaled barycentric gradients, 32 B) and the
+    three fixed-point side currents (24 B)."""
     return 48.0 * n_live + 88.0 * n_faces
 
 
@@ -48,7 +49,7 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per k_push launch from the committed counter summary, if it
+    """HBM bytes per k_particles launch from the committed counter summary, if it
     was taken on the current kernel source (else None)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -296,7 +297,7 @@ def main():
         "phase_us_per_step": {k: round(v[0] / args.steps * 1e3, 2) for k, v in tim.items() if v[1]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_push", "bytes_per_launch": pb,
+                     "kernel": "k_particles", "bytes_per_launch": pb,
                      "avg_launch_us": part_avg_s * 1e6,
                      "kernel_source_sha256_16": kernel_source_hash()},
         "cpu_baseline": cpu,

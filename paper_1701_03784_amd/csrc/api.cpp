@@ -213,12 +213,6 @@ void grow_particles(axp_ctx *c, int64_t need) {
         dfree(c, s.ur[b]); dfree(c, s.up[b]); dfree(c, s.uz[b]);
         s.cell[b] = cell; s.L0[b] = l0; s.L1[b] = l1; s.ur[b] = ur; s.up[b] = up; s.uz[b] = uz;
     }
-    dfree(c, s.mv_p); dfree(c, s.mv_c); dfree(c, s.mv_l0); dfree(c, s.mv_l1); dfree(c, s.mv_fz); dfree(c, s.mv_fr);
-    dfree(c, s.mv_n);
-    s.mv_n = zeros<int32_t>(c, cap / 1024 + 1);
-    s.mv_p = zeros<int32_t>(c, cap); s.mv_c = zeros<int32_t>(c, cap);
-    s.mv_l0 = zeros<int32_t>(c, cap); s.mv_l1 = zeros<int32_t>(c, cap);
-    s.mv_fz = zeros<float>(c, cap); s.mv_fr = zeros<float>(c, cap);
     s.capacity = cap;
 }
 
@@ -464,8 +458,7 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     const InstConst *k0 = single ? &c->ic : nullptr;
     { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(m, s, st); }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(m, s, st); }
-    { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_push(m, s, sort_now, k0, st); }
-    { PhaseScope ps(c, AXP_PHASE_WALK); launch_walk(m, s, c->cfg.max_walk, sort_now, k0, st); }
+    { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_particles(m, s, c->cfg.max_walk, sort_now, k0, st); }
     { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass(m, s, true, st); }
     { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv(m, s, st); }
     ++c->step;

@@ -97,10 +97,7 @@ struct DevState {
     float *ur[2] = {nullptr, nullptr}, *up[2] = {nullptr, nullptr}, *uz[2] = {nullptr, nullptr};
     int cur = 0;
     int64_t capacity = 0;
-    // mover list (particles leaving their face this step), capacity entries
-    int32_t *mv_p = nullptr, *mv_c = nullptr, *mv_l0 = nullptr, *mv_l1 = nullptr;
-    float *mv_fz = nullptr, *mv_fr = nullptr;
-    int32_t *mv_n = nullptr;    // movers per particle block (capacity / 1024 blocks)
+    int32_t *mv_n = nullptr;    // FP64 step: movers per particle block (capacity / 1024 blocks)
     // sort scratch
     int32_t *cnt = nullptr;     // n2 + 1
     int32_t *blk = nullptr;     // scan block sums
@@ -159,8 +156,8 @@ struct DevPlain {
 
 // ---- launchers (kernels_mixed.hip) ----
 void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
-void launch_push(const DevMesh &m, DevState &s, bool count, const InstConst *single, hipStream_t st);
-void launch_walk(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st);
+// gather, push and walk of every particle, with the charge-conserving current
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st);
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);

@@ -76,16 +76,16 @@ __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s) {
 }
 
 // -------------------------------------------------------------- particles
-// Two kernels per step:
-//   k_push   one pass over the particle array (4 consecutive particles per
-//            thread): gather, Boris, position update; a particle whose path
-//            ends in its own face deposits the single piece's current into the
-//            thread's register accumulator (consecutive particles share faces),
-//            which is reduced per face across the wave before one lane adds it
-//            to the face's fixed-point current; a particle that leaves its face
-//            is appended to the mover list.
-//   k_walk   grid-stride pass over the mover list: walk face by face, with the
-//            per-piece currents reduced per face across the wave at each piece.
+// One kernel, k_particles, over blocks of 1024 consecutive particles (4 per
+// thread).  Phase 1 (push): gather, Boris, position update; a particle whose
+// path ends in its own face deposits the single piece's current into the
+// thread's register accumulator (consecutive particles share faces), reduced
+// per face across the wave into the block's LDS window; a particle that
+// leaves its face is queued in LDS.  Phase 2 (walk): the block's threads walk
+// the queued particles face by face, each piece's current going into the same
+// window.  Phase 3: owners take their movers' final coordinates back, store
+// their four particles with vector stores, and the window is added to the
+// global face currents once.
 constexpr int kPPT = 4;          // particles per thread (consecutive in storage)
 constexpr int kWG = 256;
 
@@ -272,21 +272,25 @@ __device__ __forceinline__ void lam_change(const float4 g, float fz, float fr, i
     d2 = -d0 - d1;
 }
 
-constexpr int kChunk = kWG * kPPT;   // particles per k_push block = mover slots per block
+constexpr int kChunk = kWG * kPPT;   // particles per block
+
+// queued particle of the walk phase (LDS)
+struct Mover {
+    int cell, L0, L1;
+    float fz, fr;        // remaining meridian displacement
+};
 
 template <bool SINGLE>
-__global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_count, PushConst k0) {
+__global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int max_walk, int do_count, PushConst k0) {
     __shared__ int s_nmv;
+    __shared__ int s_base;
+    __shared__ unsigned long long s_jl[3 * kWin];
+    __shared__ int s_cl[kWin];
+    __shared__ Mover s_mv[kChunk];
     const int chunk = xcd_block(blockIdx.x, gridDim.x);
     const long long n = (long long)s.ctr->n_slots;
     const long long p0 = ((long long)chunk * kWG + threadIdx.x) * kPPT;
-    if ((long long)chunk * kChunk >= n) {                    // whole block past the end
-        if (threadIdx.x == 0) s.mv_n[chunk] = 0;
-        return;
-    }
-    __shared__ unsigned long long s_jl[3 * kWin];
-    __shared__ int s_cl[kWin];
-    __shared__ int s_base;
+    if ((long long)chunk * kChunk >= n) return;             // whole block past the end
     if (threadIdx.x == 0) {
         s_nmv = 0;
         const int c0 = s.cell[s.cur][(long long)chunk * kChunk];
@@ -321,13 +325,13 @@ __global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_coun
             else P[j] = {-1, 0u, 0u, 0.f, 0.f, 0.f};
         }
     }
+    // ---- phase 1: push
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
     int ct = -1, cc = 0;             // run-length count of the new faces (stayers only)
     bool mover[kPPT];
     float mfz[kPPT], mfr[kPPT];
-    // face data cached across the thread's particles (consecutive particles share faces)
-    int Tc = -1;
+    int Tc = -1;                     // face data cached across the thread's particles
     float4 cf0 = make_float4(0.f, 0.f, 0.f, 0.f), cf1 = cf0, cr4 = cf0, cg = cf0;
     int ic_key = -1;                 // cell word (face, species) the constants below belong to
     PushConst ic = k0;
@@ -377,28 +381,115 @@ __global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_coun
     }
     wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
     if (do_count) wave_count(w, s.cnt, ct, cc);
-    // append the movers to this block's region of the mover list (LDS counter)
+    // queue the movers in LDS (one LDS atomic per wave and particle slot)
     const int lane = threadIdx.x & 63;
-    const long long region = (long long)chunk * kChunk;
+    int slot[kPPT];
 #pragma unroll
     for (int j = 0; j < kPPT; ++j) {
+        slot[j] = -1;
         const unsigned long long mask = __ballot(mover[j]);
         if (mask == 0ull) continue;
         int base = 0;
         if (lane == __ffsll((long long)mask) - 1) base = atomicAdd(&s_nmv, __popcll(mask));
         base = __shfl(base, __ffsll((long long)mask) - 1, 64);
         if (mover[j]) {
-            const long long q = region + base + __popcll(mask & ((1ull << lane) - 1ull));
-            s.mv_p[q] = (int)(p0 + j);
-            s.mv_c[q] = P[j].cell;
-            s.mv_l0[q] = (int)P[j].L0;
-            s.mv_l1[q] = (int)P[j].L1;
-            s.mv_fz[q] = mfz[j];
-            s.mv_fr[q] = mfr[j];
+            const int q = base + __popcll(mask & ((1ull << lane) - 1ull));
+            slot[j] = q;
+            s_mv[q] = Mover{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) s.mv_n[chunk] = s_nmv;
+    // ---- phase 2: walk of the queued particles (any thread, any mover)
+    const int nmv = s_nmv;
+    for (int i = threadIdx.x; i < nmv; i += kWG) {
+        const Mover mv = s_mv[i];
+        int t = mv.cell & kCellMask;
+        const int sp = (mv.cell >> kCellBits) & 15;
+        const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
+        int L0 = mv.L0, L1 = mv.L1, L2 = kS - L0 - L1, entry = -1;
+        float fz = mv.fz, fr = mv.fr;
+        int newcell = -2;                   // -2: still walking
+        for (int seg = 0; newcell == -2; ++seg) {
+            long long c0 = 0, c1 = 0, c2 = 0;
+            const int tf = t;
+            int d0, d1, d2;
+            lam_change(m.gS[t], fz, fr, d0, d1, d2);
+            // never leave through the side just entered (rounding); slide along it instead
+            if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
+            if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
+            if (entry == 2 && d2 < 0) { d2 = 0; d1 = -d0; }
+            const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
+            if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
+                piece_current(L0, L1, L2, e0, e1, e2, kq, c0, c1, c2);
+                L0 = e0; L1 = e1; L2 = e2;
+                newcell = t | (sp << kCellBits);
+            } else {
+                // exit side: smallest Lambda_k / (-d_k) among the coordinates going negative
+                // (float comparison: any valid choice keeps the walk charge-conserving)
+                int kx = -1;
+                float best = 3.0e38f;
+                if (e0 < 0) { kx = 0; best = (float)L0 * __builtin_amdgcn_rcpf((float)(-d0)); }
+                if (e1 < 0) { const float v = (float)L1 * __builtin_amdgcn_rcpf((float)(-d1)); if (v < best) { kx = 1; best = v; } }
+                if (e2 < 0) { const float v = (float)L2 * __builtin_amdgcn_rcpf((float)(-d2)); if (v < best) { kx = 2; best = v; } }
+                const float sx = fminf(best, 1.0f);
+                // crossing point: Lambda_kx = 0, the other two keep their sum
+                const int ka = kx == 2 ? 0 : kx + 1;
+                const int kb = kx == 0 ? 2 : kx - 1;
+                const int La = sel3(ka, L0, L1, L2), da = sel3(ka, d0, d1, d2);
+                int xa = La + (int)__builtin_rintf(sx * (float)da);
+                xa = xa < 0 ? 0 : (xa > kS ? kS : xa);
+                const int xb = kS - xa;
+                const int x0 = ka == 0 ? xa : (kb == 0 ? xb : 0);
+                const int x1 = ka == 1 ? xa : (kb == 1 ? xb : 0);
+                const int x2 = ka == 2 ? xa : (kb == 2 ? xb : 0);
+                piece_current(L0, L1, L2, x0, x1, x2, kq, c0, c1, c2);
+                const float rem = 1.0f - sx;
+                fz *= rem;
+                fr *= rem;
+                const int4 nb = m.nbr[t];
+                const int nn = sel3(kx, nb.x, nb.y, nb.z);
+                if (nn < 0) {
+                    if (-nn == kTagAxis) {          // rho = 0 cannot be crossed: stay on it
+                        L0 = x0; L1 = x1; L2 = x2;
+                        newcell = t | (sp << kCellBits);
+                    } else {                        // absorbed; its charge stays on the wall nodes
+                        const int4 tn = m.tnodes[t];
+                        const int na = sel3(ka, tn.x, tn.y, tn.z), nbn = sel3(kb, tn.x, tn.y, tn.z);
+                        atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
+                        atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
+                        atomicAdd(&s.ctr->n_absorbed, 1ull);
+                        newcell = -1;
+                    }
+                } else {
+                    const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
+                    const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
+                    L0 = pa == 0 ? xa : (pb == 0 ? xb : 0);
+                    L1 = pa == 1 ? xa : (pb == 1 ? xb : 0);
+                    L2 = pa == 2 ? xa : (pb == 2 ? xb : 0);
+                    entry = q;
+                    t = nn;
+                    if (seg + 1 >= max_walk) {      // cut: the particle stops at the crossing
+                        atomicAdd(&s.ctr->walk_overflow, 1ull);
+                        newcell = t | (sp << kCellBits);
+                    }
+                }
+            }
+            win_add_j(w, s.Jloc, tf, c0, c1, c2);
+        }
+        s_mv[i].cell = newcell;
+        s_mv[i].L0 = L0;
+        s_mv[i].L1 = L1;
+        if (do_count && newcell >= 0) win_add_c(w, s.cnt, newcell & kCellMask, 1);
+    }
+    __syncthreads();
+    // ---- phase 3: movers' final coordinates back to their owners; stores; window flush
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j)
+        if (slot[j] >= 0) {
+            P[j].cell = s_mv[slot[j]].cell;
+            P[j].L0 = (uint32_t)s_mv[slot[j]].L0;
+            P[j].L1 = (uint32_t)s_mv[slot[j]].L1;
+        }
     win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
     if (full) {
         *reinterpret_cast<int4 *>(cell + p0) = make_int4(P[0].cell, P[1].cell, P[2].cell, P[3].cell);
@@ -417,127 +508,6 @@ __global__ __launch_bounds__(kWG) void k_push(DevMesh m, DevState s, int do_coun
             }
         }
     }
-}
-
-// Walk of the particles that leave their face: straight pieces face by
-// face, each piece's current deposited (reduced per face across the wave),
-// until the path ends inside a face, is absorbed by a conductor or open
-// boundary (its charge kept on the wall nodes), stops on the axis, or hits
-// the piece cap.  Writes the particle's new cell and coordinates.
-// Block b walks the movers k_push block b appended (same faces: locality).
-template <bool SINGLE>
-__global__ __launch_bounds__(kWG) void k_walk(DevMesh m, DevState s, int max_walk, int do_count, PushConst k0) {
-    __shared__ unsigned long long s_jl[3 * kWin];
-    __shared__ int s_cl[kWin];
-    const int b = blockIdx.x;
-    const int nmv = s.mv_n[b];
-    if (nmv == 0) return;
-    const long long region = (long long)b * kChunk;
-    Win w{s_jl, s_cl, (s.mv_c[region] & kCellMask) - kWinLead};
-    win_zero(w);
-    __syncthreads();
-    // uniform trip count across the block so the per-piece reductions see all lanes
-    const int rounds = (nmv + kWG - 1) / kWG;
-    const int c = s.cur;
-    for (int r = 0; r < rounds; ++r) {
-        const int ii = r * kWG + threadIdx.x;
-        const long long i = region + ii;
-        bool active = ii < nmv;
-        int t = 0, sp = 0, kq = 1, L0 = 0, L1 = 0, L2 = 0, entry = -1;
-        float fz = 0.f, fr = 0.f;
-        long long p = 0;
-        if (active) {
-            p = s.mv_p[i];
-            const int cw = s.mv_c[i];
-            t = cw & kCellMask;
-            sp = (cw >> kCellBits) & 15;
-            kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
-            L0 = s.mv_l0[i]; L1 = s.mv_l1[i]; L2 = kS - L0 - L1;
-            fz = s.mv_fz[i]; fr = s.mv_fr[i];
-        }
-        int newcell = -2;                   // -2: still walking
-        for (int seg = 0; active; ++seg) {
-            int dt_face = -1;
-            long long c0 = 0, c1 = 0, c2 = 0;
-            if (active) {
-                int d0, d1, d2;
-                lam_change(m.gS[t], fz, fr, d0, d1, d2);
-                // never leave through the side just entered (rounding); slide along it instead
-                if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
-                if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
-                if (entry == 2 && d2 < 0) { d2 = 0; d1 = -d0; }
-                const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
-                dt_face = t;
-                if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
-                    piece_current(L0, L1, L2, e0, e1, e2, kq, c0, c1, c2);
-                    L0 = e0; L1 = e1; L2 = e2;
-                    newcell = t | (sp << kCellBits);
-                    active = false;
-                } else {
-                    // exit side: smallest Lambda_k / (-d_k) among the coordinates going negative
-                    // (float comparison: any valid choice keeps the walk charge-conserving)
-                    int kx = -1;
-                    float best = 3.0e38f;
-                    if (e0 < 0) { kx = 0; best = (float)L0 * __builtin_amdgcn_rcpf((float)(-d0)); }
-                    if (e1 < 0) { const float v = (float)L1 * __builtin_amdgcn_rcpf((float)(-d1)); if (v < best) { kx = 1; best = v; } }
-                    if (e2 < 0) { const float v = (float)L2 * __builtin_amdgcn_rcpf((float)(-d2)); if (v < best) { kx = 2; best = v; } }
-                    const float sx = fminf(best, 1.0f);
-                    // crossing point: Lambda_kx = 0, the other two keep their sum
-                    const int ka = kx == 2 ? 0 : kx + 1;
-                    const int kb = kx == 0 ? 2 : kx - 1;
-                    const int La = sel3(ka, L0, L1, L2), da = sel3(ka, d0, d1, d2);
-                    int xa = La + (int)__builtin_rintf(sx * (float)da);
-                    xa = xa < 0 ? 0 : (xa > kS ? kS : xa);
-                    const int xb = kS - xa;
-                    const int x0 = ka == 0 ? xa : (kb == 0 ? xb : 0);
-                    const int x1 = ka == 1 ? xa : (kb == 1 ? xb : 0);
-                    const int x2 = ka == 2 ? xa : (kb == 2 ? xb : 0);
-                    piece_current(L0, L1, L2, x0, x1, x2, kq, c0, c1, c2);
-                    const float rem = 1.0f - sx;
-                    fz *= rem;
-                    fr *= rem;
-                    const int4 nb = m.nbr[t];
-                    const int nn = sel3(kx, nb.x, nb.y, nb.z);
-                    if (nn < 0) {
-                        if (-nn == kTagAxis) {          // rho = 0 cannot be crossed: stay on it
-                            L0 = x0; L1 = x1; L2 = x2;
-                            newcell = t | (sp << kCellBits);
-                        } else {                        // absorbed; its charge stays on the wall nodes
-                            const int4 tn = m.tnodes[t];
-                            const int na = sel3(ka, tn.x, tn.y, tn.z), nbn = sel3(kb, tn.x, tn.y, tn.z);
-                            atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
-                            atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
-                            atomicAdd(&s.ctr->n_absorbed, 1ull);
-                            newcell = -1;
-                        }
-                        active = false;
-                    } else {
-                        const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
-                        const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
-                        L0 = pa == 0 ? xa : (pb == 0 ? xb : 0);
-                        L1 = pa == 1 ? xa : (pb == 1 ? xb : 0);
-                        L2 = pa == 2 ? xa : (pb == 2 ? xb : 0);
-                        entry = q;
-                        t = nn;
-                        if (seg + 1 >= max_walk) {      // cut: the particle stops at the crossing
-                            atomicAdd(&s.ctr->walk_overflow, 1ull);
-                            newcell = t | (sp << kCellBits);
-                            active = false;
-                        }
-                    }
-                }
-            }
-            if (dt_face >= 0) win_add_j(w, s.Jloc, dt_face, c0, c1, c2);
-        }
-        if (ii < nmv) {
-            s.cell[c][p] = newcell;
-            s.L0[c][p] = (uint32_t)L0;
-            s.L1[c][p] = (uint32_t)L1;
-        }
-        if (do_count && ii < nmv && newcell >= 0) win_add_c(w, s.cnt, newcell & kCellMask, 1);
-    }
-    __syncthreads();
-    win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
 }
 
 // ------------------------------------------------------------------ edges
@@ -920,24 +890,16 @@ void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st) {
 // single: one instance with one species whose charge multiple is 1; its
 // constants travel as kernel arguments (scalar registers) instead of a
 // per-particle table lookup.
-void launch_push(const DevMesh &m, DevState &s, bool count, const InstConst *single, hipStream_t st) {
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nblk(s.capacity, kChunk));
     if (single) {
         const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1};
-        hipLaunchKernelGGL(k_push<true>, grid, dim3(kWG), 0, st, m, s, count ? 1 : 0, k0);
+        hipLaunchKernelGGL(k_particles<true>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
     } else {
         const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
-        hipLaunchKernelGGL(k_push<false>, grid, dim3(kWG), 0, st, m, s, count ? 1 : 0, k0);
+        hipLaunchKernelGGL(k_particles<false>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
     }
-}
-
-void launch_walk(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st) {
-    if (s.capacity == 0) return;
-    const dim3 grid(nblk(s.capacity, kChunk));
-    const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
-    if (single) hipLaunchKernelGGL(k_walk<true>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
-    else hipLaunchKernelGGL(k_walk<false>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
 }
 
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st) {
