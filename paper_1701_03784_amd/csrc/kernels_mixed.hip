@@ -144,41 +144,51 @@ __device__ __forceinline__ void win_add_c(const Win &w, int *cnt, int t, int v) 
     else atomicAdd(&cnt[t], v);
 }
 
-// Deposit every lane's (face t, 3 side currents): lanes holding the same face
-// are summed across the wave and one lane adds the total.  Lanes with t < 0
-// hold nothing.  All lanes of the wave must call this together.
-__device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0,
-                                             long long a1, long long a2) {
+// Deposit every lane's (face t, 3 side currents): a segmented inclusive scan
+// over runs of consecutive lanes holding the same face (lanes follow the
+// particle order, which is sorted by face), after which the last lane of
+// each run adds the run's total.  Cost is independent of how many faces the
+// wave holds.  Lanes with t < 0 hold nothing.  All lanes of the wave must
+// call this together.
+__device__ __forceinline__ int lane_run(int t) {
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        const unsigned long long pending = __ballot(t >= 0);
-        if (pending == 0ull) break;
-        const int leader = __ffsll((long long)pending) - 1;
-        const int t0 = __shfl(t, leader, 64);
-        const bool mine = (t == t0);
-        const long long s0 = wave_sum64(mine ? a0 : 0ll);
-        const long long s1 = wave_sum64(mine ? a1 : 0ll);
-        const long long s2 = wave_sum64(mine ? a2 : 0ll);
-        if (lane == leader) win_add_j(w, J, t0, s0, s1, s2);
-        if (mine) t = -1;
+    const int tp = __shfl_up(t, 1, 64);
+    const unsigned long long heads = __ballot(lane == 0 || tp != t);
+    return __popcll(heads & ((2ull << lane) - 1ull));       // 1-based index of the lane's run
+}
+
+__device__ __forceinline__ bool run_tail(int t) {
+    const int lane = threadIdx.x & 63;
+    const int tn = __shfl_down(t, 1, 64);
+    return lane == 63 || tn != t;
+}
+
+__device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0, long long a1,
+                                             long long a2) {
+    const int lane = threadIdx.x & 63;
+    const int run = lane_run(t);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ro = __shfl_up(run, off, 64);
+        const long long b0 = __shfl_up(a0, off, 64);
+        const long long b1 = __shfl_up(a1, off, 64);
+        const long long b2 = __shfl_up(a2, off, 64);
+        if (lane >= off && ro == run) { a0 += b0; a1 += b1; a2 += b2; }
     }
+    if (run_tail(t) && t >= 0) win_add_j(w, J, t, a0, a1, a2);
 }
 
 // Same for a count per face (histogram of the counting sort).
 __device__ __forceinline__ void wave_count(const Win &w, int *cnt, int t, int c) {
     const int lane = threadIdx.x & 63;
-    for (;;) {
-        const unsigned long long pending = __ballot(t >= 0);
-        if (pending == 0ull) break;
-        const int leader = __ffsll((long long)pending) - 1;
-        const int t0 = __shfl(t, leader, 64);
-        const bool mine = (t == t0);
-        int v = mine ? c : 0;
+    const int run = lane_run(t);
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == leader && v) win_add_c(w, cnt, t0, v);
-        if (mine) t = -1;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ro = __shfl_up(run, off, 64);
+        const int b = __shfl_up(c, off, 64);
+        if (lane >= off && ro == run) c += b;
     }
+    if (run_tail(t) && t >= 0 && c) win_add_c(w, cnt, t, c);
 }
 
 __device__ __forceinline__ void win_zero(const Win &w) {
