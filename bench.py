@@ -205,7 +205,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=8_000_000)
-    ap.add_argument("--sort-period", type=int, default=4)
+    ap.add_argument("--sort-period", type=int, default=0, help="0: chosen by the library's autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--plain-steps", type=int, default=20, help="timed steps of the FP64 leg (0: skip)")
@@ -221,7 +221,11 @@ def main():
 
     import paper_1701_03784_amd as axp
     axp.load_library()
-    c, m, info, desc = setup_bwo(args.particles, sort_period=args.sort_period)
+    c, m, info, desc = setup_bwo(args.particles, sort_period=max(1, args.sort_period))
+    sort_period = args.sort_period
+    if sort_period == 0:
+        sort_period = c.autotune(16)
+        log(f"autotuned sort period {sort_period} (steps so far {c.info()['step']})")
     c.step(args.warmup)
     c.sync()
     log(f"warmup {args.warmup} steps done")
@@ -290,7 +294,7 @@ def main():
         "dtype": "f32+i64",
         "data": "synthetic (seeded mesh, beam and fields)",
         "config": {"workload": desc, "faces": n2, "edges": n1, "particles": int(n_live),
-                   "precision": "mixed", "sort_period": args.sort_period},
+                   "precision": "mixed", "sort_period": sort_period},
         "field_dof_steps_per_s": (n1 + n2) * args.steps / el,
         "field_hbm_gbs": field_gbs,
         "phase_us_per_launch": per_phase,

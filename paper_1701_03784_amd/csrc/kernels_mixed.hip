@@ -419,11 +419,15 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
         int L0 = mv.L0, L1 = mv.L1, L2 = kS - L0 - L1, entry = -1;
         float fz = mv.fz, fr = mv.fr;
         int newcell = -2;                   // -2: still walking
+        // the face's gradients and neighbours are fetched together, so each
+        // piece waits for one memory latency, not two in a row
+        float4 g = m.gS[t];
+        int4 nb = m.nbr[t];
         for (int seg = 0; newcell == -2; ++seg) {
             long long c0 = 0, c1 = 0, c2 = 0;
             const int tf = t;
             int d0, d1, d2;
-            lam_change(m.gS[t], fz, fr, d0, d1, d2);
+            lam_change(g, fz, fr, d0, d1, d2);
             // never leave through the side just entered (rounding); slide along it instead
             if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
             if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
@@ -456,7 +460,6 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
                 const float rem = 1.0f - sx;
                 fz *= rem;
                 fr *= rem;
-                const int4 nb = m.nbr[t];
                 const int nn = sel3(kx, nb.x, nb.y, nb.z);
                 if (nn < 0) {
                     if (-nn == kTagAxis) {          // rho = 0 cannot be crossed: stay on it
@@ -481,6 +484,9 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
                     if (seg + 1 >= max_walk) {      // cut: the particle stops at the crossing
                         atomicAdd(&s.ctr->walk_overflow, 1ull);
                         newcell = t | (sp << kCellBits);
+                    } else {
+                        g = m.gS[t];
+                        nb = m.nbr[t];
                     }
                 }
             }
