@@ -564,7 +564,18 @@ __global__ __launch_bounds__(256) void k_spmv(DevMesh m, DevState s) {
     const float *v = m.m_val + beg + lane;
     const int32_t *c = m.m_col + beg + lane;
     float acc = 0.0f;
-    for (int j = 0; j < len; ++j) acc = fmaf(v[64 * j], s.D32[c[64 * j]], acc);
+    // four entries per trip, their loads issued before the gathers that depend on them
+    int j = 0;
+    for (; j + 4 <= len; j += 4) {
+        const int c0 = c[64 * j], c1 = c[64 * (j + 1)], c2 = c[64 * (j + 2)], c3 = c[64 * (j + 3)];
+        const float v0 = v[64 * j], v1 = v[64 * (j + 1)], v2 = v[64 * (j + 2)], v3 = v[64 * (j + 3)];
+        const float x0 = s.D32[c0], x1 = s.D32[c1], x2 = s.D32[c2], x3 = s.D32[c3];
+        acc = fmaf(v0, x0, acc);
+        acc = fmaf(v1, x1, acc);
+        acc = fmaf(v2, x2, acc);
+        acc = fmaf(v3, x3, acc);
+    }
+    for (; j < len; ++j) acc = fmaf(v[64 * j], s.D32[c[64 * j]], acc);
     s.E[i] = acc;
 }
 

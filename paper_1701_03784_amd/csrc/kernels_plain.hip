@@ -321,7 +321,17 @@ __global__ __launch_bounds__(256) void k_spmv_d(DevMesh m, DevState s, DevPlain 
     const double *v = p.m_val + beg + lane;
     const int32_t *cc = m.m_col + beg + lane;
     double acc = 0.0;
-    for (int j = 0; j < len; ++j) acc = fma(v[64 * j], s.D[cc[64 * j]], acc);
+    int j = 0;
+    for (; j + 4 <= len; j += 4) {
+        const int c0 = cc[64 * j], c1 = cc[64 * (j + 1)], c2 = cc[64 * (j + 2)], c3 = cc[64 * (j + 3)];
+        const double v0 = v[64 * j], v1 = v[64 * (j + 1)], v2 = v[64 * (j + 2)], v3 = v[64 * (j + 3)];
+        const double x0 = s.D[c0], x1 = s.D[c1], x2 = s.D[c2], x3 = s.D[c3];
+        acc = fma(v0, x0, acc);
+        acc = fma(v1, x1, acc);
+        acc = fma(v2, x2, acc);
+        acc = fma(v3, x3, acc);
+    }
+    for (; j < len; ++j) acc = fma(v[64 * j], s.D[cc[64 * j]], acc);
     p.E[i] = acc;
 }
 
