@@ -592,6 +592,22 @@ __global__ __launch_bounds__(256) void k_zero_i32(int32_t *p, int64_t n) {
 constexpr int kSortChunk = 1024;
 constexpr int kSortWin = 4096;
 
+// Runs of consecutive lanes with equal key (keys < 0 never merge: callers
+// give such lanes a unique negative key).  Returns the lane's offset in its
+// run; the run's last lane gets the run length in *len (others 0) and its
+// index in *tail.
+__device__ __forceinline__ int run_offset(int key, int *len, int *tail) {
+    const int lane = threadIdx.x & 63;
+    const int kp = __shfl_up(key, 1, 64);
+    const unsigned long long heads = __ballot(lane == 0 || kp != key);
+    const unsigned long long tails = (heads >> 1) | (1ull << 63);
+    const int start = 63 - __clzll(heads & ((2ull << lane) - 1ull));
+    const int end = __ffsll(tails & (~0ull << lane)) - 1;
+    *tail = end;
+    *len = lane == end ? end - start + 1 : 0;
+    return lane - start;
+}
+
 __global__ __launch_bounds__(256) void k_count(DevState s, int n2) {
     __shared__ int lcnt[kSortWin];
     __shared__ int s_base;
@@ -613,14 +629,9 @@ __global__ __launch_bounds__(256) void k_count(DevState s, int n2) {
         const int t = c & kCellMask, rel = t - base;
         const bool inwin = c >= 0 && rel >= 0 && rel < kSortWin;
         if (c >= 0 && !inwin) atomicAdd(&s.cnt[t], 1);
-        unsigned long long todo = __ballot(inwin);
-        while (todo) {
-            const int leader = __ffsll((long long)todo) - 1;
-            const int k0 = __shfl(t, leader, 64);
-            const unsigned long long same = __ballot(inwin && t == k0);
-            if (lane == leader) atomicAdd(&lcnt[rel], __popcll(same));
-            todo &= ~same;
-        }
+        int len, tail;
+        run_offset(inwin ? t : -2 - lane, &len, &tail);
+        if (inwin && len) atomicAdd(&lcnt[rel], len);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kSortWin; i += 256) {
@@ -714,7 +725,6 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, 
     __syncthreads();
     const int base = s_base;
     const int lane = threadIdx.x & 63;
-    const unsigned long long lt = (1ull << lane) - 1ull;
     int rank[K];
     // 1. rank of each particle among the block's particles of the same face:
     //    lanes of a wave holding the same face are ranked by ballot, and the
@@ -726,17 +736,13 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, 
         const bool inwin = c >= 0 && rel >= 0 && rel < kSortWin;
         rank[k] = -1;
         if (c >= 0 && !inwin) rank[k] = -2 - atomicAdd(&s.cnt[t], 1);   // outside the window: global slot
-        unsigned long long todo = __ballot(inwin);
-        while (todo) {
-            const int leader = __ffsll((long long)todo) - 1;
-            const int k0 = __shfl(t, leader, 64);
-            const unsigned long long same = __ballot(inwin && t == k0);
-            int off = 0;
-            if (lane == leader) off = atomicAdd(&lcnt[rel], __popcll(same));
-            off = __shfl(off, leader, 64);
-            if (inwin && t == k0) rank[k] = off + __popcll(same & lt);
-            todo &= ~same;
-        }
+        // one LDS reservation per run of lanes holding the same face
+        int len, tail;
+        const int off = run_offset(inwin ? t : -2 - lane, &len, &tail);
+        int base_run = 0;
+        if (inwin && len) base_run = atomicAdd(&lcnt[rel], len);
+        base_run = __shfl(base_run, tail, 64);
+        if (inwin) rank[k] = base_run + off;
     }
     __syncthreads();
     // 2. one global reservation per face of the window
