@@ -716,11 +716,16 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, 
         s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kSortWin / 8;
     }
     for (int i = threadIdx.x; i < kSortWin; i += 256) lcnt[i] = 0;
+    // the payload is loaded up front: its latency overlaps the ranking and
+    // the slot reservations, which do not depend on it
     int cv[K];
+    W v[NF][K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const long long p = pb + threadIdx.x + 256 * k;
         cv[k] = p < n ? cell_a[p] : -1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[f][k] = p < n ? pl.src[f][p] : W(0);
     }
     __syncthreads();
     const int base = s_base;
@@ -751,16 +756,12 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, 
         if (v != 0) lcnt[i] = atomicAdd(&s.cnt[t], v);
     }
     __syncthreads();
-    // 3. move: all loads first, then all stores
-    W v[NF][K];
+    // 3. move
     int q[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const long long p = pb + threadIdx.x + 256 * k;
         q[k] = -1;
         if (rank[k] == -1) continue;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) v[f][k] = pl.src[f][p];
         q[k] = rank[k] >= 0 ? lcnt[(cv[k] & kCellMask) - base] + rank[k] : -2 - rank[k];
     }
 #pragma unroll
