@@ -75,6 +75,7 @@ struct axp_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int graph_window = 0;
+
 };
 
 namespace {
@@ -216,11 +217,13 @@ void grow_particles(axp_ctx *c, int64_t need) {
     s.capacity = cap;
 }
 
+// Brackets one phase's launches with HIP events on stream st (eager steps).
 struct PhaseScope {
     axp_ctx *c;
     int phase;
+    hipStream_t st;
     hipEvent_t b = nullptr, e = nullptr;
-    PhaseScope(axp_ctx *ctx, int ph) : c(ctx), phase(ph) {
+    PhaseScope(axp_ctx *ctx, int ph, hipStream_t stream) : c(ctx), phase(ph), st(stream) {
         if (!c->timing) return;
         if (!c->ev_free.empty()) {
             b = c->ev_free.back().first;
@@ -230,11 +233,12 @@ struct PhaseScope {
             hcheck(hipEventCreate(&b), "event");
             hcheck(hipEventCreate(&e), "event");
         }
-        hcheck(hipEventRecord(b, c->stream), "event record");
+        hcheck(hipEventRecord(b, st), "event record");
     }
+    PhaseScope(axp_ctx *ctx, int ph) : PhaseScope(ctx, ph, ctx->stream) {}
     ~PhaseScope() {
         if (!c->timing || !b) return;
-        (void)hipEventRecord(e, c->stream);
+        (void)hipEventRecord(e, st);
         c->ev.push_back({phase, {b, e}});
     }
 };
@@ -439,30 +443,30 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     DevMesh &m = c->dm;
     DevState &s = c->ds;
     if (c->inj_on) {
-        PhaseScope ps(c, AXP_PHASE_INJECT);
+        PhaseScope ps(c, AXP_PHASE_INJECT, st);
         if (c->plain) launch_inject_plain(m, s, c->dp, c->inj_edges, c->inj, st);
         else launch_inject(m, s, c->inj_edges, c->inj, st);
     }
     if (c->plain) {
-        { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass_plain(m, s, c->dp, c->pc, st); }
-        if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(m, s, st); }
-        { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_push_plain(m, s, c->dp, c->pc, sort_now, st); }
-        { PhaseScope ps(c, AXP_PHASE_WALK); launch_walk_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, st); }
-        { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
-        { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv_plain(m, s, c->dp, st); }
+        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, st); }
+        if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
+        { PhaseScope ps(c, AXP_PHASE_PARTICLES, st); launch_push_plain(m, s, c->dp, c->pc, sort_now, st); }
+        { PhaseScope ps(c, AXP_PHASE_WALK, st); launch_walk_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, st); }
+        { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
+        { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv_plain(m, s, c->dp, st); }
         ++c->step;
-        if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_plain(m, s, c->dp, true, st); }
+        if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_plain(m, s, c->dp, true, st); }
         return;
     }
     const bool single = m.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
     const InstConst *k0 = single ? &c->ic : nullptr;
-    { PhaseScope ps(c, AXP_PHASE_FACE); launch_tri_pass(m, s, st); }
-    if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort_zero(m, s, st); }
-    { PhaseScope ps(c, AXP_PHASE_PARTICLES); launch_particles(m, s, c->cfg.max_walk, sort_now, k0, st); }
-    { PhaseScope ps(c, AXP_PHASE_EDGE); launch_edge_pass(m, s, true, st); }
-    { PhaseScope ps(c, AXP_PHASE_SPMV); launch_spmv(m, s, st); }
+    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, st); }
+    if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
+    { PhaseScope ps(c, AXP_PHASE_PARTICLES, st); launch_particles(m, s, c->cfg.max_walk, sort_now, k0, st); }
+    { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, st); }
+    { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv(m, s, st); }
     ++c->step;
-    if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT); launch_sort(m, s, true, st); }
+    if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort(m, s, true, st); }
 }
 
 void drop_graphs(axp_ctx *c) {
@@ -493,6 +497,7 @@ void launch_graph(axp_ctx *c, int W) {
     }
     hcheck(hipGraphLaunch(c->gexec[cur0], c->stream), "graph launch");
     c->step += W;
+
 }
 
 void run_steps(axp_ctx *c, int n_steps) {
@@ -504,6 +509,7 @@ void run_steps(axp_ctx *c, int n_steps) {
     const int W = 2 * sp;
     for (int i = 0; i < n_steps;) {
         const int de = c->cfg.diag_every;
+        // with timing on the steps run eagerly: HIP does not time event records inside graphs
         bool graph = c->cfg.use_graph && !c->plain && !c->timing && c->step % sp == 0 && n_steps - i >= W;
         if (graph && de > 0) {
             // a diagnostic falls inside the window: run eagerly

@@ -137,3 +137,4 @@ def test_batch_rejects_plain_members(axp):
     c.add_species(QE, ME, configs.CAVITY_WEIGHT)
     with pytest.raises(axp.AxpError):
         axp.Batch([c])
+
