@@ -372,6 +372,15 @@ def make_ctx(mesh, spai_model=None, spai_row_tol=0.01, spai_energy_tol=1e-6, spa
     return c
 
 
+DEFAULT_SPAI_MODEL = os.path.join(_HERE, "spai_mlp_l3.bin")
+
+
+def default_spai_model(device=0, stream=None):
+    """The network trained by train_spai.py on 48 seeded rippled-wall tubes
+    (level-3 pattern, 16 -> 64 -> 64 -> 1)."""
+    return Mlp.load(DEFAULT_SPAI_MODEL, device=device, stream=stream)
+
+
 def _dptr(t):
     """Device address of a contiguous torch tensor (device memory plumbing)."""
     return C.c_void_p(t.data_ptr())

@@ -206,3 +206,21 @@ def test_guard_rejects_a_broken_network(axp):
     assert cl.info()["spai_fallback_columns"] == cl.info()["n_free_edges"]
     Ml, Mp = cl.get_spai(), cp.get_spai()
     assert abs(Ml - Mp).max() <= 1e-12 * abs(Mp).max()
+
+
+def test_shipped_network_on_the_bwo_profile(axp):
+    # the network trained by train_spai.py (seeded tubes, seeds 1000-1047) on a
+    # tube it was not trained on: the construction keeps most of its columns
+    net = axp.default_spai_model()
+    assert net.info()["spai_level"] == 3
+    m = _tube(777, 0.35e-3, 0.0025, 0.0167)
+    cl = axp.make_ctx(m, spai_model=net, spai_row_tol=0.02, spai_iters=3)
+    cp = axp.make_ctx(m)
+    il, ip = cl.info(), cp.info()
+    print(f"[gpu] shipped network: {il['spai_fallback_columns']} of {il['n_free_edges']} columns fell back; "
+          f"start residual {il['spai_pred_resid_mean']:.4f}, refined {il['spai_kept_resid_mean']:.4f}; "
+          f"fro learned {il['spai_fro_residual']:.4f} plain {ip['spai_fro_residual']:.4f}", flush=True)
+    assert il["spai_mode"] == axp.SPAI_LEARNED
+    assert il["spai_fallback_columns"] < 0.05 * il["n_free_edges"]
+    assert il["spai_pred_resid_mean"] < 0.03
+    assert il["spai_fro_residual"] < 1.5 * ip["spai_fro_residual"]
