@@ -290,6 +290,99 @@ struct Mover {
     float fz, fr;        // remaining meridian displacement
 };
 
+// Walks one particle that leaves its face: straight pieces face by face,
+// each piece's current into the block's window (or global memory), until
+// the path ends inside a face, is absorbed by a conductor or open boundary
+// edge (its charge kept on the wall nodes), stops on the axis, or hits the
+// piece cap.  mv holds the start (face, coordinates, remaining
+// displacement) and receives the final cell word and coordinates.
+template <bool SINGLE>
+__device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const PushConst &k0,
+                                           int max_walk, Mover &mv) {
+    int t = mv.cell & kCellMask;
+    const int sp = (mv.cell >> kCellBits) & 15;
+    const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
+    int L0 = mv.L0, L1 = mv.L1, L2 = kS - L0 - L1, entry = -1;
+    float fz = mv.fz, fr = mv.fr;
+    int newcell = -2;                   // -2: still walking
+    // the face's gradients and neighbours are fetched together, so each
+    // piece waits for one memory latency, not two in a row
+    float4 g = m.gS[t];
+    int4 nb = m.nbr[t];
+    for (int seg = 0; newcell == -2; ++seg) {
+        long long c0 = 0, c1 = 0, c2 = 0;
+        const int tf = t;
+        int d0, d1, d2;
+        lam_change(g, fz, fr, d0, d1, d2);
+        // never leave through the side just entered (rounding); slide along it instead
+        if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
+        if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
+        if (entry == 2 && d2 < 0) { d2 = 0; d1 = -d0; }
+        const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
+        if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
+            piece_current(L0, L1, L2, e0, e1, e2, kq, c0, c1, c2);
+            L0 = e0; L1 = e1; L2 = e2;
+            newcell = t | (sp << kCellBits);
+        } else {
+            // exit side: smallest Lambda_k / (-d_k) among the coordinates going negative
+            // (float comparison: any valid choice keeps the walk charge-conserving)
+            int kx = -1;
+            float best = 3.0e38f;
+            if (e0 < 0) { kx = 0; best = (float)L0 * __builtin_amdgcn_rcpf((float)(-d0)); }
+            if (e1 < 0) { const float v = (float)L1 * __builtin_amdgcn_rcpf((float)(-d1)); if (v < best) { kx = 1; best = v; } }
+            if (e2 < 0) { const float v = (float)L2 * __builtin_amdgcn_rcpf((float)(-d2)); if (v < best) { kx = 2; best = v; } }
+            const float sx = fminf(best, 1.0f);
+            // crossing point: Lambda_kx = 0, the other two keep their sum
+            const int ka = kx == 2 ? 0 : kx + 1;
+            const int kb = kx == 0 ? 2 : kx - 1;
+            const int La = sel3(ka, L0, L1, L2), da = sel3(ka, d0, d1, d2);
+            int xa = La + (int)__builtin_rintf(sx * (float)da);
+            xa = xa < 0 ? 0 : (xa > kS ? kS : xa);
+            const int xb = kS - xa;
+            const int x0 = ka == 0 ? xa : (kb == 0 ? xb : 0);
+            const int x1 = ka == 1 ? xa : (kb == 1 ? xb : 0);
+            const int x2 = ka == 2 ? xa : (kb == 2 ? xb : 0);
+            piece_current(L0, L1, L2, x0, x1, x2, kq, c0, c1, c2);
+            const float rem = 1.0f - sx;
+            fz *= rem;
+            fr *= rem;
+            const int nn = sel3(kx, nb.x, nb.y, nb.z);
+            if (nn < 0) {
+                if (-nn == kTagAxis) {          // rho = 0 cannot be crossed: stay on it
+                    L0 = x0; L1 = x1; L2 = x2;
+                    newcell = t | (sp << kCellBits);
+                } else {                        // absorbed; its charge stays on the wall nodes
+                    const int4 tn = m.tnodes[t];
+                    const int na = sel3(ka, tn.x, tn.y, tn.z), nbn = sel3(kb, tn.x, tn.y, tn.z);
+                    atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
+                    atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
+                    atomicAdd(&s.ctr->n_absorbed, 1ull);
+                    newcell = -1;
+                }
+            } else {
+                const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
+                const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
+                L0 = pa == 0 ? xa : (pb == 0 ? xb : 0);
+                L1 = pa == 1 ? xa : (pb == 1 ? xb : 0);
+                L2 = pa == 2 ? xa : (pb == 2 ? xb : 0);
+                entry = q;
+                t = nn;
+                if (seg + 1 >= max_walk) {      // cut: the particle stops at the crossing
+                    atomicAdd(&s.ctr->walk_overflow, 1ull);
+                    newcell = t | (sp << kCellBits);
+                } else {
+                    g = m.gS[t];
+                    nb = m.nbr[t];
+                }
+            }
+        }
+        win_add_j(w, s.Jloc, tf, c0, c1, c2);
+    }
+    mv.cell = newcell;
+    mv.L0 = L0;
+    mv.L1 = L1;
+}
+
 template <bool SINGLE>
 __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int max_walk, int do_count, PushConst k0) {
     __shared__ int s_nmv;
@@ -412,90 +505,10 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
     // ---- phase 2: walk of the queued particles (any thread, any mover)
     const int nmv = s_nmv;
     for (int i = threadIdx.x; i < nmv; i += kWG) {
-        const Mover mv = s_mv[i];
-        int t = mv.cell & kCellMask;
-        const int sp = (mv.cell >> kCellBits) & 15;
-        const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
-        int L0 = mv.L0, L1 = mv.L1, L2 = kS - L0 - L1, entry = -1;
-        float fz = mv.fz, fr = mv.fr;
-        int newcell = -2;                   // -2: still walking
-        // the face's gradients and neighbours are fetched together, so each
-        // piece waits for one memory latency, not two in a row
-        float4 g = m.gS[t];
-        int4 nb = m.nbr[t];
-        for (int seg = 0; newcell == -2; ++seg) {
-            long long c0 = 0, c1 = 0, c2 = 0;
-            const int tf = t;
-            int d0, d1, d2;
-            lam_change(g, fz, fr, d0, d1, d2);
-            // never leave through the side just entered (rounding); slide along it instead
-            if (entry == 0 && d0 < 0) { d0 = 0; d2 = -d1; }
-            if (entry == 1 && d1 < 0) { d1 = 0; d2 = -d0; }
-            if (entry == 2 && d2 < 0) { d2 = 0; d1 = -d0; }
-            const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
-            if (e0 >= 0 && e1 >= 0 && e2 >= 0) {
-                piece_current(L0, L1, L2, e0, e1, e2, kq, c0, c1, c2);
-                L0 = e0; L1 = e1; L2 = e2;
-                newcell = t | (sp << kCellBits);
-            } else {
-                // exit side: smallest Lambda_k / (-d_k) among the coordinates going negative
-                // (float comparison: any valid choice keeps the walk charge-conserving)
-                int kx = -1;
-                float best = 3.0e38f;
-                if (e0 < 0) { kx = 0; best = (float)L0 * __builtin_amdgcn_rcpf((float)(-d0)); }
-                if (e1 < 0) { const float v = (float)L1 * __builtin_amdgcn_rcpf((float)(-d1)); if (v < best) { kx = 1; best = v; } }
-                if (e2 < 0) { const float v = (float)L2 * __builtin_amdgcn_rcpf((float)(-d2)); if (v < best) { kx = 2; best = v; } }
-                const float sx = fminf(best, 1.0f);
-                // crossing point: Lambda_kx = 0, the other two keep their sum
-                const int ka = kx == 2 ? 0 : kx + 1;
-                const int kb = kx == 0 ? 2 : kx - 1;
-                const int La = sel3(ka, L0, L1, L2), da = sel3(ka, d0, d1, d2);
-                int xa = La + (int)__builtin_rintf(sx * (float)da);
-                xa = xa < 0 ? 0 : (xa > kS ? kS : xa);
-                const int xb = kS - xa;
-                const int x0 = ka == 0 ? xa : (kb == 0 ? xb : 0);
-                const int x1 = ka == 1 ? xa : (kb == 1 ? xb : 0);
-                const int x2 = ka == 2 ? xa : (kb == 2 ? xb : 0);
-                piece_current(L0, L1, L2, x0, x1, x2, kq, c0, c1, c2);
-                const float rem = 1.0f - sx;
-                fz *= rem;
-                fr *= rem;
-                const int nn = sel3(kx, nb.x, nb.y, nb.z);
-                if (nn < 0) {
-                    if (-nn == kTagAxis) {          // rho = 0 cannot be crossed: stay on it
-                        L0 = x0; L1 = x1; L2 = x2;
-                        newcell = t | (sp << kCellBits);
-                    } else {                        // absorbed; its charge stays on the wall nodes
-                        const int4 tn = m.tnodes[t];
-                        const int na = sel3(ka, tn.x, tn.y, tn.z), nbn = sel3(kb, tn.x, tn.y, tn.z);
-                        atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
-                        atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
-                        atomicAdd(&s.ctr->n_absorbed, 1ull);
-                        newcell = -1;
-                    }
-                } else {
-                    const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
-                    const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
-                    L0 = pa == 0 ? xa : (pb == 0 ? xb : 0);
-                    L1 = pa == 1 ? xa : (pb == 1 ? xb : 0);
-                    L2 = pa == 2 ? xa : (pb == 2 ? xb : 0);
-                    entry = q;
-                    t = nn;
-                    if (seg + 1 >= max_walk) {      // cut: the particle stops at the crossing
-                        atomicAdd(&s.ctr->walk_overflow, 1ull);
-                        newcell = t | (sp << kCellBits);
-                    } else {
-                        g = m.gS[t];
-                        nb = m.nbr[t];
-                    }
-                }
-            }
-            win_add_j(w, s.Jloc, tf, c0, c1, c2);
-        }
-        s_mv[i].cell = newcell;
-        s_mv[i].L0 = L0;
-        s_mv[i].L1 = L1;
-        if (do_count && newcell >= 0) win_add_c(w, s.cnt, newcell & kCellMask, 1);
+        Mover mv = s_mv[i];
+        walk_mover<SINGLE>(m, s, w, k0, max_walk, mv);
+        s_mv[i] = mv;
+        if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
     }
     __syncthreads();
     // ---- phase 3: movers' final coordinates back to their owners; stores; window flush
