@@ -102,11 +102,15 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None):
 
 
 def plain_leg(n_particles, steps, warmup):
-    """The same workload on the FP64 GPU step (no graph, one instance)."""
+    """The same workload on the FP64 GPU step: same kernels structure, sort
+    period autotuned the same way, steps replayed from graphs."""
     import paper_1701_03784_amd as axp
     c, m, info, _ = setup_bwo(n_particles, precision=axp.PREC_PLAIN_FP64)
+    sp = c.autotune(16)
+    log(f"fp64 step: autotuned sort period {sp}")
     c.step(warmup)
     c.sync()
+    steps = max(2 * sp, steps // (2 * sp) * (2 * sp))
     t0 = time.perf_counter()
     c.step(steps)
     c.sync()
@@ -114,7 +118,8 @@ def plain_leg(n_particles, steps, warmup):
     d = c.diag()
     c.close()
     return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
-            "steps": steps, "precision": "plain fp64", "particles": int(d["n_live"])}
+            "steps": steps, "precision": "plain fp64", "particles": int(d["n_live"]), "sort_period": sp,
+            "graphs": True}
 
 
 def batched_leg(n_variants, steps, per_face=25, seed_note=""):

@@ -188,12 +188,6 @@ void grow_particles(axp_ctx *c, int64_t need) {
             s.cell[b] = cell;
             for (int k = 0; k < 5; ++k) { dfree(c, *old[k]); *old[k] = f[k]; }
         }
-        dfree(c, p.mv_p); dfree(c, p.mv_c); dfree(c, p.mv_l0); dfree(c, p.mv_l1); dfree(c, p.mv_fz); dfree(c, p.mv_fr);
-        dfree(c, s.mv_n);
-        s.mv_n = zeros<int32_t>(c, cap / 1024 + 1);
-        p.mv_p = zeros<int32_t>(c, cap); p.mv_c = zeros<int32_t>(c, cap);
-        p.mv_l0 = zeros<double>(c, cap); p.mv_l1 = zeros<double>(c, cap);
-        p.mv_fz = zeros<double>(c, cap); p.mv_fr = zeros<double>(c, cap);
         s.capacity = cap;
         return;
     }
@@ -450,8 +444,10 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     if (c->plain) {
         { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, st); }
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
-        { PhaseScope ps(c, AXP_PHASE_PARTICLES, st); launch_push_plain(m, s, c->dp, c->pc, sort_now, st); }
-        { PhaseScope ps(c, AXP_PHASE_WALK, st); launch_walk_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, st); }
+        {
+            PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
+            launch_particles_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, st);
+        }
         { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
         { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv_plain(m, s, c->dp, st); }
         ++c->step;
@@ -510,7 +506,7 @@ void run_steps(axp_ctx *c, int n_steps) {
     for (int i = 0; i < n_steps;) {
         const int de = c->cfg.diag_every;
         // with timing on the steps run eagerly: HIP does not time event records inside graphs
-        bool graph = c->cfg.use_graph && !c->plain && !c->timing && c->step % sp == 0 && n_steps - i >= W;
+        bool graph = c->cfg.use_graph && !c->timing && c->step % sp == 0 && n_steps - i >= W;
         if (graph && de > 0) {
             // a diagnostic falls inside the window: run eagerly
             const int64_t next = (c->step / de + 1) * de;

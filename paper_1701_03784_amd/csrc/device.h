@@ -97,7 +97,6 @@ struct DevState {
     float *ur[2] = {nullptr, nullptr}, *up[2] = {nullptr, nullptr}, *uz[2] = {nullptr, nullptr};
     int cur = 0;
     int64_t capacity = 0;
-    int32_t *mv_n = nullptr;    // FP64 step: movers per particle block (capacity / 1024 blocks)
     // sort scratch
     int32_t *cnt = nullptr;     // n2 + 1
     int32_t *blk = nullptr;     // scan block sums
@@ -149,9 +148,6 @@ struct DevPlain {
     double *Q = nullptr, *Qprev = nullptr;
     double *l0[2] = {nullptr, nullptr}, *l1[2] = {nullptr, nullptr};
     double *ur[2] = {nullptr, nullptr}, *up[2] = {nullptr, nullptr}, *uz[2] = {nullptr, nullptr};
-    // mover list
-    int32_t *mv_p = nullptr, *mv_c = nullptr;
-    double *mv_l0 = nullptr, *mv_l1 = nullptr, *mv_fz = nullptr, *mv_fr = nullptr;
 };
 
 // ---- launchers (kernels_mixed.hip) ----
@@ -175,9 +171,8 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
 
 // ---- launchers (kernels_plain.hip) ----
 void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
-void launch_push_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool count, hipStream_t st);
-void launch_walk_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk, bool count,
-                       hipStream_t st);
+void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
+                            bool count, hipStream_t st);
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
 void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st);
 void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted, hipStream_t st);

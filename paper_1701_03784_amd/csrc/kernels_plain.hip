@@ -1,14 +1,13 @@
 // FP64 variant of the time step: the reference point of the mixed step.
-// Same kernels and data flow (face pass, push + walk with a mover list,
-// edge pass, sliced-ELL SpMV, counting sort by face), but every quantity is
-// FP64: barycentric positions, momenta, the gather tile, the SPAI values,
-// E, and the currents, which are summed with FP64 atomics (so their order,
-// and the last bits, vary from run to run).
+// Same kernels and data flow (face pass, particle kernel with an LDS walk
+// queue and current window, edge pass, sliced-ELL SpMV, counting sort by
+// face), but every quantity is FP64: barycentric positions, momenta, the
+// gather tile, the SPAI values, E, and the currents, which are summed with
+// FP64 atomics (so their order, and the last bits, vary from run to run).
 //
 //   k_tri_pass_d   eq. (full_d_dfl) and the Whitney gather tile (Sec. 3.2)
-//   k_push_d       gather, relativistic Boris (eqs. DNE, DLE), axisymmetric
-//                  position update; current of a path that stays in its face
-//   k_walk_d       walk of the particles that leave their face, eq. (current)
+//   k_particles_d  gather, relativistic Boris (eqs. DNE, DLE), axisymmetric
+//                  position update, walk with the current of eq. (current)
 //   k_edge_pass_d  D += dt C^T H B^{n+1/2} - dt J (eq. full_d_dal, D-form)
 //   k_spmv_d       E = M D
 #include <hip/hip_runtime.h>
@@ -22,7 +21,7 @@ namespace {
 
 constexpr int kTagAxisD = 2;
 constexpr int kWGd = 256;
-constexpr int kChunkD = 1024;          // particles per push block = mover slots per block (as the mixed step)
+constexpr int kChunkD = 1024;          // particles per block (as the mixed step)
 constexpr int kPPTd = kChunkD / kWGd;
 
 __device__ __forceinline__ double sel3d(int k, double a, double b, double c) { return k == 0 ? a : (k == 1 ? b : c); }
@@ -74,221 +73,356 @@ __device__ __forceinline__ void piece_d(double s0, double s1, double s2, double 
     c2 = kq * (s0 * e1 - s1 * e0);
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// ---------------------------------------------------------------- particles
+// k_particles_d: the structure of the mixed step's particle kernel in FP64.
+// Blocks of 1024 consecutive particles, 4 per thread.  Phase 1: gather,
+// Boris, position update; the current of a path that stays in its face is
+// folded per face by a segmented scan across the wave into the block's LDS
+// window (FP64 LDS atomics); a particle that leaves its face is queued in
+// LDS.  Phase 2: the block walks the queue.  Phase 3: owners store their
+// particles, and the window is added to the face currents with FP64 global
+// atomics (whose order, and so the last bits, vary from run to run).
+constexpr int kWinD = 256;
+constexpr int kWinLeadD = 64;
+
+typedef __attribute__((address_space(3))) double lds_double;
+
+struct WinD {
+    lds_double *jl;  // LDS, 3 * kWinD (typed as LDS so that its adds stay ds_add_f64)
+    int *cl;         // LDS, kWinD
+    int base;
+};
+
+__device__ __forceinline__ void lds_fadd(lds_double *a, double v) {
+    if (v != 0.0) __builtin_amdgcn_ds_atomic_fadd_f64(a, v);
 }
 
-__global__ __launch_bounds__(kWGd) void k_push_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int do_count) {
+__device__ __forceinline__ void win_add_j_d(const WinD &w, double *J, int t, double a0, double a1, double a2) {
+    const int rel = t - w.base;
+    if (rel >= 0 && rel < kWinD) {
+        lds_fadd(&w.jl[3 * rel], a0);
+        lds_fadd(&w.jl[3 * rel + 1], a1);
+        lds_fadd(&w.jl[3 * rel + 2], a2);
+    } else {
+        fadd(&J[3 * t], a0);
+        fadd(&J[3 * t + 1], a1);
+        fadd(&J[3 * t + 2], a2);
+    }
+}
+
+__device__ __forceinline__ void win_add_c_d(const WinD &w, int *cnt, int t, int v) {
+    const int rel = t - w.base;
+    if (rel >= 0 && rel < kWinD) atomicAdd(&w.cl[rel], v);
+    else atomicAdd(&cnt[t], v);
+}
+
+__device__ __forceinline__ int lane_run_d(int t) {
+    const int lane = threadIdx.x & 63;
+    const int tp = __shfl_up(t, 1, 64);
+    const unsigned long long heads = __ballot(lane == 0 || tp != t);
+    return __popcll(heads & ((2ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ bool run_tail_d(int t) {
+    const int lane = threadIdx.x & 63;
+    const int tn = __shfl_down(t, 1, 64);
+    return lane == 63 || tn != t;
+}
+
+// segmented scan over runs of lanes with the same face; the run's last lane deposits
+__device__ __forceinline__ void wave_deposit_d(const WinD &w, double *J, int t, double a0, double a1, double a2) {
+    const int lane = threadIdx.x & 63;
+    const int run = lane_run_d(t);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ro = __shfl_up(run, off, 64);
+        const double b0 = __shfl_up(a0, off, 64);
+        const double b1 = __shfl_up(a1, off, 64);
+        const double b2 = __shfl_up(a2, off, 64);
+        if (lane >= off && ro == run) { a0 += b0; a1 += b1; a2 += b2; }
+    }
+    if (run_tail_d(t) && t >= 0) win_add_j_d(w, J, t, a0, a1, a2);
+}
+
+__device__ __forceinline__ void wave_count_d(const WinD &w, int *cnt, int t, int c) {
+    const int lane = threadIdx.x & 63;
+    const int run = lane_run_d(t);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ro = __shfl_up(run, off, 64);
+        const int b = __shfl_up(c, off, 64);
+        if (lane >= off && ro == run) c += b;
+    }
+    if (run_tail_d(t) && t >= 0 && c) win_add_c_d(w, cnt, t, c);
+}
+
+struct MoverD {
+    int cell;
+    double l0, l1, fz, fr;
+};
+
+struct ParticleD {
+    int cell;
+    double l0, l1, ur, up, uz;
+};
+
+// gather, relativistic Boris with u normalised by c in (rho, phi, z), push in
+// the local Cartesian frame and rotate back: returns the meridian displacement
+__device__ __forceinline__ void push_d(const DevState &s, ParticleD &P, const PlainConst &k, int sp, const double4 f0,
+                                       const double4 f1, const double4 r4, double &fz, double &fr) {
+    const double l0 = P.l0, l1 = P.l1, l2 = 1.0 - l0 - l1;
+    const double Ez = l0 * f0.x + l1 * f0.z + l2 * f1.x;
+    const double Er = l0 * f0.y + l1 * f0.w + l2 * f1.y;
+    const double Bp = f1.z, Bz = k.bz;
+    const double qe = k.qe[sp], qb = k.qb[sp];
+    const double umr = P.ur + qe * Er, ump = P.up, umz = P.uz + qe * Ez;
+    const double igm = 1.0 / sqrt(1.0 + umr * umr + ump * ump + umz * umz);
+    const double tp = qb * Bp * igm, tz = qb * Bz * igm;
+    const double f = 2.0 / (1.0 + tp * tp + tz * tz);
+    const double sp_ = f * tp, sz = f * tz;
+    const double vr = umr + (ump * tz - umz * tp);
+    const double vp = ump - umr * tz;
+    const double vz = umz + umr * tp;
+    double ur = umr + (vp * sz - vz * sp_) + qe * Er;
+    double up = ump - vr * sz;
+    double uz = umz + vr * sp_ + qe * Ez;
+    if (!(ur * ur + up * up + uz * uz < 1.0e300)) {
+        atomicAdd(&s.ctr->nan_count, 1ull);
+        ur = up = uz = 0.0;
+    }
+    const double ig = k.cdt / sqrt(1.0 + ur * ur + up * up + uz * uz);
+    const double rho = l0 * r4.x + l1 * r4.y + l2 * r4.z;
+    const double dr = ur * ig, dp = up * ig;
+    fz = uz * ig;
+    const double X = rho + dr;
+    const double r1 = sqrt(X * X + dp * dp);
+    if (r1 > 0.0) {
+        const double cs = X / r1, sn = dp / r1;
+        const double nr = cs * ur + sn * up;
+        up = -sn * ur + cs * up;
+        ur = nr;
+    }
+    const double den = r1 + rho;
+    fr = den > 0.0 ? (2.0 * rho * dr + dr * dr + dp * dp) / den : 0.0;
+    P.ur = ur; P.up = up; P.uz = uz;
+}
+
+// walk of one particle that leaves its face (see the mixed step)
+__device__ __forceinline__ void walk_mover_d(const DevMesh &m, const DevState &s, const DevPlain &p, const WinD &w,
+                                             const PlainConst &k, int max_walk, MoverD &mv) {
+    int t = mv.cell & kCellMask;
+    const int sp = (mv.cell >> kCellBits) & 15;
+    const double kq = k.kq[sp];
+    double l0 = mv.l0, l1 = mv.l1, l2 = 1.0 - l0 - l1;
+    double fz = mv.fz, fr = mv.fr;
+    int entry = -1;
+    int newcell = -2;
+    double4 g = p.grad[t];
+    int4 nb = m.nbr[t];
+    for (int seg = 0; newcell == -2; ++seg) {
+        double d0 = g.x * fz + g.y * fr, d1 = g.z * fz + g.w * fr, d2 = -d0 - d1;
+        // never leave through the side just entered (rounding): slide along it
+        if (entry == 0 && d0 < 0.0) { d0 = 0.0; d2 = -d1; }
+        if (entry == 1 && d1 < 0.0) { d1 = 0.0; d2 = -d0; }
+        if (entry == 2 && d2 < 0.0) { d2 = 0.0; d1 = -d0; }
+        const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
+        double c0, c1, c2;
+        const int tf = t;
+        if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
+            piece_d(l0, l1, l2, e0, e1, e2, kq, c0, c1, c2);
+            l0 = e0; l1 = e1; l2 = e2;
+            newcell = t | (sp << kCellBits);
+            win_add_j_d(w, p.Jloc, tf, c0, c1, c2);
+            break;
+        }
+        // exit side: smallest lambda_k / (-d_k) among the coordinates going negative
+        int kx = -1;
+        double best = 3.0;
+        if (e0 < 0.0) { kx = 0; best = l0 / (-d0); }
+        if (e1 < 0.0) { const double v = l1 / (-d1); if (v < best) { kx = 1; best = v; } }
+        if (e2 < 0.0) { const double v = l2 / (-d2); if (v < best) { kx = 2; best = v; } }
+        if (kx < 0) {                               // non-finite displacement: stop here
+            atomicAdd(&s.ctr->nan_count, 1ull);
+            newcell = t | (sp << kCellBits);
+            break;
+        }
+        const double sx = fmin(fmax(best, 0.0), 1.0);
+        const int ka = kx == 2 ? 0 : kx + 1, kb = kx == 0 ? 2 : kx - 1;
+        double xa = sel3d(ka, l0, l1, l2) + sx * sel3d(ka, d0, d1, d2);
+        xa = fmin(fmax(xa, 0.0), 1.0);
+        const double xb = 1.0 - xa;
+        const double x0 = ka == 0 ? xa : (kb == 0 ? xb : 0.0);
+        const double x1 = ka == 1 ? xa : (kb == 1 ? xb : 0.0);
+        const double x2 = ka == 2 ? xa : (kb == 2 ? xb : 0.0);
+        piece_d(l0, l1, l2, x0, x1, x2, kq, c0, c1, c2);
+        win_add_j_d(w, p.Jloc, tf, c0, c1, c2);
+        fz *= (1.0 - sx);
+        fr *= (1.0 - sx);
+        const int nn = sel3i(kx, nb.x, nb.y, nb.z);
+        if (nn < 0) {
+            if (-nn == kTagAxisD) {                 // rho = 0 cannot be crossed: stay on it
+                l0 = x0; l1 = x1; l2 = x2;
+                newcell = t | (sp << kCellBits);
+            } else {                                // absorbed; its charge stays on the wall nodes
+                const int4 tn = m.tnodes[t];
+                fadd(&p.Qres[sel3i(ka, tn.x, tn.y, tn.z)], kq * xa);
+                fadd(&p.Qres[sel3i(kb, tn.x, tn.y, tn.z)], kq * xb);
+                atomicAdd(&s.ctr->n_absorbed, 1ull);
+                newcell = -1;
+            }
+            break;
+        }
+        const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
+        const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
+        l0 = pa == 0 ? xa : (pb == 0 ? xb : 0.0);
+        l1 = pa == 1 ? xa : (pb == 1 ? xb : 0.0);
+        l2 = pa == 2 ? xa : (pb == 2 ? xb : 0.0);
+        entry = q;
+        t = nn;
+        if (seg + 1 >= max_walk) {                  // cut: the particle stops at the crossing
+            atomicAdd(&s.ctr->walk_overflow, 1ull);
+            newcell = t | (sp << kCellBits);
+            break;
+        }
+        g = p.grad[t];
+        nb = m.nbr[t];
+    }
+    mv.cell = newcell;
+    mv.l0 = l0;
+    mv.l1 = l1;
+}
+
+__global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int max_walk,
+                                                      int do_count) {
     __shared__ int s_nmv;
+    __shared__ int s_base;
+    __shared__ double s_jl[3 * kWinD];
+    __shared__ int s_cl[kWinD];
+    __shared__ MoverD s_mv[kChunkD];
     const int chunk = blockIdx.x;
     const long long n = (long long)s.ctr->n_slots;
-    if ((long long)chunk * kChunkD >= n) {
-        if (threadIdx.x == 0) s.mv_n[chunk] = 0;
-        return;
+    const long long p0 = ((long long)chunk * kWGd + threadIdx.x) * kPPTd;
+    if ((long long)chunk * kChunkD >= n) return;
+    if (threadIdx.x == 0) {
+        s_nmv = 0;
+        const int c0 = s.cell[s.cur][(long long)chunk * kChunkD];
+        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kWinLeadD;
     }
-    if (threadIdx.x == 0) s_nmv = 0;
+    for (int i = threadIdx.x; i < 3 * kWinD; i += kWGd) s_jl[i] = 0.0;
+    for (int i = threadIdx.x; i < kWinD; i += kWGd) s_cl[i] = 0;
     __syncthreads();
+    const WinD w{(lds_double *)s_jl, s_cl, s_base};
     const int c = s.cur;
-    const int lane = threadIdx.x & 63;
-    const long long region = (long long)chunk * kChunkD;
+    int32_t *cell = s.cell[c];
+    double *l0a = p.l0[c], *l1a = p.l1[c], *ura = p.ur[c], *upa = p.up[c], *uza = p.uz[c];
+    ParticleD P[kPPTd];
+#pragma unroll
     for (int j = 0; j < kPPTd; ++j) {
-        const long long i = region + j * kWGd + threadIdx.x;     // consecutive lanes, consecutive particles
-        const int cw = i < n ? s.cell[c][i] : -1;
-        int T = -1;
-        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-        bool mover = false;
-        double l0 = 0.0, l1 = 0.0, fz = 0.0, fr = 0.0;
-        if (cw >= 0) {
-            T = cw & kCellMask;
-            const int sp = (cw >> kCellBits) & 15;
-            l0 = p.l0[c][i];
-            l1 = p.l1[c][i];
-            const double l2 = 1.0 - l0 - l1;
-            const double4 f0 = p.f0[T], f1 = p.f1[T], r4 = p.rho[T];
-            const double Ez = l0 * f0.x + l1 * f0.z + l2 * f1.x;
-            const double Er = l0 * f0.y + l1 * f0.w + l2 * f1.y;
-            const double Bp = f1.z, Bz = k.bz;
-            const double qe = k.qe[sp], qb = k.qb[sp];
-            // relativistic Boris with u normalised by c; basis (rho, phi, z)
-            const double umr = p.ur[c][i] + qe * Er, ump = p.up[c][i], umz = p.uz[c][i] + qe * Ez;
-            const double igm = 1.0 / sqrt(1.0 + umr * umr + ump * ump + umz * umz);
-            const double tp = qb * Bp * igm, tz = qb * Bz * igm;
-            const double f = 2.0 / (1.0 + tp * tp + tz * tz);
-            const double sp_ = f * tp, sz = f * tz;
-            const double vr = umr + (ump * tz - umz * tp);
-            const double vp = ump - umr * tz;
-            const double vz = umz + umr * tp;
-            double ur = umr + (vp * sz - vz * sp_) + qe * Er;
-            double up = ump - vr * sz;
-            double uz = umz + vr * sp_ + qe * Ez;
-            if (!(ur * ur + up * up + uz * uz < 1.0e300)) {
-                atomicAdd(&s.ctr->nan_count, 1ull);
-                ur = up = uz = 0.0;
-            }
-            // move in the local Cartesian frame, rotate back to the meridian plane
-            const double ig = k.cdt / sqrt(1.0 + ur * ur + up * up + uz * uz);
-            const double rho = l0 * r4.x + l1 * r4.y + l2 * r4.z;
-            const double dr = ur * ig, dp = up * ig;
-            fz = uz * ig;
-            const double X = rho + dr;
-            const double r1 = sqrt(X * X + dp * dp);
-            if (r1 > 0.0) {
-                const double cs = X / r1, sn = dp / r1;
-                const double nr = cs * ur + sn * up;
-                up = -sn * ur + cs * up;
-                ur = nr;
-            }
-            const double den = r1 + rho;
-            fr = den > 0.0 ? (2.0 * rho * dr + dr * dr + dp * dp) / den : 0.0;
-            p.ur[c][i] = ur;
-            p.up[c][i] = up;
-            p.uz[c][i] = uz;
-            const double4 g = p.grad[T];
-            const double d0 = g.x * fz + g.y * fr, d1 = g.z * fz + g.w * fr, d2 = -d0 - d1;
-            const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
-            if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
-                piece_d(l0, l1, l2, e0, e1, e2, k.kq[sp], c0, c1, c2);
-                p.l0[c][i] = e0;
-                p.l1[c][i] = e1;
-                if (do_count) atomicAdd(&s.cnt[T], 1);
-            } else {
-                mover = true;
-                T = -1;
-            }
+        const long long q = p0 + j;
+        if (q < n) P[j] = {cell[q], l0a[q], l1a[q], ura[q], upa[q], uza[q]};
+        else P[j] = {-1, 0.0, 0.0, 0.0, 0.0, 0.0};
+    }
+    // ---- phase 1: push
+    int acc_t = -1;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    int ct = -1, cc = 0;
+    bool mover[kPPTd];
+    double mfz[kPPTd], mfr[kPPTd];
+    int Tc = -1;
+    double4 cf0 = make_double4(0.0, 0.0, 0.0, 0.0), cf1 = cf0, cr4 = cf0, cg = cf0;
+#pragma unroll
+    for (int j = 0; j < kPPTd; ++j) {
+        mover[j] = false;
+        mfz[j] = mfr[j] = 0.0;
+        if (P[j].cell < 0) continue;
+        const int T = P[j].cell & kCellMask;
+        const int sp = (P[j].cell >> kCellBits) & 15;
+        if (T != Tc) {
+            Tc = T;
+            cf0 = p.f0[T]; cf1 = p.f1[T]; cr4 = p.rho[T]; cg = p.grad[T];
         }
-        // lanes holding the same face are summed across the wave, one atomic per face and side
-        int t = T;
-        for (;;) {
-            const unsigned long long pending = __ballot(t >= 0);
-            if (pending == 0ull) break;
-            const int leader = __ffsll((long long)pending) - 1;
-            const int t0 = __shfl(t, leader, 64);
-            const bool mine = (t == t0);
-            const double a0 = wave_sum_d(mine ? c0 : 0.0);
-            const double a1 = wave_sum_d(mine ? c1 : 0.0);
-            const double a2 = wave_sum_d(mine ? c2 : 0.0);
-            if (lane == leader) {
-                fadd(&p.Jloc[3 * t0], a0);
-                fadd(&p.Jloc[3 * t0 + 1], a1);
-                fadd(&p.Jloc[3 * t0 + 2], a2);
+        double fz, fr;
+        const double l0 = P[j].l0, l1 = P[j].l1, l2 = 1.0 - l0 - l1;
+        push_d(s, P[j], k, sp, cf0, cf1, cr4, fz, fr);
+        const double d0 = cg.x * fz + cg.y * fr, d1 = cg.z * fz + cg.w * fr, d2 = -d0 - d1;
+        const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
+        if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
+            double c0, c1, c2;
+            piece_d(l0, l1, l2, e0, e1, e2, k.kq[sp], c0, c1, c2);
+            if (T != acc_t) {
+                if (acc_t >= 0) win_add_j_d(w, p.Jloc, acc_t, a0, a1, a2);
+                acc_t = T; a0 = a1 = a2 = 0.0;
             }
-            if (mine) t = -1;
+            a0 += c0; a1 += c1; a2 += c2;
+            P[j].l0 = e0;
+            P[j].l1 = e1;
+            if (do_count) {
+                if (T == ct) ++cc;
+                else {
+                    if (ct >= 0) win_add_c_d(w, s.cnt, ct, cc);
+                    ct = T; cc = 1;
+                }
+            }
+        } else {
+            mover[j] = true;
+            mfz[j] = fz;
+            mfr[j] = fr;
         }
-        const unsigned long long mask = __ballot(mover);
-        if (mask != 0ull) {
-            const int first = __ffsll((long long)mask) - 1;
-            int base = 0;
-            if (lane == first) base = atomicAdd(&s_nmv, __popcll(mask));
-            base = __shfl(base, first, 64);
-            if (mover) {
-                const long long q = region + base + __popcll(mask & ((1ull << lane) - 1ull));
-                p.mv_p[q] = (int)i;
-                p.mv_c[q] = cw;
-                p.mv_l0[q] = l0;
-                p.mv_l1[q] = l1;
-                p.mv_fz[q] = fz;
-                p.mv_fr[q] = fr;
-            }
+    }
+    wave_deposit_d(w, p.Jloc, acc_t, a0, a1, a2);
+    if (do_count) wave_count_d(w, s.cnt, ct, cc);
+    const int lane = threadIdx.x & 63;
+    int slot[kPPTd];
+#pragma unroll
+    for (int j = 0; j < kPPTd; ++j) {
+        slot[j] = -1;
+        const unsigned long long mask = __ballot(mover[j]);
+        if (mask == 0ull) continue;
+        int base = 0;
+        if (lane == __ffsll((long long)mask) - 1) base = atomicAdd(&s_nmv, __popcll(mask));
+        base = __shfl(base, __ffsll((long long)mask) - 1, 64);
+        if (mover[j]) {
+            const int q = base + __popcll(mask & ((1ull << lane) - 1ull));
+            slot[j] = q;
+            s_mv[q] = MoverD{P[j].cell, P[j].l0, P[j].l1, mfz[j], mfr[j]};
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) s.mv_n[chunk] = s_nmv;
-}
-
-// Walk of the movers of push block b, face by face, with FP64 atomics for
-// each piece's current.
-__global__ __launch_bounds__(kWGd) void k_walk_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int max_walk,
-                                                 int do_count) {
-    const int b = blockIdx.x;
-    const int nmv = s.mv_n[b];
-    const int c = s.cur;
-    for (int ii = threadIdx.x; ii < nmv; ii += kWGd) {
-        const long long i = (long long)b * kChunkD + ii;
-        const long long pi = p.mv_p[i];
-        const int cw = p.mv_c[i];
-        int t = cw & kCellMask;
-        const int sp = (cw >> kCellBits) & 15;
-        const double kq = k.kq[sp];
-        double l0 = p.mv_l0[i], l1 = p.mv_l1[i], l2 = 1.0 - l0 - l1;
-        double fz = p.mv_fz[i], fr = p.mv_fr[i];
-        int entry = -1;
-        int newcell = -2;
-        for (int seg = 0; newcell == -2; ++seg) {
-            const double4 g = p.grad[t];
-            double d0 = g.x * fz + g.y * fr, d1 = g.z * fz + g.w * fr, d2 = -d0 - d1;
-            // never leave through the side just entered (rounding): slide along it
-            if (entry == 0 && d0 < 0.0) { d0 = 0.0; d2 = -d1; }
-            if (entry == 1 && d1 < 0.0) { d1 = 0.0; d2 = -d0; }
-            if (entry == 2 && d2 < 0.0) { d2 = 0.0; d1 = -d0; }
-            const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
-            double c0, c1, c2;
-            if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
-                piece_d(l0, l1, l2, e0, e1, e2, kq, c0, c1, c2);
-                fadd(&p.Jloc[3 * t], c0);
-                fadd(&p.Jloc[3 * t + 1], c1);
-                fadd(&p.Jloc[3 * t + 2], c2);
-                l0 = e0; l1 = e1; l2 = e2;
-                newcell = t | (sp << kCellBits);
-                break;
-            }
-            // exit side: smallest lambda_k / (-d_k) among the coordinates going negative
-            int kx = -1;
-            double best = 3.0;
-            if (e0 < 0.0) { kx = 0; best = l0 / (-d0); }
-            if (e1 < 0.0) { const double v = l1 / (-d1); if (v < best) { kx = 1; best = v; } }
-            if (e2 < 0.0) { const double v = l2 / (-d2); if (v < best) { kx = 2; best = v; } }
-            if (kx < 0) {                               // non-finite displacement: stop here
-                atomicAdd(&s.ctr->nan_count, 1ull);
-                newcell = t | (sp << kCellBits);
-                break;
-            }
-            const double sx = fmin(fmax(best, 0.0), 1.0);
-            const int ka = kx == 2 ? 0 : kx + 1, kb = kx == 0 ? 2 : kx - 1;
-            double xa = sel3d(ka, l0, l1, l2) + sx * sel3d(ka, d0, d1, d2);
-            xa = fmin(fmax(xa, 0.0), 1.0);
-            const double xb = 1.0 - xa;
-            const double x0 = ka == 0 ? xa : (kb == 0 ? xb : 0.0);
-            const double x1 = ka == 1 ? xa : (kb == 1 ? xb : 0.0);
-            const double x2 = ka == 2 ? xa : (kb == 2 ? xb : 0.0);
-            piece_d(l0, l1, l2, x0, x1, x2, kq, c0, c1, c2);
-            fadd(&p.Jloc[3 * t], c0);
-            fadd(&p.Jloc[3 * t + 1], c1);
-            fadd(&p.Jloc[3 * t + 2], c2);
-            fz *= (1.0 - sx);
-            fr *= (1.0 - sx);
-            const int4 nb = m.nbr[t];
-            const int nn = sel3i(kx, nb.x, nb.y, nb.z);
-            if (nn < 0) {
-                if (-nn == kTagAxisD) {                 // rho = 0 cannot be crossed: stay on it
-                    l0 = x0; l1 = x1; l2 = x2;
-                    newcell = t | (sp << kCellBits);
-                } else {                                // absorbed; its charge stays on the wall nodes
-                    const int4 tn = m.tnodes[t];
-                    fadd(&p.Qres[sel3i(ka, tn.x, tn.y, tn.z)], kq * xa);
-                    fadd(&p.Qres[sel3i(kb, tn.x, tn.y, tn.z)], kq * xb);
-                    atomicAdd(&s.ctr->n_absorbed, 1ull);
-                    newcell = -1;
-                }
-                break;
-            }
-            const unsigned map = ((unsigned)nb.w >> (4 * kx)) & 15u;
-            const int pa = map & 3, pb = map >> 2, q = 3 - pa - pb;
-            l0 = pa == 0 ? xa : (pb == 0 ? xb : 0.0);
-            l1 = pa == 1 ? xa : (pb == 1 ? xb : 0.0);
-            l2 = pa == 2 ? xa : (pb == 2 ? xb : 0.0);
-            entry = q;
-            t = nn;
-            if (seg + 1 >= max_walk) {                  // cut: the particle stops at the crossing
-                atomicAdd(&s.ctr->walk_overflow, 1ull);
-                newcell = t | (sp << kCellBits);
-            }
+    // ---- phase 2: walk of the queued particles
+    const int nmv = s_nmv;
+    for (int i = threadIdx.x; i < nmv; i += kWGd) {
+        MoverD mv = s_mv[i];
+        walk_mover_d(m, s, p, w, k, max_walk, mv);
+        s_mv[i] = mv;
+        if (do_count && mv.cell >= 0) win_add_c_d(w, s.cnt, mv.cell & kCellMask, 1);
+    }
+    __syncthreads();
+    // ---- phase 3: owners take their movers back; stores; window flush
+#pragma unroll
+    for (int j = 0; j < kPPTd; ++j)
+        if (slot[j] >= 0) {
+            P[j].cell = s_mv[slot[j]].cell;
+            P[j].l0 = s_mv[slot[j]].l0;
+            P[j].l1 = s_mv[slot[j]].l1;
         }
-        s.cell[c][pi] = newcell;
-        p.l0[c][pi] = l0;
-        p.l1[c][pi] = l1;
-        if (do_count && newcell >= 0) atomicAdd(&s.cnt[newcell & kCellMask], 1);
+    for (int i = threadIdx.x; i < 3 * kWinD; i += kWGd) {
+        const double v = s_jl[i];
+        const long long gi = 3ll * w.base + i;
+        if (v != 0.0 && gi >= 0 && gi < 3ll * m.n2) unsafeAtomicAdd(&p.Jloc[gi], v);
+    }
+    if (do_count)
+        for (int i = threadIdx.x; i < kWinD; i += kWGd) {
+            const int v = s_cl[i], t = w.base + i;
+            if (v != 0 && t >= 0 && t < m.n2) atomicAdd(&s.cnt[t], v);
+        }
+#pragma unroll
+    for (int j = 0; j < kPPTd; ++j) {
+        const long long q = p0 + j;
+        if (q < n) {
+            cell[q] = P[j].cell;
+            l0a[q] = P[j].l0; l1a[q] = P[j].l1;
+            ura[q] = P[j].ur; upa[q] = P[j].up; uza[q] = P[j].uz;
+        }
     }
 }
 
@@ -472,15 +606,11 @@ void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, con
     hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt);
 }
 
-void launch_push_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool count, hipStream_t st) {
+void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
+                            bool count, hipStream_t st) {
     if (s.capacity == 0) return;
-    hipLaunchKernelGGL(k_push_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k, count ? 1 : 0);
-}
-
-void launch_walk_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk, bool count,
-                       hipStream_t st) {
-    if (s.capacity == 0) return;
-    hipLaunchKernelGGL(k_walk_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k, max_walk, count ? 1 : 0);
+    hipLaunchKernelGGL(k_particles_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k, max_walk,
+                       count ? 1 : 0);
 }
 
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {

@@ -141,3 +141,30 @@ def test_plain_and_mixed_agree_on_energy(axp, cavity):
     for k in ("W_E", "W_B", "W_K"):
         assert b[k] == pytest.approx(a[k], rel=1e-4), k
     assert a["n_absorbed"] == b["n_absorbed"]
+
+
+def test_plain_graph_replay_matches_eager(axp, cavity):
+    """Steps replayed from graphs advance the FP64 state as the eager steps
+    do; only the order of the FP64 atomic sums differs, so the bound is FP64
+    rounding carried through 48 steps."""
+    m, _, E0, B0 = cavity
+    zr, u = configs.cavity_beam(4000, seed=5)
+    out = []
+    for g in (0, 1):
+        c = _ctx(axp, m, use_graph=g, sort_period=2)
+        c.set_fields(E0, B0)
+        sp = c.add_species(QE, ME, configs.CAVITY_WEIGHT)
+        c.inject(sp, zr, u)
+        c.step(48)
+        E, B = c.get_fields()
+        zr_g, u_g, _ = c.get_particles()
+        o = np.lexsort((u_g[:, 2], zr_g[:, 1], zr_g[:, 0]))
+        out.append((E, B, zr_g[o], u_g[o], c.diag()))
+        c.close()
+    (Ea, Ba, za, ua, da), (Eb, Bb, zb, ub, db) = out
+    assert da["step"] == db["step"] == 48
+    assert len(za) == len(zb)
+    assert _rel_l2(Eb, Ea) <= 1e-11
+    assert _rel_l2(Bb, Ba) <= 1e-11
+    assert np.abs(zb - za).max() <= 1e-13
+    assert np.abs(ub - ua).max() <= 1e-11 * np.abs(ua).max()
