@@ -74,7 +74,7 @@ def field_bytes(n_edges, n_faces, spai_nnz_padded):
         (8.0 * spai_nnz_padded + 8.0 * n_edges)
 
 
-def setup_bwo(n_particles, seed=3, sort_period=4, precision=None):
+def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1):
     import synth
     from synth import configs
     import paper_1701_03784_amd as axp
@@ -83,7 +83,7 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None):
     L = m.meta["length"]
     log(f"mesh: {m.n_nodes} nodes, {m.n_tris} faces ({time.perf_counter() - t0:.1f} s)")
     kw = {} if precision is None else {"precision": precision}
-    c = axp.make_ctx(m, sort_period=sort_period, **kw)
+    c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, **kw)
     info = c.info()
     log(f"built: {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s "
         f"(limit {info['dt_cfl']:.3e}), setup {info['setup_seconds']:.1f} s")
@@ -101,11 +101,12 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None):
     return c, m, info, desc
 
 
-def plain_leg(n_particles, steps, warmup):
-    """The same workload on the FP64 GPU step: same kernels structure, sort
-    period autotuned the same way, steps replayed from graphs."""
+def plain_leg(n_particles, steps, warmup, use_graph):
+    """The same workload on the FP64 GPU step: the same kernel structure in
+    FP64, one instance, sort period autotuned the same way; launched eagerly
+    (the reference point of the speedups) or replayed from graphs."""
     import paper_1701_03784_amd as axp
-    c, m, info, _ = setup_bwo(n_particles, precision=axp.PREC_PLAIN_FP64)
+    c, m, info, _ = setup_bwo(n_particles, precision=axp.PREC_PLAIN_FP64, use_graph=use_graph)
     sp = c.autotune(16)
     log(f"fp64 step: autotuned sort period {sp}")
     c.step(warmup)
@@ -119,7 +120,7 @@ def plain_leg(n_particles, steps, warmup):
     c.close()
     return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
             "steps": steps, "precision": "plain fp64", "particles": int(d["n_live"]), "sort_period": sp,
-            "graphs": True}
+            "graphs": bool(use_graph)}
 
 
 def batched_leg(n_variants, steps, per_face=25, seed_note=""):
@@ -277,11 +278,14 @@ def main():
         log(f"copy probe: {args.copy_probe_mib} MiB x3")
 
     c.close()
-    plain = batched = None
+    plain = plain_graph = batched = None
     if args.plain_steps > 0:
-        log("plain FP64 leg ...")
-        plain = plain_leg(args.particles, args.plain_steps, 4)
+        log("plain FP64 leg (eager) ...")
+        plain = plain_leg(args.particles, args.plain_steps, 4, use_graph=0)
         log(f"plain: {plain['value']:.3e} particle-steps/s ({plain['ms_per_step']:.3f} ms/step)")
+        log("plain FP64 leg (graphs) ...")
+        plain_graph = plain_leg(args.particles, args.plain_steps, 4, use_graph=1)
+        log(f"plain, graphs: {plain_graph['value']:.3e} particle-steps/s ({plain_graph['ms_per_step']:.3f} ms/step)")
     if args.batch_variants > 0:
         log("batched leg ...")
         batched = batched_leg(args.batch_variants, args.batch_steps)
@@ -322,9 +326,11 @@ def main():
                      "kernel_source_sha256_16": kernel_source_hash()},
         "cpu_baseline": cpu,
         "plain_fp64": plain,
+        "plain_fp64_graphs": plain_graph,
         "batched_mixed": batched,
         "speedup_mixed_vs_plain": (value / plain["value"]) if plain else None,
         "speedup_batched_mixed_vs_plain": (batched["value"] / plain["value"]) if (plain and batched) else None,
+        "speedup_mixed_vs_plain_graphs": (value / plain_graph["value"]) if plain_graph else None,
     }
     print(json.dumps(out), flush=True)
 

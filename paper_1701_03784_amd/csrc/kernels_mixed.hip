@@ -283,6 +283,11 @@ __device__ __forceinline__ void lam_change(const float4 g, float fz, float fr, i
 }
 
 constexpr int kChunk = kWG * kPPT;   // particles per block
+// LDS walk queue entries per block.  About a fifth of the particles leave
+// their face in a step at half the stability limit; a block with more than
+// kQCap of them has its owners walk the rest themselves.  A queue for the
+// whole chunk would take 20 KB of LDS and cost a resident block per CU.
+constexpr int kQCap = 512;
 
 // queued particle of the walk phase (LDS)
 struct Mover {
@@ -389,20 +394,11 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
     __shared__ int s_base;
     __shared__ unsigned long long s_jl[3 * kWin];
     __shared__ int s_cl[kWin];
-    __shared__ Mover s_mv[kChunk];
+    __shared__ Mover s_mv[kQCap];
     const int chunk = xcd_block(blockIdx.x, gridDim.x);
     const long long n = (long long)s.ctr->n_slots;
     const long long p0 = ((long long)chunk * kWG + threadIdx.x) * kPPT;
     if ((long long)chunk * kChunk >= n) return;             // whole block past the end
-    if (threadIdx.x == 0) {
-        s_nmv = 0;
-        const int c0 = s.cell[s.cur][(long long)chunk * kChunk];
-        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kWinLead;
-    }
-    Win w{s_jl, s_cl, 0};
-    win_zero(w);
-    __syncthreads();
-    w.base = s_base;
     const int c = s.cur;
     int32_t *cell = s.cell[c];
     uint32_t *L0a = s.L0[c], *L1a = s.L1[c];
@@ -428,6 +424,15 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
             else P[j] = {-1, 0u, 0u, 0.f, 0.f, 0.f};
         }
     }
+    // thread 0 holds the block's first particle: the window starts at its face
+    if (threadIdx.x == 0) {
+        s_nmv = 0;
+        s_base = (P[0].cell >= 0 ? (P[0].cell & kCellMask) : 0) - kWinLead;
+    }
+    Win w{s_jl, s_cl, 0};
+    win_zero(w);
+    __syncthreads();
+    w.base = s_base;
     // ---- phase 1: push
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
@@ -497,13 +502,26 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
         base = __shfl(base, __ffsll((long long)mask) - 1, 64);
         if (mover[j]) {
             const int q = base + __popcll(mask & ((1ull << lane) - 1ull));
-            slot[j] = q;
-            s_mv[q] = Mover{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
+            if (q < kQCap) {
+                slot[j] = q;
+                s_mv[q] = Mover{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
+            } else slot[j] = -2;
         }
     }
     __syncthreads();
-    // ---- phase 2: walk of the queued particles (any thread, any mover)
-    const int nmv = s_nmv;
+    // ---- phase 2: walk of the queued particles (any thread, any mover); movers
+    // that found the queue full are walked by their owners
+    const int nmv = min(s_nmv, kQCap);
+    if (s_nmv > kQCap) {
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j)
+            if (slot[j] == -2) {
+                Mover mv{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
+                walk_mover<SINGLE>(m, s, w, k0, max_walk, mv);
+                P[j].cell = mv.cell; P[j].L0 = (uint32_t)mv.L0; P[j].L1 = (uint32_t)mv.L1;
+                if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
+            }
+    }
     for (int i = threadIdx.x; i < nmv; i += kWG) {
         Mover mv = s_mv[i];
         walk_mover<SINGLE>(m, s, w, k0, max_walk, mv);

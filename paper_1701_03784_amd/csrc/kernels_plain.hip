@@ -156,6 +156,11 @@ __device__ __forceinline__ void wave_count_d(const WinD &w, int *cnt, int t, int
     if (run_tail_d(t) && t >= 0 && c) win_add_c_d(w, cnt, t, c);
 }
 
+// LDS walk queue entries per block (about a fifth of the particles leave
+// their face in a step at half the stability limit); a block with more
+// movers has its owners walk the rest
+constexpr int kQCapD = 512;
+
 struct MoverD {
     int cell;
     double l0, l1, fz, fr;
@@ -298,20 +303,11 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
     __shared__ int s_base;
     __shared__ double s_jl[3 * kWinD];
     __shared__ int s_cl[kWinD];
-    __shared__ MoverD s_mv[kChunkD];
+    __shared__ MoverD s_mv[kQCapD];
     const int chunk = blockIdx.x;
     const long long n = (long long)s.ctr->n_slots;
     const long long p0 = ((long long)chunk * kWGd + threadIdx.x) * kPPTd;
     if ((long long)chunk * kChunkD >= n) return;
-    if (threadIdx.x == 0) {
-        s_nmv = 0;
-        const int c0 = s.cell[s.cur][(long long)chunk * kChunkD];
-        s_base = (c0 >= 0 ? (c0 & kCellMask) : 0) - kWinLeadD;
-    }
-    for (int i = threadIdx.x; i < 3 * kWinD; i += kWGd) s_jl[i] = 0.0;
-    for (int i = threadIdx.x; i < kWinD; i += kWGd) s_cl[i] = 0;
-    __syncthreads();
-    const WinD w{(lds_double *)s_jl, s_cl, s_base};
     const int c = s.cur;
     int32_t *cell = s.cell[c];
     double *l0a = p.l0[c], *l1a = p.l1[c], *ura = p.ur[c], *upa = p.up[c], *uza = p.uz[c];
@@ -322,6 +318,15 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
         if (q < n) P[j] = {cell[q], l0a[q], l1a[q], ura[q], upa[q], uza[q]};
         else P[j] = {-1, 0.0, 0.0, 0.0, 0.0, 0.0};
     }
+    // thread 0 holds the block's first particle: the window starts at its face
+    if (threadIdx.x == 0) {
+        s_nmv = 0;
+        s_base = (P[0].cell >= 0 ? (P[0].cell & kCellMask) : 0) - kWinLeadD;
+    }
+    for (int i = threadIdx.x; i < 3 * kWinD; i += kWGd) s_jl[i] = 0.0;
+    for (int i = threadIdx.x; i < kWinD; i += kWGd) s_cl[i] = 0;
+    __syncthreads();
+    const WinD w{(lds_double *)s_jl, s_cl, s_base};
     // ---- phase 1: push
     int acc_t = -1;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -383,13 +388,26 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
         base = __shfl(base, __ffsll((long long)mask) - 1, 64);
         if (mover[j]) {
             const int q = base + __popcll(mask & ((1ull << lane) - 1ull));
-            slot[j] = q;
-            s_mv[q] = MoverD{P[j].cell, P[j].l0, P[j].l1, mfz[j], mfr[j]};
+            if (q < kQCapD) {
+                slot[j] = q;
+                s_mv[q] = MoverD{P[j].cell, P[j].l0, P[j].l1, mfz[j], mfr[j]};
+            } else slot[j] = -2;
         }
     }
     __syncthreads();
-    // ---- phase 2: walk of the queued particles
-    const int nmv = s_nmv;
+    // ---- phase 2: walk of the queued particles; movers that found the queue
+    // full are walked by their owners
+    const int nmv = min(s_nmv, kQCapD);
+    if (s_nmv > kQCapD) {
+#pragma unroll
+        for (int j = 0; j < kPPTd; ++j)
+            if (slot[j] == -2) {
+                MoverD mv{P[j].cell, P[j].l0, P[j].l1, mfz[j], mfr[j]};
+                walk_mover_d(m, s, p, w, k, max_walk, mv);
+                P[j].cell = mv.cell; P[j].l0 = mv.l0; P[j].l1 = mv.l1;
+                if (do_count && mv.cell >= 0) win_add_c_d(w, s.cnt, mv.cell & kCellMask, 1);
+            }
+    }
     for (int i = threadIdx.x; i < nmv; i += kWGd) {
         MoverD mv = s_mv[i];
         walk_mover_d(m, s, p, w, k, max_walk, mv);
