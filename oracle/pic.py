@@ -50,13 +50,14 @@ def _load():
     if _lib is None:
         _lib = C.CDLL(build_oracle())
         vp = C.c_void_p
-        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double] + [vp] * 8
+        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int] + [vp] * 8
         _lib.oracle_step.restype = None
         _lib.oracle_charge.argtypes = [vp, vp, vp, vp]
         _lib.oracle_sample.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
         _lib.oracle_walk_only.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, C.c_double, vp, vp, vp]
         _lib.oracle_walk_only.restype = C.c_int
         _lib.oracle_boris.argtypes = [vp, vp, vp, C.c_double]
+        _lib.oracle_vay.argtypes = [vp, vp, vp, C.c_double]
         _lib.oracle_move.argtypes = [C.c_double, C.c_double, vp, C.c_double, vp, vp]
     return _lib
 
@@ -91,6 +92,7 @@ class OracleSim:
         self.dt_cfl, self.lam_max = cfl_dt(self.topo, self.H, self.M)
         self.dt = float(dt) if dt is not None else cfl_fraction * self.dt_cfl
         self.bz = float(bz)
+        self.pusher = 0                    # 0 relativistic Boris, 1 Vay
         self.setup_seconds = time.perf_counter() - t0
         tp = self.topo
         n0, n1, n2 = tp.n0, tp.n1, tp.n2
@@ -238,7 +240,7 @@ class OracleSim:
             if self._emit is not None:
                 self._inject_step()
                 P = self._parts()
-            lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz,
+            lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz, int(self.pusher),
                             _p(self.E), _p(self.B), _p(self.D), _p(self.J), _p(self.Qres),
                             _p(self._Bh), _p(self._rhs), _p(self.stats))
             self.n_step += 1
@@ -317,6 +319,16 @@ def boris(u, E, B, k):
     E = np.ascontiguousarray(E, dtype=np.float64)
     B = np.ascontiguousarray(B, dtype=np.float64)
     lib.oracle_boris(_p(u), _p(E), _p(B), float(k))
+    return u
+
+
+def vay(u, E, B, k):
+    """Python handle on the oracle's Vay pusher (u is modified copy)."""
+    lib = _load()
+    u = np.ascontiguousarray(u, dtype=np.float64).copy()
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    lib.oracle_vay(_p(u), _p(E), _p(B), float(k))
     return u
 
 

@@ -8,7 +8,8 @@
  *   2. gather, Sec. 3.2:            E_p = sum_e E_e W1_e(r_p),
  *                                   B_p = sum_T (B^{n+1/2}+B^{n-1/2})_T/2 W2_T
  *      plus a static axial field B_z (beam focusing, Sec. 3.2);
- *   3. push, eqs. (DNE), (DLE):     relativistic Boris rotation;
+ *   3. push, eqs. (DNE), (DLE):     relativistic Boris rotation, or Vay's
+ *      pusher (the correction the paper cites for relativistic beams);
  *      axisymmetric position update: push in the local Cartesian frame
  *      (rho-hat, phi-hat, z-hat), then rotate back to the meridian plane;
  *   4. scatter, eq. (current):      J_e += (q/2pi/dt) int_path W1_e . dr,
@@ -154,6 +155,34 @@ void oracle_boris(double u[3], const double E[3], const double B[3], double k)
     for (int i = 0; i < 3; ++i) u[i] = um[i] + c2[i] + k * E[i];
 }
 
+/* Vay's pusher: u^{n-1/2} -> u^{n+1/2} for E, B at r^n, k = q dt / (2 m).
+ * It solves u^{n+1/2} - u^{n-1/2} = 2k (E + (v^{n+1/2} + v^{n-1/2})/2 x B)
+ * for u^{n+1/2} in closed form: first u' = u^{n-1/2} + 2k E + k v^{n-1/2} x B,
+ * then the remaining equation u^{n+1/2} = u' + k v^{n+1/2} x B, whose gamma
+ * follows from a quadratic in gamma^2 (Vay, Phys. Plasmas 15, 056701, 2008). */
+void oracle_vay(double u[3], const double E[3], const double B[3], double k)
+{
+    const double c2 = O_C * O_C;
+    double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / c2);
+    double v[3], vxb[3], up[3], tau[3];
+    for (int i = 0; i < 3; ++i) v[i] = u[i] / g;
+    cross3(v, B, vxb);
+    for (int i = 0; i < 3; ++i) up[i] = u[i] + 2.0 * k * E[i] + k * vxb[i];
+    for (int i = 0; i < 3; ++i) tau[i] = k * B[i];
+    double tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+    double ustar = (up[0] * tau[0] + up[1] * tau[1] + up[2] * tau[2]) / O_C;
+    double gp2 = 1.0 + (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]) / c2;
+    double sigma = gp2 - tau2;
+    double gn = sqrt(0.5 * (sigma + sqrt(sigma * sigma + 4.0 * (tau2 + ustar * ustar))));
+    double t[3], uxt[3];
+    for (int i = 0; i < 3; ++i) t[i] = tau[i] / gn;
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double udt = up[0] * t[0] + up[1] * t[1] + up[2] * t[2];
+    cross3(up, t, uxt);
+    double s = 1.0 / (1.0 + t2);
+    for (int i = 0; i < 3; ++i) u[i] = s * (up[i] + udt * t[i] + uxt[i]);
+}
+
 /* Move along rho-hat/phi-hat/z-hat by v dt, rotate (u_rho, u_phi) into the
  * frame of the new azimuth; returns the new (z, rho). */
 void oracle_move(double z, double rho, double u[3], double dt, double *z_new, double *rho_new)
@@ -239,8 +268,9 @@ static int walk(const omesh *m, oparticles *P, int64_t p, double ze, double re,
  * D: D^n -> D^{n+1}.  J (n1) receives J^{n+1/2}.  Qres (n0) accumulates
  * the charge of absorbed particles.  Bh (n2) and rhs (n1) are scratch.
  * stats: [0] pieces walked, [1] absorbed, [2] walk overflows.
+ * pusher: 0 relativistic Boris, 1 Vay.
  */
-void oracle_step(const omesh *m, oparticles *P, double dt, double bz,
+void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher,
                  double *E, double *B, double *D, double *J, double *Qres,
                  double *Bh, double *rhs, int64_t *stats)
 {
@@ -265,7 +295,8 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz,
         double Ev[3] = {e2[1], 0.0, e2[0]};          /* (E_rho, E_phi, E_z) */
         double Bv[3] = {0.0, bphi, bz};               /* (B_rho, B_phi, B_z) */
         double *u = P->u + 3 * p;
-        oracle_boris(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
+        if (pusher == 1) oracle_vay(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
+        else oracle_boris(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
         double ze, re;
         oracle_move(P->z[p], P->rho[p], u, dt, &ze, &re);
         double q_ring = P->sp_qw[sp] / O_TWO_PI;
