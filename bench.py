@@ -74,7 +74,7 @@ def field_bytes(n_edges, n_faces, spai_nnz_padded):
         (8.0 * spai_nnz_padded + 8.0 * n_edges)
 
 
-def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1):
+def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, pusher=0):
     import synth
     from synth import configs
     import paper_1701_03784_amd as axp
@@ -83,7 +83,7 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1):
     L = m.meta["length"]
     log(f"mesh: {m.n_nodes} nodes, {m.n_tris} faces ({time.perf_counter() - t0:.1f} s)")
     kw = {} if precision is None else {"precision": precision}
-    c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, **kw)
+    c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, pusher=pusher, **kw)
     info = c.info()
     log(f"built: {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s "
         f"(limit {info['dt_cfl']:.3e}), setup {info['setup_seconds']:.1f} s")
@@ -121,6 +121,26 @@ def plain_leg(n_particles, steps, warmup, use_graph):
     return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
             "steps": steps, "precision": "plain fp64", "particles": int(d["n_live"]), "sort_period": sp,
             "graphs": bool(use_graph)}
+
+
+def vay_leg(n_particles, steps, warmup):
+    """The headline workload with Vay's pusher in place of the Boris push
+    (mixed precision, graphs, sort period autotuned)."""
+    import paper_1701_03784_amd as axp
+    c, m, info, _ = setup_bwo(n_particles, pusher=axp.PUSH_VAY)
+    sp = c.autotune(16)
+    c.step(warmup)
+    c.sync()
+    steps = max(2 * sp, steps // (2 * sp) * (2 * sp))
+    t0 = time.perf_counter()
+    c.step(steps)
+    c.sync()
+    el = time.perf_counter() - t0
+    d = c.diag()
+    c.close()
+    return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
+            "steps": steps, "precision": "mixed", "pusher": "vay", "particles": int(d["n_live"]), "sort_period": sp,
+            "graphs": True}
 
 
 def batched_leg(n_variants, steps, per_face=25, seed_note=""):
@@ -215,6 +235,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--plain-steps", type=int, default=20, help="timed steps of the FP64 leg (0: skip)")
+    ap.add_argument("--vay-steps", type=int, default=32, help="timed steps of the Vay-pusher leg (0: skip)")
     ap.add_argument("--batch-variants", type=int, default=8, help="members of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=48)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -286,6 +307,11 @@ def main():
         log("plain FP64 leg (graphs) ...")
         plain_graph = plain_leg(args.particles, args.plain_steps, 4, use_graph=1)
         log(f"plain, graphs: {plain_graph['value']:.3e} particle-steps/s ({plain_graph['ms_per_step']:.3f} ms/step)")
+    vay = None
+    if args.vay_steps > 0:
+        log("Vay pusher leg ...")
+        vay = vay_leg(args.particles, args.vay_steps, 4)
+        log(f"vay: {vay['value']:.3e} particle-steps/s ({vay['ms_per_step']:.3f} ms/step)")
     if args.batch_variants > 0:
         log("batched leg ...")
         batched = batched_leg(args.batch_variants, args.batch_steps)
@@ -327,6 +353,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64": plain,
         "plain_fp64_graphs": plain_graph,
+        "pusher_vay": vay,
         "batched_mixed": batched,
         "speedup_mixed_vs_plain": (value / plain["value"]) if plain else None,
         "speedup_batched_mixed_vs_plain": (batched["value"] / plain["value"]) if (plain and batched) else None,

@@ -81,6 +81,15 @@ enum {
                                 64-bit fixed-point current; FP64 D, B and diagnostics */
 };
 
+/* Momentum push (Sec. 3.3): the relativistic Boris rotation, or Vay's
+ * pusher, which solves the time-centred momentum equation with the average
+ * of the old and new velocities in the magnetic force exactly, so that a
+ * particle at the E x B drift velocity feels no force at any energy. */
+enum {
+    AXP_PUSH_BORIS = 0,
+    AXP_PUSH_VAY = 1
+};
+
 /* How the SPAI matrix was built (axp_info.spai_mode). */
 enum {
     AXP_SPAI_PLAIN = 0,            /* least squares per column (Sec. 3.1) */
@@ -108,6 +117,7 @@ typedef struct {
     axp_alloc_fn alloc;      /* optional device allocator (NULL: hipMalloc) */
     axp_free_fn free;
     void *alloc_user;
+    int32_t pusher;          /* AXP_PUSH_* (default AXP_PUSH_BORIS); a batch needs one pusher for all members */
 } axp_config;
 
 typedef struct {

@@ -22,6 +22,7 @@ ERRORS = {-1: "AXP_E_ARG", -2: "AXP_E_MESH", -3: "AXP_E_SPAI", -4: "AXP_E_UNSTAB
           -6: "AXP_E_HIP", -7: "AXP_E_WALK", -8: "AXP_E_FIXED_OVERFLOW", -9: "AXP_E_NAN", -10: "AXP_E_STATE"}
 BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN = 1, 2, 3, 4
 PREC_PLAIN_FP64, PREC_MIXED = 0, 1
+PUSH_BORIS, PUSH_VAY = 0, 1
 SPAI_PLAIN, SPAI_LEARNED, SPAI_LEARNED_REJECTED = 0, 1, 2
 SPAI_FEATURES = 16
 
@@ -40,7 +41,7 @@ class Config(C.Structure):
                 ("dt", C.c_double), ("cfl_fraction", C.c_double), ("spai_level", C.c_int32),
                 ("spai_drop_tol", C.c_double), ("sort_period", C.c_int32), ("diag_every", C.c_int32),
                 ("max_walk", C.c_int32), ("use_graph", C.c_int32), ("alloc", ALLOC_FN), ("free", FREE_FN),
-                ("alloc_user", C.c_void_p)]
+                ("alloc_user", C.c_void_p), ("pusher", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -191,13 +192,14 @@ class Ctx:
 
     def __init__(self, precision=PREC_MIXED, dt=0.0, cfl_fraction=0.5, spai_level=3, spai_drop_tol=1e-3,
                  sort_period=4, diag_every=0, max_walk=64, use_graph=1, device=0, stream=None,
-                 torch_memory=False):
+                 torch_memory=False, pusher=PUSH_BORIS):
         self.lib = load_library()
         cfg = Config()
         self.lib.axp_config_default(C.byref(cfg))
         cfg.device, cfg.precision, cfg.dt, cfg.cfl_fraction = device, precision, dt, cfl_fraction
         cfg.spai_level, cfg.spai_drop_tol, cfg.sort_period = spai_level, spai_drop_tol, sort_period
         cfg.diag_every, cfg.max_walk, cfg.use_graph = diag_every, max_walk, use_graph
+        cfg.pusher = pusher
         cfg.hip_stream = stream if stream is not None else current_torch_stream(device)
         self._allocator = None
         if torch_memory:

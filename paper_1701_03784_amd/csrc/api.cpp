@@ -446,7 +446,7 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
         {
             PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
-            launch_particles_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, st);
+            launch_particles_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, c->cfg.pusher == AXP_PUSH_VAY, st);
         }
         { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
         { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv_plain(m, s, c->dp, st); }
@@ -458,7 +458,10 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     const InstConst *k0 = single ? &c->ic : nullptr;
     { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, st); }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
-    { PhaseScope ps(c, AXP_PHASE_PARTICLES, st); launch_particles(m, s, c->cfg.max_walk, sort_now, k0, st); }
+    {
+        PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
+        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, st);
+    }
     { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, st); }
     { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv(m, s, st); }
     ++c->step;
@@ -544,12 +547,14 @@ void axp_config_default(axp_config *cfg) {
     cfg->diag_every = 0;
     cfg->max_walk = 64;
     cfg->use_graph = 1;
+    cfg->pusher = AXP_PUSH_BORIS;
 }
 
 axp_status axp_create(const axp_config *cfg, axp_ctx **out) {
     if (!cfg || !out) return AXP_E_ARG;
     *out = nullptr;
     if (cfg->precision != AXP_PREC_MIXED && cfg->precision != AXP_PREC_PLAIN_FP64) return AXP_E_ARG;
+    if (cfg->pusher != AXP_PUSH_BORIS && cfg->pusher != AXP_PUSH_VAY) return AXP_E_ARG;
     if (cfg->spai_level < 1 || cfg->spai_level > 6 || cfg->spai_drop_tol < 0 || cfg->sort_period < 1 ||
         cfg->max_walk < 1 || cfg->diag_every < 0)
         return AXP_E_ARG;
@@ -1442,6 +1447,7 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
         if (!c->built || c->sticky) return fail(c, AXP_E_STATE, "batch members must be built and error-free");
         if (c->plain) return fail(c, AXP_E_ARG, "batches advance the mixed-precision step only");
         if (c->cfg.device != ctxs[0]->cfg.device) return fail(c, AXP_E_ARG, "batch members must share a device");
+        if (c->cfg.pusher != ctxs[0]->cfg.pusher) return fail(c, AXP_E_ARG, "batch members must share a pusher");
         if (c->species.empty()) return fail(c, AXP_E_STATE, "batch members need a species");
         if (c->inj_on) return fail(c, AXP_E_ARG, "batch members cannot carry a continuous injector");
     }

@@ -153,7 +153,8 @@ struct DevPlain {
 // ---- launchers (kernels_mixed.hip) ----
 void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
 // gather, push and walk of every particle, with the charge-conserving current
-void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st);
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
+                      hipStream_t st);
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);
@@ -172,7 +173,7 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
 // ---- launchers (kernels_plain.hip) ----
 void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
-                            bool count, hipStream_t st);
+                            bool count, bool vay, hipStream_t st);
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
 void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st);
 void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted, hipStream_t st);

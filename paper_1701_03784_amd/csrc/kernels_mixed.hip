@@ -228,8 +228,10 @@ __device__ __forceinline__ PushConst push_const(const DevMesh &m, const PushCons
     return PushConst{ic.qe[sp], ic.qb[sp], ic.cdt, ic.bz, ic.kq[sp]};
 }
 
-// Gather, relativistic Boris and the axisymmetric position update of one
-// particle: returns the meridian displacement (dz, drho) and updates u.
+// Gather, momentum push (relativistic Boris, or Vay's pusher when VAY) and
+// the axisymmetric position update of one particle: returns the meridian
+// displacement (dz, drho) and updates u.
+template <bool VAY>
 __device__ __forceinline__ void push(const DevState &s, Particle &P, const PushConst &ic, const float4 f0,
                                      const float4 f1, const float4 r4, int L0, int L1, int L2, float &fz, float &fr) {
     const float qe = ic.qe, qb = ic.qb;
@@ -238,18 +240,42 @@ __device__ __forceinline__ void push(const DevState &s, Particle &P, const PushC
     const float Ez = l0 * f0.x + l1 * f0.z + l2 * f1.x;
     const float Er = l0 * f0.y + l1 * f0.w + l2 * f1.y;
     const float Bp = f1.z, Bz = ic.bz;
-    // relativistic Boris with u normalised by c; basis (rho, phi, z)
-    const float umr = P.ur + qe * Er, ump = P.up, umz = P.uz + qe * Ez;
-    const float igm = __builtin_amdgcn_rsqf(1.0f + umr * umr + ump * ump + umz * umz);
-    const float tp = qb * Bp * igm, tz = qb * Bz * igm;
-    const float f = 2.0f * __builtin_amdgcn_rcpf(1.0f + tp * tp + tz * tz);
-    const float sp_ = f * tp, sz = f * tz;
-    const float vr = umr + (ump * tz - umz * tp);
-    const float vp = ump - umr * tz;
-    const float vz = umz + umr * tp;
-    float ur = umr + (vp * sz - vz * sp_) + qe * Er;
-    float up = ump - vr * sz;
-    float uz = umz + vr * sp_ + qe * Ez;
+    // u normalised by c; basis (rho, phi, z); qe E = q dt E / (2 m c), tau = q dt B / (2 m)
+    float ur, up, uz;
+    if (!VAY) {
+        // relativistic Boris: half kick, rotation about B, half kick
+        const float umr = P.ur + qe * Er, ump = P.up, umz = P.uz + qe * Ez;
+        const float igm = __builtin_amdgcn_rsqf(1.0f + umr * umr + ump * ump + umz * umz);
+        const float tp = qb * Bp * igm, tz = qb * Bz * igm;
+        const float f = 2.0f * __builtin_amdgcn_rcpf(1.0f + tp * tp + tz * tz);
+        const float sp_ = f * tp, sz = f * tz;
+        const float vr = umr + (ump * tz - umz * tp);
+        const float vp = ump - umr * tz;
+        const float vz = umz + umr * tp;
+        ur = umr + (vp * sz - vz * sp_) + qe * Er;
+        up = ump - vr * sz;
+        uz = umz + vr * sp_ + qe * Ez;
+    } else {
+        // Vay: u' = u + 2 qe E + (u / gamma) x tau, then the new gamma from
+        // the quadratic in gamma^2 and the exact solve of u = u' + (u / gamma) x tau
+        const float taup = qb * Bp, tauz = qb * Bz;
+        const float ig0 = __builtin_amdgcn_rsqf(1.0f + P.ur * P.ur + P.up * P.up + P.uz * P.uz);
+        const float vr = P.ur * ig0, vp = P.up * ig0, vz = P.uz * ig0;
+        const float ar = P.ur + 2.0f * qe * Er + (vp * tauz - vz * taup);
+        const float ap = P.up - vr * tauz;
+        const float az = P.uz + 2.0f * qe * Ez + vr * taup;
+        const float tau2 = taup * taup + tauz * tauz;
+        const float ustar = ap * taup + az * tauz;
+        const float sigma = 1.0f + ar * ar + ap * ap + az * az - tau2;
+        const float g2 = 0.5f * (sigma + __builtin_sqrtf(sigma * sigma + 4.0f * (tau2 + ustar * ustar)));
+        const float ign = __builtin_amdgcn_rsqf(g2);
+        const float tp = taup * ign, tz = tauz * ign;
+        const float sc = __builtin_amdgcn_rcpf(1.0f + tp * tp + tz * tz);
+        const float at = ustar * ign;                    // u' . t
+        ur = sc * (ar + (ap * tz - az * tp));
+        up = sc * (ap + at * tp - ar * tz);
+        uz = sc * (az + at * tz + ar * tp);
+    }
     if (!(ur * ur + up * up + uz * uz < 3.0e38f)) {   // non-finite or absurd momentum: count, stop
         atomicAdd(&s.ctr->nan_count, 1ull);
         ur = up = uz = 0.0f;
@@ -388,7 +414,7 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
     mv.L1 = L1;
 }
 
-template <bool SINGLE>
+template <bool SINGLE, bool VAY>
 __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int max_walk, int do_count, PushConst k0) {
     __shared__ int s_nmv;
     __shared__ int s_base;
@@ -460,7 +486,7 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
         }
         const int L0 = (int)P[j].L0, L1 = (int)P[j].L1, L2 = kS - L0 - L1;
         float fz, fr;
-        push(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
+        push<VAY>(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
         int d0, d1, d2;
         lam_change(cg, fz, fr, d0, d1, d2);
         const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
@@ -955,15 +981,19 @@ void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st) {
 // single: one instance with one species whose charge multiple is 1; its
 // constants travel as kernel arguments (scalar registers) instead of a
 // per-particle table lookup.
-void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, hipStream_t st) {
+void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
+                      hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nblk(s.capacity, kChunk));
+    const int dc = count ? 1 : 0;
     if (single) {
         const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1};
-        hipLaunchKernelGGL(k_particles<true>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
+        if (vay) hipLaunchKernelGGL((k_particles<true, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+        else hipLaunchKernelGGL((k_particles<true, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
     } else {
         const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
-        hipLaunchKernelGGL(k_particles<false>, grid, dim3(kWG), 0, st, m, s, max_walk, count ? 1 : 0, k0);
+        if (vay) hipLaunchKernelGGL((k_particles<false, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+        else hipLaunchKernelGGL((k_particles<false, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
     }
 }
 

@@ -6,7 +6,7 @@
 // FP64 atomics (so their order, and the last bits, vary from run to run).
 //
 //   k_tri_pass_d   eq. (full_d_dfl) and the Whitney gather tile (Sec. 3.2)
-//   k_particles_d  gather, relativistic Boris (eqs. DNE, DLE), axisymmetric
+//   k_particles_d  gather, relativistic Boris or Vay push (eqs. DNE, DLE), axisymmetric
 //                  position update, walk with the current of eq. (current)
 //   k_edge_pass_d  D += dt C^T H B^{n+1/2} - dt J (eq. full_d_dal, D-form)
 //   k_spmv_d       E = M D
@@ -171,8 +171,10 @@ struct ParticleD {
     double l0, l1, ur, up, uz;
 };
 
-// gather, relativistic Boris with u normalised by c in (rho, phi, z), push in
-// the local Cartesian frame and rotate back: returns the meridian displacement
+// gather, momentum push with u normalised by c in (rho, phi, z) (relativistic
+// Boris, or Vay's pusher when VAY), push in the local Cartesian frame and
+// rotate back: returns the meridian displacement
+template <bool VAY>
 __device__ __forceinline__ void push_d(const DevState &s, ParticleD &P, const PlainConst &k, int sp, const double4 f0,
                                        const double4 f1, const double4 r4, double &fz, double &fr) {
     const double l0 = P.l0, l1 = P.l1, l2 = 1.0 - l0 - l1;
@@ -180,17 +182,39 @@ __device__ __forceinline__ void push_d(const DevState &s, ParticleD &P, const Pl
     const double Er = l0 * f0.y + l1 * f0.w + l2 * f1.y;
     const double Bp = f1.z, Bz = k.bz;
     const double qe = k.qe[sp], qb = k.qb[sp];
-    const double umr = P.ur + qe * Er, ump = P.up, umz = P.uz + qe * Ez;
-    const double igm = 1.0 / sqrt(1.0 + umr * umr + ump * ump + umz * umz);
-    const double tp = qb * Bp * igm, tz = qb * Bz * igm;
-    const double f = 2.0 / (1.0 + tp * tp + tz * tz);
-    const double sp_ = f * tp, sz = f * tz;
-    const double vr = umr + (ump * tz - umz * tp);
-    const double vp = ump - umr * tz;
-    const double vz = umz + umr * tp;
-    double ur = umr + (vp * sz - vz * sp_) + qe * Er;
-    double up = ump - vr * sz;
-    double uz = umz + vr * sp_ + qe * Ez;
+    double ur, up, uz;
+    if (!VAY) {
+        const double umr = P.ur + qe * Er, ump = P.up, umz = P.uz + qe * Ez;
+        const double igm = 1.0 / sqrt(1.0 + umr * umr + ump * ump + umz * umz);
+        const double tp = qb * Bp * igm, tz = qb * Bz * igm;
+        const double f = 2.0 / (1.0 + tp * tp + tz * tz);
+        const double sp_ = f * tp, sz = f * tz;
+        const double vr = umr + (ump * tz - umz * tp);
+        const double vp = ump - umr * tz;
+        const double vz = umz + umr * tp;
+        ur = umr + (vp * sz - vz * sp_) + qe * Er;
+        up = ump - vr * sz;
+        uz = umz + vr * sp_ + qe * Ez;
+    } else {
+        // u' = u + 2 qe E + (u / gamma) x tau; new gamma from the quadratic in
+        // gamma^2; exact solve of u = u' + (u / gamma) x tau
+        const double taup = qb * Bp, tauz = qb * Bz;
+        const double ig0 = 1.0 / sqrt(1.0 + P.ur * P.ur + P.up * P.up + P.uz * P.uz);
+        const double vr = P.ur * ig0, vp = P.up * ig0, vz = P.uz * ig0;
+        const double ar = P.ur + 2.0 * qe * Er + (vp * tauz - vz * taup);
+        const double ap = P.up - vr * tauz;
+        const double az = P.uz + 2.0 * qe * Ez + vr * taup;
+        const double tau2 = taup * taup + tauz * tauz;
+        const double ustar = ap * taup + az * tauz;
+        const double sigma = 1.0 + ar * ar + ap * ap + az * az - tau2;
+        const double gn = sqrt(0.5 * (sigma + sqrt(sigma * sigma + 4.0 * (tau2 + ustar * ustar))));
+        const double tp = taup / gn, tz = tauz / gn;
+        const double sc = 1.0 / (1.0 + tp * tp + tz * tz);
+        const double at = ustar / gn;
+        ur = sc * (ar + (ap * tz - az * tp));
+        up = sc * (ap + at * tp - ar * tz);
+        uz = sc * (az + at * tz + ar * tp);
+    }
     if (!(ur * ur + up * up + uz * uz < 1.0e300)) {
         atomicAdd(&s.ctr->nan_count, 1ull);
         ur = up = uz = 0.0;
@@ -297,6 +321,7 @@ __device__ __forceinline__ void walk_mover_d(const DevMesh &m, const DevState &s
     mv.l1 = l1;
 }
 
+template <bool VAY>
 __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int max_walk,
                                                       int do_count) {
     __shared__ int s_nmv;
@@ -348,7 +373,7 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
         }
         double fz, fr;
         const double l0 = P[j].l0, l1 = P[j].l1, l2 = 1.0 - l0 - l1;
-        push_d(s, P[j], k, sp, cf0, cf1, cr4, fz, fr);
+        push_d<VAY>(s, P[j], k, sp, cf0, cf1, cr4, fz, fr);
         const double d0 = cg.x * fz + cg.y * fr, d1 = cg.z * fz + cg.w * fr, d2 = -d0 - d1;
         const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
         if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
@@ -625,10 +650,11 @@ void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, con
 }
 
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
-                            bool count, hipStream_t st) {
+                            bool count, bool vay, hipStream_t st) {
     if (s.capacity == 0) return;
-    hipLaunchKernelGGL(k_particles_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k, max_walk,
-                       count ? 1 : 0);
+    const dim3 grid(nb_(s.capacity, kChunkD));
+    if (vay) hipLaunchKernelGGL(k_particles_d<true>, grid, dim3(kWGd), 0, st, m, s, p, k, max_walk, count ? 1 : 0);
+    else hipLaunchKernelGGL(k_particles_d<false>, grid, dim3(kWGd), 0, st, m, s, p, k, max_walk, count ? 1 : 0);
 }
 
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {

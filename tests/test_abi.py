@@ -43,6 +43,8 @@ def test_enum_values_match_binding():
     assert val["AXP_BC_EMITTER"] == ax.BC_EMITTER == synth.BC_EMITTER
     assert val["AXP_BC_OPEN"] == ax.BC_OPEN == synth.BC_OPEN
     assert val["AXP_PREC_MIXED"] == ax.PREC_MIXED
+    assert val["AXP_PUSH_BORIS"] == ax.PUSH_BORIS
+    assert val["AXP_PUSH_VAY"] == ax.PUSH_VAY
     for k, v in ax.ERRORS.items():
         assert val[v] == k
 
@@ -52,7 +54,8 @@ def _c_layout():
     import subprocess
     import tempfile
     fields = {"axp_config": ["device", "hip_stream", "precision", "dt", "cfl_fraction", "spai_level", "spai_drop_tol",
-                             "sort_period", "diag_every", "max_walk", "use_graph", "alloc", "free", "alloc_user"],
+                             "sort_period", "diag_every", "max_walk", "use_graph", "alloc", "free", "alloc_user",
+                             "pusher"],
               "axp_info": ["n_nodes", "n_edges", "n_faces", "n_free_edges", "n_free_nodes", "spai_nnz",
                            "spai_fro_residual", "spai_max_col_residual", "dt", "dt_cfl", "setup_seconds",
                            "particle_capacity", "n_particles", "step", "precision", "n_species", "spai_mode",
