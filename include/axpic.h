@@ -198,6 +198,27 @@ axp_status axp_get_spai(const axp_ctx *ctx, int64_t capacity, int64_t *nnz, int6
  * is solved by conjugate gradients in FP64. */
 axp_status axp_set_fields(axp_ctx *ctx, const double *E0, const double *B_mhalf);
 
+/* Electrostatic, Gauss-consistent fields at step 0.  The scheme keeps the
+ * Gauss residual D~div [*eps]_a E - Q at its initial value (Sec. 3.4.2), so
+ * it is zero for all steps only if it is zero at step 0; applied voltages
+ * (the cathode-anode field of Sec. 5.2) enter as potentials of conductors.
+ * Computes the nodal potential phi with phi = phi_conductor on conductor
+ * nodes (nodes on AXP_BC_PEC or AXP_BC_EMITTER segments) such that
+ * E^0 = -G phi (edge value phi_tail - phi_head; 0 on conductor edges) and
+ * D^0 = M^-1 E^0 satisfy D~div D^0 = Q on every free node, to 1e-13 of the
+ * larger of |Q| and the summed |D| at a node; sets E^0, D^0 and B^{-1/2} = 0.
+ * E^0 is curl-free, so without particles the state does not move.
+ *   phi_conductor  [n_nodes] volts, read on conductor nodes only; NULL: 0 V.
+ *   with_charge    1: Q is the nodal charge of the particles present plus
+ *                  the wall charge (per radian, as axp_get_sources returns);
+ *                  0: Q = 0.
+ *   phi_out        optional [n_nodes]: the potential on every node.
+ * Host FP64 solve (setup): defect correction on D~div M^-1 D~div^T with the
+ * rho-weighted P1 stiffness D~div A D~div^T as preconditioner.  Errors:
+ * AXP_E_STATE before axp_build; AXP_E_NAN for a non-finite potential;
+ * AXP_E_SPAI if the solve does not converge (fields unchanged). */
+axp_status axp_set_electrostatic(axp_ctx *ctx, const double *phi_conductor, int32_t with_charge, double *phi_out);
+
 /* Uniform static axial field B_z [T] added at the gather (beam focusing, Sec. 3.2). */
 axp_status axp_set_external_bz(axp_ctx *ctx, double bz);
 

@@ -64,7 +64,7 @@ class Diag(C.Structure):
 
 
 EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary", "axp_build",
-           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_external_bz",
+           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_electrostatic", "axp_set_external_bz",
            "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
         "axp_get_edges": (i32, [vp, vp]),
         "axp_get_spai": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
         "axp_set_fields": (i32, [vp, vp, vp]),
+        "axp_set_electrostatic": (i32, [vp, vp, i32, vp]),
         "axp_set_external_bz": (i32, [vp, dbl]),
         "axp_add_species": (i32, [vp, dbl, dbl, i64, C.POINTER(i32)]),
         "axp_inject": (i32, [vp, i32, i64, vp, vp]),
@@ -268,6 +269,16 @@ class Ctx:
         E0 = np.ascontiguousarray(E0, dtype=np.float64)
         B = np.ascontiguousarray(B_mhalf, dtype=np.float64)
         self._check(self.lib.axp_set_fields(self.h, _ptr(E0), _ptr(B)))
+
+    def set_electrostatic(self, phi_conductor=None, with_charge=False):
+        """Gauss-consistent electrostatic fields (axp_set_electrostatic);
+        returns the nodal potential."""
+        n0 = self.info()["n_nodes"]
+        phi = np.zeros(n0)
+        pc = None if phi_conductor is None else np.ascontiguousarray(phi_conductor, dtype=np.float64)
+        self._check(self.lib.axp_set_electrostatic(self.h, None if pc is None else _ptr(pc), int(bool(with_charge)),
+                                                   _ptr(phi)))
+        return phi
 
     def set_external_bz(self, bz):
         self._check(self.lib.axp_set_external_bz(self.h, float(bz)))

@@ -734,6 +734,56 @@ axp_status axp_set_fields(axp_ctx *c, const double *E0, const double *B_mhalf) {
     });
 }
 
+axp_status axp_set_electrostatic(axp_ctx *c, const double *phi_conductor, int32_t with_charge, double *phi_out) {
+    if (!c || (with_charge != 0 && with_charge != 1)) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        const HostMesh &m = c->hm;
+        std::vector<double> phic(m.n0, 0.0), Q(m.n0, 0.0);
+        if (phi_conductor)
+            for (int v = 0; v < m.n0; ++v) {
+                if (m.nfree[v]) continue;
+                if (!std::isfinite(phi_conductor[v])) throw ApiError{AXP_E_NAN, "non-finite conductor potential"};
+                phic[v] = phi_conductor[v];
+            }
+        if (with_charge) {
+            // nodal charge of the particles present and of the wall reservoirs [C/rad]
+            run_diag(c);
+            if (c->plain) {
+                hcheck(hipMemcpyAsync(Q.data(), c->dp.Q, m.n0 * 8, hipMemcpyDeviceToHost, c->stream), "Q");
+                hcheck(hipStreamSynchronize(c->stream), "sync");
+                for (int v = 0; v < m.n0; ++v) Q[v] *= c->pc.qunit;
+            } else {
+                std::vector<long long> q(m.n0);
+                hcheck(hipMemcpyAsync(q.data(), c->ds.Qfx, m.n0 * 8, hipMemcpyDeviceToHost, c->stream), "Q");
+                hcheck(hipStreamSynchronize(c->stream), "sync");
+                for (int v = 0; v < m.n0; ++v) Q[v] = double(q[v]) * c->ic.qscale;
+            }
+        }
+        std::vector<double> phi, E, D;
+        double res = 0.0;
+        const int it = electrostatic_state(m, phic.data(), Q.data(), 1e-13, 60, phi, E, D, res);
+        if (it < 0) throw ApiError{AXP_E_SPAI, "electrostatic solve did not converge (residual " + std::to_string(res) + ")"};
+        std::vector<double> B(m.n2, 0.0);
+        std::vector<float> E32(m.n1), D32(m.n1);
+        for (int i = 0; i < m.n1; ++i) { E32[i] = float(E[i]); D32[i] = float(D[i]); }
+        DevState &s = c->ds;
+        hcheck(hipMemcpyAsync(s.B, B.data(), m.n2 * 8, hipMemcpyHostToDevice, c->stream), "B");
+        hcheck(hipMemcpyAsync(s.D, D.data(), m.n1 * 8, hipMemcpyHostToDevice, c->stream), "D");
+        if (c->plain) {
+            hcheck(hipMemcpyAsync(c->dp.E, E.data(), m.n1 * 8, hipMemcpyHostToDevice, c->stream), "E");
+        } else {
+            hcheck(hipMemcpyAsync(s.D32, D32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "D32");
+            hcheck(hipMemcpyAsync(s.E, E32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "E");
+        }
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        c->g0_set = false;
+        c->last_diag_step = -1;
+        if (phi_out) std::memcpy(phi_out, phi.data(), sizeof(double) * m.n0);
+        return AXP_OK;
+    });
+}
+
 axp_status axp_set_external_bz(axp_ctx *c, double bz) {
     if (!c || !std::isfinite(bz)) return AXP_E_ARG;
     return guarded(c, [&]() -> axp_status {

@@ -793,6 +793,109 @@ int cg_solve_M(const HostMesh &m, const double *b, double *x, double rtol, int m
     return it;
 }
 
+// ------------------------------------------------------------ electrostatics
+// The scheme's Gauss law (Sec. 3.4.2) holds for all steps if the initial
+// state satisfies D~div D = Q on the free nodes with D = [*eps]_a E = M^-1 E.
+// With E = -G phi = D~div^T phi the field is curl-free (C G = 0) and
+// K phi = Q with K = D~div M^-1 D~div^T (free nodes; phi fixed on conductor
+// nodes).  K is applied through a CG solve with M; it is solved by defect
+// correction preconditioned with L = D~div A D~div^T (the rho-weighted P1
+// stiffness, close to K since M approximates A^-1), L itself by Jacobi PCG.
+namespace {
+
+// E = D~div^T phi on every edge (phi_tail - phi_head), 0 on conductor edges
+void grad_field(const HostMesh &m, const double *phi, double *E) {
+    for (int e = 0; e < m.n1; ++e) E[e] = m.efree[e] ? phi[m.ev[e][0]] - phi[m.ev[e][1]] : 0.0;
+}
+
+// y_v = (D~div x)_v on the free nodes (0 elsewhere)
+void node_div(const HostMesh &m, const double *x, double *y) {
+    for (int v = 0; v < m.n0; ++v) {
+        double s = 0.0;
+        if (m.nfree[v])
+            for (int64_t q = m.nptr[v]; q < m.nptr[v + 1]; ++q) s += m.nsign[q] * x[m.nedge[q]];
+        y[v] = s;
+    }
+}
+
+double a_entry(const Csr &A, int e, int f) {
+    const int32_t *b = A.col.data() + A.ptr[e], *en = A.col.data() + A.ptr[e + 1];
+    const int32_t *it = std::lower_bound(b, en, f);
+    return (it != en && *it == f) ? A.val[it - A.col.data()] : 0.0;
+}
+
+}  // namespace
+
+int electrostatic_state(const HostMesh &m, const double *phi_c, const double *Q, double rtol, int max_outer,
+                        std::vector<double> &phi, std::vector<double> &E, std::vector<double> &D, double &res_rel) {
+    const int n0 = m.n0, n1 = m.n1;
+    phi.assign(n0, 0.0);
+    E.assign(n1, 0.0);
+    D.assign(n1, 0.0);
+    for (int v = 0; v < n0; ++v) phi[v] = m.nfree[v] ? 0.0 : phi_c[v];
+    // Jacobi preconditioner of L: diag(L)_v = sum_{e,f at v} s_ve s_vf A_ef
+    std::vector<double> dl(n0, 1.0);
+    for (int v = 0; v < n0; ++v) {
+        if (!m.nfree[v]) continue;
+        double s = 0.0;
+        for (int64_t a = m.nptr[v]; a < m.nptr[v + 1]; ++a)
+            for (int64_t b = m.nptr[v]; b < m.nptr[v + 1]; ++b)
+                s += m.nsign[a] * m.nsign[b] * a_entry(m.A, m.nedge[a], m.nedge[b]);
+        dl[v] = s > 0.0 ? s : 1.0;
+    }
+    std::vector<double> te(n1), ta(n1), r(n0), x(n0), z(n0), p(n0), q(n0), dphi(n0);
+    auto apply_L = [&](const double *in, double *out) {
+        grad_field(m, in, te.data());
+        m.A.spmv(te.data(), ta.data());
+        node_div(m, ta.data(), out);
+    };
+    // Jacobi PCG for L x = b on the free nodes (x, b zero elsewhere)
+    auto solve_L = [&](const double *b, double *xo, double tol) {
+        double bb = 0.0;
+        for (int v = 0; v < n0; ++v) { xo[v] = 0.0; r[v] = m.nfree[v] ? b[v] : 0.0; bb += r[v] * r[v]; }
+        if (bb == 0.0) return;
+        double rz = 0.0;
+        for (int v = 0; v < n0; ++v) { z[v] = r[v] / dl[v]; p[v] = z[v]; rz += r[v] * z[v]; }
+        for (int it = 0; it < 20 * n0 + 100; ++it) {
+            apply_L(p.data(), q.data());
+            double pq = 0.0;
+            for (int v = 0; v < n0; ++v) pq += p[v] * q[v];
+            if (!(pq > 0.0)) break;
+            const double a = rz / pq;
+            double rr = 0.0;
+            for (int v = 0; v < n0; ++v) { xo[v] += a * p[v]; r[v] -= a * q[v]; rr += r[v] * r[v]; }
+            if (rr <= tol * tol * bb) break;
+            double rzn = 0.0;
+            for (int v = 0; v < n0; ++v) { z[v] = r[v] / dl[v]; rzn += r[v] * z[v]; }
+            const double beta = rzn / rz;
+            rz = rzn;
+            for (int v = 0; v < n0; ++v) p[v] = z[v] + beta * p[v];
+        }
+    };
+    res_rel = 1e300;
+    for (int outer = 0; outer < max_outer; ++outer) {
+        grad_field(m, phi.data(), E.data());
+        cg_solve_M(m, E.data(), D.data(), 1e-15, 20000);
+        node_div(m, D.data(), x.data());
+        double rmax = 0.0, scale = 0.0;
+        for (int v = 0; v < n0; ++v) {
+            if (!m.nfree[v]) continue;
+            double sa = 0.0;                        // summed |D| at the node: the scale of its residual
+            for (int64_t k = m.nptr[v]; k < m.nptr[v + 1]; ++k) sa += std::fabs(D[m.nedge[k]]);
+            x[v] = Q[v] - x[v];
+            rmax = std::max(rmax, std::fabs(x[v]));
+            scale = std::max(scale, std::max(std::fabs(Q[v]), sa));
+        }
+        res_rel = scale > 0.0 ? rmax / scale : 0.0;
+        if (res_rel <= rtol) return outer;
+        std::vector<double> rhs(x.begin(), x.end());
+        solve_L(rhs.data(), dphi.data(), 1e-10);
+        for (int v = 0; v < n0; ++v)
+            if (m.nfree[v]) phi[v] += dphi[v];
+    }
+    return -1;
+}
+
 void build_locator(HostMesh &m) {
     double zmin = 1e300, zmax = -1e300, rmin = 1e300, rmax = -1e300;
     for (int i = 0; i < m.n0; ++i) {

@@ -117,6 +117,12 @@ double leapfrog_energy_drift(const HostMesh &m, double dt, int steps, uint64_t s
 double cfl_dt(const HostMesh &m, int iters);
 // Solves M x = b on free edges (conjugate gradients, FP64); returns iterations.
 int cg_solve_M(const HostMesh &m, const double *b, double *x, double rtol, int max_iter);
+// Electrostatic initial state: potential phi (phi_c on conductor nodes),
+// E = -G phi (zero on conductor edges), D = M^-1 E with D~div D = Q on the
+// free nodes.  Returns the outer iterations, or -1 without convergence;
+// res_rel receives max |D~div D - Q| over the free nodes / the D scale.
+int electrostatic_state(const HostMesh &m, const double *phi_c, const double *Q, double rtol, int max_outer,
+                        std::vector<double> &phi, std::vector<double> &E, std::vector<double> &D, double &res_rel);
 void build_locator(HostMesh &m);
 // Locates (z, rho); returns the internal face and barycentric coordinates, or -1.
 int32_t locate_point(const HostMesh &m, double z, double rho, double lam[3]);
