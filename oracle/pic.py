@@ -50,7 +50,7 @@ def _load():
     if _lib is None:
         _lib = C.CDLL(build_oracle())
         vp = C.c_void_p
-        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int] + [vp] * 8
+        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp] + [vp] * 8
         _lib.oracle_step.restype = None
         _lib.oracle_charge.argtypes = [vp, vp, vp, vp]
         _lib.oracle_sample.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -93,6 +93,9 @@ class OracleSim:
         self.dt = float(dt) if dt is not None else cfl_fraction * self.dt_cfl
         self.bz = float(bz)
         self.pusher = 0                    # 0 relativistic Boris, 1 Vay
+        self.sources = []                  # magnetic point sources: (face, amplitude, t0, sigma, omega)
+        self.probe = None                  # (face, z, rho) of the field probe
+        self.probe_signal = []             # (E_z, E_rho) at the probe at t^n, one per step
         self.setup_seconds = time.perf_counter() - t0
         tp = self.topo
         n0, n1, n2 = tp.n0, tp.n1, tp.n2
@@ -233,14 +236,38 @@ class OracleSim:
         self.pspecies = np.concatenate([self.pspecies, np.full(k, sp_, dtype=np.int64)])
 
     # ------------------------------------------------------------------ step
+    def add_point_source(self, z, rho, amplitude, t0, sigma, omega):
+        """Magnetic point source of Sec. 5.1 at (z, rho): the magnetic current
+        M(t) = amplitude exp(-((t - t0) / (2 sigma))^2) cos(omega (t - t0))
+        drives the flux of the face holding the point."""
+        face = int(self.locate(np.array([[z, rho]]))[0])
+        self.sources.append((face, float(amplitude), float(t0), float(sigma), float(omega)))
+
+    def set_probe(self, z, rho):
+        """Record (E_z, E_rho) at (z, rho) at the start of every step (t^n)."""
+        self.probe = (int(self.locate(np.array([[z, rho]]))[0]), float(z), float(rho))
+        self.probe_signal = []
+
+    def _source_values(self):
+        t = self.n_step * self.dt
+        return np.array([a * np.exp(-((t - t0) / (2.0 * sg)) ** 2) * np.cos(w * (t - t0))
+                         for (_, a, t0, sg, w) in self.sources], dtype=np.float64)
+
     def step(self, n=1):
         lib = _load()
         P = self._parts()
+        src_face = np.array([f for (f, *_r) in self.sources], dtype=np.int64)
         for _ in range(n):
             if self._emit is not None:
                 self._inject_step()
                 P = self._parts()
+            if self.probe is not None:
+                f, z, r = self.probe
+                e = self.sample(np.array([f]), np.array([z]), np.array([r]))[0]
+                self.probe_signal.append((e[0], e[1]))
+            src_val = self._source_values()
             lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz, int(self.pusher),
+                            len(src_face), _p(src_face), _p(src_val),
                             _p(self.E), _p(self.B), _p(self.D), _p(self.J), _p(self.Qres),
                             _p(self._Bh), _p(self._rhs), _p(self.stats))
             self.n_step += 1

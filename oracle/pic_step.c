@@ -5,6 +5,7 @@
  *
  * Order of one step n -> n+1 (Sec. 3.1-3.4):
  *   1. Faraday, eq. (full_d_dfl):   B^{n+1/2} = B^{n-1/2} - dt C E^n
+ *      (- dt M(t^n) on the faces of magnetic point sources, Sec. 5.1)
  *   2. gather, Sec. 3.2:            E_p = sum_e E_e W1_e(r_p),
  *                                   B_p = sum_T (B^{n+1/2}+B^{n-1/2})_T/2 W2_T
  *      plus a static axial field B_z (beam focusing, Sec. 3.2);
@@ -268,19 +269,23 @@ static int walk(const omesh *m, oparticles *P, int64_t p, double ze, double re,
  * D: D^n -> D^{n+1}.  J (n1) receives J^{n+1/2}.  Qres (n0) accumulates
  * the charge of absorbed particles.  Bh (n2) and rhs (n1) are scratch.
  * stats: [0] pieces walked, [1] absorbed, [2] walk overflows.
- * pusher: 0 relativistic Boris, 1 Vay.
+ * pusher: 0 relativistic Boris, 1 Vay.  src_face/src_val: the nsrc point
+ * sources' faces and their magnetic currents at t^n.
  */
 void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher,
+                 int64_t nsrc, const int64_t *src_face, const double *src_val,
                  double *E, double *B, double *D, double *J, double *Qres,
                  double *Bh, double *rhs, int64_t *stats)
 {
-    /* 1. Faraday */
+    /* 1. Faraday, with the magnetic point sources (Sec. 5.1): a magnetic
+     *    current M(t^n) at a point drives the flux of the face holding it */
     for (int64_t t = 0; t < m->n2; ++t) {
         double circ = 0.0;
         for (int k = 0; k < 3; ++k)
             circ += (double)m->tri_signs[3 * t + k] * E[m->tri_edges[3 * t + k]];
         Bh[t] = B[t] - dt * circ;
     }
+    for (int64_t k = 0; k < nsrc; ++k) Bh[src_face[k]] -= dt * src_val[k];
     memset(J, 0, sizeof(double) * m->n1);
 
     /* 2-4. gather, push, scatter */
