@@ -219,6 +219,32 @@ axp_status axp_set_fields(axp_ctx *ctx, const double *E0, const double *B_mhalf)
  * AXP_E_SPAI if the solve does not converge (fields unchanged). */
 axp_status axp_set_electrostatic(axp_ctx *ctx, const double *phi_conductor, int32_t with_charge, double *phi_out);
 
+/* Magnetic point source (Sec. 5.1): a magnetic current M(t) at (z, rho)
+ * [m], a ring about the axis, drives the flux of the face holding the
+ * point: B_T^{n+1/2} = B_T^{n-1/2} - dt (C E^n)_T - dt M(t^n), t^n = n dt,
+ * with the Gaussian-modulated pulse
+ * M(t) = amplitude exp(-((t - t0) / (2 sigma))^2) cos(omega (t - t0))
+ * (amplitude [V], t0 and sigma [s], omega [rad/s]).  Up to 8 sources;
+ * they stay until axp_clear_point_sources and are not saved by axp_save.
+ * Errors: AXP_E_ARG for a point outside the mesh, sigma <= 0, non-finite
+ * values or a ninth source; AXP_E_STATE before axp_build.  Contexts with
+ * sources cannot join a batch. */
+axp_status axp_add_point_source(axp_ctx *ctx, double z, double rho, double amplitude, double t0, double sigma,
+                                double omega);
+axp_status axp_clear_point_sources(axp_ctx *ctx);
+
+/* Field probe (Sec. 5.1): from the next step on, the E field at (z, rho)
+ * (Whitney interpolation of the edge values, the gather of Sec. 3.2) is
+ * recorded at t^n at the start of every step, for the next `capacity`
+ * steps, in a device buffer the context owns (16 bytes per step).
+ * capacity 0 removes the probe.  axp_get_probe copies the samples recorded
+ * so far, (E_z, E_rho) [V/m] per step, into E_z_rho[2 * n]; *n receives
+ * their count (with E_z_rho NULL only the count; AXP_E_ARG if it exceeds
+ * capacity).  Not saved by axp_save; contexts with a probe cannot join a
+ * batch. */
+axp_status axp_set_probe(axp_ctx *ctx, double z, double rho, int64_t capacity);
+axp_status axp_get_probe(axp_ctx *ctx, int64_t capacity, int64_t *n, double *E_z_rho);
+
 /* Uniform static axial field B_z [T] added at the gather (beam focusing, Sec. 3.2). */
 axp_status axp_set_external_bz(axp_ctx *ctx, double bz);
 

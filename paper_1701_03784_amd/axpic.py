@@ -64,7 +64,8 @@ class Diag(C.Structure):
 
 
 EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary", "axp_build",
-           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_electrostatic", "axp_set_external_bz",
+           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_electrostatic", "axp_add_point_source",
+           "axp_clear_point_sources", "axp_set_probe", "axp_get_probe", "axp_set_external_bz",
            "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
@@ -104,6 +105,10 @@ def load_library(path: str = LIB_PATH):
         "axp_get_spai": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
         "axp_set_fields": (i32, [vp, vp, vp]),
         "axp_set_electrostatic": (i32, [vp, vp, i32, vp]),
+        "axp_add_point_source": (i32, [vp, dbl, dbl, dbl, dbl, dbl, dbl]),
+        "axp_clear_point_sources": (i32, [vp]),
+        "axp_set_probe": (i32, [vp, dbl, dbl, i64]),
+        "axp_get_probe": (i32, [vp, i64, C.POINTER(i64), vp]),
         "axp_set_external_bz": (i32, [vp, dbl]),
         "axp_add_species": (i32, [vp, dbl, dbl, i64, C.POINTER(i32)]),
         "axp_inject": (i32, [vp, i32, i64, vp, vp]),
@@ -279,6 +284,27 @@ class Ctx:
         self._check(self.lib.axp_set_electrostatic(self.h, None if pc is None else _ptr(pc), int(bool(with_charge)),
                                                    _ptr(phi)))
         return phi
+
+    def add_point_source(self, z, rho, amplitude, t0, sigma, omega):
+        """Magnetic point source with a Gaussian-modulated pulse (axp_add_point_source)."""
+        self._check(self.lib.axp_add_point_source(self.h, float(z), float(rho), float(amplitude), float(t0),
+                                                  float(sigma), float(omega)))
+
+    def clear_point_sources(self):
+        self._check(self.lib.axp_clear_point_sources(self.h))
+
+    def set_probe(self, z, rho, capacity):
+        """Record E at (z, rho) at the start of each of the next `capacity` steps."""
+        self._check(self.lib.axp_set_probe(self.h, float(z), float(rho), int(capacity)))
+
+    def get_probe(self):
+        """(n, 2) array of (E_z, E_rho) recorded so far."""
+        n = C.c_int64()
+        self._check(self.lib.axp_get_probe(self.h, 0, C.byref(n), None))
+        out = np.zeros((n.value, 2))
+        if n.value:
+            self._check(self.lib.axp_get_probe(self.h, n.value, C.byref(n), _ptr(out)))
+        return out
 
     def set_external_bz(self, bz):
         self._check(self.lib.axp_set_external_bz(self.h, float(bz)))

@@ -75,7 +75,9 @@ struct axp_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int graph_window = 0;
-
+    // magnetic point sources and field probe (Sec. 5.1)
+    FieldSrc fs{};
+    unsigned long long step_upload = 0;   // host image of the device step counter (async copy source)
 };
 
 namespace {
@@ -442,7 +444,7 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
         else launch_inject(m, s, c->inj_edges, c->inj, st);
     }
     if (c->plain) {
-        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, st); }
+        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, c->fs, st); }
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
         {
             PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
@@ -456,7 +458,7 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     }
     const bool single = m.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
     const InstConst *k0 = single ? &c->ic : nullptr;
-    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, st); }
+    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, c->fs, st); }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
         PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
@@ -500,6 +502,12 @@ void launch_graph(axp_ctx *c, int W) {
 }
 
 void run_steps(axp_ctx *c, int n_steps) {
+    if ((c->fs.n_src > 0 || c->fs.probe_face >= 0) && n_steps > 0) {
+        // sources and probe read the step index on the device: start it at the host's
+        c->step_upload = (unsigned long long)c->step;
+        hcheck(hipMemcpyAsync(&c->ds.ctr->step, &c->step_upload, sizeof(unsigned long long), hipMemcpyHostToDevice,
+                              c->stream), "step counter");
+    }
     if (c->inj_on && n_steps > 0) {
         const DevCounters h = read_counters(c);
         grow_particles(c, int64_t(h.n_slots) + int64_t(n_steps) * c->inj.per_step);
@@ -780,6 +788,79 @@ axp_status axp_set_electrostatic(axp_ctx *c, const double *phi_conductor, int32_
         c->g0_set = false;
         c->last_diag_step = -1;
         if (phi_out) std::memcpy(phi_out, phi.data(), sizeof(double) * m.n0);
+        return AXP_OK;
+    });
+}
+
+axp_status axp_add_point_source(axp_ctx *c, double z, double rho, double amplitude, double t0, double sigma,
+                                double omega) {
+    if (!c || !std::isfinite(z) || !std::isfinite(rho) || !std::isfinite(amplitude) || !std::isfinite(t0) ||
+        !(sigma > 0.0) || !std::isfinite(sigma) || !std::isfinite(omega))
+        return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        if (c->fs.n_src >= kMaxSources) throw ApiError{AXP_E_ARG, "too many point sources"};
+        double lam[3];
+        const int32_t t = locate_point(c->hm, z, rho, lam);
+        if (t < 0) throw ApiError{AXP_E_ARG, "point source outside the mesh"};
+        const int k = c->fs.n_src++;
+        c->fs.src_face[k] = t;
+        c->fs.amp[k] = amplitude;
+        c->fs.t0[k] = t0;
+        c->fs.sig[k] = sigma;
+        c->fs.w[k] = omega;
+        c->fs.dt = c->dt;
+        drop_graphs(c);
+        return AXP_OK;
+    });
+}
+
+axp_status axp_clear_point_sources(axp_ctx *c) {
+    if (!c) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        c->fs.n_src = 0;
+        drop_graphs(c);
+        return AXP_OK;
+    });
+}
+
+axp_status axp_set_probe(axp_ctx *c, double z, double rho, int64_t capacity) {
+    if (!c || capacity < 0 || !std::isfinite(z) || !std::isfinite(rho)) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        dfree(c, c->fs.probe);
+        c->fs.probe = nullptr;
+        c->fs.probe_face = -1;
+        c->fs.probe_cap = 0;
+        drop_graphs(c);
+        if (capacity == 0) return AXP_OK;
+        double lam[3];
+        const int32_t t = locate_point(c->hm, z, rho, lam);
+        if (t < 0) throw ApiError{AXP_E_ARG, "probe outside the mesh"};
+        c->fs.probe = zeros<double>(c, size_t(2) * size_t(capacity));
+        c->fs.probe_face = t;
+        c->fs.probe_l0 = lam[0];
+        c->fs.probe_l1 = lam[1];
+        c->fs.probe_cap = capacity;
+        c->fs.probe_start = c->step;
+        c->fs.dt = c->dt;
+        return AXP_OK;
+    });
+}
+
+axp_status axp_get_probe(axp_ctx *c, int64_t capacity, int64_t *n, double *E_z_rho) {
+    if (!c || !n || capacity < 0) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        *n = 0;
+        if (c->fs.probe_face < 0) return AXP_OK;
+        const int64_t have = std::min<int64_t>(c->step - c->fs.probe_start, c->fs.probe_cap);
+        *n = have;
+        if (!E_z_rho) return AXP_OK;
+        if (have > capacity) return fail(c, AXP_E_ARG, "capacity too small");
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        if (have > 0)
+            hcheck(hipMemcpy(E_z_rho, c->fs.probe, size_t(have) * 2 * sizeof(double), hipMemcpyDeviceToHost), "probe");
         return AXP_OK;
     });
 }
@@ -1500,6 +1581,8 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
         if (c->cfg.pusher != ctxs[0]->cfg.pusher) return fail(c, AXP_E_ARG, "batch members must share a pusher");
         if (c->species.empty()) return fail(c, AXP_E_STATE, "batch members need a species");
         if (c->inj_on) return fail(c, AXP_E_ARG, "batch members cannot carry a continuous injector");
+        if (c->fs.n_src > 0 || c->fs.probe_face >= 0)
+            return fail(c, AXP_E_ARG, "batch members cannot carry point sources or a probe");
     }
     auto *b = new (std::nothrow) axp_batch();
     if (!b) return AXP_E_OOM;

@@ -63,7 +63,26 @@ struct DevCounters {
     unsigned long long nan_count;
     unsigned long long fixed_overflow;
     unsigned long long inj_step;      // step index of the next emission (random-stream counter)
-    unsigned long long pad[2];
+    unsigned long long step;          // index n of the step in flight (time t^n = n dt of sources and probe)
+    unsigned long long pad;
+};
+
+constexpr int kMaxSources = 8;
+
+// Magnetic point sources and the field probe (Sec. 5.1), passed by value to
+// the face pass.  Source k adds -dt M_k(t^n) to the flux of face src_face[k],
+// M_k(t) = amp exp(-((t - t0) / (2 sig))^2) cos(w (t - t0)); the probe writes
+// (E_z, E_rho) at barycentric (probe_l0, probe_l1) of probe_face at t^n into
+// probe[2 (n - probe_start) + {0, 1}] while that index is below probe_cap.
+struct FieldSrc {
+    int32_t n_src = 0;
+    int32_t src_face[kMaxSources] = {};
+    double amp[kMaxSources] = {}, t0[kMaxSources] = {}, sig[kMaxSources] = {}, w[kMaxSources] = {};
+    double dt = 0.0;
+    int32_t probe_face = -1;
+    double probe_l0 = 0.0, probe_l1 = 0.0;
+    double *probe = nullptr;
+    long long probe_cap = 0, probe_start = 0;
 };
 
 struct DevDiag {
@@ -151,7 +170,7 @@ struct DevPlain {
 };
 
 // ---- launchers (kernels_mixed.hip) ----
-void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st);
+void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, hipStream_t st);
 // gather, push and walk of every particle, with the charge-conserving current
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
                       hipStream_t st);
@@ -171,7 +190,8 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
                          void *const *dst, hipStream_t st);
 
 // ---- launchers (kernels_plain.hip) ----
-void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
+void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, const FieldSrc &fs,
+                           hipStream_t st);
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
                             bool count, bool vay, hipStream_t st);
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);

@@ -39,7 +39,14 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
 __device__ __forceinline__ int sel3(int k, int a, int b, int c) { return k == 0 ? a : (k == 1 ? b : c); }
 
 // ------------------------------------------------------------------ faces
-__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s) {
+// magnetic current of point source k at step n (Sec. 5.1)
+__device__ __forceinline__ double source_current(const FieldSrc &fs, int k, unsigned long long n) {
+    const double tt = double(n) * fs.dt - fs.t0[k];
+    const double a = tt / (2.0 * fs.sig[k]);
+    return fs.amp[k] * exp(-a * a) * cos(fs.w[k] * tt);
+}
+
+__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.n2) return;
     const int4 e = m.tedge[t];
@@ -50,7 +57,9 @@ __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s) {
     if (e.w & 2) E1 = -E1;
     if (e.w & 4) E2 = -E2;
     const double bo = s.B[t];
-    const double bn = bo - dt * ((double)E0 + (double)E1 + (double)E2);   // circulation along the CCW boundary
+    double bn = bo - dt * ((double)E0 + (double)E1 + (double)E2);   // circulation along the CCW boundary
+    for (int k = 0; k < fs.n_src; ++k)
+        if (t == fs.src_face[k]) bn -= dt * source_current(fs, k, s.ctr->step);
     s.B[t] = bn;
     s.Bprev[t] = bo;
     s.HBdt[t] = m.Hdt[t] * bn;
@@ -70,6 +79,14 @@ __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s) {
     f1.w = 0.0f;
     s.f0[t] = f0;
     s.f1[t] = f1;
+    if (t == fs.probe_face) {                   // E^n at the probe point (Whitney gather)
+        const long long i = (long long)s.ctr->step - fs.probe_start;
+        if (i >= 0 && i < fs.probe_cap) {
+            const double l0 = fs.probe_l0, l1 = fs.probe_l1, l2 = 1.0 - l0 - l1;
+            fs.probe[2 * i] = l0 * f0.x + l1 * f0.z + l2 * f1.x;
+            fs.probe[2 * i + 1] = l0 * f0.y + l1 * f0.w + l2 * f1.y;
+        }
+    }
     s.Jloc[3 * t] = 0ull;
     s.Jloc[3 * t + 1] = 0ull;
     s.Jloc[3 * t + 2] = 0ull;
@@ -588,6 +605,7 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
 // bit 4 left sign negative, bit 5 right sign negative, bit 6 free edge.
 __global__ __launch_bounds__(256) void k_edge_pass(DevMesh m, DevState s, int keep_j) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) s.ctr->step = s.ctr->step + 1ull;   // the face pass of this step has read it
     if (e >= m.n1) return;
     const int4 et = m.etri[e];
     const int inst = et.w;
@@ -973,9 +991,9 @@ __global__ __launch_bounds__(256) void k_energy_kin_final(DevState s, const doub
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-void launch_tri_pass(const DevMesh &m, DevState &s, hipStream_t st) {
+void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s);
+    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s, fs);
 }
 
 // single: one instance with one species whose charge multiple is 1; its

@@ -31,7 +31,7 @@ __device__ __forceinline__ void fadd(double *a, double v) {
     if (v != 0.0) unsafeAtomicAdd(a, v);       // hardware FP64 atomic add
 }
 
-__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt) {
+__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt, FieldSrc fs) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.n2) return;
     const int4 e = m.tedge[t];
@@ -40,7 +40,13 @@ __global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPl
     if (e.w & 2) E1 = -E1;
     if (e.w & 4) E2 = -E2;
     const double bo = s.B[t];
-    const double bn = bo - dt * (E0 + E1 + E2);
+    double bn = bo - dt * (E0 + E1 + E2);
+    for (int k = 0; k < fs.n_src; ++k)          // magnetic point sources (Sec. 5.1)
+        if (t == fs.src_face[k]) {
+            const double tt = double(s.ctr->step) * fs.dt - fs.t0[k];
+            const double a = tt / (2.0 * fs.sig[k]);
+            bn -= dt * fs.amp[k] * exp(-a * a) * cos(fs.w[k] * tt);
+        }
     s.B[t] = bn;
     s.Bprev[t] = bo;
     s.HBdt[t] = m.Hdt[t] * bn;
@@ -59,6 +65,14 @@ __global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPl
     f1.w = 0.0;
     p.f0[t] = f0;
     p.f1[t] = f1;
+    if (t == fs.probe_face) {                   // E^n at the probe point (Whitney gather)
+        const long long i = (long long)s.ctr->step - fs.probe_start;
+        if (i >= 0 && i < fs.probe_cap) {
+            const double l0 = fs.probe_l0, l1 = fs.probe_l1, l2 = 1.0 - l0 - l1;
+            fs.probe[2 * i] = l0 * f0.x + l1 * f0.z + l2 * f1.x;
+            fs.probe[2 * i + 1] = l0 * f0.y + l1 * f0.w + l2 * f1.y;
+        }
+    }
     p.Jloc[3 * t] = 0.0;
     p.Jloc[3 * t + 1] = 0.0;
     p.Jloc[3 * t + 2] = 0.0;
@@ -471,6 +485,7 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
 
 __global__ __launch_bounds__(256) void k_edge_pass_d(DevMesh m, DevState s, DevPlain p, double qunit) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) s.ctr->step = s.ctr->step + 1ull;   // the face pass of this step has read it
     if (e >= m.n1) return;
     const int4 et = m.etri[e];
     const int kl = et.z & 3, kr = (et.z >> 2) & 3;
@@ -644,9 +659,10 @@ inline unsigned nb_(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 
 }  // namespace
 
-void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {
+void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, const FieldSrc &fs,
+                           hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt);
+    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt, fs);
 }
 
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
