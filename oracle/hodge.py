@@ -52,14 +52,20 @@ def _int_lam3(i, j, k, area):
     return 2.0 * area * num / factorial(sum(cnt) + 2)
 
 
-def local_eps_matrix(nodes_T, edge_local):
+def local_eps_matrix(nodes_T, edge_local, component=None):
     """Local [*eps]/eps0 of one triangle (3x3) for sides given as oriented
-    local node pairs edge_local[k] = (a, b): W1_k = lam_a grad lam_b - lam_b grad lam_a."""
+    local node pairs edge_local[k] = (a, b): W1_k = lam_a grad lam_b - lam_b grad lam_a.
+    component 'z' or 'rho' keeps only that component of W1_k . W1_l (the two
+    parts add up to the whole; used by the stretched-coordinate layer)."""
     tri = np.array([[0, 1, 2]])
     g, area = grad_lambda(np.asarray(nodes_T, float), tri)
     g, area = g[0], float(area[0])
     rho = np.asarray(nodes_T, float)[:, 1]
-    gg = g @ g.T
+    if component is None:
+        gg = g @ g.T
+    else:
+        c = {"z": 0, "rho": 1}[component]
+        gg = np.outer(g[:, c], g[:, c])
     T = np.zeros((3, 3))
     for k, (a, b) in enumerate(edge_local):
         for l, (c, d) in enumerate(edge_local):
@@ -71,6 +77,27 @@ def local_eps_matrix(nodes_T, edge_local):
                                + _int_lam3(m, b, d, area) * gg[a, c])
             T[k, l] = s
     return T
+
+
+def _local_edges(topo, t):
+    tri = topo.tris[t]
+    loc = []
+    for k in range(3):
+        tail, head = topo.edges[topo.tri_edges[t, k]]
+        loc.append((int(np.where(tri == tail)[0][0]), int(np.where(tri == head)[0][0])))
+    return loc
+
+
+def pml_parts(topo: Topology, faces):
+    """eps0 times the z and rho parts of the local [*eps] of the given faces:
+    two (len(faces), 3, 3) arrays over each face's sides k = 0, 1, 2."""
+    Az = np.zeros((len(faces), 3, 3))
+    Ar = np.zeros((len(faces), 3, 3))
+    for i, t in enumerate(faces):
+        loc = _local_edges(topo, t)
+        Az[i] = EPS0 * local_eps_matrix(topo.nodes[topo.tris[t]], loc, "z")
+        Ar[i] = EPS0 * local_eps_matrix(topo.nodes[topo.tris[t]], loc, "rho")
+    return Az, Ar
 
 
 def hodge_eps(topo: Topology) -> sp.csr_matrix:

@@ -50,7 +50,7 @@ def _load():
     if _lib is None:
         _lib = C.CDLL(build_oracle())
         vp = C.c_void_p
-        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp] + [vp] * 8
+        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp, vp] + [vp] * 8
         _lib.oracle_step.restype = None
         _lib.oracle_charge.argtypes = [vp, vp, vp, vp]
         _lib.oracle_sample.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -77,20 +77,74 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+class _OPml(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in ("face", "beta", "Az", "Ar", "h", "q", "eprev")]
+
+
+def pml_sigma(topo, z_left, z_right, sigma_max, order):
+    """Conductivity of the absorbing layers on each face (at its centroid):
+    sigma_max (depth / thickness)^order beyond z_left (towards smaller z) and
+    beyond z_right, 0 in between."""
+    zc = topo.nodes[topo.tris][:, :, 0].mean(axis=1)
+    z0, z1 = topo.nodes[:, 0].min(), topo.nodes[:, 0].max()
+    sig = np.zeros(topo.n2)
+    if z_left is not None and z_left > z0:
+        m = zc < z_left
+        sig[m] = sigma_max * ((z_left - zc[m]) / (z_left - z0)) ** order
+    if z_right is not None and z_right < z1:
+        m = zc > z_right
+        sig[m] = sigma_max * ((zc[m] - z_right) / (z1 - z_right)) ** order
+    return sig
+
+
 class OracleSim:
     """Plain FP64 simulation of one meridian device."""
 
     def __init__(self, nodes, tris, seg, tag, dt=None, bz=0.0, spai_level=3, drop_tol=1e-3,
-                 cfl_fraction=0.5, M=None):
+                 cfl_fraction=0.5, M=None, pml=None):
+        """pml: optional dict(z_left, z_right, sigma_max, order) of the
+        stretched-coordinate absorbing layers at the two ends (the time step
+        is fixed first, without the layers; M is then the SPAI of the
+        stretched Hodge)."""
         t0 = time.perf_counter()
         self.topo = build_topology(nodes, tris, seg, tag)
         self.A = hodge_eps(self.topo)
         self.H = hodge_mu_inv(self.topo)
-        self.M = M if M is not None else spai(self.A, self.topo.edge_free, spai_level, drop_tol)
+        if pml is not None and dt is None:
+            if M is not None:
+                raise ValueError("with absorbing layers and a given M, give dt too")
+            M0 = sp.csr_matrix(spai(self.A, self.topo.edge_free, spai_level, drop_tol))
+            dt = cfl_fraction * cfl_dt(self.topo, self.H, M0)[0]
+        self.pml = None
+        self._pml_c = None
+        self.K = self.A
+        if pml is not None:
+            from .hodge import pml_parts
+            sig = pml_sigma(self.topo, pml.get("z_left"), pml.get("z_right"), pml["sigma_max"], pml.get("order", 3))
+            faces = np.flatnonzero(sig > 0).astype(np.int64)
+            beta = sig[faces] * dt / (2.0 * EPS0)
+            Az, Ar = pml_parts(self.topo, faces)
+            rows, cols, vals = [], [], []
+            for i, t in enumerate(faces):
+                ed = self.topo.tri_edges[t]
+                dK = beta[i] * Ar[i] + (1.0 / (1.0 + beta[i]) - 1.0) * Az[i]
+                for k in range(3):
+                    for l in range(3):
+                        rows.append(ed[k]); cols.append(ed[l]); vals.append(dK[k, l])
+            self.K = (self.A + sp.csr_matrix((vals, (rows, cols)), shape=self.A.shape)).tocsr()
+            self.pml = dict(face=faces, beta=np.ascontiguousarray(beta), Az=np.ascontiguousarray(Az.reshape(-1, 9)),
+                            Ar=np.ascontiguousarray(Ar.reshape(-1, 9)), h=np.zeros(len(faces)),
+                            q=np.zeros((len(faces), 3)), eprev=np.zeros((len(faces), 3)), sigma=sig)
+        self.M = M if M is not None else spai(self.K, self.topo.edge_free, spai_level, drop_tol)
         self.M = sp.csr_matrix(self.M)
         self.M.sort_indices()
         self.dt_cfl, self.lam_max = cfl_dt(self.topo, self.H, self.M)
         self.dt = float(dt) if dt is not None else cfl_fraction * self.dt_cfl
+        if self.pml is not None:
+            if self.dt > self.dt_cfl:
+                raise ValueError(f"dt {self.dt:.3e} above the stability limit {self.dt_cfl:.3e} of the layered scheme")
+            P = self.pml
+            self._pml_c = _OPml(len(P["face"]), *[_p(P[k]) for k in ("face", "beta", "Az", "Ar", "h", "q", "eprev")])
         self.bz = float(bz)
         self.pusher = 0                    # 0 relativistic Boris, 1 Vay
         self.sources = []                  # magnetic point sources: (face, amplitude, t0, sigma, omega)
@@ -147,6 +201,13 @@ class OracleSim:
         self.E = np.where(free, np.asarray(E0, dtype=np.float64), 0.0)
         self.B = np.asarray(B_mhalf, dtype=np.float64).copy()
         self.D = self.eps_a(self.E)
+        if self.pml is not None:
+            # layer state of fields at rest: h = H B, q = A_z e, e^{-1} = e^0
+            P = self.pml
+            P["h"][:] = self.H[P["face"]] * self.B[P["face"]]
+            ed = self.topo.tri_edges[P["face"]]
+            P["eprev"][:] = self.E[ed]
+            P["q"][:] = np.einsum("ikl,il->ik", P["Az"].reshape(-1, 3, 3), self.E[ed])
 
     def eps_a(self, E):
         """[*eps]_a E = M^-1 E on free edges (sparse direct solve)."""
@@ -268,6 +329,7 @@ class OracleSim:
             src_val = self._source_values()
             lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz, int(self.pusher),
                             len(src_face), _p(src_face), _p(src_val),
+                            None if self._pml_c is None else C.byref(self._pml_c),
                             _p(self.E), _p(self.B), _p(self.D), _p(self.J), _p(self.Qres),
                             _p(self._Bh), _p(self._rhs), _p(self.stats))
             self.n_step += 1

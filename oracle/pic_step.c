@@ -264,6 +264,24 @@ static int walk(const omesh *m, oparticles *P, int64_t p, double ze, double re,
     return -1;
 }
 
+/* Stretched-coordinate absorbing layer (the PML of the ports, Sec. 5.3):
+ * the z coordinate is stretched by s_z = 1 + sigma / (j omega eps0) on the
+ * layer's faces, i.e. eps_rho = eps0 s_z, eps_z = eps0 / s_z, mu_phi = mu0 s_z.
+ * Per layer face f (n faces), beta = sigma dt / (2 eps0); Az, Ar: the z and
+ * rho parts of eps0 int rho W1_k . W1_l over the face (3x3, its sides k, l);
+ * h: the face's H-image flux (H B / s_z), q: (A_z / s_z) e on its sides,
+ * eprev: its side values of E at the previous step. */
+typedef struct {
+    int64_t n;
+    const int64_t *face;
+    const double *beta;
+    const double *Az;     /* [n][9] */
+    const double *Ar;     /* [n][9] */
+    double *h;            /* [n] */
+    double *q;            /* [n][3] */
+    double *eprev;        /* [n][3] */
+} opml;
+
 /*
  * One step.  E: E^n (n1) -> E^{n+1}.  B: B^{n-1/2} (n2) -> B^{n+1/2}.
  * D: D^n -> D^{n+1}.  J (n1) receives J^{n+1/2}.  Qres (n0) accumulates
@@ -273,7 +291,7 @@ static int walk(const omesh *m, oparticles *P, int64_t p, double ze, double re,
  * sources' faces and their magnetic currents at t^n.
  */
 void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher,
-                 int64_t nsrc, const int64_t *src_face, const double *src_val,
+                 int64_t nsrc, const int64_t *src_face, const double *src_val, const opml *pml,
                  double *E, double *B, double *D, double *J, double *Qres,
                  double *Bh, double *rhs, int64_t *stats)
 {
@@ -309,20 +327,70 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher
         if (nseg > 0) stats[0] += nseg;
     }
 
-    /* 5. Ampere: rhs = C^T H B^{n+1/2} - J on free edges */
+    /* 5. Ampere: rhs = C^T H B^{n+1/2} - J on free edges; in the absorbing
+     *    layer the face's H-image obeys s_z h = H B, integrated by the
+     *    trapezoidal rule: h^{n+1/2} = ((1 - beta) h^{n-1/2} + H (B^{n+1/2} - B^{n-1/2})) / (1 + beta) */
     memset(rhs, 0, sizeof(double) * m->n1);
-    for (int64_t t = 0; t < m->n2; ++t)
+    for (int64_t t = 0; t < m->n2; ++t) {
+        double hb = m->H[t] * Bh[t];
         for (int k = 0; k < 3; ++k)
-            rhs[m->tri_edges[3 * t + k]] += (double)m->tri_signs[3 * t + k] * m->H[t] * Bh[t];
+            rhs[m->tri_edges[3 * t + k]] += (double)m->tri_signs[3 * t + k] * hb;
+    }
+    if (pml)
+        for (int64_t i = 0; i < pml->n; ++i) {
+            int64_t t = pml->face[i];
+            double b = pml->beta[i];
+            double hn = ((1.0 - b) * pml->h[i] + m->H[t] * (Bh[t] - B[t])) / (1.0 + b);
+            double dh = hn - m->H[t] * Bh[t];          /* replace H B by h on this face */
+            for (int k = 0; k < 3; ++k)
+                rhs[m->tri_edges[3 * t + k]] += (double)m->tri_signs[3 * t + k] * dh;
+            pml->h[i] = hn;
+        }
     for (int64_t e = 0; e < m->n1; ++e)
         rhs[e] = m->edge_free[e] ? rhs[e] - J[e] : 0.0;
-    for (int64_t e = 0; e < m->n1; ++e) {
-        if (!m->edge_free[e]) { E[e] = 0.0; continue; }
-        double acc = 0.0;
-        for (int64_t j = m->m_ptr[e]; j < m->m_ptr[e + 1]; ++j)
-            acc += m->m_val[j] * rhs[m->m_col[j]];
-        E[e] += dt * acc;
-        D[e] += dt * rhs[e];
+    if (!pml) {
+        for (int64_t e = 0; e < m->n1; ++e) {
+            if (!m->edge_free[e]) { E[e] = 0.0; continue; }
+            double acc = 0.0;
+            for (int64_t j = m->m_ptr[e]; j < m->m_ptr[e + 1]; ++j)
+                acc += m->m_val[j] * rhs[m->m_col[j]];
+            E[e] += dt * acc;
+            D[e] += dt * rhs[e];
+        }
+    } else {
+        /* D-form with the layer: D is the quantity with E = M D, M the SPAI
+         * of the stretched Hodge sum_T [(1 + beta) A_rho + A_z / (1 + beta)].
+         * After E^{n+1} = M (D^n + dt rhs), each layer face updates
+         *   q^{n+1} = ((1 - beta) q^n + A_z (e^{n+1} - e^n)) / (1 + beta)
+         *   D      -= 2 beta (A_rho e^{n+1} - q^{n+1} / (1 + beta))   on its sides */
+        for (int64_t e = 0; e < m->n1; ++e) D[e] = m->edge_free[e] ? D[e] + dt * rhs[e] : 0.0;
+        for (int64_t e = 0; e < m->n1; ++e) {
+            if (!m->edge_free[e]) { E[e] = 0.0; continue; }
+            double acc = 0.0;
+            for (int64_t j = m->m_ptr[e]; j < m->m_ptr[e + 1]; ++j)
+                acc += m->m_val[j] * D[m->m_col[j]];
+            E[e] = acc;
+        }
+        for (int64_t i = 0; i < pml->n; ++i) {
+            int64_t t = pml->face[i];
+            double b = pml->beta[i], en[3], de[3];
+            for (int k = 0; k < 3; ++k) {
+                en[k] = E[m->tri_edges[3 * t + k]];
+                de[k] = en[k] - pml->eprev[3 * i + k];
+            }
+            for (int k = 0; k < 3; ++k) {
+                double az = 0.0, ar = 0.0;
+                for (int l = 0; l < 3; ++l) {
+                    az += pml->Az[9 * i + 3 * k + l] * de[l];
+                    ar += pml->Ar[9 * i + 3 * k + l] * en[l];
+                }
+                double qn = ((1.0 - b) * pml->q[3 * i + k] + az) / (1.0 + b);
+                pml->q[3 * i + k] = qn;
+                int64_t e = m->tri_edges[3 * t + k];
+                if (m->edge_free[e]) D[e] -= 2.0 * b * (ar - qn / (1.0 + b));
+            }
+            for (int k = 0; k < 3; ++k) pml->eprev[3 * i + k] = en[k];
+        }
     }
     memcpy(B, Bh, sizeof(double) * m->n2);
 }
