@@ -140,6 +140,7 @@ typedef struct {
     double spai_kept_resid_mean;     /* same after refinement, over the columns kept */
     double spai_energy_drift;        /* learned SPAI: relative energy drift of the guard run */
     double spai_seconds;             /* host time of the SPAI construction */
+    int64_t n_layer_faces;           /* faces of the absorbing layers (axp_set_layers) */
 } axp_info;
 
 typedef struct {
@@ -218,6 +219,27 @@ axp_status axp_set_fields(axp_ctx *ctx, const double *E0, const double *B_mhalf)
  * AXP_E_STATE before axp_build; AXP_E_NAN for a non-finite potential;
  * AXP_E_SPAI if the solve does not converge (fields unchanged). */
 axp_status axp_set_electrostatic(axp_ctx *ctx, const double *phi_conductor, int32_t with_charge, double *phi_out);
+
+/* Absorbing layers at the z ends of the domain (the PML terminating the
+ * ports and the cathode side, Sec. 5.3), set before axp_build.  The layers
+ * stretch z by s_z = 1 + sigma / (j omega eps0), i.e. the meridian medium
+ * becomes eps_rho = eps0 s_z, eps_z = eps0 / s_z, mu_phi = mu0 s_z; sigma
+ * grows as sigma_max (depth / thickness)^order from the layer's inner face
+ * to the end of the mesh (faces with their centroid below z_left when bit 0
+ * of sides is set, above z_right when bit 1 is set; sigma evaluated at the
+ * centroid).  The step keeps D with E = M D, M the SPAI of the stretched
+ * Hodge sum_T [(1 + beta) A_rho + A_z / (1 + beta)], beta = sigma dt /
+ * (2 eps0), with auxiliary values on the layer faces: h (s_z h = H B) and
+ * q (s_z q = A_z e), both by the trapezoidal rule, and the correction
+ * D -= 2 beta (A_rho e - q / (1 + beta)) after E = M D.  The time step is
+ * fixed first without the layers (axp_config), the stability limit checked
+ * again with them (AXP_E_UNSTABLE).  The outer end of a layer should be a
+ * conductor.  sigma_max [S/m] = 0 removes the layers.  Inside the layers
+ * the conduction current changes the Gauss residual; outside it is kept.
+ * Contexts with layers need the least-squares SPAI, cannot join a batch
+ * and cannot be saved.  Errors: AXP_E_ARG (sides outside 0..3, order
+ * outside 0..8, negative or non-finite values), AXP_E_STATE after axp_build. */
+axp_status axp_set_layers(axp_ctx *ctx, int32_t sides, double z_left, double z_right, double sigma_max, int32_t order);
 
 /* Magnetic point source (Sec. 5.1): a magnetic current M(t) at (z, rho)
  * [m], a ring about the axis, drives the flux of the face holding the

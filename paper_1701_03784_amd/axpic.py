@@ -52,7 +52,8 @@ class Info(C.Structure):
                 ("particle_capacity", C.c_int64), ("n_particles", C.c_int64), ("step", C.c_int64),
                 ("precision", C.c_int32), ("n_species", C.c_int32), ("spai_mode", C.c_int32), ("pad_", C.c_int32),
                 ("spai_fallback_columns", C.c_int64), ("spai_pred_resid_mean", C.c_double),
-                ("spai_kept_resid_mean", C.c_double), ("spai_energy_drift", C.c_double), ("spai_seconds", C.c_double)]
+                ("spai_kept_resid_mean", C.c_double), ("spai_energy_drift", C.c_double), ("spai_seconds", C.c_double),
+                ("n_layer_faces", C.c_int64)]
 
 
 class Diag(C.Structure):
@@ -64,7 +65,7 @@ class Diag(C.Structure):
 
 
 EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary", "axp_build",
-           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_electrostatic", "axp_add_point_source",
+           "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_electrostatic", "axp_set_layers", "axp_add_point_source",
            "axp_clear_point_sources", "axp_set_probe", "axp_get_probe", "axp_set_external_bz",
            "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH):
         "axp_get_spai": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
         "axp_set_fields": (i32, [vp, vp, vp]),
         "axp_set_electrostatic": (i32, [vp, vp, i32, vp]),
+        "axp_set_layers": (i32, [vp, i32, dbl, dbl, dbl, i32]),
         "axp_add_point_source": (i32, [vp, dbl, dbl, dbl, dbl, dbl, dbl]),
         "axp_clear_point_sources": (i32, [vp]),
         "axp_set_probe": (i32, [vp, dbl, dbl, i64]),
@@ -400,11 +402,18 @@ class Ctx:
         return zr[:n.value], u[:n.value], sp[:n.value]
 
 
-def make_ctx(mesh, spai_model=None, spai_row_tol=0.01, spai_energy_tol=1e-6, spai_iters=3, **kw):
-    """Context with mesh and boundary set and built (mesh: synth.Mesh-like)."""
+def make_ctx(mesh, spai_model=None, spai_row_tol=0.01, spai_energy_tol=1e-6, spai_iters=3, layers=None, **kw):
+    """Context with mesh and boundary set and built (mesh: synth.Mesh-like).
+    layers: optional dict(z_left=None, z_right=None, sigma_max, order=3) of
+    absorbing layers (axp_set_layers)."""
     c = Ctx(**kw)
     c.set_mesh(mesh.nodes, mesh.tris)
     c.set_boundary(mesh.seg, mesh.tag)
+    if layers is not None:
+        zl, zr = layers.get("z_left"), layers.get("z_right")
+        sides = (1 if zl is not None else 0) | (2 if zr is not None else 0)
+        c._check(c.lib.axp_set_layers(c.h, sides, float(zl or 0.0), float(zr or 0.0), float(layers["sigma_max"]),
+                                      int(layers.get("order", 3))))
     if spai_model is not None:
         c.set_spai_model(spai_model, spai_row_tol, spai_energy_tol, spai_iters)
     c.build()

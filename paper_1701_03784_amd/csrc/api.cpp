@@ -75,6 +75,10 @@ struct axp_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int graph_window = 0;
+    // stretched-coordinate absorbing layers
+    LayerConfig layer_cfg{};
+    HostLayers hl{};
+    DevLayers dl{};
     // magnetic point sources and field probe (Sec. 5.1)
     FieldSrc fs{};
     unsigned long long step_upload = 0;   // host image of the device step counter (async copy source)
@@ -429,7 +433,66 @@ void build_device(axp_ctx *c) {
     c->ic.dt = c->dt;
     c->ic.cdt = float(kC * c->dt);
     upload_inst(c);
+    const HostLayers &L = c->hl;
+    std::vector<int32_t> face_layer;
+    std::vector<double> Hf;
+    std::vector<int4> ledges;
+    if (!L.face.empty()) {
+        const int nl = int(L.face.size());
+        face_layer.assign(m.n2, -1);
+        Hf.resize(nl);
+        std::vector<int4> byedge(m.n1, make_int4(-1, -1, -1, 0));
+        for (int i = 0; i < nl; ++i) {
+            const int t = L.face[i];
+            face_layer[t] = i;
+            Hf[i] = m.H[t];
+            for (int k = 0; k < 3; ++k) {
+                int4 &r = byedge[m.tedge[t][k]];
+                if (r.y < 0) r.y = 4 * i + k;
+                else r.z = 4 * i + k;
+            }
+        }
+        for (int e = 0; e < m.n1; ++e)
+            if (byedge[e].y >= 0) ledges.push_back(make_int4(e, byedge[e].y, byedge[e].z, 0));
+        DevLayers &d = c->dl;
+        d.n = nl;
+        d.n_edges = int32_t(ledges.size());
+        d.face = upload(c, L.face);
+        d.face_layer = upload(c, face_layer);
+        d.beta = upload(c, L.beta);
+        d.Hf = upload(c, Hf);
+        d.Az = upload(c, L.Az);
+        d.Ar = upload(c, L.Ar);
+        d.h = zeros<double>(c, nl);
+        d.q = zeros<double>(c, size_t(3) * nl);
+        d.eprev = zeros<double>(c, size_t(3) * nl);
+        d.corr = zeros<double>(c, size_t(3) * nl);
+        d.edges = upload(c, ledges);
+    }
     hcheck(hipStreamSynchronize(c->stream), "build sync");
+}
+
+// Layer state of fields at rest (E, B in internal order): h = H B, eprev = e,
+// q = A_z e on each layer face.
+void layers_at_rest(axp_ctx *c, const std::vector<double> &E, const std::vector<double> &B) {
+    const HostLayers &L = c->hl;
+    const int nl = int(L.face.size());
+    if (nl == 0) return;
+    const HostMesh &m = c->hm;
+    std::vector<double> h(nl), q(size_t(3) * nl), ep(size_t(3) * nl);
+    for (int i = 0; i < nl; ++i) {
+        const int t = L.face[i];
+        h[i] = m.H[t] * B[t];
+        double e[3];
+        for (int k = 0; k < 3; ++k) e[k] = ep[3 * i + k] = E[m.tedge[t][k]];
+        for (int k = 0; k < 3; ++k)
+            q[3 * i + k] = L.Az[9 * i + 3 * k] * e[0] + L.Az[9 * i + 3 * k + 1] * e[1] + L.Az[9 * i + 3 * k + 2] * e[2];
+    }
+    hcheck(hipMemcpyAsync(c->dl.h, h.data(), sizeof(double) * nl, hipMemcpyHostToDevice, c->stream), "layer h");
+    hcheck(hipMemcpyAsync(c->dl.q, q.data(), sizeof(double) * 3 * nl, hipMemcpyHostToDevice, c->stream), "layer q");
+    hcheck(hipMemcpyAsync(c->dl.eprev, ep.data(), sizeof(double) * 3 * nl, hipMemcpyHostToDevice, c->stream),
+           "layer e");
+    hcheck(hipStreamSynchronize(c->stream), "sync");
 }
 
 
@@ -444,28 +507,36 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
         else launch_inject(m, s, c->inj_edges, c->inj, st);
     }
     if (c->plain) {
-        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, c->fs, st); }
+        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, c->fs, c->dl, st); }
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
         {
             PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
             launch_particles_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, c->cfg.pusher == AXP_PUSH_VAY, st);
         }
         { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
-        { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv_plain(m, s, c->dp, st); }
+        {
+            PhaseScope ps(c, AXP_PHASE_SPMV, st);
+            launch_spmv_plain(m, s, c->dp, st);
+            launch_layers_post(m, s, (const double *)c->dp.E, c->dl, st);
+        }
         ++c->step;
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_plain(m, s, c->dp, true, st); }
         return;
     }
     const bool single = m.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
     const InstConst *k0 = single ? &c->ic : nullptr;
-    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, c->fs, st); }
+    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, c->fs, c->dl, st); }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
         PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
         launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, st);
     }
     { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, st); }
-    { PhaseScope ps(c, AXP_PHASE_SPMV, st); launch_spmv(m, s, st); }
+    {
+        PhaseScope ps(c, AXP_PHASE_SPMV, st);
+        launch_spmv(m, s, st);
+        launch_layers_post(m, s, (const float *)s.E, c->dl, st);
+    }
     ++c->step;
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort(m, s, true, st); }
 }
@@ -645,6 +716,18 @@ axp_status axp_build(axp_ctx *c) {
                 c->dt = c->cfg.dt > 0 ? c->cfg.dt : c->cfg.cfl_fraction * c->dt_cfl;
             }
         }
+        if (c->layer_cfg.sides) {
+            // the time step is fixed without the layers; the SPAI then inverts
+            // the stretched Hodge, and the stability limit is that of the result
+            if (c->spai_model) throw ApiError{AXP_E_ARG, "absorbing layers need the least-squares SPAI"};
+            if (!(c->dt > 0)) throw ApiError{AXP_E_UNSTABLE, "no time step"};
+            Csr K;
+            build_layers(m, c->dt, c->layer_cfg, c->hl, K);
+            std::swap(m.A, K);
+            build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+            std::swap(m.A, K);
+            c->dt_cfl = cfl_dt(m, 400);
+        }
         if (!(c->dt > 0) || c->dt > c->dt_cfl * (1.0 + 1e-9))
             throw ApiError{AXP_E_UNSTABLE, "dt " + std::to_string(c->dt) + " exceeds the stability limit " +
                                                std::to_string(c->dt_cfl)};
@@ -674,6 +757,7 @@ axp_status axp_info_get(const axp_ctx *c, axp_info *out) {
     out->spai_kept_resid_mean = c->spai_stats.kept_resid_mean;
     out->spai_energy_drift = c->spai_energy_drift;
     out->spai_seconds = c->spai_seconds;
+    out->n_layer_faces = int64_t(c->hl.face.size());
     return c->built ? AXP_OK : AXP_E_STATE;
 }
 
@@ -736,10 +820,24 @@ axp_status axp_set_fields(axp_ctx *c, const double *E0, const double *B_mhalf) {
             hcheck(hipMemcpyAsync(s.E, E32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "E");
         }
         hcheck(hipStreamSynchronize(c->stream), "sync");
+        layers_at_rest(c, E, B);
         c->g0_set = false;
         c->last_diag_step = -1;
         return AXP_OK;
     });
+}
+
+axp_status axp_set_layers(axp_ctx *c, int32_t sides, double z_left, double z_right, double sigma_max, int32_t order) {
+    if (!c || sides < 0 || sides > 3 || !std::isfinite(z_left) || !std::isfinite(z_right) || !(sigma_max >= 0.0) ||
+        !std::isfinite(sigma_max) || order < 0 || order > 8)
+        return AXP_E_ARG;
+    if (c->built) return fail(c, AXP_E_STATE, "absorbing layers are set before axp_build");
+    c->layer_cfg.sides = sigma_max > 0.0 ? sides : 0;
+    c->layer_cfg.z_left = z_left;
+    c->layer_cfg.z_right = z_right;
+    c->layer_cfg.sigma_max = sigma_max;
+    c->layer_cfg.order = order;
+    return AXP_OK;
 }
 
 axp_status axp_set_electrostatic(axp_ctx *c, const double *phi_conductor, int32_t with_charge, double *phi_out) {
@@ -785,6 +883,7 @@ axp_status axp_set_electrostatic(axp_ctx *c, const double *phi_conductor, int32_
             hcheck(hipMemcpyAsync(s.E, E32.data(), m.n1 * 4, hipMemcpyHostToDevice, c->stream), "E");
         }
         hcheck(hipStreamSynchronize(c->stream), "sync");
+        layers_at_rest(c, E, B);
         c->g0_set = false;
         c->last_diag_step = -1;
         if (phi_out) std::memcpy(phi_out, phi.data(), sizeof(double) * m.n0);
@@ -1301,6 +1400,7 @@ axp_status axp_save(axp_ctx *c, const char *path) {
     if (!c || !path) return AXP_E_ARG;
     return guarded(c, [&]() -> axp_status {
         require_built(c);
+        if (c->dl.n) throw ApiError{AXP_E_STATE, "checkpoints of contexts with absorbing layers are not supported"};
         const DevCounters h = read_counters(c);
         CkptHeader H{};
         std::memcpy(H.magic, kCkptMagic, 8);
@@ -1583,6 +1683,7 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
         if (c->inj_on) return fail(c, AXP_E_ARG, "batch members cannot carry a continuous injector");
         if (c->fs.n_src > 0 || c->fs.probe_face >= 0)
             return fail(c, AXP_E_ARG, "batch members cannot carry point sources or a probe");
+        if (c->dl.n) return fail(c, AXP_E_ARG, "batch members cannot carry absorbing layers");
     }
     auto *b = new (std::nothrow) axp_batch();
     if (!b) return AXP_E_OOM;

@@ -67,6 +67,21 @@ struct DevCounters {
     unsigned long long pad;
 };
 
+// Stretched-coordinate absorbing layers (the PML of the ports): per layer
+// face i its internal face, beta = sigma dt / (2 eps0), H, the 3x3 z and rho
+// parts of its local [*eps] (sides k, l), and the state h (H B / s_z), q
+// (A_z e / s_z on its sides), eprev (its side values of E at the previous
+// step) and corr (its three corrections of D in the step in flight).
+// face_layer[t]: layer index of face t, or -1.  edges: per edge of a layer
+// face, (edge, 4 i_a + k_a, 4 i_b + k_b or -1, 0).
+struct DevLayers {
+    int32_t n = 0, n_edges = 0;
+    const int32_t *face = nullptr, *face_layer = nullptr;
+    const double *beta = nullptr, *Hf = nullptr, *Az = nullptr, *Ar = nullptr;
+    double *h = nullptr, *q = nullptr, *eprev = nullptr, *corr = nullptr;
+    const int4 *edges = nullptr;
+};
+
 constexpr int kMaxSources = 8;
 
 // Magnetic point sources and the field probe (Sec. 5.1), passed by value to
@@ -170,7 +185,10 @@ struct DevPlain {
 };
 
 // ---- launchers (kernels_mixed.hip) ----
-void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, hipStream_t st);
+void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, hipStream_t st);
+// layer update after E^{n+1}: q, eprev and the corrections of D (E: FP32 or FP64 edge values)
+void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const DevLayers &lay, hipStream_t st);
+void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st);
 // gather, push and walk of every particle, with the charge-conserving current
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
                       hipStream_t st);
@@ -191,7 +209,7 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
 
 // ---- launchers (kernels_plain.hip) ----
 void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, const FieldSrc &fs,
-                           hipStream_t st);
+                           const DevLayers &lay, hipStream_t st);
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
                             bool count, bool vay, hipStream_t st);
 void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);

@@ -207,41 +207,54 @@ static double moment3(int i, int j, int k, double area) {
     return 2.0 * area * fact[c[0]] * fact[c[1]] * fact[c[2]] / 120.0;
 }
 
+void local_hodge(const HostMesh &m, int t, int comp, double out[3][3]) {
+    // eps0 int_T rho W_k . W_l over the face's sides k, l (edge orientation of
+    // each side), W_(a,b) = lam_a grad lam_b - lam_b grad lam_a; comp 0 keeps
+    // the z components of the product only, 1 the rho components, -1 both
+    const auto &g = m.grad[t];
+    double gg[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            gg[a][b] = (comp != 1 ? g[2 * a] * g[2 * b] : 0.0) + (comp != 0 ? g[2 * a + 1] * g[2 * b + 1] : 0.0);
+    const double rho[3] = {m.r[m.tv[t][0]], m.r[m.tv[t][1]], m.r[m.tv[t][2]]};
+    int ta[3], hb[3];
+    for (int k = 0; k < 3; ++k) {
+        const int32_t e = m.tedge[t][k];
+        const int la = (k + 1) % 3, lb = (k + 2) % 3;   // CCW side from la to lb
+        if (m.tv[t][la] == m.ev[e][0]) { ta[k] = la; hb[k] = lb; } else { ta[k] = lb; hb[k] = la; }
+    }
+    const double A = m.area[t];
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            const int a = ta[k], b = hb[k], c = ta[l], d = hb[l];
+            double s = 0;
+            for (int q = 0; q < 3; ++q)
+                s += rho[q] * (moment3(q, a, c, A) * gg[b][d] - moment3(q, a, d, A) * gg[b][c] -
+                               moment3(q, b, c, A) * gg[a][d] + moment3(q, b, d, A) * gg[a][c]);
+            out[k][l] = kEps0 * s;
+        }
+}
+
 void assemble_hodge(HostMesh &m) {
     // [*eps]_ij = eps0 int rho W_i . W_j, W_(a,b) = lam_a grad lam_b - lam_b grad lam_a
     std::vector<std::vector<std::pair<int32_t, double>>> rows(m.n1);
     for (auto &r : rows) r.reserve(5);
     m.H.resize(m.n2);
     for (int t = 0; t < m.n2; ++t) {
-        const auto &g = m.grad[t];
-        double gg[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) gg[a][b] = g[2 * a] * g[2 * b] + g[2 * a + 1] * g[2 * b + 1];
-        double rho[3] = {m.r[m.tv[t][0]], m.r[m.tv[t][1]], m.r[m.tv[t][2]]};
-        int ta[3], hb[3];
-        for (int k = 0; k < 3; ++k) {
-            int32_t e = m.tedge[t][k];
-            int la = (k + 1) % 3, lb = (k + 2) % 3;   // CCW side from la to lb
-            if (m.tv[t][la] == m.ev[e][0]) { ta[k] = la; hb[k] = lb; } else { ta[k] = lb; hb[k] = la; }
-        }
+        double T[3][3];
+        local_hodge(m, t, -1, T);
         for (int k = 0; k < 3; ++k) {
             for (int l = 0; l < 3; ++l) {
-                int a = ta[k], b = hb[k], c = ta[l], d = hb[l];
-                double s = 0;
-                for (int q = 0; q < 3; ++q) {
-                    double A = m.area[t];
-                    s += rho[q] * (moment3(q, a, c, A) * gg[b][d] - moment3(q, a, d, A) * gg[b][c] -
-                                   moment3(q, b, c, A) * gg[a][d] + moment3(q, b, d, A) * gg[a][c]);
-                }
                 int32_t ek = m.tedge[t][k], el = m.tedge[t][l];
                 auto &row = rows[ek];
                 bool found = false;
                 for (auto &p : row)
-                    if (p.first == el) { p.second += kEps0 * s; found = true; break; }
-                if (!found) row.push_back({el, kEps0 * s});
+                    if (p.first == el) { p.second += T[k][l]; found = true; break; }
+                if (!found) row.push_back({el, T[k][l]});
             }
         }
         // [*mu^-1]_T = (1/mu0) int_T rho (W2)^2, W2 = 1/Area
+        const double rho[3] = {m.r[m.tv[t][0]], m.r[m.tv[t][1]], m.r[m.tv[t][2]]};
         m.H[t] = (rho[0] + rho[1] + rho[2]) / (3.0 * kMu0 * m.area[t]);
     }
     m.A.n = m.n1;
@@ -791,6 +804,40 @@ int cg_solve_M(const HostMesh &m, const double *b, double *x, double rtol, int m
         for (int e = 0; e < n; ++e) p[e] = r[e] + beta * p[e];
     }
     return it;
+}
+
+// ------------------------------------------------------------ absorbing layers
+void build_layers(const HostMesh &m, double dt, const LayerConfig &cfg, HostLayers &L, Csr &K) {
+    double z0 = 1e300, z1 = -1e300;
+    for (int v = 0; v < m.n0; ++v) { z0 = std::min(z0, m.z[v]); z1 = std::max(z1, m.z[v]); }
+    L = HostLayers{};
+    K = m.A;
+    for (int t = 0; t < m.n2; ++t) {
+        const double zc = (m.z[m.tv[t][0]] + m.z[m.tv[t][1]] + m.z[m.tv[t][2]]) / 3.0;
+        double sig = 0.0;
+        if ((cfg.sides & 1) && zc < cfg.z_left && cfg.z_left > z0)
+            sig = cfg.sigma_max * std::pow((cfg.z_left - zc) / (cfg.z_left - z0), cfg.order);
+        if ((cfg.sides & 2) && zc > cfg.z_right && cfg.z_right < z1)
+            sig = cfg.sigma_max * std::pow((zc - cfg.z_right) / (z1 - cfg.z_right), cfg.order);
+        if (!(sig > 0.0)) continue;
+        const double beta = sig * dt / (2.0 * kEps0);
+        double Az[3][3], Ar[3][3];
+        local_hodge(m, t, 0, Az);
+        local_hodge(m, t, 1, Ar);
+        L.face.push_back(t);
+        L.beta.push_back(beta);
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+                L.Az.push_back(Az[k][l]);
+                L.Ar.push_back(Ar[k][l]);
+                // stretched Hodge: (1 + beta) A_rho + A_z / (1 + beta) on the face
+                const double dk = beta * Ar[k][l] + (1.0 / (1.0 + beta) - 1.0) * Az[k][l];
+                const int32_t ek = m.tedge[t][k], el = m.tedge[t][l];
+                const int32_t *b = K.col.data() + K.ptr[ek], *e = K.col.data() + K.ptr[ek + 1];
+                const int32_t *it = std::lower_bound(b, e, el);
+                K.val[it - K.col.data()] += dk;
+            }
+    }
 }
 
 // ------------------------------------------------------------ electrostatics

@@ -100,9 +100,28 @@ struct LearnedSpaiStats {
 };
 
 // Builds topology, locality order and incidence.  seg: boundary segments.
+// Stretched-coordinate absorbing layers at the z ends (sides: bit 0 below
+// z_left, bit 1 above z_right), conductivity sigma_max (depth/thickness)^order.
+struct LayerConfig {
+    int sides = 0;
+    double z_left = 0.0, z_right = 0.0, sigma_max = 0.0;
+    int order = 3;
+};
+
+// Faces of the layers: beta = sigma dt / (2 eps0), and the z and rho parts of
+// their local [*eps] (9 values each, sides k, l of the face).
+struct HostLayers {
+    std::vector<int32_t> face;
+    std::vector<double> beta, Az, Ar;
+};
+
 void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tris, const int32_t *tri,
                     int32_t n_seg, const int32_t *seg, const uint8_t *tag);
 void assemble_hodge(HostMesh &m);
+// eps0 int_T rho W_k . W_l on face t: comp 0 z parts, 1 rho parts, -1 all
+void local_hodge(const HostMesh &m, int t, int comp, double out[3][3]);
+// layer faces and the stretched Hodge K (the pattern of A, values changed on layer faces)
+void build_layers(const HostMesh &m, double dt, const LayerConfig &cfg, HostLayers &L, Csr &K);
 void build_spai(HostMesh &m, int level, double drop_tol, int n_threads);
 void scaled_hodge(const HostMesh &m, ScaledHodge &h);
 // least-squares columns (all free columns if cols is null), after the drop rule

@@ -46,7 +46,7 @@ __device__ __forceinline__ double source_current(const FieldSrc &fs, int k, unsi
     return fs.amp[k] * exp(-a * a) * cos(fs.w[k] * tt);
 }
 
-__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs) {
+__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.n2) return;
     const int4 e = m.tedge[t];
@@ -62,7 +62,15 @@ __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSr
         if (t == fs.src_face[k]) bn -= dt * source_current(fs, k, s.ctr->step);
     s.B[t] = bn;
     s.Bprev[t] = bo;
-    s.HBdt[t] = m.Hdt[t] * bn;
+    const int il = lay.n ? lay.face_layer[t] : -1;
+    if (il < 0) {
+        s.HBdt[t] = m.Hdt[t] * bn;
+    } else {                                    // layer face: s_z h = H B, trapezoidal in time
+        const double b = lay.beta[il];
+        const double hn = ((1.0 - b) * lay.h[il] + lay.Hf[il] * (bn - bo)) / (1.0 + b);
+        lay.h[il] = hn;
+        s.HBdt[t] = dt * hn;
+    }
     const float4 g = m.gS[t];
     const float4 r = m.rho4[t];
     const float g0z = g.x * kInvS, g0r = g.y * kInvS, g1z = g.z * kInvS, g1r = g.w * kInvS;
@@ -988,12 +996,67 @@ __global__ __launch_bounds__(256) void k_energy_kin_final(DevState s, const doub
     if (threadIdx.x == 0) s.diag->WK = v;
 }
 
+// ------------------------------------------------------- absorbing layers
+// After E^{n+1} = M (D^n + dt rhs): per layer face, with e its side values,
+//   q^{n+1} = ((1 - beta) q^n + A_z (e^{n+1} - e^n)) / (1 + beta)
+//   corr_k  = 2 beta ((A_rho e^{n+1})_k - q_k^{n+1} / (1 + beta));
+// then D -= corr on every free side (each edge adds its faces' corrections in
+// a fixed order, so the update is deterministic).  E values are taken as
+// stored (edge orientation), as the local matrices are.
+template <class T>
+__global__ __launch_bounds__(256) void k_layer_faces(DevMesh m, const T *E, DevLayers lay) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= lay.n) return;
+    const int4 te = m.tedge[lay.face[i]];
+    const double en[3] = {(double)E[te.x], (double)E[te.y], (double)E[te.z]};
+    double de[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) de[k] = en[k] - lay.eprev[3 * i + k];
+    const double b = lay.beta[i];
+    const double *Az = lay.Az + 9 * i, *Ar = lay.Ar + 9 * i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double az = Az[3 * k] * de[0] + Az[3 * k + 1] * de[1] + Az[3 * k + 2] * de[2];
+        const double ar = Ar[3 * k] * en[0] + Ar[3 * k + 1] * en[1] + Ar[3 * k + 2] * en[2];
+        const double qn = ((1.0 - b) * lay.q[3 * i + k] + az) / (1.0 + b);
+        lay.q[3 * i + k] = qn;
+        lay.corr[3 * i + k] = 2.0 * b * (ar - qn / (1.0 + b));
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lay.eprev[3 * i + k] = en[k];
+}
+
+__global__ __launch_bounds__(256) void k_layer_edges(DevMesh m, DevState s, DevLayers lay) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= lay.n_edges) return;
+    const int4 r = lay.edges[j];
+    if (!(m.etri[r.x].z & 64)) return;          // conductor edge: D stays
+    double c = lay.corr[3 * (r.y >> 2) + (r.y & 3)];
+    if (r.z >= 0) c += lay.corr[3 * (r.z >> 2) + (r.z & 3)];
+    s.D[r.x] -= c;
+}
+
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, hipStream_t st) {
+void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s, fs);
+    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s, fs, lay);
+}
+
+template <class T>
+void layers_post(const DevMesh &m, DevState &s, const T *E, const DevLayers &lay, hipStream_t st) {
+    if (lay.n == 0) return;
+    hipLaunchKernelGGL((k_layer_faces<T>), dim3(nblk(lay.n, 256)), dim3(256), 0, st, m, E, lay);
+    hipLaunchKernelGGL(k_layer_edges, dim3(nblk(lay.n_edges, 256)), dim3(256), 0, st, m, s, lay);
+}
+
+void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const DevLayers &lay, hipStream_t st) {
+    layers_post(m, s, E, lay, st);
+}
+
+void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st) {
+    layers_post(m, s, E, lay, st);
 }
 
 // single: one instance with one species whose charge multiple is 1; its

@@ -31,7 +31,8 @@ __device__ __forceinline__ void fadd(double *a, double v) {
     if (v != 0.0) unsafeAtomicAdd(a, v);       // hardware FP64 atomic add
 }
 
-__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt, FieldSrc fs) {
+__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt, FieldSrc fs,
+                                                    DevLayers lay) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.n2) return;
     const int4 e = m.tedge[t];
@@ -49,7 +50,15 @@ __global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPl
         }
     s.B[t] = bn;
     s.Bprev[t] = bo;
-    s.HBdt[t] = m.Hdt[t] * bn;
+    const int il = lay.n ? lay.face_layer[t] : -1;
+    if (il < 0) {
+        s.HBdt[t] = m.Hdt[t] * bn;
+    } else {                                    // layer face: s_z h = H B, trapezoidal in time
+        const double b = lay.beta[il];
+        const double hn = ((1.0 - b) * lay.h[il] + lay.Hf[il] * (bn - bo)) / (1.0 + b);
+        lay.h[il] = hn;
+        s.HBdt[t] = dt * hn;
+    }
     const double4 g = p.grad[t];
     const double g0z = g.x, g0r = g.y, g1z = g.z, g1r = g.w;
     const double g2z = -(g0z + g1z), g2r = -(g0r + g1r);
@@ -660,9 +669,9 @@ inline unsigned nb_(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 }  // namespace
 
 void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, const FieldSrc &fs,
-                           hipStream_t st) {
+                           const DevLayers &lay, hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt, fs);
+    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt, fs, lay);
 }
 
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,

@@ -60,7 +60,7 @@ def _c_layout():
                            "spai_fro_residual", "spai_max_col_residual", "dt", "dt_cfl", "setup_seconds",
                            "particle_capacity", "n_particles", "step", "precision", "n_species", "spai_mode",
                            "spai_fallback_columns", "spai_pred_resid_mean", "spai_kept_resid_mean",
-                           "spai_energy_drift", "spai_seconds"],
+                           "spai_energy_drift", "spai_seconds", "n_layer_faces"],
               "axp_diag": ["step", "n_live", "n_absorbed", "walk_overflow", "nan_count", "fixed_overflow",
                            "dce_max_abs", "dce_max_rel", "gauss_max_drift", "gauss_max_abs", "gauss_scale", "W_E",
                            "W_B", "W_K", "Q_total"]}
