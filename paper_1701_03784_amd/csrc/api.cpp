@@ -1039,8 +1039,9 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
                 for (int k = 0; k < 3; ++k) { lam[k] = std::max(0.0, lam[k]); s += lam[k]; }
                 cell[i] = t | (species << kCellBits);
                 if (plain) {
-                    dl0[i] = lam[0] / s;
-                    dl1[i] = lam[1] / s;
+                    // lambda_2 = 1 - l0 - l1 must not come out negative by rounding
+                    dl0[i] = std::min(1.0, lam[0] / s);
+                    dl1[i] = std::min(lam[1] / s, 1.0 - dl0[i]);
                     dur[i] = u[3 * i] / kC;
                     dup[i] = u[3 * i + 1] / kC;
                     duz[i] = u[3 * i + 2] / kC;

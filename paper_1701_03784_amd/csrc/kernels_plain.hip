@@ -280,7 +280,8 @@ __device__ __forceinline__ void walk_mover_d(const DevMesh &m, const DevState &s
         const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
         double c0, c1, c2;
         const int tf = t;
-        if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
+        // the path leaves through side k only if lambda_k decreases and goes negative
+        if ((e0 >= 0.0 || d0 >= 0.0) && (e1 >= 0.0 || d1 >= 0.0) && (e2 >= 0.0 || d2 >= 0.0)) {
             piece_d(l0, l1, l2, e0, e1, e2, kq, c0, c1, c2);
             l0 = e0; l1 = e1; l2 = e2;
             newcell = t | (sp << kCellBits);
@@ -290,9 +291,9 @@ __device__ __forceinline__ void walk_mover_d(const DevMesh &m, const DevState &s
         // exit side: smallest lambda_k / (-d_k) among the coordinates going negative
         int kx = -1;
         double best = 3.0;
-        if (e0 < 0.0) { kx = 0; best = l0 / (-d0); }
-        if (e1 < 0.0) { const double v = l1 / (-d1); if (v < best) { kx = 1; best = v; } }
-        if (e2 < 0.0) { const double v = l2 / (-d2); if (v < best) { kx = 2; best = v; } }
+        if (e0 < 0.0 && d0 < 0.0) { kx = 0; best = l0 / (-d0); }
+        if (e1 < 0.0 && d1 < 0.0) { const double v = l1 / (-d1); if (v < best) { kx = 1; best = v; } }
+        if (e2 < 0.0 && d2 < 0.0) { const double v = l2 / (-d2); if (v < best) { kx = 2; best = v; } }
         if (kx < 0) {                               // non-finite displacement: stop here
             atomicAdd(&s.ctr->nan_count, 1ull);
             newcell = t | (sp << kCellBits);
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
         push_d<VAY>(s, P[j], k, sp, cf0, cf1, cr4, fz, fr);
         const double d0 = cg.x * fz + cg.y * fr, d1 = cg.z * fz + cg.w * fr, d2 = -d0 - d1;
         const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
-        if (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) {
+        if ((e0 >= 0.0 || d0 >= 0.0) && (e1 >= 0.0 || d1 >= 0.0) && (e2 >= 0.0 || d2 >= 0.0)) {
             double c0, c1, c2;
             piece_d(l0, l1, l2, e0, e1, e2, k.kq[sp], c0, c1, c2);
             if (T != acc_t) {
