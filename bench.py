@@ -242,8 +242,9 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the workload is measured at N=1 and the multi-GPU path "
-              "is a design (z-slab decomposition), not part of this build", file=sys.stderr)
+        print("bench.py runs on one GPU only: the workload is measured at N=1; the multi-GPU path "
+              "(z-slab decomposition, independent batch members per GPU) is a design, not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import paper_1701_03784_amd as axp

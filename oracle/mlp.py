@@ -4,7 +4,7 @@ loss, backward and Adam; and the pair features it reads.
 TEST INFRASTRUCTURE ONLY (see the package header).
 
 The paper computes its SPAI by least squares (Sec. 3.1); the network is an
-addition of this build and is checked, not derived, here:
+addition to the method and is checked, not derived, here:
   * network: n_in -> H (tanh) -> ... -> H (tanh) -> 1 (linear), with
     n_layers >= 1 hidden layers.  Parameter vector: for each layer in order,
     W[n_out][n_in] row-major, then b[n_out];
