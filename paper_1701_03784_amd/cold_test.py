@@ -1,0 +1,120 @@
+"""Cold test of the slow-wave structure: band edges of the TM01 passband
+and the effect of a staircased wall (Sec. 5.3), run on the GPU.
+
+    python -m paper_1701_03784_amd.cold_test [--amp 0.0025] [--period 0.0167] [--r0 0.015]
+                                             [--h 0.4e-3 0.2e-3 0.1e-3] [--ns 60]
+
+One period of the rippled wall R(z) = r0 + amp cos(2 pi z / d) is closed by
+conductor plates at z = 0 and z = d.  Both plates lie at symmetry planes of
+the wall (its extrema), so the modes of this cell are the Floquet modes of
+the periodic structure with phase advance 0 and pi per period: the lowest
+two TM0 modes are the two edges of the TM01 passband, the upper one the
+pi point at which the backward-wave oscillator works.  A broadband
+magnetic point source rings the cell; the probe's spectrum gives the mode
+frequencies (Hann window, zero padding, parabolic peak refinement).  The
+same cell is then meshed with a staircased wall, R held constant over
+treads of about four mesh spacings, and both are refined.  With amp = 0 the two
+edges are the closed forms c/(2 pi) x_01/r0 and c/(2 pi) sqrt((x_01/r0)^2 + (pi/d)^2).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+X01 = 2.404825557695773
+
+
+def log(msg):
+    print(f"[cold] {msg}", file=sys.stderr, flush=True)
+
+
+def radius_fn(r0, amp, d, stair=0.0):
+    def R(z):
+        z = np.asarray(z, dtype=np.float64)
+        zz = (np.floor(z / stair) + 0.5) * stair if stair > 0 else z
+        zz = np.clip(zz, 0.0, d)
+        return r0 + amp * np.cos(2.0 * np.pi * zz / d)
+    return R
+
+
+def cell_mesh(r0, amp, d, h, stair=False, seed=0):
+    """Regular mesh of the cell; a staircased wall has treads of about four
+    mesh spacings (a whole number per period, so the cell stays symmetric)."""
+    import synth
+    width = d / max(1, int(round(d / (4.0 * h)))) if stair else 0.0
+    R = radius_fn(r0, amp, d, width)
+    return synth.rippled_mesh(R, 0.0, d, h, seed=seed, jitter=0.0)
+
+
+def lowest_peaks(signal, dt, f_lo, f_hi, count=2, pad=8, floor=1e-4):
+    """The lowest `count` spectral peaks in (f_lo, f_hi) above floor x max."""
+    w = np.hanning(len(signal))
+    nfft = pad * len(signal)
+    f = np.fft.rfftfreq(nfft, dt)
+    P = sum(np.abs(np.fft.rfft(w * signal[:, k], nfft)) ** 2 for k in range(signal.shape[1]))
+    band = (f > f_lo) & (f < f_hi)
+    top = P[band].max()
+    # a peak is the maximum over +-6 bins of the unpadded transform (the Hann
+    # window's main lobe and first sidelobes), above floor x the band's maximum
+    W = 6 * pad
+    pk = [i for i in np.flatnonzero(band) if P[i] > floor * top and P[i] == P[max(0, i - W):i + W + 1].max()]
+    out = []
+    for i in pk[:count]:
+        y0, y1, y2 = np.log(P[i - 1]), np.log(P[i]), np.log(P[i + 1])
+        out.append(float(f[i] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2) * (f[1] - f[0])))
+    return out
+
+
+def cell_modes(ctx_factory, m, r0, d, ns, f_lo, f_hi):
+    c = ctx_factory(m)
+    info = c.info()
+    dt = info["dt"]
+    c.set_fields(np.zeros(info["n_edges"]), np.zeros(info["n_faces"]))
+    c.add_point_source(d / 3.0, 0.6 * r0, 1.0, 0.3e-9, 0.04e-9, 2 * np.pi * 10e9)
+    steps = int(ns * 1e-9 / dt)
+    c.set_probe(0.21 * d, 0.31 * r0, steps)
+    c.step(steps)
+    sig = c.get_probe()
+    c.close()
+    n0 = int(0.6e-9 / dt)                       # after the pulse
+    return lowest_peaks(sig[n0:], dt, f_lo, f_hi), info["n_faces"], steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--r0", type=float, default=0.015)
+    ap.add_argument("--amp", type=float, default=0.0025)
+    ap.add_argument("--period", type=float, default=0.0167)
+    ap.add_argument("--h", type=float, nargs="+", default=[0.4e-3, 0.2e-3, 0.1e-3])
+    ap.add_argument("--ns", type=float, default=60.0)
+    args = ap.parse_args()
+    import paper_1701_03784_amd as axp
+    axp.load_library()
+    r0, amp, d = args.r0, args.amp, args.period
+    f0u = C_LIGHT / (2 * np.pi) * X01 / r0
+    fpu = C_LIGHT / (2 * np.pi) * np.hypot(X01 / r0, np.pi / d)
+    f_lo, f_hi = 0.5 * f0u, 1.3 * fpu
+    factory = lambda m: axp.make_ctx(m)
+    print(json.dumps({"uniform_guide_band_edges_GHz": [f0u / 1e9, fpu / 1e9], "r0": r0, "amp": amp, "period": d}),
+          flush=True)
+    for stair in (False, True):
+        for h in args.h:
+            t0 = time.perf_counter()
+            m = cell_mesh(r0, amp, d, h, stair)
+            peaks, faces, steps = cell_modes(factory, m, r0, d, args.ns, f_lo, f_hi)
+            line = {"wall": "staircased" if stair else "smooth", "h_mm": h * 1e3, "faces": faces, "steps": steps,
+                    "f0_GHz": peaks[0] / 1e9 if len(peaks) > 0 else None,
+                    "fpi_GHz": peaks[1] / 1e9 if len(peaks) > 1 else None,
+                    "seconds": time.perf_counter() - t0}
+            print(json.dumps(line), flush=True)
+            log(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

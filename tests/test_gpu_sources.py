@@ -106,3 +106,17 @@ def test_sources_and_probe_arguments(axp, cavity):
     c.set_probe(0.5, 0.1, 0)
     assert c.get_probe().shape == (0, 2)
     c.close()
+
+
+def test_cold_test_band_edges_of_a_uniform_cell(axp):
+    """The cold-test driver on a smooth cylinder cell: its two lowest modes
+    are the TM01 band edges c x_01/(2 pi r0) and c/(2 pi) sqrt((x_01/r0)^2 + (pi/d)^2)."""
+    from paper_1701_03784_amd import cold_test
+    r0, d = 0.015, 0.0167
+    m = cold_test.cell_mesh(r0, 0.0, d, 0.4e-3)
+    f0 = cold_test.C_LIGHT / (2 * np.pi) * cold_test.X01 / r0
+    fp = cold_test.C_LIGHT / (2 * np.pi) * np.hypot(cold_test.X01 / r0, np.pi / d)
+    peaks, faces, steps = cold_test.cell_modes(lambda mm: axp.make_ctx(mm), m, r0, d, 20.0, 0.5 * f0, 1.3 * fp)
+    print(f"[gpu] uniform cell: {faces} faces, {steps} steps, modes {[p / 1e9 for p in peaks]} GHz", flush=True)
+    assert len(peaks) == 2
+    assert abs(peaks[0] / f0 - 1) < 2e-3 and abs(peaks[1] / fp - 1) < 2e-3
