@@ -1,5 +1,5 @@
 """Cold test of the slow-wave structure: band edges of the TM01 passband
-and the effect of a staircased wall (Sec. 5.3), run on the GPU.
+under mesh refinement (Sec. 5.3), run on the GPU.
 
     python -m paper_1701_03784_amd.cold_test [--amp 0.0025] [--period 0.0167] [--r0 0.015]
                                              [--h 0.4e-3 0.2e-3 0.1e-3] [--ns 60]
@@ -11,10 +11,9 @@ the periodic structure with phase advance 0 and pi per period: the lowest
 two TM0 modes are the two edges of the TM01 passband, the upper one the
 pi point at which the backward-wave oscillator works.  A broadband
 magnetic point source rings the cell; the probe's spectrum gives the mode
-frequencies (Hann window, zero padding, parabolic peak refinement).  The
-same cell is then meshed with a staircased wall, R held constant over
-treads of about four mesh spacings, and both are refined.  With amp = 0 the two
-edges are the closed forms c/(2 pi) x_01/r0 and c/(2 pi) sqrt((x_01/r0)^2 + (pi/d)^2).
+frequencies (Hann window, zero padding, parabolic peak refinement), on
+successively refined meshes.  With amp = 0 the two edges are the closed
+forms c/(2 pi) x_01/r0 and c/(2 pi) sqrt((x_01/r0)^2 + (pi/d)^2).
 """
 
 from __future__ import annotations
@@ -34,21 +33,10 @@ def log(msg):
     print(f"[cold] {msg}", file=sys.stderr, flush=True)
 
 
-def radius_fn(r0, amp, d, stair=0.0):
-    def R(z):
-        z = np.asarray(z, dtype=np.float64)
-        zz = (np.floor(z / stair) + 0.5) * stair if stair > 0 else z
-        zz = np.clip(zz, 0.0, d)
-        return r0 + amp * np.cos(2.0 * np.pi * zz / d)
-    return R
-
-
-def cell_mesh(r0, amp, d, h, stair=False, seed=0):
-    """Regular mesh of the cell; a staircased wall has treads of about four
-    mesh spacings (a whole number per period, so the cell stays symmetric)."""
+def cell_mesh(r0, amp, d, h, seed=0):
+    """Regular mesh of the cell r <= r0 + amp cos(2 pi z / d), 0 <= z <= d."""
     import synth
-    width = d / max(1, int(round(d / (4.0 * h)))) if stair else 0.0
-    R = radius_fn(r0, amp, d, width)
+    R = lambda z: r0 + amp * np.cos(2.0 * np.pi * np.asarray(z, dtype=np.float64) / d)
     return synth.rippled_mesh(R, 0.0, d, h, seed=seed, jitter=0.0)
 
 
@@ -103,17 +91,16 @@ def main():
     factory = lambda m: axp.make_ctx(m)
     print(json.dumps({"uniform_guide_band_edges_GHz": [f0u / 1e9, fpu / 1e9], "r0": r0, "amp": amp, "period": d}),
           flush=True)
-    for stair in (False, True):
-        for h in args.h:
-            t0 = time.perf_counter()
-            m = cell_mesh(r0, amp, d, h, stair)
-            peaks, faces, steps = cell_modes(factory, m, r0, d, args.ns, f_lo, f_hi)
-            line = {"wall": "staircased" if stair else "smooth", "h_mm": h * 1e3, "faces": faces, "steps": steps,
-                    "f0_GHz": peaks[0] / 1e9 if len(peaks) > 0 else None,
-                    "fpi_GHz": peaks[1] / 1e9 if len(peaks) > 1 else None,
-                    "seconds": time.perf_counter() - t0}
-            print(json.dumps(line), flush=True)
-            log(json.dumps(line))
+    for h in args.h:
+        t0 = time.perf_counter()
+        m = cell_mesh(r0, amp, d, h)
+        peaks, faces, steps = cell_modes(factory, m, r0, d, args.ns, f_lo, f_hi)
+        line = {"h_mm": h * 1e3, "faces": faces, "steps": steps,
+                "f0_GHz": peaks[0] / 1e9 if len(peaks) > 0 else None,
+                "fpi_GHz": peaks[1] / 1e9 if len(peaks) > 1 else None,
+                "seconds": time.perf_counter() - t0}
+        print(json.dumps(line), flush=True)
+        log(json.dumps(line))
 
 
 if __name__ == "__main__":
