@@ -3,6 +3,7 @@ under mesh refinement (Sec. 5.3), run on the GPU.
 
     python -m paper_1701_03784_amd.cold_test [--amp 0.0025] [--period 0.0167] [--r0 0.015]
                                              [--h 0.4e-3 0.2e-3 0.1e-3] [--ns 60]
+                                             [--mesh hex grid staircase]
 
 One period of the rippled wall R(z) = r0 + amp cos(2 pi z / d) is closed by
 conductor plates at z = 0 and z = d.  Both plates lie at symmetry planes of
@@ -14,6 +15,11 @@ magnetic point source rings the cell; the probe's spectrum gives the mode
 frequencies (Hann window, zero padding, parabolic peak refinement), on
 successively refined meshes.  With amp = 0 the two edges are the closed
 forms c/(2 pi) x_01/r0 and c/(2 pi) sqrt((x_01/r0)^2 + (pi/d)^2).
+
+The staircasing study of Sec. 5.3 compares a wall that follows R(z) with
+the step-cell wall a structured grid would impose: 'grid' and 'staircase'
+meshes share their triangles and differ only at the wall, so the change of
+the pi-point frequency between them is the staircasing error alone.
 """
 
 from __future__ import annotations
@@ -33,11 +39,23 @@ def log(msg):
     print(f"[cold] {msg}", file=sys.stderr, flush=True)
 
 
-def cell_mesh(r0, amp, d, h, seed=0):
-    """Regular mesh of the cell r <= r0 + amp cos(2 pi z / d), 0 <= z <= d."""
+MESH_KINDS = ("hex", "grid", "staircase")
+
+
+def cell_mesh(r0, amp, d, h, seed=0, kind="hex"):
+    """Mesh of the cell r <= r0 + amp cos(2 pi z / d), 0 <= z <= d.
+
+    kind 'hex': a regular (unjittered) hexagonal lattice mapped onto the wall;
+    'grid': a checkerboard-split grid mapped onto the wall; 'staircase': the
+    same grid with the wall rounded to whole grid rows per column (the
+    step-cell wall of a structured grid, with vertical risers)."""
     import synth
     R = lambda z: r0 + amp * np.cos(2.0 * np.pi * np.asarray(z, dtype=np.float64) / d)
-    return synth.rippled_mesh(R, 0.0, d, h, seed=seed, jitter=0.0)
+    if kind == "hex":
+        return synth.rippled_mesh(R, 0.0, d, h, seed=seed, jitter=0.0)
+    if kind in ("grid", "staircase"):
+        return synth.grid_mesh(R, 0.0, d, h, staircase=kind == "staircase")
+    raise ValueError(f"unknown mesh kind {kind!r}")
 
 
 def lowest_peaks(signal, dt, f_lo, f_hi, count=2, pad=8, floor=1e-4):
@@ -81,6 +99,7 @@ def main():
     ap.add_argument("--period", type=float, default=0.0167)
     ap.add_argument("--h", type=float, nargs="+", default=[0.4e-3, 0.2e-3, 0.1e-3])
     ap.add_argument("--ns", type=float, default=60.0)
+    ap.add_argument("--mesh", nargs="+", choices=MESH_KINDS, default=["hex"])
     args = ap.parse_args()
     import paper_1701_03784_amd as axp
     axp.load_library()
@@ -91,16 +110,17 @@ def main():
     factory = lambda m: axp.make_ctx(m)
     print(json.dumps({"uniform_guide_band_edges_GHz": [f0u / 1e9, fpu / 1e9], "r0": r0, "amp": amp, "period": d}),
           flush=True)
-    for h in args.h:
-        t0 = time.perf_counter()
-        m = cell_mesh(r0, amp, d, h)
-        peaks, faces, steps = cell_modes(factory, m, r0, d, args.ns, f_lo, f_hi)
-        line = {"h_mm": h * 1e3, "faces": faces, "steps": steps,
-                "f0_GHz": peaks[0] / 1e9 if len(peaks) > 0 else None,
-                "fpi_GHz": peaks[1] / 1e9 if len(peaks) > 1 else None,
-                "seconds": time.perf_counter() - t0}
-        print(json.dumps(line), flush=True)
-        log(json.dumps(line))
+    for kind in args.mesh:
+        for h in args.h:
+            t0 = time.perf_counter()
+            m = cell_mesh(r0, amp, d, h, kind=kind)
+            peaks, faces, steps = cell_modes(factory, m, r0, d, args.ns, f_lo, f_hi)
+            line = {"mesh": kind, "h_mm": h * 1e3, "faces": faces, "steps": steps,
+                    "f0_GHz": peaks[0] / 1e9 if len(peaks) > 0 else None,
+                    "fpi_GHz": peaks[1] / 1e9 if len(peaks) > 1 else None,
+                    "seconds": time.perf_counter() - t0}
+            print(json.dumps(line), flush=True)
+            log(json.dumps(line))
 
 
 if __name__ == "__main__":

@@ -14,7 +14,7 @@ plane carry the azimuthal unit vector as their normal.
 
 from .meshes import (  # noqa: F401
     Mesh, BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN, BC_NAMES,
-    canonical_edges, rect_mesh, rippled_mesh, tiny_mesh,
+    canonical_edges, rect_mesh, rippled_mesh, grid_mesh, tiny_mesh,
 )
 from .fields import tm010_fields, uniform_field_dofs, edge_line_integrals, face_flux_integrals  # noqa: F401
 from .particles import (  # noqa: F401

@@ -183,6 +183,70 @@ def rippled_mesh(radius_fn, z0, z1, h, seed, jitter=0.3, tags=None, meta=None):
     return _build(z0, z1, radius_fn, h, seed, jitter, rule, m)
 
 
+def grid_mesh(radius_fn, z0, z1, h, staircase=False, tags=None, meta=None):
+    """Structured mesh of 0 <= rho <= R(z) on columns of width dz = (z1 - z0) / nz,
+    nz = round((z1 - z0) / h); every quadrilateral cell is split into two
+    triangles, the diagonal alternating like a checkerboard.
+
+    staircase=False: the mapped grid.  Column line i carries n rows at
+      rho = k R(z_i) / n (n = round(mean R / h)), so every wall node lies on
+      R(z) and the wall is the polyline through them.
+    staircase=True: the step-cell wall of a structured grid.  Nodes sit at
+      (z_i, k h); column j keeps the rows k < n_j = round(R(z_j + dz/2) / h),
+      so the wall is made of grid lines, with vertical risers where two
+      neighbouring columns differ.
+
+    The two share the triangle topology, so comparing them isolates the error
+    of the staircased wall from the grid's own dispersion.  For a constant R
+    that is a whole number of rows h the two meshes coincide.
+
+    Default tags: axis at rho = 0, PEC on the wall (risers included) and on
+    both end plates; a tags dict or rule sees the sides 'bottom', 'top'
+    (the wall), 'left' and 'right'."""
+    if tags is None:
+        tags = {"bottom": BC_AXIS, "top": BC_PEC, "left": BC_PEC, "right": BC_PEC}
+    rule = tags if callable(tags) else (lambda s, z, r: tags[s])
+    nz = max(1, int(round((z1 - z0) / h)))
+    dz = (z1 - z0) / nz
+    zi = z0 + dz * np.arange(nz + 1)
+    zi[-1] = z1
+    R = lambda z: np.asarray(radius_fn(np.asarray(z, dtype=np.float64)), dtype=np.float64)
+    if staircase:
+        rows = np.maximum(1, np.rint(R(zi[:-1] + 0.5 * dz) / h).astype(np.int64))      # rows of column j
+        top = np.maximum(np.concatenate([[0], rows]), np.concatenate([rows, [0]]))       # rows at line i
+        height = lambda i, k: k * h
+    else:
+        n = max(1, int(round(float(np.mean(R(np.linspace(z0, z1, 257)))) / h)))
+        rows = np.full(nz, n, dtype=np.int64)
+        top = np.full(nz + 1, n, dtype=np.int64)
+        Ri = R(zi)
+        height = lambda i, k: k * Ri[i] / n
+    off = np.concatenate([[0], np.cumsum(top + 1)])
+    nodes = np.array([[zi[i], height(i, k)] for i in range(nz + 1) for k in range(top[i] + 1)],
+                     dtype=np.float64)
+    tris = []
+    for j in range(nz):
+        for k in range(rows[j]):
+            a, b = off[j] + k, off[j + 1] + k
+            c, d = b + 1, a + 1
+            tris += [(a, b, c), (a, c, d)] if (j + k) % 2 == 0 else [(a, b, d), (b, c, d)]
+    tris = np.array(tris, dtype=np.int32)
+    seg = _boundary_segments(tris)
+    pa, pb = nodes[seg[:, 0]], nodes[seg[:, 1]]
+    side = np.full(len(seg), "top", dtype=object)
+    side[(pa[:, 1] == 0.0) & (pb[:, 1] == 0.0)] = "bottom"
+    side[(pa[:, 0] == z0) & (pb[:, 0] == z0)] = "left"
+    side[(pa[:, 0] == z1) & (pb[:, 0] == z1)] = "right"
+    mid = 0.5 * (pa + pb)
+    tag = np.array([rule(s, q[0], q[1]) for s, q in zip(side, mid)], dtype=np.uint8)
+    m = dict(kind="staircase" if staircase else "grid", z0=z0, z1=z1, h=h, nz=nz)
+    m.update(meta or {})
+    mesh = Mesh(nodes=nodes, tris=tris, seg=seg, tag=tag, meta=m)
+    if np.any(mesh.signed_areas() <= 0):
+        raise RuntimeError("grid mesh has a non-positive triangle")
+    return mesh
+
+
 def tiny_mesh(kind: str) -> Mesh:
     """Hand-built meshes for brute-force checks.
 
