@@ -228,21 +228,31 @@ class OracleSim:
 
     def locate(self, zr):
         """Containing triangle of each point: the face among the nearest
-        centroids whose smallest barycentric coordinate is largest."""
+        centroids whose smallest barycentric coordinate is largest.  The 8
+        nearest centroids are tried first and the 24 nearest only for points
+        none of those contains (a point inside a face has no larger smallest
+        coordinate in any other face, so the wider search finds the same
+        face)."""
         tp = self.topo
         if self._tree is None:
             self._tree = scipy.spatial.cKDTree(tp.nodes[tp.tris].mean(axis=1))
         zr = np.asarray(zr, dtype=np.float64).reshape(-1, 2)
-        k = min(24, tp.n2)
         out = np.empty(len(zr), dtype=np.int64)
-        bad = []
-        for a in range(0, len(zr), 65536):           # bounded memory
-            z = zr[a:a + 65536]
-            _, cand = self._tree.query(z, k=k)
-            cand = np.asarray(cand).reshape(len(z), -1)
-            minlam = _bary_many(tp.nodes[tp.tris[cand]], z[:, None, :]).min(axis=-1)
-            out[a:a + len(z)] = cand[np.arange(len(z)), np.argmax(minlam, axis=1)]
-            bad.extend(a + np.flatnonzero(minlam.max(axis=1) < -1e-12))
+
+        def nearest(ids, k):
+            """Best of the k nearest centroids; ids of points none contains."""
+            miss = []
+            for a in range(0, len(ids), 65536):      # bounded memory
+                sel = ids[a:a + 65536]
+                z = zr[sel]
+                _, cand = self._tree.query(z, k=min(k, tp.n2))
+                cand = np.asarray(cand).reshape(len(z), -1)
+                minlam = _bary_many(tp.nodes[tp.tris[cand]], z[:, None, :]).min(axis=-1)
+                out[sel] = cand[np.arange(len(z)), np.argmax(minlam, axis=1)]
+                miss.extend(sel[minlam.max(axis=1) < -1e-12])
+            return np.asarray(miss, dtype=np.int64)
+
+        bad = nearest(nearest(np.arange(len(zr)), 8), 24)
         for i in bad:                        # far from any centroid: scan all faces
             ml = _bary_many(tp.nodes[tp.tris], zr[i][None, :]).min(axis=-1)
             if ml.max() < -1e-9:

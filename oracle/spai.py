@@ -22,7 +22,31 @@ def spai_pattern(A_hat: sp.csr_matrix, level: int) -> sp.csc_matrix:
     P = S.copy()
     for _ in range(level - 1):
         P = (P @ S).astype(bool).astype(np.int64)
-    return P.tocsc()
+    P = P.tocsc()
+    P.sort_indices()
+    return P
+
+
+def _scaled(A: sp.spmatrix, free: np.ndarray):
+    """Step 1: free-edge ids, the scaled block A^ (CSC) and diag(A)^1/2."""
+    A = sp.csr_matrix(A)
+    idx = np.flatnonzero(free)
+    Af = A[idx][:, idx].tocsc()
+    s = np.sqrt(Af.diagonal())
+    Dinv = sp.diags(1.0 / s)
+    return idx, (Dinv @ Af @ Dinv).tocsc(), s
+
+
+def _column(Ah: sp.csc_matrix, J: np.ndarray, k: int, drop_tol: float):
+    """Steps 3-4 for column k over the pattern entries J (ascending): the
+    kept rows and values of m_k."""
+    sub = Ah[:, J]
+    I = np.unique(sub.indices)
+    Ad = sub[I].toarray()
+    rhs = (I == k).astype(float)
+    m, *_ = np.linalg.lstsq(Ad, rhs, rcond=None)
+    keep = np.abs(m) >= drop_tol * np.abs(m).max()
+    return J[keep], m[keep]
 
 
 def spai(A: sp.spmatrix, free: np.ndarray, level: int = 3, drop_tol: float = 1e-3,
@@ -30,32 +54,72 @@ def spai(A: sp.spmatrix, free: np.ndarray, level: int = 3, drop_tol: float = 1e-
     """Returns M (N1 x N1 CSR, zero outside the free rows/columns).  With
     symmetric=False the column-wise least-squares solution is returned
     before step 5's averaging (still unscaled back by S^-1/2)."""
-    A = sp.csr_matrix(A)
-    idx = np.flatnonzero(free)
-    Af = A[idx][:, idx].tocsc()
-    n = Af.shape[0]
-    s = np.sqrt(Af.diagonal())
-    Dinv = sp.diags(1.0 / s)
-    Ah = (Dinv @ Af @ Dinv).tocsc()
+    idx, Ah, s = _scaled(A, free)
+    n = Ah.shape[0]
     P = spai_pattern(Ah.tocsr(), level)
 
     rows, cols, vals = [], [], []
     for k in range(n):
-        J = P.indices[P.indptr[k]:P.indptr[k + 1]]
-        sub = Ah[:, J]
-        I = np.unique(sub.indices)
-        Ad = sub[I].toarray()
-        rhs = (I == k).astype(float)
-        m, *_ = np.linalg.lstsq(Ad, rhs, rcond=None)
-        keep = np.abs(m) >= drop_tol * np.abs(m).max()
-        rows.extend(J[keep]); cols.extend([k] * int(keep.sum())); vals.extend(m[keep])
+        Jk, mk = _column(Ah, P.indices[P.indptr[k]:P.indptr[k + 1]], k, drop_tol)
+        rows.extend(Jk); cols.extend([k] * len(Jk)); vals.extend(mk)
     Mh = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
     if symmetric:
         Mh = 0.5 * (Mh + Mh.T)
+    Dinv = sp.diags(1.0 / s)
     Mf = (Dinv @ Mh @ Dinv).tocoo()
     M = sp.csr_matrix((Mf.data, (idx[Mf.row], idx[Mf.col])), shape=A.shape)
     M.sort_indices()
     return M
+
+
+def spai_rows(A: sp.spmatrix, free: np.ndarray, rows, level: int = 3, drop_tol: float = 1e-3):
+    """Rows `rows` (ids of free edges) of spai(A, free, level, drop_tol), as a
+    len(rows) x N1 CSR matrix, from only the column problems they need.
+
+    Row e of the symmetrised M^ is the average of column e and of entry e of
+    every column k whose pattern holds e.  The pattern, the structure of a
+    power of the symmetric A^, is symmetric, so those are the columns in
+    the pattern of column e.  Each column is solved exactly as spai() solves
+    it; the pattern of a set of columns is the structure of A^^level applied
+    to them."""
+    idx, Ah, s = _scaled(A, free)
+    n = Ah.shape[0]
+    pos = -np.ones(sp.csr_matrix(A).shape[0], dtype=np.int64)
+    pos[idx] = np.arange(n)
+    r = pos[np.asarray(rows, dtype=np.int64)]
+    if np.any(r < 0):
+        raise ValueError("spai_rows: every row must be a free edge")
+    S = (Ah != 0).astype(np.int64).tocsc()
+
+    def pattern_of(cols):
+        X = S[:, cols]
+        for _ in range(level - 1):
+            X = (S @ X).astype(bool).astype(np.int64)
+        X = X.tocsc()
+        X.sort_indices()
+        return X
+
+    Pr = pattern_of(r)
+    need = np.unique(np.concatenate([Pr.indices, r]))
+    Pn = pattern_of(need)
+    solved = {}
+    for i, k in enumerate(need):
+        solved[int(k)] = _column(Ah, Pn.indices[Pn.indptr[i]:Pn.indptr[i + 1]], int(k), drop_tol)
+    out_r, out_c, out_v = [], [], []
+    for i, e in enumerate(r):
+        e = int(e)
+        vals = {}
+        Je, me = solved[e]                         # column e: entries M^(j, e)
+        for j, v in zip(Je, me):
+            vals[int(j)] = vals.get(int(j), 0.0) + 0.5 * v
+        for k in Pr.indices[Pr.indptr[i]:Pr.indptr[i + 1]]:
+            Jk, mk = solved[int(k)]                # entry M^(e, k) of column k
+            hit = np.flatnonzero(Jk == e)
+            if len(hit):
+                vals[int(k)] = vals.get(int(k), 0.0) + 0.5 * mk[hit[0]]
+        for j, v in vals.items():
+            out_r.append(i); out_c.append(idx[j]); out_v.append(v / (s[e] * s[j]))
+    return sp.csr_matrix((out_v, (out_r, out_c)), shape=(len(r), sp.csr_matrix(A).shape[0]))
 
 
 def spai_residuals(A: sp.spmatrix, M: sp.spmatrix, free: np.ndarray):

@@ -120,3 +120,51 @@ def test_cold_test_band_edges_of_a_uniform_cell(axp):
     print(f"[gpu] uniform cell: {faces} faces, {steps} steps, modes {[p / 1e9 for p in peaks]} GHz", flush=True)
     assert len(peaks) == 2
     assert abs(peaks[0] / f0 - 1) < 2e-3 and abs(peaks[1] / fp - 1) < 2e-3
+
+
+def test_cold_test_dispersion_of_a_uniform_guide(axp):
+    """Four smooth-guide periods between the plates, on the mapped grid: the
+    five lowest modes are the TM01 dispersion curve at phase advance k pi / 4
+    per period, c/(2 pi) sqrt((x_01/r0)^2 + (k pi / (4 d))^2)."""
+    from paper_1701_03784_amd import cold_test
+    r0, d, N = 0.015, 0.0167, 4
+    m = cold_test.cell_mesh(r0, 0.0, d, 0.4e-3, kind="grid", periods=N)
+    ref = cold_test.uniform_dispersion(r0, d, np.pi * np.arange(N + 1) / N)
+    peaks, faces, steps = cold_test.cell_modes(lambda mm: axp.make_ctx(mm), m, r0, d, 40.0, 0.5 * ref[0],
+                                               1.3 * ref[-1], count=N + 1)
+    print(f"[gpu] 4-period guide: {faces} faces, {steps} steps, modes {[p / 1e9 for p in peaks]} GHz", flush=True)
+    assert len(peaks) == N + 1
+    np.testing.assert_allclose(np.array(peaks) / ref, 1.0, rtol=0, atol=2e-3)
+
+
+
+def test_cold_test_modes_are_the_discrete_eigenvalues(axp):
+    """Rippled cell, which has no closed form: the driver's two lowest modes
+    are eigenfrequencies of the semi-discrete operator M K.  Here M is the
+    oracle's SPAI and K = C^T [*mu^-1] C on free edges, found by a
+    shift-invert eigensolve.  Each is mapped through the leapfrog's own time
+    dispersion, omega_h = (2/dt) asin(omega dt / 2).  Bound: 1e-5 relative,
+    set by the spectral peak estimate."""
+    import scipy.sparse.linalg as spla
+    from paper_1701_03784_amd import cold_test
+    from oracle.topology import build_topology
+    from oracle.hodge import hodge_eps, hodge_mu_inv
+    from oracle.cfl import curl_curl, cfl_dt
+    from oracle.spai import spai
+    r0, amp, d = 0.015, 0.0025, 0.0167
+    m = cold_test.cell_mesh(r0, amp, d, 0.8e-3)
+    topo = build_topology(m.nodes, m.tris, m.seg, m.tag)
+    A, H = hodge_eps(topo), hodge_mu_inv(topo)
+    M = spai(A, topo.edge_free, 3, 1e-3)
+    dt = 0.4 * cfl_dt(topo, H, M)[0]
+    idx = np.flatnonzero(topo.edge_free)
+    MK = (M[idx][:, idx] @ curl_curl(topo, H)[idx][:, idx]).tocsc()
+    lam = spla.eigs(MK, k=6, sigma=(2 * np.pi * 8.5e9) ** 2, which="LM", return_eigenvectors=False).real
+    omega = np.sort(np.sqrt(lam[lam > (2 * np.pi * 1e9) ** 2]))[:2]
+    f_ref = 2.0 / dt * np.arcsin(0.5 * omega * dt) / (2 * np.pi)
+    f_lo = 0.5 * cold_test.uniform_dispersion(r0, d, 0.0)
+    f_hi = 1.3 * cold_test.uniform_dispersion(r0, d, np.pi)
+    peaks, faces, steps = cold_test.cell_modes(lambda mm: axp.make_ctx(mm, dt=dt), m, r0, d, 60.0, f_lo, f_hi)
+    print(f"[gpu] rippled cell: modes {[p / 1e9 for p in peaks]} GHz, eigen {list(f_ref / 1e9)} GHz", flush=True)
+    assert len(peaks) == 2
+    np.testing.assert_allclose(np.array(peaks) / f_ref, 1.0, rtol=0, atol=1e-5)

@@ -264,3 +264,23 @@ def test_table1_analytic_frequencies():
         n, p = relabel.get(fa, (int(n), int(p)))
         f = c / (2 * np.pi) * np.hypot(x[n - 1] / 0.5, p * np.pi / 1.0) / 1e9
         assert abs(f - fa) < 1.0e-3
+
+
+def test_spai_rows_are_the_rows_of_the_spai():
+    """Rows of the SPAI computed alone, from only the column problems they
+    need, equal the rows of the whole SPAI (to the rounding of the
+    averaging order); conductor edges are refused."""
+    import scipy.sparse as sp
+    from oracle.spai import spai, spai_rows
+    from synth import configs
+    m = configs.cavity_mesh()
+    topo = build_topology(m.nodes, m.tris, m.seg, m.tag)
+    A = hodge_eps(topo)
+    M = sp.csr_matrix(spai(A, topo.edge_free, 3, 1e-3))
+    rows = np.random.default_rng(3).choice(np.flatnonzero(topo.edge_free), 40, replace=False)
+    R = spai_rows(A, topo.edge_free, rows, 3, 1e-3)
+    assert R.shape == (40, topo.n1)
+    assert abs(R - M[rows]).max() <= 1e-15 * abs(M).max()
+    assert R.nnz == M[rows].nnz
+    with pytest.raises(ValueError):
+        spai_rows(A, topo.edge_free, np.flatnonzero(~topo.edge_free)[:1])
