@@ -139,9 +139,12 @@ __device__ __forceinline__ long long wave_sum64(long long v) {
 // kWin consecutive faces live in LDS; faces outside the window go straight to
 // global memory.  A block's particles are sorted by face, so nearly all of
 // its deposits land in the window, and the window is added to global memory
-// once per face at the end of the block.
-constexpr int kWin = 256;
-constexpr int kWinLead = 64;     // window starts this many faces before the block's first face
+// once per face at the end of the block.  Between sorts the particles drift
+// off their faces' order; 512 faces still hold most of them 16 steps after
+// a sort.  With the walk queue that is 24.6 KB of LDS per block, which keeps
+// the 6 waves per SIMD the registers allow.
+constexpr int kWin = 512;
+constexpr int kWinLead = 128;    // window starts this many faces before the block's first face
 
 struct Win {
     unsigned long long *jl;      // LDS, 3 * kWin
