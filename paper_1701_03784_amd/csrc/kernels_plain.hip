@@ -105,8 +105,8 @@ __device__ __forceinline__ void piece_d(double s0, double s1, double s2, double 
 // LDS.  Phase 2: the block walks the queue.  Phase 3: owners store their
 // particles, and the window is added to the face currents with FP64 global
 // atomics (whose order, and so the last bits, vary from run to run).
-constexpr int kWinD = 256;
-constexpr int kWinLeadD = 64;
+constexpr int kWinD = 512;
+constexpr int kWinLeadD = 128;
 
 typedef __attribute__((address_space(3))) double lds_double;
 
