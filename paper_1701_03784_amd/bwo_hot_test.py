@@ -127,13 +127,19 @@ def main():
     f = np.fft.rfftfreq(nfft, dt)
     P = sum(np.abs(np.fft.rfft(np.hanning(len(tail)) * tail[:, k], nfft)) ** 2 for k in range(2))
     band = (f > 2e9) & (f < 20e9)
-    i = int(np.flatnonzero(band)[np.argmax(P[band])])
-    y0, y1, y2 = np.log(P[i - 1]), np.log(P[i]), np.log(P[i + 1])
-    f_peak = float(f[i] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2) * (f[1] - f[0]))
-    frac = float(P[band][np.abs(f[band] - f_peak) < 0.2e9].sum() / P[band].sum())
+    idx = np.flatnonzero(band)
+    W = 6 * 8                                    # +-6 bins of the unpadded transform
+    local = [i for i in idx if P[i] == P[max(0, i - W):i + W + 1].max()]
+    lines = []
+    for i in sorted(local, key=lambda i: -P[i])[:3]:
+        y0, y1, y2 = np.log(P[i - 1]), np.log(P[i]), np.log(P[i + 1])
+        fi = float(f[i] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2) * (f[1] - f[0]))
+        lines.append((fi, float(P[band][np.abs(f[band] - fi) < 0.2e9].sum() / P[band].sum())))
+    f_peak, frac = lines[0]
     out = {"ns": steps * dt * 1e9, "run_s": run_s, "ms_per_step": run_s * 1e3 / steps, "live": d["n_live"],
            "absorbed": d["n_absorbed"], "dce_max_abs_worst": worst_dce, "walk_overflow": d["walk_overflow"],
            "nan_count": d["nan_count"], "f_peak_GHz": f_peak / 1e9, "power_within_200MHz": frac,
+           "lines_GHz_and_power_fraction": [(fi / 1e9, fr) for fi, fr in lines],
            "envelope_V_per_m_per_ns": env}
     print(json.dumps(out), flush=True)
 
