@@ -131,3 +131,66 @@ def test_layer_restrictions(axp, oracle_runs, tmp_path):
     with pytest.raises(axp.AxpError):
         axp.Batch([c2])
     c2.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "plain"])
+def test_particles_crossing_into_the_layer_match_oracle(axp, prec):
+    """A beam that crosses into the layer and reaches the end wall: 3,000
+    electrons (weight 10^4) in 4.5 cm <= z <= 7.5 cm at 0.5 c along z in
+    B_z = 0.5 T, 250 steps.  The layer stretches only the fields; the
+    particles deposit into layer faces like any other, so continuity stays
+    exact (mixed) or to FP64 rounding.  E to rel-L2 1e-9 (FP64 step) /
+    1e-4 (mixed); the same number absorbed; the survivors' positions to
+    1e-12 m / 2e-7 m (the FP32 rounding of 250 steps, as in the diode).
+    With no applied field, E is the beam's own field, so its mixed error is
+    the current's.  The FP32 momenta are off by up to 1e-5 of the largest,
+    each deposit follows its particle's displacement, and a face sums the
+    deposits of its particles: the bound of the staircased-wall test."""
+    from oracle.pic import OracleSim
+    m = _guide(0.08)
+    rng = np.random.default_rng(31)
+    n = 3000
+    zr = np.stack([rng.uniform(0.045, 0.075, n), np.sqrt(rng.uniform(0.0, 0.008 ** 2, n))], axis=1)
+    g = 0.5 / np.sqrt(0.75) * 299792458.0
+    u = np.zeros((n, 3))
+    u[:, 2] = g * (1.0 + 0.1 * np.arange(n) / n)
+    u[:, 0] = 0.05 * g * rng.standard_normal(n)
+    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, bz=0.5, pml=LAYER)
+    sim.set_fields(np.zeros(sim.topo.n1), np.zeros(sim.topo.n2))
+    sim.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, 10000)
+    sim.inject(0, zr, u)
+    tight = prec == "plain"
+    c = axp.make_ctx(m, dt=sim.dt, diag_every=1, layers=LAYER,
+                     precision=axp.PREC_PLAIN_FP64 if tight else axp.PREC_MIXED)
+    c.set_fields(np.zeros(c.info()["n_edges"]), np.zeros(c.info()["n_faces"]))
+    c.set_external_bz(0.5)
+    sp = c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, 10000)
+    c.inject(sp, zr, u)
+    c.diag()
+    print(f"[gpu] layer with particles {prec}", flush=True)
+    for _ in range(5):
+        c.step(50)
+        sim.step(50)
+        d = c.diag()
+        if tight:
+            assert d["dce_max_rel"] <= 1e-12
+        else:
+            assert d["dce_max_abs"] == 0
+        assert d["walk_overflow"] == 0 and d["nan_count"] == 0
+    assert int(sim.stats[1]) > 500
+    assert d["n_absorbed"] == int(sim.stats[1])
+    E, _ = c.get_fields()
+    e_E = _rel_l2(E, sim.E)
+    zr_g, u_g, _ = c.get_particles()
+    zr_o, u_o, _ = sim.particles()
+    assert len(zr_g) == len(zr_o)
+    import scipy.spatial
+    _, idx = scipy.spatial.cKDTree(np.concatenate([zr_o / 1e-6, u_o / 1e3], axis=1)).query(
+        np.concatenate([zr_g / 1e-6, u_g / 1e3], axis=1))
+    assert len(np.unique(idx)) == len(idx)
+    e_pos = np.abs(zr_g - zr_o[idx]).max()
+    print(f"[gpu] layer with particles {prec}: absorbed {d['n_absorbed']}, E rel-L2 {e_E:.2e}, positions {e_pos:.1e} m",
+          flush=True)
+    assert e_E <= (1e-9 if tight else 1e-4)
+    assert e_pos <= (1e-12 if tight else 2e-7)
+    c.close()
