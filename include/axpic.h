@@ -145,7 +145,7 @@ typedef struct {
 
 typedef struct {
     int64_t step;
-    int64_t n_live;              /* live particles */
+    int64_t n_live;              /* live particles, counted when the diagnostics are computed */
     int64_t n_absorbed;          /* particles absorbed at walls (cumulative) */
     int64_t walk_overflow;       /* paths cut at the segment cap (cumulative) */
     int64_t nan_count;           /* non-finite momenta seen (cumulative) */

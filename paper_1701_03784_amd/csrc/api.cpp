@@ -1190,8 +1190,7 @@ axp_status axp_diag_get(axp_ctx *c, axp_diag *out) {
         DevCounters h = read_counters(c);
         std::memset(out, 0, sizeof(*out));
         out->step = c->step;
-        // live count: slots minus dead ones is not tracked per step; count after compaction
-        out->n_live = int64_t(h.n_slots);
+        out->n_live = int64_t(d.n_live);     // counted by the charge pass of the diagnostics
         out->n_absorbed = int64_t(h.n_absorbed);
         out->walk_overflow = int64_t(h.walk_overflow);
         out->nan_count = int64_t(h.nan_count);

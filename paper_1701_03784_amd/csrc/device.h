@@ -108,6 +108,7 @@ struct DevDiag {
     double WE, WB, WK, Qtot;
     unsigned long long dce_abs_bits;      // FP64 step: max |dQ + Ddiv J| (charge units)
     unsigned long long qmax_bits;         // FP64 step: max |Q|
+    unsigned long long n_live;            // particles with a face (slots minus absorbed ones not yet compacted)
 };
 
 struct DevState {

@@ -879,12 +879,13 @@ __global__ __launch_bounds__(256) void k_charge(DevMesh m, DevState s) {
     const long long n = (long long)s.ctr->n_slots;
     const long long p0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 8;
     int run_t = -1;
-    long long q0 = 0, q1 = 0, q2 = 0;
+    long long q0 = 0, q1 = 0, q2 = 0, nl = 0;
     for (int j = 0; j < 8; ++j) {
         const long long p = p0 + j;
         if (p >= n) break;
         const int c = s.cell[s.cur][p];
         if (c < 0) continue;
+        ++nl;
         const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
         const int inst = m.tinst ? m.tinst[T] : 0;
         const long long kq = m.inst[inst].kq[sp];
@@ -906,6 +907,8 @@ __global__ __launch_bounds__(256) void k_charge(DevMesh m, DevState s) {
         atomicAdd((unsigned long long *)&s.Qfx[tn.y], (unsigned long long)q1);
         atomicAdd((unsigned long long *)&s.Qfx[tn.z], (unsigned long long)q2);
     }
+    nl = wave_sum64(nl);
+    if ((threadIdx.x & 63) == 0 && nl) atomicAdd(&s.diag->n_live, (unsigned long long)nl);
 }
 
 __device__ __forceinline__ void atomic_max_pos(unsigned long long *a, double v) {

@@ -546,8 +546,9 @@ __global__ __launch_bounds__(256) void k_charge_init_d(DevMesh m, DevPlain p) {
 __global__ __launch_bounds__(256) void k_charge_d(DevMesh m, DevState s, DevPlain p, PlainConst k) {
     const long long n = (long long)s.ctr->n_slots;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = s.cell[s.cur][i];
+    const int c = i < n ? s.cell[s.cur][i] : -1;
+    const unsigned long long live = __ballot(c >= 0);
+    if ((threadIdx.x & 63) == 0 && live) atomicAdd(&s.diag->n_live, (unsigned long long)__popcll(live));
     if (c < 0) return;
     const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
     const double kq = k.kq[sp];
