@@ -407,6 +407,30 @@ void axp_mlp_destroy(axp_mlp *net);
  * (AXP_SPAI_LEARNED_REJECTED).  The network is borrowed during axp_build. */
 axp_status axp_set_spai_model(axp_ctx *ctx, axp_mlp *net, double row_tol, double energy_drift_tol, int32_t iters);
 
+/* Loads a network saved by axp_mlp_save or axp_spai_model_train and uses it
+ * for this context's SPAI as axp_set_spai_model does, with row_tol 0.01,
+ * energy_drift_tol 1e-6 and 3 refinement steps.  The context owns the
+ * network (freed by axp_destroy).  Call before axp_build.  Errors: AXP_E_ARG
+ * (NULL argument, or a network of another SPAI level), AXP_E_STATE (after
+ * axp_build), the status of axp_mlp_load for an unreadable file. */
+axp_status axp_spai_model_load(axp_ctx *ctx, const char *model_path);
+
+/* Trains a learned-SPAI network on device 0 (default stream) and saves it
+ * to out_model (axp_mlp_save format).  mesh_list: a text file with one
+ * mesh file per line (blank lines and lines starting with '#' are skipped).
+ * A mesh file is text: "axpic-mesh 1", then "n_nodes n_tris n_seg", then
+ * n_nodes lines "z rho" [m], n_tris lines of three node ids
+ * (counter-clockwise) and n_seg boundary segments "a b tag" (AXP_BC_*),
+ * as axp_set_mesh and axp_set_boundary take them.  For every mesh the plain
+ * level-3 SPAI is built and at most 150,000 of its pattern pairs are drawn
+ * (axp_spai_pairs); the network (16 -> 64 -> 64 -> 1) then takes 40 epochs
+ * of Adam over minibatches of 4,096 after one shuffle, the learning rate
+ * falling linearly from 3e-3 to 1e-4.  Random draws (pair samples, shuffle,
+ * initial weights) follow `seed`.  Errors: AXP_E_ARG (unreadable list or
+ * mesh file, no pairs), AXP_E_OOM, AXP_E_HIP, or the status of the first
+ * failing library call (a bad mesh gives AXP_E_MESH). */
+axp_status axp_spai_model_train(const char *mesh_list, const char *out_model, uint64_t seed);
+
 /* Training data of a built context: features X[n][16] of every pattern pair,
  * the scaled entry y[n] = M^_kj of the context's SPAI (0 where dropped) and
  * the canonical edge indices kj[n][2].  *n receives the pair count; with

@@ -74,7 +74,8 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_batch_set_timing", "axp_batch_get_timing", "axp_batch_info", "axp_batch_last_error",
            "axp_mlp_create", "axp_mlp_n_params", "axp_mlp_set_params", "axp_mlp_get_params", "axp_mlp_forward",
            "axp_mlp_loss_grad", "axp_mlp_adam_step", "axp_mlp_info", "axp_mlp_save", "axp_mlp_load",
-           "axp_mlp_last_error", "axp_mlp_destroy", "axp_set_spai_model", "axp_spai_pairs"]
+           "axp_mlp_last_error", "axp_mlp_destroy", "axp_set_spai_model", "axp_spai_pairs",
+           "axp_spai_model_load", "axp_spai_model_train"]
 PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject", "walk"]
 
 _lib = None
@@ -151,6 +152,8 @@ def load_library(path: str = LIB_PATH):
         "axp_mlp_destroy": (None, [vp]),
         "axp_set_spai_model": (i32, [vp, vp, dbl, dbl, i32]),
         "axp_spai_pairs": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
+        "axp_spai_model_load": (i32, [vp, C.c_char_p]),
+        "axp_spai_model_train": (i32, [C.c_char_p, C.c_char_p, C.c_uint64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -352,6 +355,11 @@ class Ctx:
         self._check(self.lib.axp_set_spai_model(self.h, net.h if net is not None else None, float(row_tol),
                                                 float(energy_drift_tol), int(iters)))
 
+    def spai_model_load(self, path):
+        """Learned SPAI for the next build from a saved network file
+        (axp_spai_model_load; the context owns the loaded network)."""
+        self._check(self.lib.axp_spai_model_load(self.h, str(path).encode()))
+
     def spai_pairs(self):
         """(X[n][16] float32, y[n] float32, kj[n][2] int32) of the built context."""
         n = C.c_int64()
@@ -400,6 +408,29 @@ class Ctx:
         sp = np.zeros(cap, dtype=np.int32)
         self._check(self.lib.axp_get_particles(self.h, cap, C.byref(n), _ptr(zr), _ptr(u), _ptr(sp)))
         return zr[:n.value], u[:n.value], sp[:n.value]
+
+
+def write_mesh(path, mesh):
+    """Writes a mesh (synth.Mesh-like: nodes, tris, seg, tag) in the text
+    format axp_spai_model_train reads."""
+    nodes = np.asarray(mesh.nodes, dtype=np.float64)
+    tris = np.asarray(mesh.tris, dtype=np.int64)
+    seg = np.asarray(mesh.seg, dtype=np.int64)
+    tag = np.asarray(mesh.tag, dtype=np.int64)
+    with open(path, "w") as f:
+        f.write(f"axpic-mesh 1\n{len(nodes)} {len(tris)} {len(seg)}\n")
+        np.savetxt(f, nodes, fmt="%.17g")
+        np.savetxt(f, tris, fmt="%d")
+        np.savetxt(f, np.column_stack([seg, tag]), fmt="%d")
+
+
+def spai_model_train(mesh_list, out_model, seed=0):
+    """Trains and saves a learned-SPAI network natively (axp_spai_model_train):
+    mesh_list is a text file naming one write_mesh file per line."""
+    lib = load_library()
+    st = lib.axp_spai_model_train(str(mesh_list).encode(), str(out_model).encode(), int(seed))
+    if st != AXP_OK:
+        raise AxpError(st, "axp_spai_model_train")
 
 
 def make_ctx(mesh, spai_model=None, spai_row_tol=0.01, spai_energy_tol=1e-6, spai_iters=3, layers=None, **kw):

@@ -56,6 +56,7 @@ struct axp_ctx {
     int64_t n_live_host = 0;
     // continuous injector
     bool inj_on = false;
+    axp_mlp *owned_model = nullptr;     // network loaded by axp_spai_model_load
     InjParams inj{};
     EmitEdge *inj_edges = nullptr;
     // per-phase timing
@@ -1539,6 +1540,7 @@ void axp_destroy(axp_ctx *c) {
     for (auto &r : c->ev) { (void)hipEventDestroy(r.second.first); (void)hipEventDestroy(r.second.second); }
     for (auto &r : c->ev_free) { (void)hipEventDestroy(r.first); (void)hipEventDestroy(r.second); }
     for (void *p : std::vector<void *>(c->allocs)) dfree(c, p);
+    if (c->owned_model) axp_mlp_destroy(c->owned_model);
     delete c;
 }
 
@@ -1553,6 +1555,22 @@ axp_status axp_set_spai_model(axp_ctx *c, axp_mlp *net, double row_tol, double e
     c->spai_row_tol = row_tol;
     c->spai_energy_tol = energy_drift_tol;
     c->spai_iters = iters;
+    return AXP_OK;
+}
+
+axp_status axp_spai_model_load(axp_ctx *c, const char *model_path) {
+    if (!c || !model_path) return AXP_E_ARG;
+    if (c->built) return fail(c, AXP_E_STATE, "load the SPAI model before axp_build");
+    axp_mlp *net = nullptr;
+    const axp_status st = axp_mlp_load(c->cfg.device, c->cfg.hip_stream, model_path, &net);
+    if (st != AXP_OK) return fail(c, st, std::string("cannot load the SPAI model ") + model_path);
+    const axp_status s2 = axp_set_spai_model(c, net, 0.01, 1e-6, 3);
+    if (s2 != AXP_OK) {
+        axp_mlp_destroy(net);
+        return s2;
+    }
+    if (c->owned_model) axp_mlp_destroy(c->owned_model);
+    c->owned_model = net;
     return AXP_OK;
 }
 
