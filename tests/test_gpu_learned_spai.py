@@ -273,6 +273,16 @@ def test_native_trainer_and_model_file(axp, torch, tmp_path):
     assert il["spai_mode"] == axp.SPAI_LEARNED
     assert il["spai_energy_drift"] <= 1e-6
     assert il["spai_fallback_columns"] < 0.1 * il["n_edges"]
+    with pytest.raises(axp.AxpError):
+        c.spai_model_load(str(out))                      # after axp_build
     c.close()
+    c2 = axp.Ctx()
+    with pytest.raises(axp.AxpError):
+        c2.spai_model_load(str(tmp_path / "missing.bin"))
+    c2.close()
     with pytest.raises(axp.AxpError):
         axp.spai_model_train(tmp_path / "missing.txt", out, seed=7)
+    bad = tmp_path / "bad.txt"
+    bad.write_text(str(tmp_path / "meshes.txt") + "\n")   # a list file is not a mesh file
+    with pytest.raises(axp.AxpError):
+        axp.spai_model_train(bad, out, seed=7)
