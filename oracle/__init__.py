@@ -24,7 +24,7 @@ Readings of the paper where it is silent, ambiguous or garbled:
   * SPAI pattern, drop rule and symmetrisation are not given (Sec. 3.1);
     level-L pattern of the Jacobi-scaled matrix, relative drop tolerance,
     symmetric average;
-  * Boris "with a correction" (Sec. 3.3) is the relativistic Boris rotation
+  * the corrected Boris algorithm of Sec. 3.3 is the relativistic Boris rotation
     with gamma taken from the half-accelerated momentum; the axisymmetric
     position update pushes in the local Cartesian frame and rotates back.
 """
