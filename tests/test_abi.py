@@ -99,3 +99,18 @@ def test_spai_enum_values():
     assert val["AXP_SPAI_PLAIN"] == ax.SPAI_PLAIN
     assert val["AXP_SPAI_LEARNED"] == ax.SPAI_LEARNED
     assert val["AXP_SPAI_LEARNED_REJECTED"] == ax.SPAI_LEARNED_REJECTED
+
+
+def test_spai_model_train_rejects_bad_arguments_before_any_device_work(tmp_path):
+    """axp_spai_model_train checks its arguments and the mesh list before it
+    touches the device: NULL arguments and an unreadable or empty list give
+    AXP_E_ARG (runs without a GPU)."""
+    import paper_1701_03784_amd as pkg
+    lib = pkg.load_library()
+    assert lib.axp_spai_model_train(None, b"x.bin", 0) == -1
+    assert lib.axp_spai_model_train(str(tmp_path / "no_such_list.txt").encode(), None, 0) == -1
+    assert lib.axp_spai_model_train(str(tmp_path / "no_such_list.txt").encode(), b"x.bin", 0) == -1
+    empty = tmp_path / "empty.txt"
+    empty.write_text("# nothing but a comment\n\n")
+    assert lib.axp_spai_model_train(str(empty).encode(), str(tmp_path / "x.bin").encode(), 0) == -1
+    assert not (tmp_path / "x.bin").exists()
