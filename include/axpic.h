@@ -152,7 +152,7 @@ typedef struct {
     int64_t fixed_overflow;      /* fixed-point headroom violations (cumulative) */
     int64_t dce_max_abs;         /* max over nodes |2^23 (Q^{n+1}-Q^n) + Ddiv J| in fixed point (mixed; 0 = exact) */
     double dce_max_rel;          /* same, relative to max |Q| (plain FP64 mode) */
-    double gauss_max_drift;      /* max over free nodes |res^n - res^0| (Sec. 3.4.2) */
+    double gauss_max_drift;      /* max over free nodes |res^n - res^0| (Sec. 3.5.2) */
     double gauss_max_abs;        /* max over free nodes |res^n| */
     double gauss_scale;          /* max over free nodes of sum |D_e| at the node */
     double W_E, W_B, W_K;        /* energies per radian [J/rad]: 1/2 E^T[*eps]E, 1/2 B^{n+1/2} H B^{n-1/2}, sum w(gamma-1)mc^2/2pi */
@@ -200,9 +200,9 @@ axp_status axp_get_spai(const axp_ctx *ctx, int64_t capacity, int64_t *nnz, int6
 axp_status axp_set_fields(axp_ctx *ctx, const double *E0, const double *B_mhalf);
 
 /* Electrostatic, Gauss-consistent fields at step 0.  The scheme keeps the
- * Gauss residual D~div [*eps]_a E - Q at its initial value (Sec. 3.4.2), so
+ * Gauss residual D~div [*eps]_a E - Q at its initial value (Sec. 3.5.2), so
  * it is zero for all steps only if it is zero at step 0; applied voltages
- * (the cathode-anode field of Sec. 5.2) enter as potentials of conductors.
+ * (the cathode-anode field of the diode, Sec. 4.2) enter as potentials of conductors.
  * Computes the nodal potential phi with phi = phi_conductor on conductor
  * nodes (nodes on AXP_BC_PEC or AXP_BC_EMITTER segments) such that
  * E^0 = -G phi (edge value phi_tail - phi_head; 0 on conductor edges) and
@@ -221,7 +221,7 @@ axp_status axp_set_fields(axp_ctx *ctx, const double *E0, const double *B_mhalf)
 axp_status axp_set_electrostatic(axp_ctx *ctx, const double *phi_conductor, int32_t with_charge, double *phi_out);
 
 /* Absorbing layers at the z ends of the domain (the PML terminating the
- * ports and the cathode side, Sec. 5.3), set before axp_build.  The layers
+ * ports and the cathode side, Sec. 5.1), set before axp_build.  The layers
  * stretch z by s_z = 1 + sigma / (j omega eps0), i.e. the meridian medium
  * becomes eps_rho = eps0 s_z, eps_z = eps0 / s_z, mu_phi = mu0 s_z; sigma
  * grows as sigma_max (depth / thickness)^order from the layer's inner face
@@ -241,7 +241,7 @@ axp_status axp_set_electrostatic(axp_ctx *ctx, const double *phi_conductor, int3
  * outside 0..8, negative or non-finite values), AXP_E_STATE after axp_build. */
 axp_status axp_set_layers(axp_ctx *ctx, int32_t sides, double z_left, double z_right, double sigma_max, int32_t order);
 
-/* Magnetic point source (Sec. 5.1): a magnetic current M(t) at (z, rho)
+/* Magnetic point source (Sec. 4.1): a magnetic current M(t) at (z, rho)
  * [m], a ring about the axis, drives the flux of the face holding the
  * point: B_T^{n+1/2} = B_T^{n-1/2} - dt (C E^n)_T - dt M(t^n), t^n = n dt,
  * with the Gaussian-modulated pulse
@@ -255,7 +255,7 @@ axp_status axp_add_point_source(axp_ctx *ctx, double z, double rho, double ampli
                                 double omega);
 axp_status axp_clear_point_sources(axp_ctx *ctx);
 
-/* Field probe (Sec. 5.1): from the next step on, the E field at (z, rho)
+/* Field probe (Sec. 4.1): from the next step on, the E field at (z, rho)
  * (Whitney interpolation of the edge values, the gather of Sec. 3.2) is
  * recorded at t^n at the start of every step, for the next `capacity`
  * steps, in a device buffer the context owns (16 bytes per step).

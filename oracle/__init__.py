@@ -16,7 +16,7 @@ Readings of the paper where it is silent, ambiguous or garbled:
   * edge current is (q/dt) * line integral of the Whitney 1-form along the
     path, i.e. (q/dt)(lam_t^n lam_h^{n+1} - lam_h^n lam_t^{n+1}) with
     t < h; the printed eq. (current) has the opposite sign of its own
-    DCE derivation (Sec. 3.4.1), and only this sign satisfies the DCE with
+    DCE derivation (Sec. 3.5.1), and only this sign satisfies the DCE with
     the divergence incidence of App. D;
   * ring sources carry charge and current per radian (q / 2 pi);
   * the App. B local entry T22 is garbled; Hodge entries are computed by

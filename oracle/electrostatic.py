@@ -3,11 +3,11 @@
 TEST INFRASTRUCTURE ONLY: the GPU library never imports this module.
 
 The scheme carries the Gauss law as the invariant
-res = D~div [*eps]_a E - Q on the free nodes (Sec. 3.4.2), with
+res = D~div [*eps]_a E - Q on the free nodes (Sec. 3.5.2), with
 [*eps]_a = M^-1 the inverse of the sparse approximate inverse; it stays at
 its initial value for all steps, and it is zero only if the initial state
 makes it zero (the consistency the paper asks of the initial conditions).
-An applied voltage (the cathode-anode field of Sec. 5.2) enters as the
+An applied voltage (the cathode-anode field of the diode, Sec. 4.2) enters as the
 potential phi on the conductor nodes.  The initial state is then
 
     E = -G phi  (curl-free: C G = 0, so the face fluxes B do not move),

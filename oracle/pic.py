@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 State is kept in the E-form of eqs. (full_d_dfl)/(full_d_dal): E^n on
 edges, B^{n-1/2} on faces, particles with global (z, rho), their triangle
 and u = gamma v.  D^n = [*eps]_a E^n is carried beside it for the discrete
-Gauss law check of Sec. 3.4.2 ([*eps]_a = M^-1).
+Gauss law check of Sec. 3.5.2 ([*eps]_a = M^-1).
 """
 
 from __future__ import annotations
@@ -50,7 +50,7 @@ def _load():
     if _lib is None:
         _lib = C.CDLL(build_oracle())
         vp = C.c_void_p
-        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp, vp] + [vp] * 8
+        _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp, vp] + [vp] * 9
         _lib.oracle_step.restype = None
         _lib.oracle_charge.argtypes = [vp, vp, vp, vp]
         _lib.oracle_sample.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -162,6 +162,14 @@ class OracleSim:
         self._rhs = np.zeros(n1)
         self.stats = np.zeros(3, dtype=np.int64)
         self.n_step = 0
+        # energies of every step's starting time level n when log_energies is
+        # set: (n, W_E, W_B, W_K, W_E_exact) per radian [J/rad] with
+        # W_E = 1/2 E^n [*eps]_a E^n, W_B = 1/2 B^{n+1/2} H B^{n-1/2},
+        # W_K = 1/2 (K^{n-1/2} + K^{n+1/2}) and W_E_exact = 1/2 E^n [*eps] E^n
+        # (the exact Hodge); see oracle_step
+        self.log_energies = False
+        self.energy_log = []
+        self._energy = np.zeros(4)
         # contiguous arrays handed to C
         self._arr = dict(
             nodes=np.ascontiguousarray(tp.nodes, dtype=np.float64),
@@ -308,7 +316,7 @@ class OracleSim:
 
     # ------------------------------------------------------------------ step
     def add_point_source(self, z, rho, amplitude, t0, sigma, omega):
-        """Magnetic point source of Sec. 5.1 at (z, rho): the magnetic current
+        """Magnetic point source of Sec. 4.1 at (z, rho): the magnetic current
         M(t) = amplitude exp(-((t - t0) / (2 sigma))^2) cos(omega (t - t0))
         drives the flux of the face holding the point."""
         face = int(self.locate(np.array([[z, rho]]))[0])
@@ -337,11 +345,16 @@ class OracleSim:
                 e = self.sample(np.array([f]), np.array([z]), np.array([r]))[0]
                 self.probe_signal.append((e[0], e[1]))
             src_val = self._source_values()
+            log = self.log_energies
+            we_exact = 0.5 * self.E @ (self.A @ self.E) if log else 0.0
             lib.oracle_step(C.byref(self._mesh), C.byref(P), self.dt, self.bz, int(self.pusher),
                             len(src_face), _p(src_face), _p(src_val),
                             None if self._pml_c is None else C.byref(self._pml_c),
                             _p(self.E), _p(self.B), _p(self.D), _p(self.J), _p(self.Qres),
-                            _p(self._Bh), _p(self._rhs), _p(self.stats))
+                            _p(self._Bh), _p(self._rhs), _p(self.stats), _p(self._energy) if log else None)
+            if log:
+                e = self._energy
+                self.energy_log.append((self.n_step, float(e[0]), float(e[1]), float(e[2]), float(we_exact)))
             self.n_step += 1
 
     # ----------------------------------------------------------- diagnostics
@@ -354,20 +367,18 @@ class OracleSim:
         return Q
 
     def gauss_residual(self, D=None):
-        """res^n = D~div [*eps]_a E^n - Q^n (Sec. 3.4.2), on every node."""
+        """res^n = D~div [*eps]_a E^n - Q^n (Sec. 3.5.2), on every node."""
         D = self.D if D is None else D
         return self.topo.Ddiv @ D - self.charge()
 
-    def energies(self):
-        """(W_E, W_B, W_K) per radian: 1/2 E^T [*eps] E, 1/2 B^{n-1/2} H B^{n-1/2},
-        sum w (gamma - 1) m c^2 / (2 pi)."""
-        WE = 0.5 * self.E @ (self.A @ self.E)
-        WB = 0.5 * self.B @ (self.H * self.B)
+    def kinetic_energy(self):
+        """sum over live particles of (m w c^2 / 2 pi)(gamma - 1) [J/rad] at
+        the momenta held now (u^{n-1/2} after n steps)."""
         a = self.palive.astype(bool)
-        g = np.sqrt(1.0 + (self.pu[a] ** 2).sum(axis=1) / C_LIGHT ** 2)
+        w2 = (self.pu[a] ** 2).sum(axis=1) / C_LIGHT ** 2
         sp_ = self.pspecies[a]
-        WK = float(np.sum(self.sp_w[sp_] * self.sp_m[sp_] * (g - 1.0)) * C_LIGHT ** 2 / TWO_PI)
-        return float(WE), float(WB), WK
+        return float(np.sum(self.sp_w[sp_] * self.sp_m[sp_] * (w2 / (np.sqrt(1.0 + w2) + 1.0)))
+                     * C_LIGHT ** 2 / TWO_PI)
 
     def sample(self, tri, z, rho):
         lib = _load()

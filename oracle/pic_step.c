@@ -5,7 +5,7 @@
  *
  * Order of one step n -> n+1 (Sec. 3.1-3.4):
  *   1. Faraday, eq. (full_d_dfl):   B^{n+1/2} = B^{n-1/2} - dt C E^n
- *      (- dt M(t^n) on the faces of magnetic point sources, Sec. 5.1)
+ *      (- dt M(t^n) on the faces of magnetic point sources, Sec. 4.1)
  *   2. gather, Sec. 3.2:            E_p = sum_e E_e W1_e(r_p),
  *                                   B_p = sum_T (B^{n+1/2}+B^{n-1/2})_T/2 W2_T
  *      plus a static axial field B_z (beam focusing, Sec. 3.2);
@@ -19,7 +19,7 @@
  *   5. Ampere, eq. (full_d_dal):    E^{n+1} = E^n + dt M (C^T H B^{n+1/2} - J)
  *      with M the sparse approximate inverse of [*eps]; also
  *      D^{n+1} = D^n + dt (C^T H B^{n+1/2} - J), the quantity whose discrete
- *      divergence minus the nodal charge is invariant (Sec. 3.4.2).
+ *      divergence minus the nodal charge is invariant (Sec. 3.5.2).
  *
  * Charges and currents of a ring are per radian: a macro-particle of
  * charge q contributes q/(2 pi).  Units are SI; momenta are u = gamma v.
@@ -264,7 +264,7 @@ static int walk(const omesh *m, oparticles *P, int64_t p, double ze, double re,
     return -1;
 }
 
-/* Stretched-coordinate absorbing layer (the PML of the ports, Sec. 5.3):
+/* Stretched-coordinate absorbing layer (the PML of the ports, Sec. 5.1):
  * the z coordinate is stretched by s_z = 1 + sigma / (j omega eps0) on the
  * layer's faces, i.e. eps_rho = eps0 s_z, eps_z = eps0 / s_z, mu_phi = mu0 s_z.
  * Per layer face f (n faces), beta = sigma dt / (2 eps0); Az, Ar: the z and
@@ -289,13 +289,35 @@ typedef struct {
  * stats: [0] pieces walked, [1] absorbed, [2] walk overflows.
  * pusher: 0 relativistic Boris, 1 Vay.  src_face/src_val: the nsrc point
  * sources' faces and their magnetic currents at t^n.
+ *
+ * energy (may be NULL) receives the energies of time level n, the step's
+ * start, per radian [J/rad]; a step is where their ingredients meet:
+ *   [0] W_E = 1/2 E^n . D^n = 1/2 E^n [*eps]_a E^n  (the scheme's Hodge)
+ *   [1] W_B = 1/2 B^{n+1/2} . H B^{n-1/2}
+ *   [2] W_K = 1/2 (K^{n-1/2} + K^{n+1/2}),
+ *       K = sum_p (m w c^2 / 2 pi)(gamma_p - 1) over the particles pushed
+ *       (those absorbed during the step included)
+ *   [3] K^{n+1/2}
+ * Without sources W_E + W_B is the invariant of the leapfrog pair
+ * (full_d_dfl)/(full_d_dal): its change over a step is
+ * 1/2 (E^{n+1} + E^n) . dt C^T H B^{n+1/2} - 1/2 dt C (E^{n+1} + E^n) . H B^{n+1/2} = 0.
  */
+/* gamma - 1 of momentum u = gamma v, without cancellation for slow particles */
+static double gamma_m1(const double u[3])
+{
+    double w2 = (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (O_C * O_C);
+    return w2 / (sqrt(1.0 + w2) + 1.0);
+}
+
 void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher,
                  int64_t nsrc, const int64_t *src_face, const double *src_val, const opml *pml,
                  double *E, double *B, double *D, double *J, double *Qres,
-                 double *Bh, double *rhs, int64_t *stats)
+                 double *Bh, double *rhs, int64_t *stats, double *energy)
 {
-    /* 1. Faraday, with the magnetic point sources (Sec. 5.1): a magnetic
+    double we = 0.0, wb = 0.0, k_old = 0.0, k_new = 0.0;
+    if (energy)
+        for (int64_t e = 0; e < m->n1; ++e) we += E[e] * D[e];
+    /* 1. Faraday, with the magnetic point sources (Sec. 4.1): a magnetic
      *    current M(t^n) at a point drives the flux of the face holding it */
     for (int64_t t = 0; t < m->n2; ++t) {
         double circ = 0.0;
@@ -304,6 +326,8 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher
         Bh[t] = B[t] - dt * circ;
     }
     for (int64_t k = 0; k < nsrc; ++k) Bh[src_face[k]] -= dt * src_val[k];
+    if (energy)
+        for (int64_t t = 0; t < m->n2; ++t) wb += Bh[t] * m->H[t] * B[t];
     memset(J, 0, sizeof(double) * m->n1);
 
     /* 2-4. gather, push, scatter */
@@ -318,8 +342,12 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher
         double Ev[3] = {e2[1], 0.0, e2[0]};          /* (E_rho, E_phi, E_z) */
         double Bv[3] = {0.0, bphi, bz};               /* (B_rho, B_phi, B_z) */
         double *u = P->u + 3 * p;
+        /* m w c^2 / (2 pi) of the macro-particle: m w = (q w) / (q / m) */
+        double mwc2 = P->sp_qw[sp] / P->sp_qm[sp] * O_C * O_C / O_TWO_PI;
+        if (energy) k_old += mwc2 * gamma_m1(u);
         if (pusher == 1) oracle_vay(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
         else oracle_boris(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
+        if (energy) k_new += mwc2 * gamma_m1(u);
         double ze, re;
         oracle_move(P->z[p], P->rho[p], u, dt, &ze, &re);
         double q_ring = P->sp_qw[sp] / O_TWO_PI;
@@ -393,6 +421,12 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher
         }
     }
     memcpy(B, Bh, sizeof(double) * m->n2);
+    if (energy) {
+        energy[0] = 0.5 * we;
+        energy[1] = 0.5 * wb;
+        energy[2] = 0.5 * (k_old + k_new);
+        energy[3] = k_new;
+    }
 }
 
 /* Nodal charge, eq. (charge): Q_v = sum_p (q/2pi) lam_v(r_p) + Qres_v */

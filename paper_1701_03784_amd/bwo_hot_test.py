@@ -1,4 +1,4 @@
-"""Hot test of the backward-wave oscillator (Sec. 5.3, synthetic geometry).
+"""Hot test of the backward-wave oscillator (Sec. 5.1, synthetic geometry).
 
     python -m paper_1701_03784_amd.bwo_hot_test [--ns 40] [--h 0.19e-3] [--per-step 300]
 

@@ -1,11 +1,11 @@
-"""The cavity validation of Sec. 5.1 run on the GPU.
+"""The cavity validation of Sec. 4.1 run on the GPU.
 
     python -m paper_1701_03784_amd.cavity_spectrum [--steps 2000000] [--dt 1e-12] [--h 0.00854]
                                                    [--precision mixed|plain] [--out spectrum.json]
 
 A PEC cylinder of radius a = 0.5 m and height h = 1 m (the meridian plane
 meshed with about 15,800 faces at the default spacing), excited by the two
-magnetic point sources of Sec. 5.1 (Gaussian-modulated pulses centred at
+magnetic point sources of Sec. 4.1 (Gaussian-modulated pulses centred at
 20 and 40 ns, sigma = 1 ns, carrier 0.5 GHz), with the field probe at
 (z = 0.71 m, rho = 0.39 m) (the printed probe position lies outside the
 cavity; its two coordinates are read swapped).  The probe signal of the

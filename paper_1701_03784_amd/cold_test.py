@@ -1,5 +1,5 @@
 """Cold test of the slow-wave structure: band edges of the TM01 passband
-under mesh refinement (Sec. 5.3), run on the GPU.
+under mesh refinement (the cold test of Sec. 5 and the staircasing study of Sec. 5.1.2), run on the GPU.
 
     python -m paper_1701_03784_amd.cold_test [--amp 0.0025] [--period 0.0167] [--r0 0.015]
                                              [--h 0.4e-3 0.2e-3 0.1e-3] [--ns 60]
@@ -22,7 +22,7 @@ modes sample the TM01 dispersion curve at those phases, without periodic
 (Floquet) boundaries; for a smooth guide they are the closed form
 c/(2 pi) sqrt((x_01/r0)^2 + (k pi / (N d))^2).
 
-The staircasing study of Sec. 5.3 compares a wall that follows R(z) with
+The staircasing study of Sec. 5.1.2 compares a wall that follows R(z) with
 the step-cell wall a structured grid would impose: 'grid' and 'staircase'
 meshes share their triangles and differ only at the wall, so the change of
 the pi-point frequency between them is the staircasing error alone.

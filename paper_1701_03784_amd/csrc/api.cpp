@@ -80,7 +80,7 @@ struct axp_ctx {
     LayerConfig layer_cfg{};
     HostLayers hl{};
     DevLayers dl{};
-    // magnetic point sources and field probe (Sec. 5.1)
+    // magnetic point sources and field probe (Sec. 4.1)
     FieldSrc fs{};
     unsigned long long step_upload = 0;   // host image of the device step counter (async copy source)
 };

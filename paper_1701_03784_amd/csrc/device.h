@@ -84,7 +84,7 @@ struct DevLayers {
 
 constexpr int kMaxSources = 8;
 
-// Magnetic point sources and the field probe (Sec. 5.1), passed by value to
+// Magnetic point sources and the field probe (Sec. 4.1), passed by value to
 // the face pass.  Source k adds -dt M_k(t^n) to the flux of face src_face[k],
 // M_k(t) = amp exp(-((t - t0) / (2 sig))^2) cos(w (t - t0)); the probe writes
 // (E_z, E_rho) at barycentric (probe_l0, probe_l1) of probe_face at t^n into

@@ -841,7 +841,7 @@ void build_layers(const HostMesh &m, double dt, const LayerConfig &cfg, HostLaye
 }
 
 // ------------------------------------------------------------ electrostatics
-// The scheme's Gauss law (Sec. 3.4.2) holds for all steps if the initial
+// The scheme's Gauss law (Sec. 3.5.2) holds for all steps if the initial
 // state satisfies D~div D = Q on the free nodes with D = [*eps]_a E = M^-1 E.
 // With E = -G phi = D~div^T phi the field is curl-free (C G = 0) and
 // K phi = Q with K = D~div M^-1 D~div^T (free nodes; phi fixed on conductor

@@ -39,7 +39,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
 __device__ __forceinline__ int sel3(int k, int a, int b, int c) { return k == 0 ? a : (k == 1 ? b : c); }
 
 // ------------------------------------------------------------------ faces
-// magnetic current of point source k at step n (Sec. 5.1)
+// magnetic current of point source k at step n (Sec. 4.1)
 __device__ __forceinline__ double source_current(const FieldSrc &fs, int k, unsigned long long n) {
     const double tt = double(n) * fs.dt - fs.t0[k];
     const double a = tt / (2.0 * fs.sig[k]);

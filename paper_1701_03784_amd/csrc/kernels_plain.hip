@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPl
     if (e.w & 4) E2 = -E2;
     const double bo = s.B[t];
     double bn = bo - dt * (E0 + E1 + E2);
-    for (int k = 0; k < fs.n_src; ++k)          // magnetic point sources (Sec. 5.1)
+    for (int k = 0; k < fs.n_src; ++k)          // magnetic point sources (Sec. 4.1)
         if (t == fs.src_face[k]) {
             const double tt = double(s.ctr->step) * fs.dt - fs.t0[k];
             const double a = tt / (2.0 * fs.sig[k]);

@@ -1,4 +1,4 @@
-"""Magnetic point sources and the field probe (Sec. 5.1) on the GPU against
+"""Magnetic point sources and the field probe (Sec. 4.1) on the GPU against
 the FP64 oracle, both precisions.
 
 Workload: the paper's cavity (a = 0.5 m, h = 1 m) on a coarse 25 mm mesh,

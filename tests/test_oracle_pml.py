@@ -1,5 +1,5 @@
 """Pins of the FP64 stretched-coordinate absorbing layer (the PML of the
-ports and cathode side, Sec. 5.3).
+ports and cathode side, Sec. 5.1).
 
 The layer stretches z by s_z = 1 + sigma / (j omega eps0): eps_rho = eps0 s_z,
 eps_z = eps0 / s_z, mu_phi = mu0 s_z, with auxiliary face and edge

@@ -48,7 +48,7 @@ def test_exact_sequence_identities(c1, ripple):
     for topo in (c1[1], ripple[1]):
         G = gradient_incidence(topo)
         assert abs(topo.C @ G).max() == 0                            # curl grad = 0
-        assert abs(topo.Ddiv @ topo.C.T).max() == 0                  # div curl = 0 (Sec. 3.4.2)
+        assert abs(topo.Ddiv @ topo.C.T).max() == 0                  # div curl = 0 (Sec. 3.5.2)
         assert np.all(np.abs(topo.C.data) == 1) and np.all(np.diff(topo.C.indptr) == 3)
 
 

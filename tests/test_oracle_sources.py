@@ -1,4 +1,4 @@
-"""Pins of the FP64 magnetic point sources and field probe (Sec. 5.1).
+"""Pins of the FP64 magnetic point sources and field probe (Sec. 4.1).
 
 The source term: from zero fields, one step leaves -dt M(0) on the face
 that holds the source point (found here by brute force) and nothing
