@@ -74,7 +74,7 @@ def field_bytes(n_edges, n_faces, spai_nnz_padded):
         (8.0 * spai_nnz_padded + 8.0 * n_edges)
 
 
-def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, pusher=0):
+def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, pusher=0, diag_every=0):
     import synth
     from synth import configs
     import paper_1701_03784_amd as axp
@@ -83,7 +83,7 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, p
     L = m.meta["length"]
     log(f"mesh: {m.n_nodes} nodes, {m.n_tris} faces ({time.perf_counter() - t0:.1f} s)")
     kw = {} if precision is None else {"precision": precision}
-    c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, pusher=pusher, **kw)
+    c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, pusher=pusher, diag_every=diag_every, **kw)
     info = c.info()
     log(f"built: {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s "
         f"(limit {info['dt_cfl']:.3e}), setup {info['setup_seconds']:.1f} s")
@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--vay-steps", type=int, default=32, help="timed steps of the Vay-pusher leg (0: skip)")
     ap.add_argument("--batch-variants", type=int, default=8, help="members of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=48)
+    ap.add_argument("--diag-every", type=int, default=0,
+                    help="diagnostic steps (nodal charge, Gauss and continuity residuals, energies) every this many steps")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -249,7 +251,7 @@ def main():
 
     import paper_1701_03784_amd as axp
     axp.load_library()
-    c, m, info, desc = setup_bwo(args.particles, sort_period=max(1, args.sort_period))
+    c, m, info, desc = setup_bwo(args.particles, sort_period=max(1, args.sort_period), diag_every=args.diag_every)
     sort_period = args.sort_period
     if sort_period == 0:
         sort_period = c.autotune(16)

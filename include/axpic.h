@@ -111,7 +111,9 @@ typedef struct {
     int32_t spai_level;      /* SPAI a-priori pattern level L (pattern of A^L), default 3 */
     double spai_drop_tol;    /* relative drop tolerance within each SPAI column, default 1e-3 */
     int32_t sort_period;     /* re-sort particles by triangle every this many steps (>= 1) */
-    int32_t diag_every;      /* device diagnostics every this many steps (0 = only on axp_diag) */
+    int32_t diag_every;      /* the step from level n to n+1 is a diagnostic step when n+1 is a multiple of
+                                diag_every: inside its own kernels it evaluates level n+1 (charge, Gauss and
+                                continuity residuals) and records the energies of level n (0: only axp_diag_get) */
     int32_t max_walk;        /* cap on path pieces per particle and step (default 64) */
     int32_t use_graph;       /* 1: capture axp_step's launches in a hipGraph and replay it */
     axp_alloc_fn alloc;      /* optional device allocator (NULL: hipMalloc) */
@@ -144,19 +146,27 @@ typedef struct {
 } axp_info;
 
 typedef struct {
-    int64_t step;
-    int64_t n_live;              /* live particles, counted when the diagnostics are computed */
+    int64_t step;                /* time level evaluated: the number of steps taken */
+    int64_t n_live;              /* live particles at that level */
     int64_t n_absorbed;          /* particles absorbed at walls (cumulative) */
     int64_t walk_overflow;       /* paths cut at the segment cap (cumulative) */
     int64_t nan_count;           /* non-finite momenta seen (cumulative) */
     int64_t fixed_overflow;      /* fixed-point headroom violations (cumulative) */
-    int64_t dce_max_abs;         /* max over nodes |2^23 (Q^{n+1}-Q^n) + Ddiv J| in fixed point (mixed; 0 = exact) */
-    double dce_max_rel;          /* same, relative to max |Q| (plain FP64 mode) */
-    double gauss_max_drift;      /* max over free nodes |res^n - res^0| (Sec. 3.5.2) */
-    double gauss_max_abs;        /* max over free nodes |res^n| */
-    double gauss_scale;          /* max over free nodes of sum |D_e| at the node */
-    double W_E, W_B, W_K;        /* energies per radian [J/rad]: 1/2 E^T[*eps]E, 1/2 B^{n+1/2} H B^{n-1/2}, sum w(gamma-1)mc^2/2pi */
-    double Q_total;              /* total charge per radian incl. wall charge [C/rad] */
+    int64_t dce_max_abs;         /* mixed: max over the evaluations since the reference of max over nodes
+                                    |2^23 (Q^n - Q^{n-1}) + Ddiv J^{n-1/2}| in fixed point, taken where
+                                    level n-1 was evaluated too (Sec. 3.5.1; 0 = exact) */
+    double dce_max_rel;          /* FP64 step: the same maximum of |Q^n - Q^{n-1} + Ddiv J^{n-1/2}| / max|Q| */
+    double gauss_max_drift;      /* max over the evaluations since the reference and over free nodes of
+                                    |res^n - res^ref|, res = Ddiv [*eps]_a E - Q (Sec. 3.5.2) */
+    double gauss_max_abs;        /* this level: max over free nodes |res^n| */
+    double gauss_scale;          /* this level: max over free nodes of sum |D_e| at the node */
+    double W_E, W_B, W_K;        /* energies per radian [J/rad] of level energy_step (the last diagnostic
+                                    step): 1/2 E^n [*eps]_a E^n, 1/2 B^{n+1/2} H B^{n-1/2},
+                                    1/2 (K^{n-1/2} + K^{n+1/2}) with K = sum w (gamma - 1) m c^2 / 2 pi */
+    double Q_total;              /* this level: total charge per radian incl. wall charge [C/rad] */
+    int64_t energy_step;         /* level of W_E, W_B, W_K; -1 before the first diagnostic step */
+    int64_t n_evals;             /* evaluations since the reference */
+    double W_E_now;              /* this level: 1/2 E^n [*eps]_a E^n [J/rad] */
 } axp_diag;
 
 /* Fills cfg with defaults: device 0, default stream, mixed precision,
@@ -270,15 +280,20 @@ axp_status axp_get_probe(axp_ctx *ctx, int64_t capacity, int64_t *n, double *E_z
 /* Uniform static axial field B_z [T] added at the gather (beam focusing, Sec. 3.2). */
 axp_status axp_set_external_bz(axp_ctx *ctx, double bz);
 
-/* Particle species: q [C] and m [kg] of one physical particle, and the
+/* Particle species (the macro-particles of Sec. 2.2 and 3.3, rings of
+ * charge about the axis): q [C] and m [kg] of one physical particle, and the
  * number of physical particles per macro-particle (weight >= 1).  In mixed
  * precision every species' macro charge q*weight must be an integer multiple
  * of the first species' macro charge (the fixed-point charge unit).
  * *species_id receives the new id (at most 16 species). */
 axp_status axp_add_species(axp_ctx *ctx, double q, double m, int64_t weight, int32_t *species_id);
 
-/* Adds n macro-particles at zr[n][2] with momenta u[n][3]; each is located
- * in the mesh (AXP_E_ARG if outside).  Enqueued on the stream. */
+/* Adds n macro-particles at zr[n][2] (meridian positions (z, rho), rho >= 0)
+ * with momenta u[n][3] = gamma v (u_rho, u_phi, u_z) [m/s], the state of the
+ * push of Sec. 3.3 at t = -dt/2; each is located in the mesh (AXP_E_ARG if
+ * outside or non-finite; nothing is added then) and stored element-local.
+ * Host arrays are copied.  Breaks the continuity chain of the diagnostics
+ * (the next evaluation has no previous level).  Synchronous. */
 axp_status axp_inject(axp_ctx *ctx, int32_t species, int64_t n, const double *zr, const double *u);
 
 /* Continuous injection from the AXP_BC_EMITTER boundary (the emission of
@@ -301,14 +316,47 @@ axp_status axp_inject(axp_ctx *ctx, int32_t species, int64_t n, const double *zr
 axp_status axp_set_injector(axp_ctx *ctx, int32_t species, int64_t per_step, const double u_mean[3],
                             double u_spread, uint64_t seed);
 
-/* Enqueues n_steps time steps on cfg.hip_stream and returns. */
+/* Enqueues n_steps time steps on cfg.hip_stream and returns (Sec. 3; the
+ * order of one step n -> n+1): Faraday B^{n+1/2} = B^{n-1/2} - dt C E^n,
+ * eq. (full_d_dfl); the gather of E^n and of the face field averaged over
+ * B^{n-1/2}, B^{n+1/2} (Sec. 3.2); the relativistic push, eqs. (DNE)/(DLE)
+ * (Sec. 3.3); the walk of each path across faces with the charge-conserving
+ * edge current of eq. (current) (Sec. 3.4); Ampere
+ * D^{n+1} = D^n + dt (C^T H B^{n+1/2} - J^{n+1/2}), E^{n+1} = M D^{n+1},
+ * eq. (full_d_dal) with the SPAI M (Sec. 3.1).  Diagnostic steps (diag_every)
+ * also evaluate their start level.  Errors raised by the kernels surface at
+ * axp_sync.  AXP_E_ARG if n_steps < 0. */
 axp_status axp_step(axp_ctx *ctx, int32_t n_steps);
 
 /* Waits for the stream and raises sticky errors from device flags. */
 axp_status axp_sync(axp_ctx *ctx);
 
-/* Computes the diagnostics of the current state (syncs first). */
+/* Diagnostics of the current level n (the number of steps taken; evaluated
+ * now unless the last diagnostic step or call already did), syncs first:
+ * the nodal charge of eq. (charge) from the particles' element-local
+ * coordinates plus the wall charge, the discrete Gauss law's residual and its
+ * drift from the reference level (Sec. 3.5.2), the continuity residual
+ * against level n-1 (Sec. 3.5.1), the total charge, and the energies of the
+ * last diagnostic step.  The reference level is the first evaluation after
+ * axp_set_fields / axp_set_electrostatic; axp_inject only breaks the
+ * continuity chain.  Returns the sticky errors of axp_sync. */
 axp_status axp_diag_get(axp_ctx *ctx, axp_diag *out);
+
+/* Energy record of one diagnostic step n -> n+1 (its start level n), per radian. */
+typedef struct {
+    int64_t step;                /* level n */
+    int64_t n_live;              /* live particles at level n */
+    double W_E, W_B, W_K;        /* as in axp_diag */
+    double Q_total;              /* reserved (0): the total charge is in axp_diag */
+} axp_energy;
+
+/* Energy records of the diagnostic steps not yet returned, oldest first:
+ * at most capacity of them into out[capacity]; *n receives the count.  The
+ * device keeps the last 4096 records; older ones not yet read are skipped.
+ * W_E + W_B is the invariant of the leapfrog pair (full_d_dfl)/(full_d_dal)
+ * without sources; with particles W_E + W_B + W_K is conserved up to the
+ * push's and the deposit's time discretisation. */
+axp_status axp_get_energies(axp_ctx *ctx, int64_t capacity, int64_t *n, axp_energy *out);
 
 /* E^n[n_edges] (canonical edge order) and B^{n-1/2}[n_faces] (input face
  * order); either pointer may be NULL. */

@@ -61,13 +61,20 @@ class Diag(C.Structure):
                 ("walk_overflow", C.c_int64), ("nan_count", C.c_int64), ("fixed_overflow", C.c_int64),
                 ("dce_max_abs", C.c_int64), ("dce_max_rel", C.c_double), ("gauss_max_drift", C.c_double),
                 ("gauss_max_abs", C.c_double), ("gauss_scale", C.c_double), ("W_E", C.c_double),
-                ("W_B", C.c_double), ("W_K", C.c_double), ("Q_total", C.c_double)]
+                ("W_B", C.c_double), ("W_K", C.c_double), ("Q_total", C.c_double),
+                ("energy_step", C.c_int64), ("n_evals", C.c_int64), ("W_E_now", C.c_double)]
+
+
+class Energy(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_live", C.c_int64), ("W_E", C.c_double), ("W_B", C.c_double),
+                ("W_K", C.c_double), ("Q_total", C.c_double)]
 
 
 EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary", "axp_build",
            "axp_info_get", "axp_get_edges", "axp_get_spai", "axp_set_fields", "axp_set_electrostatic", "axp_set_layers", "axp_add_point_source",
            "axp_clear_point_sources", "axp_set_probe", "axp_get_probe", "axp_set_external_bz",
            "axp_add_species", "axp_inject", "axp_set_injector", "axp_step", "axp_sync", "axp_diag_get",
+           "axp_get_energies",
            "axp_get_fields", "axp_get_sources", "axp_get_particles", "axp_save", "axp_load",
            "axp_last_error", "axp_destroy", "axp_batch_create", "axp_batch_step", "axp_batch_sync",
            "axp_batch_destroy", "axp_set_timing", "axp_get_timing", "axp_autotune", "axp_batch_autotune",
@@ -119,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "axp_step": (i32, [vp, i32]),
         "axp_sync": (i32, [vp]),
         "axp_diag_get": (i32, [vp, C.POINTER(Diag)]),
+        "axp_get_energies": (i32, [vp, i64, C.POINTER(i64), C.POINTER(Energy)]),
         "axp_get_fields": (i32, [vp, vp, vp]),
         "axp_get_sources": (i32, [vp, vp, vp, vp]),
         "axp_get_particles": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
@@ -340,6 +348,19 @@ class Ctx:
         self._check(self.lib.axp_diag_get(self.h, C.byref(d)))
         return {k: getattr(d, k) for k, _ in Diag._fields_}
 
+    def energies(self, capacity=4096):
+        """Energy records of the diagnostic steps not yet returned, oldest
+        first: a structured array (step, n_live, W_E, W_B, W_K, Q_total)."""
+        buf = (Energy * max(1, int(capacity)))()
+        n = C.c_int64()
+        self._check(self.lib.axp_get_energies(self.h, int(capacity), C.byref(n), buf))
+        dt = np.dtype([(k, np.int64 if t is C.c_int64 else np.float64) for k, t in Energy._fields_])
+        out = np.zeros(n.value, dtype=dt)
+        for i in range(n.value):
+            for k, _ in Energy._fields_:
+                out[i][k] = getattr(buf[i], k)
+        return out
+
     def set_timing(self, on=True):
         self._check(self.lib.axp_set_timing(self.h, 1 if on else 0))
 
@@ -465,11 +486,28 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _check_dev(name, t, device, shape):
+    """Rejects what the network kernels cannot read: host or other-device
+    tensors, dtypes other than float32, non-contiguous views, wrong shapes."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: a torch tensor is required")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name}: must live on cuda:{device} (got {t.device})")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name}: float32 required (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
 class Mlp:
     """The learned-SPAI network (axp_mlp_*): its kernels run on the device."""
 
     def __init__(self, n_hidden=64, n_layers=2, spai_level=3, seed=0, device=0, stream=None, _handle=None):
         self.lib = load_library()
+        self.device = int(device)
         if _handle is not None:
             self.h = _handle
         else:
@@ -488,7 +526,7 @@ class Mlp:
                               str(path).encode(), C.byref(h))
         if st != AXP_OK:
             raise AxpError(st, f"axp_mlp_load {path}")
-        return cls(_handle=h)
+        return cls(_handle=h, device=device)
 
     def _check(self, st):
         if st != AXP_OK:
@@ -512,14 +550,31 @@ class Mlp:
         assert p.size == self.n_params()
         self._check(self.lib.axp_mlp_set_params(self.h, _ptr(p)))
 
+    def _n_in(self):
+        return self.info()["n_in"]
+
     def forward(self, X, y_out):
-        """X, y_out: contiguous float32 torch tensors on the device."""
-        self._check(self.lib.axp_mlp_forward(self.h, _dptr(X), int(X.shape[0]), _dptr(y_out)))
+        """X (n, n_in), y_out (n,): contiguous float32 torch tensors on the
+        network's device (ValueError otherwise, before any launch)."""
+        _check_dev("X", X, self.device, None)
+        _check_dev("y_out", y_out, self.device, None)
+        n = int(X.shape[0]) if X.dim() == 2 else -1
+        _check_dev("X", X, self.device, (n, self._n_in()))
+        _check_dev("y_out", y_out, self.device, (n,))
+        self._check(self.lib.axp_mlp_forward(self.h, _dptr(X), n, _dptr(y_out)))
 
     def loss_grad(self, X, y, w, want_grad=False):
+        """X (n, n_in), y and w (n,): contiguous float32 tensors on the
+        network's device (ValueError otherwise, before any launch)."""
+        for name, t in (("X", X), ("y", y), ("w", w)):
+            _check_dev(name, t, self.device, None)
+        n = int(X.shape[0]) if X.dim() == 2 else -1
+        _check_dev("X", X, self.device, (n, self._n_in()))
+        _check_dev("y", y, self.device, (n,))
+        _check_dev("w", w, self.device, (n,))
         loss = C.c_double()
         g = np.zeros(self.n_params(), dtype=np.float32) if want_grad else None
-        self._check(self.lib.axp_mlp_loss_grad(self.h, _dptr(X), _dptr(y), _dptr(w), int(X.shape[0]), C.byref(loss),
+        self._check(self.lib.axp_mlp_loss_grad(self.h, _dptr(X), _dptr(y), _dptr(w), n, C.byref(loss),
                                                _ptr(g)))
         return (loss.value, g) if want_grad else loss.value
 

@@ -51,8 +51,8 @@ struct axp_ctx {
     std::vector<Species> species;
     double q_unit = 0;
     int64_t step = 0;
-    int64_t last_diag_step = -1;  // step at which Qprev was computed
-    bool g0_set = false;
+    int64_t last_eval_level = -1;  // time level of the last diagnostic evaluation enqueued (-1: none)
+    int64_t energy_read = 0;       // energy records already returned by axp_get_energies
     int64_t n_live_host = 0;
     // continuous injector
     bool inj_on = false;
@@ -196,6 +196,8 @@ void grow_particles(axp_ctx *c, int64_t need) {
             for (int k = 0; k < 5; ++k) { dfree(c, *old[k]); *old[k] = f[k]; }
         }
         s.capacity = cap;
+        dfree(c, s.part_kin);
+        s.part_kin = zeros<double>(c, size_t(3) * ((cap + 1023) / 1024));
         return;
     }
     for (int b = 0; b < 2; ++b) {
@@ -216,6 +218,8 @@ void grow_particles(axp_ctx *c, int64_t need) {
         s.cell[b] = cell; s.L0[b] = l0; s.L1[b] = l1; s.ur[b] = ur; s.up[b] = up; s.uz[b] = uz;
     }
     s.capacity = cap;
+    dfree(c, s.part_kin);
+    s.part_kin = zeros<double>(c, size_t(3) * ((cap + 1023) / 1024));
 }
 
 // Brackets one phase's launches with HIP events on stream st (eager steps).
@@ -257,15 +261,41 @@ void collect_timing(axp_ctx *c) {
     c->ev.clear();
 }
 
+// Diagnostic evaluation of the current state (level = steps taken), on demand.
 void run_diag(axp_ctx *c) {
-    bool have_prev = (c->last_diag_step == c->step - 1) && c->step > 0;
     {
         PhaseScope ps(c, AXP_PHASE_DIAG);
-        if (c->plain) launch_diag_plain(c->dm, c->ds, c->dp, c->pc, have_prev, !c->g0_set, c->stream);
-        else launch_diag(c->dm, c->ds, have_prev, !c->g0_set, c->stream);
+        if (c->plain) {
+            launch_charge_plain(c->dm, c->ds, c->dp, c->pc, c->stream);
+            launch_diag_plain(c->dm, c->ds, c->dp, c->pc, false, c->stream);
+        } else {
+            launch_diag_now(c->dm, c->ds, c->stream);
+        }
     }
-    c->g0_set = true;
-    c->last_diag_step = c->step;
+    c->last_eval_level = c->step;
+}
+
+// Restarts the diagnostics' references: g0 (the Gauss residual's reference
+// level) when reset_gauss, and always the continuity chain (the next
+// evaluation has no previous level to compare with).  Host-to-device copies:
+// never inside a graph.
+void reset_diag_refs(axp_ctx *c, bool reset_gauss) {
+    DevCounters h = read_counters(c);
+    h.diag_level1 = 0;
+    if (reset_gauss) h.g0_set = 0;
+    hcheck(hipMemcpyAsync(c->ds.ctr, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+    if (reset_gauss) {
+        DevDiag d{};
+        hcheck(hipMemcpyAsync(&d, c->ds.diag, sizeof(d), hipMemcpyDeviceToHost, c->stream), "diag");
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        d.gauss_drift_max_bits = 0;
+        d.dce_max = 0;
+        d.dce_rel_max_bits = 0;
+        d.n_evals = 0;
+        hcheck(hipMemcpyAsync(c->ds.diag, &d, sizeof(d), hipMemcpyHostToDevice, c->stream), "diag");
+    }
+    hcheck(hipStreamSynchronize(c->stream), "sync");
+    c->last_eval_level = -1;
 }
 
 // Host images of the device tables of one instance or of a pool of them.
@@ -275,6 +305,7 @@ struct HostTables {
     std::vector<double> Hdt;
     std::vector<int32_t> tinst, ninst;
     std::vector<int32_t> nptr{0}, nedge;
+    std::vector<int32_t> ncptr{0}, ncorner;   // face corners 3 t + k at each node
     std::vector<int8_t> nsign;
     std::vector<uint8_t> nfree;
     Csr M, A;   // pooled rows, column indices offset per instance
@@ -308,6 +339,19 @@ void append_instance(HostTables &h, const HostMesh &m, double dt, int inst) {
         if (R >= 0 && m.tsign[R][kr] < 0) packed |= 32;
         if (m.efree[e]) packed |= 64;
         h.etri.push_back(make_int4(L + fo, R >= 0 ? R + fo : -1, packed, inst));
+    }
+    {
+        std::vector<int32_t> cnt(size_t(m.n0) + 1, 0), fill;
+        for (int t = 0; t < m.n2; ++t)
+            for (int k = 0; k < 3; ++k) ++cnt[m.tv[t][k] + 1];
+        for (int v = 0; v < m.n0; ++v) cnt[v + 1] += cnt[v];
+        fill.assign(cnt.begin(), cnt.end() - 1);
+        std::vector<int32_t> corner(size_t(3) * m.n2);
+        for (int t = 0; t < m.n2; ++t)
+            for (int k = 0; k < 3; ++k) corner[fill[m.tv[t][k]]++] = 3 * (t + fo) + k;
+        const int32_t base = int32_t(h.ncorner.size());
+        for (int v = 0; v < m.n0; ++v) h.ncptr.push_back(base + cnt[v + 1]);
+        h.ncorner.insert(h.ncorner.end(), corner.begin(), corner.end());
     }
     for (int v = 0; v < m.n0; ++v) {
         for (int q = m.nptr[v]; q < m.nptr[v + 1]; ++q) {
@@ -381,6 +425,7 @@ void upload_tables(axp_ctx *c, const HostTables &h, bool pooled, int n_inst) {
     d.etri = upload(c, h.etri);
     d.nptr = upload(c, h.nptr); d.nedge = upload(c, h.nedge); d.nsign = upload(c, h.nsign);
     d.nfree = upload(c, h.nfree); d.ninst = pooled ? upload(c, h.ninst) : nullptr;
+    d.ncptr = upload(c, h.ncptr); d.ncorner = upload(c, h.ncorner);
     d.m_sptr = upload(c, sptr); d.m_slen = upload(c, slen); d.m_col = upload(c, mcol);
     d.m_val = c->plain ? nullptr : upload(c, mval);
     d.a_ptr = upload(c, h.A.ptr); d.a_col = upload(c, h.A.col); d.a_val = upload(c, h.A.val);
@@ -402,12 +447,25 @@ void upload_tables(axp_ctx *c, const HostTables &h, bool pooled, int n_inst) {
         s.D32 = zeros<float>(c, h.n1); s.E = zeros<float>(c, h.n1);
         s.Jfx = zeros<long long>(c, h.n1);
         s.Qres = zeros<long long>(c, h.n0); s.Qfx = zeros<long long>(c, h.n0); s.Qprev = zeros<long long>(c, h.n0);
+        s.Qloc = zeros<unsigned long long>(c, size_t(3) * h.n2);
     }
     s.cnt = zeros<int32_t>(c, size_t(h.n2) + 1);
     s.blk = zeros<int32_t>(c, size_t(h.n2) / 1024 + 2);
     s.ctr = zeros<DevCounters>(c, 1);
     s.diag = zeros<DevDiag>(c, 1);
-    s.kin_part = zeros<double>(c, 1024);
+    {
+        DevDiag d{};
+        d.level = -1;
+        d.dce_last = -1;
+        d.energy.level = -1;
+        hcheck(hipMemcpyAsync(s.diag, &d, sizeof(d), hipMemcpyHostToDevice, c->stream), "diag");
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+    }
+    s.part_face = zeros<double>(c, (size_t(h.n2) + 255) / 256);
+    s.part_edge = zeros<double>(c, (size_t(h.n1) + 255) / 256);
+    s.part_node = zeros<double>(c, size_t(kDiagSlots) * ((size_t(std::max(h.n0, h.n1)) + 255) / 256));
+    s.part_kin = zeros<double>(c, 3);
+    s.energy = zeros<DevEnergy>(c, kEnergyRing);
     s.capacity = 0;
     s.cur = 0;
 }
@@ -497,9 +555,14 @@ void layers_at_rest(axp_ctx *c, const std::vector<double> &E, const std::vector<
 }
 
 
+// Whether the step from level n to n + 1 is a diagnostic step: it evaluates
+// level n + 1 (a multiple of diag_every) and records the energies of level n.
+bool diag_step(const axp_ctx *c, int64_t n) { return c->cfg.diag_every > 0 && (n + 1) % c->cfg.diag_every == 0; }
+
 // One time step enqueued on st (c->stream unless a graph is being captured).
 void enqueue_step(axp_ctx *c, hipStream_t st) {
     const bool sort_now = (c->step + 1) % c->cfg.sort_period == 0;
+    const bool diag = diag_step(c, c->step);
     DevMesh &m = c->dm;
     DevState &s = c->ds;
     if (c->inj_on) {
@@ -508,37 +571,46 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
         else launch_inject(m, s, c->inj_edges, c->inj, st);
     }
     if (c->plain) {
-        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, c->fs, c->dl, st); }
+        { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass_plain(m, s, c->dp, c->pc, c->fs, c->dl, diag, st); }
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
         {
             PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
-            launch_particles_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, c->cfg.pusher == AXP_PUSH_VAY, st);
+            launch_particles_plain(m, s, c->dp, c->pc, c->cfg.max_walk, sort_now, c->cfg.pusher == AXP_PUSH_VAY, diag,
+                                   st);
         }
-        { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass_plain(m, s, c->dp, c->pc, st); }
+        { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass_plain(m, s, c->dp, c->pc, diag, st); }
         {
             PhaseScope ps(c, AXP_PHASE_SPMV, st);
             launch_spmv_plain(m, s, c->dp, st);
             launch_layers_post(m, s, (const double *)c->dp.E, c->dl, st);
         }
+        if (diag) {
+            PhaseScope ps(c, AXP_PHASE_DIAG, st);
+            launch_charge_plain(m, s, c->dp, c->pc, st);
+            launch_diag_plain(m, s, c->dp, c->pc, true, st);
+        }
         ++c->step;
+        if (diag) c->last_eval_level = c->step;
         if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_plain(m, s, c->dp, true, st); }
         return;
     }
     const bool single = m.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
     const InstConst *k0 = single ? &c->ic : nullptr;
-    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, c->fs, c->dl, st); }
+    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, c->fs, c->dl, diag, st); }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
         PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
-        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, st);
+        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, diag, st);
     }
-    { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, st); }
+    { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, diag, st); }
     {
         PhaseScope ps(c, AXP_PHASE_SPMV, st);
         launch_spmv(m, s, st);
         launch_layers_post(m, s, (const float *)s.E, c->dl, st);
     }
+    if (diag) { PhaseScope ps(c, AXP_PHASE_DIAG, st); launch_diag_in_step(m, s, st); }
     ++c->step;
+    if (diag) c->last_eval_level = c->step;
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort(m, s, true, st); }
 }
 
@@ -555,13 +627,14 @@ void launch_graph(axp_ctx *c, int W) {
     if (!c->gexec[cur0]) {
         if (!c->cap_stream) hcheck(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
         const DevState saved = c->ds;
-        const int64_t saved_step = c->step;
+        const int64_t saved_step = c->step, saved_eval = c->last_eval_level;
         hcheck(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
         for (int k = 0; k < W; ++k) enqueue_step(c, c->cap_stream);
         hipGraph_t g = nullptr;
         const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
         c->ds = saved;              // the captured launches have not run
         c->step = saved_step;
+        c->last_eval_level = saved_eval;
         hcheck(e1, "end capture");
         const hipError_t e2 = hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -569,6 +642,8 @@ void launch_graph(axp_ctx *c, int W) {
         c->graph_window = W;
     }
     hcheck(hipGraphLaunch(c->gexec[cur0], c->stream), "graph launch");
+    for (int64_t n = c->step; n < c->step + W; ++n)
+        if (diag_step(c, n)) c->last_eval_level = n + 1;
     c->step += W;
 
 }
@@ -586,14 +661,15 @@ void run_steps(axp_ctx *c, int n_steps) {
     }
     const int sp = c->cfg.sort_period;
     const int W = 2 * sp;
+    const int de = c->cfg.diag_every;
     for (int i = 0; i < n_steps;) {
-        const int de = c->cfg.diag_every;
         // with timing on the steps run eagerly: HIP does not time event records inside graphs
         bool graph = c->cfg.use_graph && !c->timing && c->step % sp == 0 && n_steps - i >= W;
-        if (graph && de > 0) {
-            // a diagnostic falls inside the window: run eagerly
-            const int64_t next = (c->step / de + 1) * de;
-            if (next <= c->step + W) graph = false;
+        if (graph && de > 0 && sp % de != 0) {
+            // a window's diagnostic steps would differ from one replay to the next:
+            // replay only windows without one
+            for (int64_t n = c->step; n < c->step + W; ++n)
+                if (diag_step(c, n)) { graph = false; break; }
         }
         if (graph && c->graph_window != 0 && c->graph_window != W) drop_graphs(c);
         if (graph) {
@@ -603,7 +679,6 @@ void run_steps(axp_ctx *c, int n_steps) {
         }
         enqueue_step(c, c->stream);
         ++i;
-        if (de > 0 && c->step % de == 0) run_diag(c);
         if (c->ev.size() > 4096) collect_timing(c);
     }
     hcheck(hipGetLastError(), "step launch");
@@ -822,8 +897,7 @@ axp_status axp_set_fields(axp_ctx *c, const double *E0, const double *B_mhalf) {
         }
         hcheck(hipStreamSynchronize(c->stream), "sync");
         layers_at_rest(c, E, B);
-        c->g0_set = false;
-        c->last_diag_step = -1;
+        reset_diag_refs(c, true);
         return AXP_OK;
     });
 }
@@ -885,8 +959,7 @@ axp_status axp_set_electrostatic(axp_ctx *c, const double *phi_conductor, int32_
         }
         hcheck(hipStreamSynchronize(c->stream), "sync");
         layers_at_rest(c, E, B);
-        c->g0_set = false;
-        c->last_diag_step = -1;
+        reset_diag_refs(c, true);
         if (phi_out) std::memcpy(phi_out, phi.data(), sizeof(double) * m.n0);
         return AXP_OK;
     });
@@ -1091,7 +1164,7 @@ axp_status axp_inject(axp_ctx *c, int32_t species, int64_t n, const double *zr, 
         hcheck(hipGetLastError(), "sort launch");
         hcheck(hipStreamSynchronize(c->stream), "inject sync");
         c->n_live_host = int64_t(read_counters(c).n_slots);
-        c->last_diag_step = -1;
+        reset_diag_refs(c, false);      // the added charge breaks the continuity chain
         return AXP_OK;
     });
 }
@@ -1185,7 +1258,7 @@ axp_status axp_diag_get(axp_ctx *c, axp_diag *out) {
     if (!c || !out) return AXP_E_ARG;
     return guarded(c, [&]() -> axp_status {
         require_built(c);
-        if (c->last_diag_step != c->step) run_diag(c);
+        if (c->last_eval_level != c->step) run_diag(c);
         DevDiag d{};
         hcheck(hipMemcpyAsync(&d, c->ds.diag, sizeof(d), hipMemcpyDeviceToHost, c->stream), "diag");
         DevCounters h = read_counters(c);
@@ -1196,20 +1269,46 @@ axp_status axp_diag_get(axp_ctx *c, axp_diag *out) {
         out->walk_overflow = int64_t(h.walk_overflow);
         out->nan_count = int64_t(h.nan_count);
         out->fixed_overflow = int64_t(h.fixed_overflow);
-        out->dce_max_abs = int64_t(d.dce_max);
+        out->dce_max_abs = c->plain ? 0 : int64_t(d.dce_max);
         double v;
-        std::memcpy(&v, &d.gauss_drift_bits, 8); out->gauss_max_drift = v;
-        std::memcpy(&v, &d.gauss_abs_bits, 8); out->gauss_max_abs = v;
-        std::memcpy(&v, &d.gauss_scale_bits, 8); out->gauss_scale = v;
-        out->W_E = d.WE; out->W_B = d.WB; out->W_K = d.WK; out->Q_total = d.Qtot;
-        if (c->plain) {
-            double da, qm;
-            std::memcpy(&da, &d.dce_abs_bits, 8);
-            std::memcpy(&qm, &d.qmax_bits, 8);
-            out->dce_max_abs = 0;
-            out->dce_max_rel = qm > 0 ? da / qm : da;
-        }
+        std::memcpy(&v, &d.gauss_drift_max_bits, 8); out->gauss_max_drift = v;
+        out->gauss_max_abs = d.gauss_abs;
+        out->gauss_scale = d.gauss_scale;
+        out->Q_total = d.q_total;
+        out->W_E_now = d.WE_now;
+        out->n_evals = int64_t(d.n_evals);
+        out->energy_step = d.energy.level;
+        if (d.energy.level >= 0) { out->W_E = d.energy.WE; out->W_B = d.energy.WB; out->W_K = d.energy.WK; }
+        if (c->plain) { std::memcpy(&v, &d.dce_rel_max_bits, 8); out->dce_max_rel = v; }
         return axp_sync(c);
+    });
+}
+
+axp_status axp_get_energies(axp_ctx *c, int64_t capacity, int64_t *n, axp_energy *out) {
+    if (!c || !n || capacity < 0 || (capacity > 0 && !out)) return AXP_E_ARG;
+    return guarded(c, [&]() -> axp_status {
+        require_built(c);
+        const DevCounters h = read_counters(c);
+        const int64_t written = int64_t(h.energy_count);
+        int64_t from = std::max<int64_t>(c->energy_read, written - kEnergyRing);
+        const int64_t k = std::min<int64_t>(capacity, written - from);
+        *n = k;
+        if (k <= 0) { c->energy_read = from; return AXP_OK; }
+        std::vector<DevEnergy> ring(kEnergyRing);
+        hcheck(hipMemcpyAsync(ring.data(), c->ds.energy, sizeof(DevEnergy) * kEnergyRing, hipMemcpyDeviceToHost,
+                              c->stream), "energies");
+        hcheck(hipStreamSynchronize(c->stream), "sync");
+        for (int64_t i = 0; i < k; ++i) {
+            const DevEnergy &e = ring[size_t((from + i) % kEnergyRing)];
+            out[i].step = e.level;
+            out[i].n_live = e.n_live;
+            out[i].W_E = e.WE;
+            out[i].W_B = e.WB;
+            out[i].W_K = e.WK;
+            out[i].Q_total = e.Qtot;
+        }
+        c->energy_read = from + k;
+        return AXP_OK;
     });
 }
 
@@ -1262,13 +1361,13 @@ axp_status axp_get_sources(axp_ctx *c, double *D, double *J_dt, double *Q) {
             for (int k = 0; k < m.n1; ++k) J_dt[k] = double(j[m.edge_int[k]]) * c->ic.jscale;
         }
         if (Q && c->plain) {
-            if (c->last_diag_step != c->step) run_diag(c);
+            if (c->last_eval_level != c->step) run_diag(c);
             std::vector<double> q(m.n0);
             hcheck(hipMemcpyAsync(q.data(), c->dp.Q, m.n0 * 8, hipMemcpyDeviceToHost, c->stream), "Q");
             hcheck(hipStreamSynchronize(c->stream), "sync");
             for (int v = 0; v < m.n0; ++v) Q[v] = q[v] * c->pc.qunit;
         } else if (Q) {
-            if (c->last_diag_step != c->step) run_diag(c);
+            if (c->last_eval_level != c->step) run_diag(c);
             std::vector<long long> q(m.n0);
             hcheck(hipMemcpyAsync(q.data(), c->ds.Qfx, m.n0 * 8, hipMemcpyDeviceToHost, c->stream), "Q");
             hcheck(hipStreamSynchronize(c->stream), "sync");
@@ -1410,9 +1509,9 @@ axp_status axp_save(axp_ctx *c, const char *path) {
         H.n0 = c->hm.n0; H.n1 = c->hm.n1; H.n2 = c->hm.n2;
         H.dt = c->dt;
         H.step = c->step;
-        H.last_diag_step = c->last_diag_step;
+        H.last_diag_step = c->last_eval_level;
         H.n_slots = int64_t(h.n_slots);
-        H.g0_set = c->g0_set;
+        H.g0_set = int32_t(h.g0_set);
         H.n_species = int32_t(c->species.size());
         H.inj_on = c->inj_on;
         H.q_unit = c->q_unit;
@@ -1491,11 +1590,12 @@ axp_status axp_load(axp_ctx *c, const char *path) {
             restore(c, f, s.L0[b], np); restore(c, f, s.L1[b], np);
             restore(c, f, s.ur[b], np); restore(c, f, s.up[b], np); restore(c, f, s.uz[b], np);
         }
+        H.ctr.energy_count = 0;          // the energy records are not part of a checkpoint
         hcheck(hipMemcpyAsync(s.ctr, &H.ctr, sizeof(DevCounters), hipMemcpyHostToDevice, c->stream), "counters");
         hcheck(hipStreamSynchronize(c->stream), "sync");
         c->step = H.step;
-        c->last_diag_step = H.last_diag_step;
-        c->g0_set = H.g0_set != 0;
+        c->last_eval_level = H.last_diag_step;
+        c->energy_read = 0;
         c->n_live_host = H.n_slots;
         if (H.inj_on) {
             c->inj_on = false;
@@ -1805,6 +1905,7 @@ axp_status axp_batch_sync(axp_batch *b) {
             const int64_t nk = start[k + 1] - start[k];
             DevCounters h = read_counters(c);
             h.n_slots = 0;
+            h.diag_level1 = 0;            // the pooled steps' charges are not the member's chain
             hcheck(hipMemcpyAsync(cs.ctr, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
             grow_particles(c, nk);
             hcheck(hipStreamSynchronize(c->stream), "sync");
@@ -1824,12 +1925,13 @@ axp_status axp_batch_sync(axp_batch *b) {
             d2d(p, cs.E, ps.E + b->eo[k], m.n1);
             d2d(p, cs.Jfx, ps.Jfx + b->eo[k], m.n1);
             d2d(p, cs.Qres, ps.Qres + b->no[k], m.n0);
+            c->step += p->step - b->synced_step;
+            c->last_eval_level = -1;
             h.n_slots = (unsigned long long)nk;
             h.n_absorbed += (unsigned long long)std::max<int64_t>(0, b->live[k] - nk);
+            h.step = (unsigned long long)c->step;    // the device's level counter follows the pooled steps
             hcheck(hipMemcpyAsync(cs.ctr, &h, sizeof(h), hipMemcpyHostToDevice, p->stream), "counters");
             hcheck(hipStreamSynchronize(p->stream), "sync");
-            c->step += p->step - b->synced_step;
-            c->last_diag_step = -1;
             c->n_live_host = nk;
             b->live[k] = nk;
         }

@@ -39,8 +39,9 @@ struct DevMesh {
     const int32_t *tinst = nullptr; // instance of each face (pooled batches), or null
     // edges
     const int4 *etri = nullptr;     // left face, right face (-1), packed sides/signs/free, instance
-    // nodes: incident edges with divergence sign
+    // nodes: incident edges with divergence sign; incident face corners (3 t + k)
     const int32_t *nptr = nullptr, *nedge = nullptr;
+    const int32_t *ncptr = nullptr, *ncorner = nullptr;
     const int8_t *nsign = nullptr;
     const uint8_t *nfree = nullptr;
     const int32_t *ninst = nullptr; // instance of each node, or null
@@ -64,6 +65,10 @@ struct DevCounters {
     unsigned long long fixed_overflow;
     unsigned long long inj_step;      // step index of the next emission (random-stream counter)
     unsigned long long step;          // index n of the step in flight (time t^n = n dt of sources and probe)
+    unsigned long long diag_level1;   // 1 + time level of the last diagnostic evaluation (0: none, or
+                                      // the continuity reference was invalidated)
+    unsigned long long g0_set;        // the Gauss residual of the reference level is stored in g0
+    unsigned long long energy_count;  // energy records written to the ring so far
     unsigned long long pad;
 };
 
@@ -100,15 +105,34 @@ struct FieldSrc {
     long long probe_cap = 0, probe_start = 0;
 };
 
+// Diagnostics.  An evaluation at time level n (a step's start, or the
+// current state on demand) writes per-block partials; k_diag_final reduces
+// them in a fixed order into DevDiag, so no value depends on the order in
+// which blocks ran.  Maxima of non-negative doubles are kept as their bit
+// patterns (which order like the values).
+constexpr int kDiagSlots = 12;       // per node-pass block: sums Qtot, W_E, W_B, W_K, n_live; maxima drift,
+                                     // |res|, scale, dce, qmax; 2 unused
+constexpr int kEnergyRing = 4096;    // energy records kept on the device
+
+struct DevEnergy {
+    long long level;     // time level n
+    long long n_live;    // live particles at level n
+    double WE, WB, WK;   // 1/2 E^n [*eps]_a E^n, 1/2 B^{n+1/2} H B^{n-1/2}, 1/2 (K^{n-1/2} + K^{n+1/2})
+    double Qtot;         // total charge incl. wall charge [C/rad]
+};
+
 struct DevDiag {
-    unsigned long long gauss_drift_bits;  // max |res^n - res^0| (double bits, >= 0)
-    unsigned long long gauss_abs_bits;
-    unsigned long long gauss_scale_bits;
-    unsigned long long dce_max;           // max |2^23 dQ + Ddiv J| (fixed point)
-    double WE, WB, WK, Qtot;
-    unsigned long long dce_abs_bits;      // FP64 step: max |dQ + Ddiv J| (charge units)
-    unsigned long long qmax_bits;         // FP64 step: max |Q|
-    unsigned long long n_live;            // particles with a face (slots minus absorbed ones not yet compacted)
+    long long level;                      // time level of the latest evaluation (-1: none)
+    long long n_live;                     // live particles at that level
+    double gauss_abs, gauss_scale;        // max over free nodes |res^n|, max of the summed |D| at a node
+    double q_total, qmax;                 // total charge [C/rad]; FP64 step: max |Q| (charge units)
+    double WE_now;                        // 1/2 E^n [*eps]_a E^n at that level
+    long long dce_last;                   // max |2^23 dQ + Ddiv J| of that level (-1: no previous level)
+    unsigned long long gauss_drift_max_bits;   // running maxima over every evaluation since the reference
+    unsigned long long dce_max;                // mixed: fixed point; FP64 step: double bits of |dQ + Ddiv J|
+    unsigned long long dce_rel_max_bits;       // FP64 step: running max of |dQ + Ddiv J| / max|Q|
+    unsigned long long n_evals;                // evaluations since the reference
+    DevEnergy energy;                     // latest energy record (level -1: none)
 };
 
 struct DevState {
@@ -137,7 +161,14 @@ struct DevState {
     int32_t *blk = nullptr;     // scan block sums
     DevCounters *ctr = nullptr;
     DevDiag *diag = nullptr;
-    double *kin_part = nullptr;  // 1024 partial sums of the kinetic energy
+    // diagnostics: face-corner charge of the particles (3 per face, fixed
+    // point), per-block partials and the ring of energy records
+    unsigned long long *Qloc = nullptr;
+    double *part_face = nullptr;   // W_B per face-pass block
+    double *part_edge = nullptr;   // W_E per edge-pass block
+    double *part_node = nullptr;   // kDiagSlots per node-pass block
+    double *part_kin = nullptr;    // per particle block: W_K, live at the start, live at the end
+    DevEnergy *energy = nullptr;   // kEnergyRing records
 };
 
 // Emitter edge of the continuous injector (canonical edge order).
@@ -186,18 +217,28 @@ struct DevPlain {
 };
 
 // ---- launchers (kernels_mixed.hip) ----
-void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, hipStream_t st);
+void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
+                     hipStream_t st);
 // layer update after E^{n+1}: q, eprev and the corrections of D (E: FP32 or FP64 edge values)
 void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const DevLayers &lay, hipStream_t st);
 void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st);
 // gather, push and walk of every particle, with the charge-conserving current
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
-                      hipStream_t st);
+                      bool diag, hipStream_t st);
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
-void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st);
+void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, bool diag, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st);
-void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st);
+// Diagnostics of a diagnostic step (the face pass, the particle kernel and
+// the edge pass ran with diag on): the evaluation of its end level n + 1 and
+// the energy record of its start level n, launched after the field update.
+void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st);
+// Diagnostics of the current state (level = steps taken), on demand.
+void launch_diag_now(const DevMesh &m, DevState &s, hipStream_t st);
+// clears the face-corner charge accumulators (a fill kernel, graph-safe)
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
+// reduces the partials of an evaluation (shared by both precisions)
+void launch_diag_final(const DevMesh &m, DevState &s, bool in_step, bool plain, hipStream_t st);
 // Counting sort of the particle arrays by face: cell words in s.cell plus
 // n_fields payload arrays of `width` bytes (4 or 8) per particle, src[f] ->
 // dst[f].  counted: s.cnt already holds the face histogram.
@@ -210,15 +251,20 @@ void launch_sort_payload(const DevMesh &m, DevState &s, bool counted, int width,
 
 // ---- launchers (kernels_plain.hip) ----
 void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, const FieldSrc &fs,
-                           const DevLayers &lay, hipStream_t st);
+                           const DevLayers &lay, bool diag, hipStream_t st);
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
-                            bool count, bool vay, hipStream_t st);
-void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
+                            bool count, bool vay, bool diag, hipStream_t st);
+// nodal charge Q^n of the particles at their current positions plus the wall charge
+void launch_charge_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st);
+void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool diag,
+                            hipStream_t st);
 void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st);
 void launch_sort_plain(const DevMesh &m, DevState &s, DevPlain &p, bool counted, hipStream_t st);
 void launch_inject_plain(const DevMesh &m, DevState &s, const DevPlain &p, const EmitEdge *ee, const InjParams &ip,
                          hipStream_t st);
-void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool have_prev_q,
-                       bool first, hipStream_t st);
+// FP64 step: node pass and reduction of an evaluation whose charge (launch_charge_plain)
+// was computed at the level evaluated
+void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool in_step,
+                       hipStream_t st);
 
 }  // namespace axp

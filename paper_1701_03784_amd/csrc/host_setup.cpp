@@ -56,7 +56,14 @@ void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tr
         m.r[i] = zr[2 * i + 1];
         if (!(m.r[i] >= 0.0) || !std::isfinite(m.z[i])) throw SetupError{AXP_E_MESH, "node with rho < 0 or non-finite"};
     }
-    // locality order of faces: Hilbert index of the centroid
+    // Locality order of faces.  The particle kernel accumulates a block's
+    // currents and charges in an LDS window of consecutive faces (from 192
+    // before the block's first face to 320 after it); a path that ends in a
+    // face outside it costs a global atomic.  Strips: columns about one edge
+    // length wide across the long axis, each ordered along the short axis,
+    // so a face's neighbours lie within about one column's face count of it.
+    // Used while a column holds few enough faces for the window; wider
+    // meshes take the Hilbert index of the centroid.
     double zmin = 1e300, zmax = -1e300, rmin = 1e300, rmax = -1e300;
     for (int i = 0; i < n_nodes; ++i) {
         zmin = std::min(zmin, m.z[i]); zmax = std::max(zmax, m.z[i]);
@@ -64,6 +71,17 @@ void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tr
     }
     double ext = std::max(zmax - zmin, rmax - rmin);
     if (!(ext > 0)) throw SetupError{AXP_E_MESH, "degenerate node set"};
+    double area_sum = 0.0;
+    for (int t = 0; t < n_tris; ++t) {
+        const int32_t *v = tri + 3 * t;
+        area_sum += 0.5 * std::fabs((m.z[v[1]] - m.z[v[0]]) * (m.r[v[2]] - m.r[v[0]]) -
+                                    (m.z[v[2]] - m.z[v[0]]) * (m.r[v[1]] - m.r[v[0]]));
+    }
+    const double hcol = std::sqrt(2.0 * area_sum / std::max(1, n_tris));   // about one edge length
+    const bool z_long = (zmax - zmin) >= (rmax - rmin);
+    const double short_ext = z_long ? rmax - rmin : zmax - zmin;
+    const bool strips = hcol > 0.0 && 2.0 * short_ext / hcol <= double(kStripMaxFaces);
+    m.strip_order = strips;
     std::vector<std::pair<uint64_t, int32_t>> order(n_tris);
     for (int t = 0; t < n_tris; ++t) {
         const int32_t *v = tri + 3 * t;
@@ -74,7 +92,14 @@ void build_topology(HostMesh &m, int32_t n_nodes, const double *zr, int32_t n_tr
         double cz = (m.z[v[0]] + m.z[v[1]] + m.z[v[2]]) / 3.0, cr = (m.r[v[0]] + m.r[v[1]] + m.r[v[2]]) / 3.0;
         uint32_t qx = uint32_t(std::min(65535.0, std::floor((cz - zmin) / ext * 65536.0)));
         uint32_t qy = uint32_t(std::min(65535.0, std::floor((cr - rmin) / ext * 65536.0)));
-        order[t] = {hilbert_index(qx, qy, 16), t};
+        if (strips) {
+            const double cl = z_long ? cz - zmin : cr - rmin, cs = z_long ? cr - rmin : cz - zmin;
+            const uint64_t col = uint64_t(cl / hcol);
+            const uint64_t pos = uint64_t(std::min(4294967295.0, std::floor(cs / ext * 4294967296.0)));
+            order[t] = {(col << 32) | pos, t};
+        } else {
+            order[t] = {hilbert_index(qx, qy, 16), t};
+        }
     }
     std::sort(order.begin(), order.end());
     m.tri_user.resize(n_tris);

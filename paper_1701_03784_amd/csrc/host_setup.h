@@ -35,11 +35,17 @@ struct SetupError {
 // opposite its side k; side k runs from local node k+1 to k+2 (counter-
 // clockwise), so its incidence sign is +1 when that direction agrees with
 // the edge orientation tail -> head (tail < head, global node ids).
+// Strip ordering of faces is used while a strip holds at most this many
+// faces (about 2 x short extent / edge length): the neighbours of a face
+// then stay inside the particle kernel's accumulation window.
+constexpr int kStripMaxFaces = 224;
+
 struct HostMesh {
     int32_t n0 = 0, n1 = 0, n2 = 0;
     std::vector<double> z, r;                      // node coordinates, user order
     std::vector<int32_t> tri_user;                 // internal face -> user face
     std::vector<int32_t> tri_int;                  // user face -> internal face
+    bool strip_order = false;                      // faces in strips (else along a Hilbert curve)
     std::vector<std::array<int32_t, 3>> tv;        // internal face -> nodes (CCW)
     std::vector<std::array<int32_t, 2>> ev;        // internal edge -> (tail, head)
     std::vector<int32_t> edge_can;                 // internal edge -> canonical edge

@@ -21,7 +21,10 @@
 // node's Lambda, so the continuity equation holds bit-exactly.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
+#include "diag.h"
 #include "inject.h"
 
 namespace axp {
@@ -46,9 +49,24 @@ __device__ __forceinline__ double source_current(const FieldSrc &fs, int k, unsi
     return fs.amp[k] * exp(-a * a) * cos(fs.w[k] * tt);
 }
 
-__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m.n2) return;
+// Sum of v over the 256 threads of a block in a fixed order (deterministic);
+// every thread of the block must call it.
+__device__ __forceinline__ double block_sum256(double v) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// One face: returns 1/2 B^{n+1/2} H B^{n-1/2}, its share of the magnetic energy of level n.
+__device__ __forceinline__ double tri_pass_face(const DevMesh &m, const DevState &s, const FieldSrc &fs,
+                                                const DevLayers &lay, int t, bool diag) {
     const int4 e = m.tedge[t];
     const int inst = m.tinst ? m.tinst[t] : 0;
     const double dt = m.inst[inst].dt;
@@ -98,6 +116,22 @@ __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSr
     s.Jloc[3 * t] = 0ull;
     s.Jloc[3 * t + 1] = 0ull;
     s.Jloc[3 * t + 2] = 0ull;
+    if (!diag) return 0.0;
+    s.Qloc[3 * t] = 0ull;                       // the particle kernel adds the charge of level n
+    s.Qloc[3 * t + 1] = 0ull;
+    s.Qloc[3 * t + 2] = 0ull;
+    return 0.5 * (m.Hdt[t] / dt) * bn * bo;
+}
+
+// Faraday update of every face (and its gather tile).  diag: the step
+// evaluates the diagnostics of its start level; the face pass then clears
+// the corner charges and leaves one partial of W_B per block.
+__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay, int diag) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const double wb = t < m.n2 ? tri_pass_face(m, s, fs, lay, t, diag != 0) : 0.0;
+    if (!diag) return;                          // uniform across the grid
+    const double tot = block_sum256(wb);
+    if (threadIdx.x == 0) s.part_face[blockIdx.x] = tot;
 }
 
 // -------------------------------------------------------------- particles
@@ -144,7 +178,7 @@ __device__ __forceinline__ long long wave_sum64(long long v) {
 // a sort.  With the walk queue that is 24.6 KB of LDS per block, which keeps
 // the 6 waves per SIMD the registers allow.
 constexpr int kWin = 512;
-constexpr int kWinLead = 128;    // window starts this many faces before the block's first face
+constexpr int kWinLead = 192;    // window starts this many faces before the block's first face
 
 struct Win {
     unsigned long long *jl;      // LDS, 3 * kWin
@@ -206,6 +240,68 @@ __device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J
     if (run_tail(t) && t >= 0) win_add_j(w, J, t, a0, a1, a2);
 }
 
+// Charge of the particles' end positions in a diagnostic step (eq. charge):
+// per face of the window its three corner sums kq Lambda_k (units 2^-23 of
+// the charge unit), in LDS words of type QA.  Single case (charge multiple 1):
+// 32-bit words, every added value below 2^32 and non-negative, a wrap-around
+// carried exactly into the 64-bit global accumulator; otherwise 64-bit words.
+template <class QA>
+struct QWinL {
+    QA *ql;                      // LDS, 3 * kWin
+    int base;
+};
+
+__device__ __forceinline__ void qadd1(unsigned *l, unsigned long long *g, long long q) {
+    if (!q) return;
+    const unsigned v = (unsigned)q;
+    const unsigned old = atomicAdd(l, v);
+    if ((unsigned)(old + v) < old) atomicAdd(g, 1ull << 32);
+}
+
+__device__ __forceinline__ void qadd1(unsigned long long *l, unsigned long long *g, long long q) {
+    if (q) atomicAdd(l, (unsigned long long)q);
+}
+
+template <class QA>
+__device__ __forceinline__ void qwin_add3(const QWinL<QA> &w, unsigned long long *Qloc, int t, long long q0,
+                                          long long q1, long long q2) {
+    const int rel = t - w.base;
+    if (rel >= 0 && rel < kWin) {
+        qadd1(&w.ql[3 * rel], &Qloc[3 * t], q0);
+        qadd1(&w.ql[3 * rel + 1], &Qloc[3 * t + 1], q1);
+        qadd1(&w.ql[3 * rel + 2], &Qloc[3 * t + 2], q2);
+    } else {
+        if (q0) atomicAdd(&Qloc[3 * t], (unsigned long long)q0);
+        if (q1) atomicAdd(&Qloc[3 * t + 1], (unsigned long long)q1);
+        if (q2) atomicAdd(&Qloc[3 * t + 2], (unsigned long long)q2);
+    }
+}
+
+// wave_deposit of a diagnostic step: the stayers' currents and end-position
+// charges (the same faces) share one segmented scan
+template <class QA>
+__device__ __forceinline__ void wave_deposit_q(const Win &w, unsigned long long *J, const QWinL<QA> &qw,
+                                               unsigned long long *Qloc, int t, long long a0, long long a1,
+                                               long long a2, QA q0, QA q1, QA q2) {
+    const int lane = threadIdx.x & 63;
+    const int run = lane_run(t);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ro = __shfl_up(run, off, 64);
+        const long long b0 = __shfl_up(a0, off, 64);
+        const long long b1 = __shfl_up(a1, off, 64);
+        const long long b2 = __shfl_up(a2, off, 64);
+        const QA c0 = __shfl_up(q0, off, 64);
+        const QA c1 = __shfl_up(q1, off, 64);
+        const QA c2 = __shfl_up(q2, off, 64);
+        if (lane >= off && ro == run) { a0 += b0; a1 += b1; a2 += b2; q0 += c0; q1 += c1; q2 += c2; }
+    }
+    if (run_tail(t) && t >= 0) {
+        win_add_j(w, J, t, a0, a1, a2);
+        qwin_add3(qw, Qloc, t, (long long)q0, (long long)q1, (long long)q2);
+    }
+}
+
 // Same for a count per face (histogram of the counting sort).
 __device__ __forceinline__ void wave_count(const Win &w, int *cnt, int t, int c) {
     const int lane = threadIdx.x & 63;
@@ -247,13 +343,14 @@ struct Particle {
 struct PushConst {
     float qe, qb, cdt, bz;
     int kq;
+    float mw;        // m w c^2 / (2 pi) of the species [J/rad] (kinetic-energy diagnostic; 1 in the single case)
 };
 
 template <bool SINGLE>
 __device__ __forceinline__ PushConst push_const(const DevMesh &m, const PushConst &k0, int T, int sp) {
     if (SINGLE) return k0;
     const InstConst &ic = m.inst[m.tinst ? m.tinst[T] : 0];
-    return PushConst{ic.qe[sp], ic.qb[sp], ic.cdt, ic.bz, ic.kq[sp]};
+    return PushConst{ic.qe[sp], ic.qb[sp], ic.cdt, ic.bz, ic.kq[sp], (float)ic.mw[sp]};
 }
 
 // Gather, momentum push (relativistic Boris, or Vay's pusher when VAY) and
@@ -355,9 +452,9 @@ struct Mover {
 // edge (its charge kept on the wall nodes), stops on the axis, or hits the
 // piece cap.  mv holds the start (face, coordinates, remaining
 // displacement) and receives the final cell word and coordinates.
-template <bool SINGLE>
+template <bool SINGLE, bool DIAG, class QA>
 __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const PushConst &k0,
-                                           int max_walk, Mover &mv) {
+                                           int max_walk, const QWinL<QA> &qw, int *nabs, Mover &mv) {
     int t = mv.cell & kCellMask;
     const int sp = (mv.cell >> kCellBits) & 15;
     const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
@@ -416,6 +513,7 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
                     atomicAdd((unsigned long long *)&s.Qres[na], (unsigned long long)((long long)xa * kq));
                     atomicAdd((unsigned long long *)&s.Qres[nbn], (unsigned long long)((long long)xb * kq));
                     atomicAdd(&s.ctr->n_absorbed, 1ull);
+                    if (DIAG) atomicAdd(nabs, 1);
                     newcell = -1;
                 }
             } else {
@@ -440,15 +538,151 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
     mv.cell = newcell;
     mv.L0 = L0;
     mv.L1 = L1;
+    if (DIAG && newcell >= 0)        // the end position's charge (level n+1)
+        qwin_add3(qw, s.Qloc, t, (long long)kq * L0, (long long)kq * L1, (long long)kq * (kS - L0 - L1));
 }
 
-template <bool SINGLE, bool VAY>
-__global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int max_walk, int do_count, PushConst k0) {
+// Inclusive sum of N values over runs of consecutive lanes holding the same
+// key t (segmented scan); the run's last lane then holds the run's sums.  All
+// lanes of the wave must call it together.
+template <class V, int N>
+__device__ __forceinline__ void wave_run_sums(int t, V (&a)[N]) {
+    const int lane = threadIdx.x & 63;
+    const int run = lane_run(t);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ro = __shfl_up(run, off, 64);
+        V b[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) b[k] = __shfl_up(a[k], off, 64);
+        if (lane >= off && ro == run)
+#pragma unroll
+            for (int k = 0; k < N; ++k) a[k] += b[k];
+    }
+}
+
+__device__ __forceinline__ void corner_add(unsigned long long *Qloc, int t, long long q0, long long q1, long long q2) {
+    if (q0) atomicAdd(&Qloc[3 * t], (unsigned long long)q0);
+    if (q1) atomicAdd(&Qloc[3 * t + 1], (unsigned long long)q1);
+    if (q2) atomicAdd(&Qloc[3 * t + 2], (unsigned long long)q2);
+}
+
+// Charge window of a block: the corner charges of `len` consecutive faces
+// from base on accumulate in LDS; other faces go to global memory.
+struct QWin {
+    unsigned long long *ql;      // LDS, 3 * len
+    int base, len;
+};
+
+__device__ __forceinline__ void qwin_add(const QWin &w, unsigned long long *Qloc, int t, long long q0, long long q1,
+                                         long long q2) {
+    const int rel = t - w.base;
+    if (rel >= 0 && rel < w.len) {
+        if (q0) atomicAdd(&w.ql[3 * rel], (unsigned long long)q0);
+        if (q1) atomicAdd(&w.ql[3 * rel + 1], (unsigned long long)q1);
+        if (q2) atomicAdd(&w.ql[3 * rel + 2], (unsigned long long)q2);
+    } else {
+        corner_add(Qloc, t, q0, q1, q2);
+    }
+}
+
+// after a barrier: add the charge window to the corner accumulators
+__device__ __forceinline__ void qwin_flush(const QWin &w, unsigned long long *Qloc, int n2) {
+    for (int i = threadIdx.x; i < 3 * w.len; i += blockDim.x) {
+        const unsigned long long v = w.ql[i];
+        const long long gi = 3ll * w.base + i;
+        if (v != 0ull && gi >= 0 && gi < 3ll * n2) atomicAdd(&Qloc[gi], v);
+    }
+}
+
+// Nodal charge of the particles at their current positions, eq. (charge):
+// a particle in face T adds kq Lambda_k (units 2^-23 of the charge unit) to
+// corner k of T.  The thread folds its particles face by face, the wave sums
+// runs of lanes holding the same face, and each run's last lane adds the
+// three sums to the block's charge window (the particles are sorted by face,
+// so a wave holds a few runs and a block a few dozen faces).  In the single
+// case (charge multiple 1) a wave's sums stay below 2^32 (256 particles of at
+// most 2^23 each) and the scan runs on 32-bit words.
+template <bool SINGLE>
+__device__ __forceinline__ void charge_deposit(const DevMesh &m, const QWin &w, unsigned long long *Qloc,
+                                               const Particle (&P)[kPPT]) {
+    using Acc = typename std::conditional<SINGLE, unsigned, long long>::type;
+    int qt = -1;
+    Acc q[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j) {
+        if (P[j].cell < 0) continue;
+        const int T = P[j].cell & kCellMask;
+        if (T != qt) {
+            if (qt >= 0) qwin_add(w, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
+            qt = T;
+            q[0] = q[1] = q[2] = 0;
+        }
+        const Acc L0 = (Acc)P[j].L0, L1 = (Acc)P[j].L1, L2 = (Acc)kS - L0 - L1;
+        if (SINGLE) {
+            q[0] += L0; q[1] += L1; q[2] += L2;
+        } else {
+            const InstConst &ic = m.inst[m.tinst ? m.tinst[T] : 0];
+            const Acc kq = (Acc)ic.kq[(P[j].cell >> kCellBits) & 15];
+            q[0] += kq * L0; q[1] += kq * L1; q[2] += kq * L2;
+        }
+    }
+    wave_run_sums<Acc, 3>(qt, q);
+    if (run_tail(qt) && qt >= 0) qwin_add(w, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
+}
+
+// gamma - 1 of u / c without cancellation for slow particles
+__device__ __forceinline__ float gamma_m1(float ur, float up, float uz) {
+    const float u2 = ur * ur + up * up + uz * uz;
+    const float w = 1.0f + u2;
+    return u2 * __builtin_amdgcn_rcpf(w * __builtin_amdgcn_rsqf(w) + 1.0f);   // u^2 / (gamma + 1)
+}
+
+// Per-wave sums in a fixed butterfly (deterministic); every lane gets the total.
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// (gamma - 1) m w c^2 / (2 pi) summed over the particles of mask in P, in
+// units of the species' mw when SINGLE (FP64 sums of FP32 terms: the storage
+// order within a face changes only their rounding)
+template <bool SINGLE>
+__device__ __forceinline__ double kin_sum(const DevMesh &m, const PushConst &k0, const Particle (&P)[kPPT],
+                                          unsigned mask) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j)
+        if (mask >> j & 1u) {
+            const int T = P[j].cell & kCellMask;
+            const float mw = SINGLE ? 1.0f : push_const<SINGLE>(m, k0, T, (P[j].cell >> kCellBits) & 15).mw;
+            v += (double)(mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
+        }
+    return v;
+}
+
+template <bool SINGLE, bool VAY, bool DIAG>
+__global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
+                                                               PushConst k0) {
     __shared__ int s_nmv;
     __shared__ int s_base;
     __shared__ unsigned long long s_jl[3 * kWin];
     __shared__ int s_cl[kWin];
     __shared__ Mover s_mv[kQCap];
+    // diagnostic steps: the end positions' charge window, per wave the
+    // kinetic energy and live count, the block's absorbed count
+    using QA = typename std::conditional<SINGLE, unsigned, unsigned long long>::type;
+    __shared__ QA s_ql[DIAG ? 3 * kWin : 1];
+    __shared__ double s_wk[kWG / 64];
+    __shared__ int s_nl[kWG / 64];
+    __shared__ int s_nabs;
     const int chunk = xcd_block(blockIdx.x, gridDim.x);
     const long long n = (long long)s.ctr->n_slots;
     const long long p0 = ((long long)chunk * kWG + threadIdx.x) * kPPT;
@@ -481,12 +715,25 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
     // thread 0 holds the block's first particle: the window starts at its face
     if (threadIdx.x == 0) {
         s_nmv = 0;
+        s_nabs = 0;
         s_base = (P[0].cell >= 0 ? (P[0].cell & kCellMask) : 0) - kWinLead;
     }
     Win w{s_jl, s_cl, 0};
     win_zero(w);
+    unsigned live0 = 0;              // particles live at the start (diagnostic steps)
+    if (DIAG) {
+        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
+        // level n: live count and the kinetic energy of u^{n-1/2}
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) live0 |= (P[j].cell >= 0 ? 1u : 0u) << j;
+        const double v = wave_sum_d(kin_sum<SINGLE>(m, k0, P, live0));
+        const int nl = wave_sum_i(__popc(live0));
+        if ((threadIdx.x & 63) == 0) { s_wk[threadIdx.x >> 6] = v; s_nl[threadIdx.x >> 6] = nl; }
+    }
     __syncthreads();
     w.base = s_base;
+    const QWinL<QA> qw{s_ql, s_base};
+    QA q0 = 0, q1 = 0, q2 = 0;       // end-position charge of the stayers of face acc_t
     // ---- phase 1: push
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
@@ -522,10 +769,18 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
             long long c0, c1, c2;
             piece_current(L0, L1, L2, e0, e1, e2, SINGLE ? 1 : ic.kq, c0, c1, c2);
             if (T != acc_t) {
-                if (acc_t >= 0) win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
+                if (acc_t >= 0) {
+                    win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
+                    if (DIAG) qwin_add3(qw, s.Qloc, acc_t, (long long)q0, (long long)q1, (long long)q2);
+                }
                 acc_t = T; a0 = a1 = a2 = 0;
+                q0 = q1 = q2 = 0;
             }
             a0 += c0; a1 += c1; a2 += c2;
+            if (DIAG) {
+                const QA kq = SINGLE ? (QA)1 : (QA)(long long)ic.kq;
+                q0 += kq * (QA)e0; q1 += kq * (QA)e1; q2 += kq * (QA)e2;
+            }
             P[j].L0 = (uint32_t)e0;
             P[j].L1 = (uint32_t)e1;
             if (do_count) {
@@ -541,7 +796,14 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
             mfr[j] = fr;
         }
     }
-    wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
+    if (DIAG) {
+        wave_deposit_q<QA>(w, s.Jloc, qw, s.Qloc, acc_t, a0, a1, a2, q0, q1, q2);
+        // kinetic energy of u^{n+1/2} of every particle pushed (absorbed ones included)
+        const double v = wave_sum_d(kin_sum<SINGLE>(m, k0, P, live0));
+        if ((threadIdx.x & 63) == 0) s_wk[threadIdx.x >> 6] += v;
+    } else {
+        wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
+    }
     if (do_count) wave_count(w, s.cnt, ct, cc);
     // queue the movers in LDS (one LDS atomic per wave and particle slot)
     const int lane = threadIdx.x & 63;
@@ -571,14 +833,14 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
         for (int j = 0; j < kPPT; ++j)
             if (slot[j] == -2) {
                 Mover mv{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
-                walk_mover<SINGLE>(m, s, w, k0, max_walk, mv);
+                walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, qw, &s_nabs, mv);
                 P[j].cell = mv.cell; P[j].L0 = (uint32_t)mv.L0; P[j].L1 = (uint32_t)mv.L1;
                 if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
             }
     }
     for (int i = threadIdx.x; i < nmv; i += kWG) {
         Mover mv = s_mv[i];
-        walk_mover<SINGLE>(m, s, w, k0, max_walk, mv);
+        walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, qw, &s_nabs, mv);
         s_mv[i] = mv;
         if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
     }
@@ -592,6 +854,23 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
             P[j].L1 = (uint32_t)s_mv[slot[j]].L1;
         }
     win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
+    if (DIAG) {                      // the charge window, and the block's partials of level n and n+1
+        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) {
+            const unsigned long long v = (unsigned long long)s_ql[i];
+            const long long gi = 3ll * w.base + i;
+            if (v != 0ull && gi >= 0 && gi < 3ll * m.n2) atomicAdd(&s.Qloc[gi], v);
+        }
+        if (threadIdx.x == 0) {
+            double v = 0.0;
+            int nl = 0;
+#pragma unroll
+            for (int k = 0; k < kWG / 64; ++k) { v += s_wk[k]; nl += s_nl[k]; }
+            v *= 0.5;                // W_K = 1/2 (K^{n-1/2} + K^{n+1/2})
+            s.part_kin[3 * chunk] = SINGLE ? v * m.inst[0].mw[0] : v;
+            s.part_kin[3 * chunk + 1] = (double)nl;
+            s.part_kin[3 * chunk + 2] = (double)(nl - s_nabs);
+        }
+    }
     if (full) {
         *reinterpret_cast<int4 *>(cell + p0) = make_int4(P[0].cell, P[1].cell, P[2].cell, P[3].cell);
         *reinterpret_cast<uint4 *>(L0a + p0) = make_uint4(P[0].L0, P[1].L0, P[2].L0, P[3].L0);
@@ -614,10 +893,9 @@ __global__ __launch_bounds__(kWG) void k_particles(DevMesh m, DevState s, int ma
 // ------------------------------------------------------------------ edges
 // etri.z packs: bits 0-1 side in left face, 2-3 side in right face,
 // bit 4 left sign negative, bit 5 right sign negative, bit 6 free edge.
-__global__ __launch_bounds__(256) void k_edge_pass(DevMesh m, DevState s, int keep_j) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) s.ctr->step = s.ctr->step + 1ull;   // the face pass of this step has read it
-    if (e >= m.n1) return;
+// diag: the step evaluates the energies of its start level n; the edge pass
+// reads D^n and E^n before the update and leaves 1/2 E^n D^n per block.
+__device__ __forceinline__ double edge_update(const DevMesh &m, const DevState &s, int e, int keep_j, bool diag) {
     const int4 et = m.etri[e];
     const int inst = et.w;
     const double js = m.inst[inst].jscale;
@@ -634,10 +912,21 @@ __global__ __launch_bounds__(256) void k_edge_pass(DevMesh m, DevState s, int ke
     }
     if (jfx > (1ll << 62) || jfx < -(1ll << 62)) atomicAdd(&s.ctr->fixed_overflow, 1ull);
     if (keep_j) s.Jfx[e] = jfx;        // every edge: conductor edges carry current too (continuity check)
-    if (!(et.z & 64)) return;          // conductor edge: tangential E stays 0
-    const double d = s.D[e] + acc;
+    if (!(et.z & 64)) return 0.0;      // conductor edge: tangential E stays 0
+    const double dn = s.D[e];
+    const double d = dn + acc;
     s.D[e] = d;
     s.D32[e] = (float)d;
+    return diag ? 0.5 * (double)s.E[e] * dn : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_edge_pass(DevMesh m, DevState s, int keep_j, int diag) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) s.ctr->step = s.ctr->step + 1ull;   // the face pass of this step has read it
+    const double we = e < m.n1 ? edge_update(m, s, e, keep_j, diag != 0) : 0.0;
+    if (!diag) return;                              // uniform across the grid
+    const double tot = block_sum256(we);
+    if (threadIdx.x == 0) s.part_edge[blockIdx.x] = tot;
 }
 
 // ------------------------------------------------------------------- SpMV
@@ -869,137 +1158,176 @@ __global__ __launch_bounds__(256) void k_offset_cells(int32_t *cell, int64_t n, 
 }
 
 // ------------------------------------------------------------ diagnostics
-__global__ __launch_bounds__(256) void k_charge_init(DevMesh m, DevState s) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < m.n0) s.Qfx[v] = s.Qres[v];
-}
+// An evaluation at time level n.  In a diagnostic step the face pass and the
+// particle kernel have left the corner charges of level n, the W_B and W_K
+// partials and the live counts; on demand k_charge_now leaves the charges and
+// counts.  k_node_diag then runs while D^n and J^{n-1/2} (the last step's
+// edge current) are still in place, and k_diag_final reduces the partials.
 
-__global__ __launch_bounds__(256) void k_charge(DevMesh m, DevState s) {
-    // each thread sums 8 consecutive particles, one atomic per run of equal faces
+// on-demand charge of the current positions (blocks of kChunk particles, as
+// k_particles, with the same charge window) and the live count
+template <bool SINGLE>
+__global__ __launch_bounds__(kWG) void k_charge_now(DevMesh m, DevState s) {
+    __shared__ unsigned long long s_q[3 * kWin];
+    __shared__ int s_base;
+    __shared__ int s_nl[kWG / 64];
     const long long n = (long long)s.ctr->n_slots;
-    const long long p0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 8;
-    int run_t = -1;
-    long long q0 = 0, q1 = 0, q2 = 0, nl = 0;
-    for (int j = 0; j < 8; ++j) {
-        const long long p = p0 + j;
-        if (p >= n) break;
-        const int c = s.cell[s.cur][p];
-        if (c < 0) continue;
-        ++nl;
-        const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
-        const int inst = m.tinst ? m.tinst[T] : 0;
-        const long long kq = m.inst[inst].kq[sp];
-        const long long L0 = s.L0[s.cur][p], L1 = s.L1[s.cur][p], L2 = kS - L0 - L1;
-        if (T != run_t) {
-            if (run_t >= 0) {
-                const int4 tn = m.tnodes[run_t];
-                atomicAdd((unsigned long long *)&s.Qfx[tn.x], (unsigned long long)q0);
-                atomicAdd((unsigned long long *)&s.Qfx[tn.y], (unsigned long long)q1);
-                atomicAdd((unsigned long long *)&s.Qfx[tn.z], (unsigned long long)q2);
-            }
-            run_t = T; q0 = q1 = q2 = 0;
-        }
-        q0 += kq * L0; q1 += kq * L1; q2 += kq * L2;
+    const int chunk = blockIdx.x;
+    if ((long long)chunk * kChunk >= n) return;
+    const long long p0 = ((long long)chunk * kWG + threadIdx.x) * kPPT;
+    const int c = s.cur;
+    Particle P[kPPT];
+    int live = 0;
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j) {
+        const long long q = p0 + j;
+        P[j] = {-1, 0u, 0u, 0.f, 0.f, 0.f};
+        if (q < n) { P[j].cell = s.cell[c][q]; P[j].L0 = s.L0[c][q]; P[j].L1 = s.L1[c][q]; }
+        live += P[j].cell >= 0;
     }
-    if (run_t >= 0) {
-        const int4 tn = m.tnodes[run_t];
-        atomicAdd((unsigned long long *)&s.Qfx[tn.x], (unsigned long long)q0);
-        atomicAdd((unsigned long long *)&s.Qfx[tn.y], (unsigned long long)q1);
-        atomicAdd((unsigned long long *)&s.Qfx[tn.z], (unsigned long long)q2);
-    }
-    nl = wave_sum64(nl);
-    if ((threadIdx.x & 63) == 0 && nl) atomicAdd(&s.diag->n_live, (unsigned long long)nl);
-}
-
-__device__ __forceinline__ void atomic_max_pos(unsigned long long *a, double v) {
-    atomicMax(a, (unsigned long long)__double_as_longlong(v));
-}
-
-// Gauss residual res_v = (Ddiv D)_v - Q_v, its drift from res^0, and the
-// continuity residual 2^23 (Q^{n+1} - Q^n) + (Ddiv J)_v in fixed point.
-__global__ __launch_bounds__(256) void k_node_diag(DevMesh m, DevState s, int have_prev, int first) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= m.n0) return;
-    const int inst = m.ninst ? m.ninst[v] : 0;
-    double div = 0.0, mag = 0.0;
-    long long divj = 0;
-    for (int k = m.nptr[v]; k < m.nptr[v + 1]; ++k) {
-        const int e = m.nedge[k];
-        const double d = s.D[e];
-        div += m.nsign[k] > 0 ? d : -d;
-        mag += fabs(d);
-        if (have_prev) divj += m.nsign[k] > 0 ? s.Jfx[e] : -s.Jfx[e];
-    }
-    const double q = (double)s.Qfx[v] * m.inst[inst].qscale;
-    const double g = div - q;
-    if (have_prev) {
-        const long long dce = (long long)kS * (s.Qfx[v] - s.Qprev[v]) + divj;
-        atomicMax(&s.diag->dce_max, (unsigned long long)(dce < 0 ? -dce : dce));
-    }
-    s.Qprev[v] = s.Qfx[v];
-    if (m.nfree[v]) {
-        if (first) s.g0[v] = g;
-        atomic_max_pos(&s.diag->gauss_drift_bits, fabs(g - s.g0[v]));
-        atomic_max_pos(&s.diag->gauss_abs_bits, fabs(g));
-        atomic_max_pos(&s.diag->gauss_scale_bits, mag);
-    }
-    atomicAdd(&s.diag->Qtot, q);
-}
-
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double sh[256];
-    sh[threadIdx.x] = v;
+    for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_q[i] = 0ull;
+    if (threadIdx.x == 0) s_base = (P[0].cell >= 0 ? (P[0].cell & kCellMask) : 0) - kWinLead;
+    const int nl = wave_sum_i(live);
+    if ((threadIdx.x & 63) == 0) s_nl[threadIdx.x >> 6] = nl;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    const QWin qw{s_q, s_base, kWin};
+    charge_deposit<SINGLE>(m, qw, s.Qloc, P);
     __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(256) void k_energy_fields(DevMesh m, DevState s) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double we = 0.0, wb = 0.0;
-    if (i < m.n1) {
-        double ae = 0.0;
-        for (int64_t k = m.a_ptr[i]; k < m.a_ptr[i + 1]; ++k) ae += m.a_val[k] * (double)s.E[m.a_col[k]];
-        we = 0.5 * (double)s.E[i] * ae;
-    }
-    if (i < m.n2) {
-        const int inst = m.tinst ? m.tinst[i] : 0;
-        wb = 0.5 * (m.Hdt[i] / m.inst[inst].dt) * s.B[i] * s.Bprev[i];
-    }
-    we = block_sum(we);
-    wb = block_sum(wb);
+    qwin_flush(qw, s.Qloc, m.n2);
     if (threadIdx.x == 0) {
-        atomicAdd(&s.diag->WE, we);
-        atomicAdd(&s.diag->WB, wb);
+        int t = 0;
+#pragma unroll
+        for (int k = 0; k < kWG / 64; ++k) t += s_nl[k];
+        s.part_kin[3 * chunk + 2] = (double)t;
     }
 }
 
-__global__ __launch_bounds__(256) void k_energy_kin(DevMesh m, DevState s, double *part) {
-    const long long n = (long long)s.ctr->n_slots;
-    double wk = 0.0;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
-        const int c = s.cell[s.cur][p];
-        if (c < 0) continue;
-        const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
-        const int inst = m.tinst ? m.tinst[T] : 0;
-        const double a = s.ur[s.cur][p], b = s.up[s.cur][p], z = s.uz[s.cur][p];
-        const double u2 = a * a + b * b + z * z;
-        wk += m.inst[inst].mw[sp] * (u2 / (sqrt(1.0 + u2) + 1.0));   // (gamma - 1) without cancellation
+// Node pass of an evaluation at level n = ctr->step (in a diagnostic step,
+// after its field update: n is the step's end level): Q^n from the wall
+// charge and the corner charges, the Gauss residual res = Ddiv D^n - Q^n
+// (Sec. 3.5.2) and its drift from the reference level, the continuity
+// residual 2^23 (Q^n - Q^{n-1}) + Ddiv J^{n-1/2} (Sec. 3.5.1) when level n-1
+// was evaluated, the total charge; per edge 1/2 E^n D^n (W_E with the
+// scheme's [*eps]_a).  Each block also folds its slice of the step's
+// particle, face and edge partials (in_step).
+__global__ __launch_bounds__(256) void k_node_diag(DevMesh m, DevState s, int in_step, int nb_face, int nb_edge) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long n = s.ctr->step;
+    const bool have_prev = s.ctr->diag_level1 == n && n > 0;
+    const bool first = s.ctr->g0_set == 0;
+    DiagVals v{};
+    if (i < m.n0) {
+        const int inst = m.ninst ? m.ninst[i] : 0;
+        long long Q = s.Qres[i];
+        for (int k = m.ncptr[i]; k < m.ncptr[i + 1]; ++k) Q += (long long)s.Qloc[m.ncorner[k]];
+        double div = 0.0, mag = 0.0;
+        long long divj = 0;
+        for (int k = m.nptr[i]; k < m.nptr[i + 1]; ++k) {
+            const int e = m.nedge[k];
+            const double d = s.D[e];
+            div += m.nsign[k] > 0 ? d : -d;
+            mag += fabs(d);
+            divj += m.nsign[k] > 0 ? s.Jfx[e] : -s.Jfx[e];
+        }
+        const double q = (double)Q * m.inst[inst].qscale;
+        if (have_prev) {
+            const long long r = (long long)kS * (Q - s.Qprev[i]) + divj;
+            v.mx[3] = (unsigned long long)(r < 0 ? -r : r);
+        }
+        s.Qprev[i] = Q;
+        s.Qfx[i] = Q;
+        if (m.nfree[i]) {
+            const double g = div - q;
+            if (first) s.g0[i] = g;
+            v.mx[0] = dbits(fabs(g - s.g0[i]));
+            v.mx[1] = dbits(fabs(g));
+            v.mx[2] = dbits(mag);
+        }
+        v.sum[0] = q;
     }
-    wk = block_sum(wk);
-    if (threadIdx.x == 0) part[blockIdx.x] = wk;
+    if (i < m.n1) v.sum[1] = 0.5 * (double)s.E[i] * s.D[i];
+    fold_slices(s, v, in_step, nb_face, nb_edge);
+    const DiagVals r = block_reduce_diag(v);
+    if (threadIdx.x == 0) store_partials(s.part_node + (size_t)kDiagSlots * blockIdx.x, r);
 }
 
-__global__ __launch_bounds__(256) void k_energy_kin_final(DevState s, const double *part, int np) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < np; i += 256) v += part[i];
-    v = block_sum(v);
-    if (threadIdx.x == 0) s.diag->WK = v;
+// Reduces the node-pass partials of an evaluation at level n = ctr->step in
+// a fixed order into DevDiag; in a step (whose start level is n - 1),
+// appends the energy record of level n - 1 to the ring.  Sets the reference
+// flags of the next evaluation.  plain: the FP64 step's continuity residual
+// is a double (|dQ + Ddiv J| in charge units) judged against max |Q|.
+constexpr int kFinalThreads = 64 * kDiagSlots;      // one wave per slot
+
+__global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb_node, int in_step, int plain) {
+    __shared__ double res[kDiagSlots];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;   // wave w reduces slot w over the node-pass blocks
+    if (w < kDiagSums) {
+        double x = 0.0;
+        for (int b = l; b < nb_node; b += 64) x += s.part_node[(size_t)kDiagSlots * b + w];
+        x = wave_sum64d(x);
+        if (l == 0) res[w] = x;
+    } else if (w < kDiagSums + kDiagMaxes) {
+        unsigned long long x = 0;
+        for (int b = l; b < nb_node; b += 64) {
+            const unsigned long long y = dbits(s.part_node[(size_t)kDiagSlots * b + w]);
+            x = y > x ? y : x;
+        }
+        x = wave_max64(x);
+        if (l == 0) res[w] = __longlong_as_double((long long)x);
+    }
+    __syncthreads();
+    DiagVals r{};
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kDiagSums; ++k) r.sum[k] = res[k];
+#pragma unroll
+        for (int k = 0; k < kDiagMaxes; ++k) r.mx[k] = dbits(res[kDiagSums + k]);
+    }
+    if (threadIdx.x != 0) return;
+    DevCounters &ctr = *s.ctr;
+    DevDiag &d = *s.diag;
+    const unsigned long long n = ctr.step;
+    const bool have_prev = ctr.diag_level1 == n && n > 0;
+    d.level = (long long)n;
+    d.n_live = (long long)r.sum[kSumLiveNow];
+    d.q_total = r.sum[kSumQ];
+    d.WE_now = r.sum[kSumWEnow];
+    d.gauss_abs = __longlong_as_double((long long)r.mx[1]);
+    d.gauss_scale = __longlong_as_double((long long)r.mx[2]);
+    const double qmax = __longlong_as_double((long long)r.mx[4]);
+    d.qmax = qmax;
+    if (r.mx[0] > d.gauss_drift_max_bits) d.gauss_drift_max_bits = r.mx[0];
+    if (have_prev) {
+        const unsigned long long x = r.mx[3];
+        d.dce_last = (long long)x;
+        if (x > d.dce_max) d.dce_max = x;
+        if (plain) {
+            const double rel = __longlong_as_double((long long)x) / (qmax > 0.0 ? qmax : 1.0);
+            if (dbits(rel) > d.dce_rel_max_bits) d.dce_rel_max_bits = dbits(rel);
+        }
+    } else {
+        d.dce_last = -1;
+    }
+    d.n_evals += 1;
+    if (in_step) {
+        DevEnergy e;
+        e.level = (long long)n - 1;
+        e.n_live = (long long)r.sum[kSumLiveStart];
+        e.WE = r.sum[kSumWE];
+        e.WB = r.sum[kSumWB];
+        e.WK = r.sum[kSumWK];
+        e.Qtot = 0.0;
+        s.energy[ctr.energy_count % kEnergyRing] = e;
+        ctr.energy_count += 1;
+        d.energy = e;
+    }
+    ctr.diag_level1 = n + 1;
+    ctr.g0_set = 1;
+}
+
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
 }
 
 // ------------------------------------------------------- absorbing layers
@@ -1045,9 +1373,10 @@ __global__ __launch_bounds__(256) void k_layer_edges(DevMesh m, DevState s, DevL
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, hipStream_t st) {
+void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
+                     hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s, fs, lay);
+    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s, fs, lay, diag ? 1 : 0);
 }
 
 template <class T>
@@ -1068,19 +1397,26 @@ void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const De
 // single: one instance with one species whose charge multiple is 1; its
 // constants travel as kernel arguments (scalar registers) instead of a
 // per-particle table lookup.
+template <bool SINGLE, bool VAY>
+static void launch_particles_t(const DevMesh &m, DevState &s, int max_walk, int dc, PushConst k0, bool diag,
+                               dim3 grid, hipStream_t st) {
+    if (diag) hipLaunchKernelGGL((k_particles<SINGLE, VAY, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+    else hipLaunchKernelGGL((k_particles<SINGLE, VAY, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+}
+
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
-                      hipStream_t st) {
+                      bool diag, hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nblk(s.capacity, kChunk));
     const int dc = count ? 1 : 0;
     if (single) {
-        const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1};
-        if (vay) hipLaunchKernelGGL((k_particles<true, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
-        else hipLaunchKernelGGL((k_particles<true, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+        const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1, 1.0f};
+        if (vay) launch_particles_t<true, true>(m, s, max_walk, dc, k0, diag, grid, st);
+        else launch_particles_t<true, false>(m, s, max_walk, dc, k0, diag, grid, st);
     } else {
-        const PushConst k0{0.f, 0.f, 0.f, 0.f, 1};
-        if (vay) hipLaunchKernelGGL((k_particles<false, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
-        else hipLaunchKernelGGL((k_particles<false, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+        const PushConst k0{0.f, 0.f, 0.f, 0.f, 1, 1.0f};
+        if (vay) launch_particles_t<false, true>(m, s, max_walk, dc, k0, diag, grid, st);
+        else launch_particles_t<false, false>(m, s, max_walk, dc, k0, diag, grid, st);
     }
 }
 
@@ -1088,8 +1424,8 @@ void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_i32, dim3(nblk(m.n2 + 1, 256)), dim3(256), 0, st, s.cnt, (int64_t)m.n2 + 1);
 }
 
-void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, hipStream_t st) {
-    hipLaunchKernelGGL(k_edge_pass, dim3(nblk(m.n1, 256)), dim3(256), 0, st, m, s, keep_j ? 1 : 0);
+void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, bool diag, hipStream_t st) {
+    hipLaunchKernelGGL(k_edge_pass, dim3(nblk(m.n1, 256)), dim3(256), 0, st, m, s, keep_j ? 1 : 0, diag ? 1 : 0);
 }
 
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st) {
@@ -1176,18 +1512,29 @@ void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st) {
     launch_sort_payload(m, s, counted, 4, 5, src, dst, st);
 }
 
-void launch_diag(const DevMesh &m, DevState &s, bool have_prev_q, bool first, hipStream_t st) {
-    (void)hipMemsetAsync(s.diag, 0, sizeof(DevDiag), st);
-    hipLaunchKernelGGL(k_charge_init, dim3(nblk(m.n0, 256)), dim3(256), 0, st, m, s);
-    if (s.capacity) hipLaunchKernelGGL(k_charge, dim3(nblk(s.capacity, 256 * 8)), dim3(256), 0, st, m, s);
-    hipLaunchKernelGGL(k_node_diag, dim3(nblk(m.n0, 256)), dim3(256), 0, st, m, s, have_prev_q ? 1 : 0, first ? 1 : 0);
-    const int64_t ne = m.n1 > m.n2 ? m.n1 : m.n2;
-    hipLaunchKernelGGL(k_energy_fields, dim3(nblk(ne, 256)), dim3(256), 0, st, m, s);
-    if (s.capacity) {
-        const int np = 1024;   // partial sums (s.blk-sized scratch is int; use the Jfx-free diag buffer)
-        hipLaunchKernelGGL(k_energy_kin, dim3(np), dim3(256), 0, st, m, s, s.kin_part);
-        hipLaunchKernelGGL(k_energy_kin_final, dim3(1), dim3(256), 0, st, s, s.kin_part, np);
-    }
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_zero_u64, dim3(nblk(n, 256)), dim3(256), 0, st, p, n);
+}
+
+static int node_blocks(const DevMesh &m) { return (int)nblk(m.n0 > m.n1 ? m.n0 : m.n1, 256); }
+
+void launch_diag_final(const DevMesh &m, DevState &s, bool in_step, bool plain, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kFinalThreads), 0, st, s, node_blocks(m), in_step ? 1 : 0,
+                       plain ? 1 : 0);
+}
+
+void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_node_diag, dim3(node_blocks(m)), dim3(256), 0, st, m, s, 1, (int)nblk(m.n2, 256),
+                       (int)nblk(m.n1, 256));
+    launch_diag_final(m, s, true, false, st);
+}
+
+void launch_diag_now(const DevMesh &m, DevState &s, hipStream_t st) {
+    launch_zero_u64(s.Qloc, 3ll * m.n2, st);
+    if (s.capacity)   // general charge multiples (the on-demand path is not the hot one)
+        hipLaunchKernelGGL(k_charge_now<false>, dim3(nblk(s.capacity, kChunk)), dim3(kWG), 0, st, m, s);
+    hipLaunchKernelGGL(k_node_diag, dim3(node_blocks(m)), dim3(256), 0, st, m, s, 0, 0, 0);
+    launch_diag_final(m, s, false, false, st);
 }
 
 }  // namespace axp

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "diag.h"
 #include "inject.h"
 
 namespace axp {
@@ -31,10 +32,22 @@ __device__ __forceinline__ void fadd(double *a, double v) {
     if (v != 0.0) unsafeAtomicAdd(a, v);       // hardware FP64 atomic add
 }
 
-__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt, FieldSrc fs,
-                                                    DevLayers lay) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m.n2) return;
+__device__ __forceinline__ double block_sum_d(double v) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// one face of the FP64 face pass; returns 1/2 B^{n+1/2} H B^{n-1/2} when diag
+__device__ __forceinline__ double tri_face_d(const DevMesh &m, const DevState &s, const DevPlain &p, double dt,
+                                             const FieldSrc &fs, const DevLayers &lay, int t, bool diag) {
     const int4 e = m.tedge[t];
     double E0 = p.E[e.x], E1 = p.E[e.y], E2 = p.E[e.z];
     if (e.w & 1) E0 = -E0;
@@ -85,6 +98,16 @@ __global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPl
     p.Jloc[3 * t] = 0.0;
     p.Jloc[3 * t + 1] = 0.0;
     p.Jloc[3 * t + 2] = 0.0;
+    return diag ? 0.5 * (m.Hdt[t] / dt) * bn * bo : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_tri_pass_d(DevMesh m, DevState s, DevPlain p, double dt, FieldSrc fs,
+                                                    DevLayers lay, int diag) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const double wb = t < m.n2 ? tri_face_d(m, s, p, dt, fs, lay, t, diag != 0) : 0.0;
+    if (!diag) return;                          // uniform across the grid
+    const double tot = block_sum_d(wb);
+    if (threadIdx.x == 0) s.part_face[blockIdx.x] = tot;
 }
 
 // current of the straight piece s -> e inside one face, per side k
@@ -106,7 +129,7 @@ __device__ __forceinline__ void piece_d(double s0, double s1, double s2, double 
 // particles, and the window is added to the face currents with FP64 global
 // atomics (whose order, and so the last bits, vary from run to run).
 constexpr int kWinD = 512;
-constexpr int kWinLeadD = 128;
+constexpr int kWinLeadD = 192;
 
 typedef __attribute__((address_space(3))) double lds_double;
 
@@ -345,9 +368,21 @@ __device__ __forceinline__ void walk_mover_d(const DevMesh &m, const DevState &s
     mv.l1 = l1;
 }
 
-template <bool VAY>
+// gamma - 1 of u / c without cancellation for slow particles
+__device__ __forceinline__ double gamma_m1_d(double ur, double up, double uz) {
+    const double u2 = ur * ur + up * up + uz * uz;
+    return u2 / (sqrt(1.0 + u2) + 1.0);
+}
+
+// DIAG: the step evaluates the diagnostics of its start level; the kernel
+// then leaves per block W_K = 1/2 (K^{n-1/2} + K^{n+1/2}) over the particles
+// it pushes and their count (each wave summed by a fixed butterfly, the
+// waves in order).
+template <bool VAY, bool DIAG>
 __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, DevPlain p, PlainConst k, int max_walk,
                                                       int do_count) {
+    __shared__ double s_wk[kWGd / 64];
+    __shared__ int s_nl[kWGd / 64];
     __shared__ int s_nmv;
     __shared__ int s_base;
     __shared__ double s_jl[3 * kWinD];
@@ -384,6 +419,8 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
     double mfz[kPPTd], mfr[kPPTd];
     int Tc = -1;
     double4 cf0 = make_double4(0.0, 0.0, 0.0, 0.0), cf1 = cf0, cr4 = cf0, cg = cf0;
+    double wk = 0.0;
+    int nlive = 0;
 #pragma unroll
     for (int j = 0; j < kPPTd; ++j) {
         mover[j] = false;
@@ -397,7 +434,12 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
         }
         double fz, fr;
         const double l0 = P[j].l0, l1 = P[j].l1, l2 = 1.0 - l0 - l1;
+        if (DIAG) {
+            ++nlive;
+            wk += k.mw[sp] * gamma_m1_d(P[j].ur, P[j].up, P[j].uz);
+        }
         push_d<VAY>(s, P[j], k, sp, cf0, cf1, cr4, fz, fr);
+        if (DIAG) wk += k.mw[sp] * gamma_m1_d(P[j].ur, P[j].up, P[j].uz);
         const double d0 = cg.x * fz + cg.y * fr, d1 = cg.z * fz + cg.w * fr, d2 = -d0 - d1;
         const double e0 = l0 + d0, e1 = l1 + d1, e2 = l2 + d2;
         if ((e0 >= 0.0 || d0 >= 0.0) && (e1 >= 0.0 || d1 >= 0.0) && (e2 >= 0.0 || d2 >= 0.0)) {
@@ -425,6 +467,16 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
     }
     wave_deposit_d(w, p.Jloc, acc_t, a0, a1, a2);
     if (do_count) wave_count_d(w, s.cnt, ct, cc);
+    if (DIAG) {
+        double v = 0.5 * wk;
+        int nl = nlive;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            v += __shfl_xor(v, off, 64);
+            nl += __shfl_xor(nl, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) { s_wk[threadIdx.x >> 6] = v; s_nl[threadIdx.x >> 6] = nl; }
+    }
     const int lane = threadIdx.x & 63;
     int slot[kPPTd];
 #pragma unroll
@@ -482,6 +534,14 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
             const int v = s_cl[i], t = w.base + i;
             if (v != 0 && t >= 0 && t < m.n2) atomicAdd(&s.cnt[t], v);
         }
+    if (DIAG && threadIdx.x == 0) {
+        double v = 0.0;
+        int nl = 0;
+#pragma unroll
+        for (int q = 0; q < kWGd / 64; ++q) { v += s_wk[q]; nl += s_nl[q]; }
+        s.part_kin[3 * chunk] = v;
+        s.part_kin[3 * chunk + 1] = (double)nl;
+    }
 #pragma unroll
     for (int j = 0; j < kPPTd; ++j) {
         const long long q = p0 + j;
@@ -493,10 +553,10 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
     }
 }
 
-__global__ __launch_bounds__(256) void k_edge_pass_d(DevMesh m, DevState s, DevPlain p, double qunit) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) s.ctr->step = s.ctr->step + 1ull;   // the face pass of this step has read it
-    if (e >= m.n1) return;
+// diag: also 1/2 E^n D^n per block, read before the update (the energy
+// record of the step's start level)
+__device__ __forceinline__ double edge_update_d(const DevMesh &m, const DevState &s, const DevPlain &p, double qunit,
+                                                int e, bool diag) {
     const int4 et = m.etri[e];
     const int kl = et.z & 3, kr = (et.z >> 2) & 3;
     const double jl = p.Jloc[3 * et.x + kl];
@@ -510,8 +570,19 @@ __global__ __launch_bounds__(256) void k_edge_pass_d(DevMesh m, DevState s, DevP
         jfx += sr * jr;
     }
     p.Jfx[e] = jfx;                    // every edge: conductor edges carry current too (continuity check)
-    if (!(et.z & 64)) return;          // conductor edge: tangential E stays 0
-    s.D[e] += acc;
+    if (!(et.z & 64)) return 0.0;      // conductor edge: tangential E stays 0
+    const double dn = s.D[e];
+    s.D[e] = dn + acc;
+    return diag ? 0.5 * p.E[e] * dn : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_edge_pass_d(DevMesh m, DevState s, DevPlain p, double qunit, int diag) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) s.ctr->step = s.ctr->step + 1ull;   // the face pass of this step has read it
+    const double we = e < m.n1 ? edge_update_d(m, s, p, qunit, e, diag != 0) : 0.0;
+    if (!diag) return;                              // uniform across the grid
+    const double tot = block_sum_d(we);
+    if (threadIdx.x == 0) s.part_edge[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_spmv_d(DevMesh m, DevState s, DevPlain p) {
@@ -538,107 +609,84 @@ __global__ __launch_bounds__(256) void k_spmv_d(DevMesh m, DevState s, DevPlain 
 }
 
 // ------------------------------------------------------------ diagnostics
+// Nodal charge of the particles at their current positions, eq. (charge),
+// plus the wall charge: Q = Qres + sum_p kq lambda_k (charge units, FP64
+// atomics).  Blocks of kChunkD particles; each block also leaves its live
+// count.
 __global__ __launch_bounds__(256) void k_charge_init_d(DevMesh m, DevPlain p) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v < m.n0) p.Q[v] = p.Qres[v];
 }
 
-__global__ __launch_bounds__(256) void k_charge_d(DevMesh m, DevState s, DevPlain p, PlainConst k) {
+__global__ __launch_bounds__(kWGd) void k_charge_d(DevMesh m, DevState s, DevPlain p, PlainConst k) {
+    __shared__ int s_nl[kWGd / 64];
     const long long n = (long long)s.ctr->n_slots;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = i < n ? s.cell[s.cur][i] : -1;
-    const unsigned long long live = __ballot(c >= 0);
-    if ((threadIdx.x & 63) == 0 && live) atomicAdd(&s.diag->n_live, (unsigned long long)__popcll(live));
-    if (c < 0) return;
-    const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
-    const double kq = k.kq[sp];
-    const double l0 = p.l0[s.cur][i], l1 = p.l1[s.cur][i];
-    const int4 tn = m.tnodes[T];
-    fadd(&p.Q[tn.x], kq * l0);
-    fadd(&p.Q[tn.y], kq * l1);
-    fadd(&p.Q[tn.z], kq * (1.0 - l0 - l1));
-}
-
-__device__ __forceinline__ void amax_pos(unsigned long long *a, double v) {
-    atomicMax(a, (unsigned long long)__double_as_longlong(v));
-}
-
-__global__ __launch_bounds__(256) void k_node_diag_d(DevMesh m, DevState s, DevPlain p, double qunit, int have_prev,
-                                                     int first) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= m.n0) return;
-    double div = 0.0, mag = 0.0, divj = 0.0;
-    for (int q = m.nptr[v]; q < m.nptr[v + 1]; ++q) {
-        const int e = m.nedge[q];
-        const double d = s.D[e];
-        div += m.nsign[q] > 0 ? d : -d;
-        mag += fabs(d);
-        if (have_prev) divj += m.nsign[q] > 0 ? p.Jfx[e] : -p.Jfx[e];
-    }
-    const double Qv = p.Q[v];
-    const double g = div - Qv * qunit;
-    if (have_prev) amax_pos(&s.diag->dce_abs_bits, fabs((Qv - p.Qprev[v]) + divj));
-    amax_pos(&s.diag->qmax_bits, fabs(Qv));
-    p.Qprev[v] = Qv;
-    if (m.nfree[v]) {
-        if (first) s.g0[v] = g;
-        amax_pos(&s.diag->gauss_drift_bits, fabs(g - s.g0[v]));
-        amax_pos(&s.diag->gauss_abs_bits, fabs(g));
-        amax_pos(&s.diag->gauss_scale_bits, mag);
-    }
-    unsafeAtomicAdd(&s.diag->Qtot, Qv * qunit);
-}
-
-__device__ __forceinline__ double block_sum_d(double v) {
-    __shared__ double sh[256];
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(256) void k_energy_fields_d(DevMesh m, DevState s, DevPlain p, double dt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double we = 0.0, wb = 0.0;
-    if (i < m.n1) {
-        double ae = 0.0;
-        for (int64_t q = m.a_ptr[i]; q < m.a_ptr[i + 1]; ++q) ae += m.a_val[q] * p.E[m.a_col[q]];
-        we = 0.5 * p.E[i] * ae;
-    }
-    if (i < m.n2) wb = 0.5 * (m.Hdt[i] / dt) * s.B[i] * s.Bprev[i];
-    we = block_sum_d(we);
-    wb = block_sum_d(wb);
-    if (threadIdx.x == 0) {
-        atomicAdd(&s.diag->WE, we);
-        atomicAdd(&s.diag->WB, wb);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_energy_kin_d(DevState s, DevPlain p, PlainConst k, double *part) {
-    const long long n = (long long)s.ctr->n_slots;
-    double wk = 0.0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = s.cell[s.cur][i];
+    const int chunk = blockIdx.x;
+    if ((long long)chunk * kChunkD >= n) return;
+    int live = 0;
+    for (int j = 0; j < kPPTd; ++j) {
+        const long long i = ((long long)chunk * kWGd + threadIdx.x) * kPPTd + j;
+        const int c = i < n ? s.cell[s.cur][i] : -1;
         if (c < 0) continue;
-        const int sp = (c >> kCellBits) & 15;
-        const double a = p.ur[s.cur][i], b = p.up[s.cur][i], z = p.uz[s.cur][i];
-        const double u2 = a * a + b * b + z * z;
-        wk += k.mw[sp] * (u2 / (sqrt(1.0 + u2) + 1.0));
+        ++live;
+        const int T = c & kCellMask, sp = (c >> kCellBits) & 15;
+        const double kq = k.kq[sp];
+        const double l0 = p.l0[s.cur][i], l1 = p.l1[s.cur][i];
+        const int4 tn = m.tnodes[T];
+        fadd(&p.Q[tn.x], kq * l0);
+        fadd(&p.Q[tn.y], kq * l1);
+        fadd(&p.Q[tn.z], kq * (1.0 - l0 - l1));
     }
-    wk = block_sum_d(wk);
-    if (threadIdx.x == 0) part[blockIdx.x] = wk;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) live += __shfl_xor(live, off, 64);
+    if ((threadIdx.x & 63) == 0) s_nl[threadIdx.x >> 6] = live;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nl = 0;
+        for (int q = 0; q < kWGd / 64; ++q) nl += s_nl[q];
+        s.part_kin[3 * chunk + 2] = (double)nl;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_energy_kin_final_d(DevState s, const double *part, int np) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < np; i += 256) v += part[i];
-    v = block_sum_d(v);
-    if (threadIdx.x == 0) s.diag->WK = v;
+// Node pass of an evaluation at level n = ctr->step (the FP64 step's
+// version of k_node_diag): Q^n from k_charge_d, the Gauss residual and its
+// drift, |Q^n - Q^{n-1} + Ddiv J^{n-1/2}| when level n-1 was evaluated, the
+// total charge, max |Q|; per edge 1/2 E^n D^n; and this block's slice of the
+// face and particle partials.  Block partials in the layout k_diag_final
+// reads.
+__global__ __launch_bounds__(256) void k_node_diag_d(DevMesh m, DevState s, DevPlain p, double qunit, int in_step,
+                                                     int nb_face, int nb_edge) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long n = s.ctr->step;
+    const bool have_prev = s.ctr->diag_level1 == n && n > 0;
+    const bool first = s.ctr->g0_set == 0;
+    DiagVals d{};
+    if (v < m.n0) {
+        double div = 0.0, mag = 0.0, divj = 0.0;
+        for (int q = m.nptr[v]; q < m.nptr[v + 1]; ++q) {
+            const int e = m.nedge[q];
+            const double x = s.D[e];
+            div += m.nsign[q] > 0 ? x : -x;
+            mag += fabs(x);
+            divj += m.nsign[q] > 0 ? p.Jfx[e] : -p.Jfx[e];
+        }
+        const double Qv = p.Q[v];
+        if (have_prev) d.mx[3] = dbits(fabs((Qv - p.Qprev[v]) + divj));
+        d.mx[4] = dbits(fabs(Qv));
+        p.Qprev[v] = Qv;
+        if (m.nfree[v]) {
+            const double g = div - Qv * qunit;
+            if (first) s.g0[v] = g;
+            d.mx[0] = dbits(fabs(g - s.g0[v]));
+            d.mx[1] = dbits(fabs(g));
+            d.mx[2] = dbits(mag);
+        }
+        d.sum[kSumQ] = Qv * qunit;
+    }
+    if (v < m.n1) d.sum[kSumWEnow] = 0.5 * p.E[v] * s.D[v];
+    fold_slices(s, d, in_step, nb_face, nb_edge);
+    const DiagVals r = block_reduce_diag(d);
+    if (threadIdx.x == 0) store_partials(s.part_node + (size_t)kDiagSlots * blockIdx.x, r);
 }
 
 // emission: as the mixed step, with FP64 coordinates and wall charge
@@ -671,21 +719,29 @@ inline unsigned nb_(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 }  // namespace
 
 void launch_tri_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, const FieldSrc &fs,
-                           const DevLayers &lay, hipStream_t st) {
+                           const DevLayers &lay, bool diag, hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt, fs, lay);
+    hipLaunchKernelGGL(k_tri_pass_d, dim3(nb_(m.n2, 256)), dim3(256), 0, st, m, s, p, k.dt, fs, lay, diag ? 1 : 0);
+}
+
+template <bool VAY>
+static void launch_particles_plain_t(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k,
+                                     int max_walk, int dc, bool diag, dim3 grid, hipStream_t st) {
+    if (diag) hipLaunchKernelGGL((k_particles_d<VAY, true>), grid, dim3(kWGd), 0, st, m, s, p, k, max_walk, dc);
+    else hipLaunchKernelGGL((k_particles_d<VAY, false>), grid, dim3(kWGd), 0, st, m, s, p, k, max_walk, dc);
 }
 
 void launch_particles_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, int max_walk,
-                            bool count, bool vay, hipStream_t st) {
+                            bool count, bool vay, bool diag, hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nb_(s.capacity, kChunkD));
-    if (vay) hipLaunchKernelGGL(k_particles_d<true>, grid, dim3(kWGd), 0, st, m, s, p, k, max_walk, count ? 1 : 0);
-    else hipLaunchKernelGGL(k_particles_d<false>, grid, dim3(kWGd), 0, st, m, s, p, k, max_walk, count ? 1 : 0);
+    if (vay) launch_particles_plain_t<true>(m, s, p, k, max_walk, count ? 1 : 0, diag, grid, st);
+    else launch_particles_plain_t<false>(m, s, p, k, max_walk, count ? 1 : 0, diag, grid, st);
 }
 
-void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {
-    hipLaunchKernelGGL(k_edge_pass_d, dim3(nb_(m.n1, 256)), dim3(256), 0, st, m, s, p, k.qunit);
+void launch_edge_pass_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool diag,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_edge_pass_d, dim3(nb_(m.n1, 256)), dim3(256), 0, st, m, s, p, k.qunit, diag ? 1 : 0);
 }
 
 void launch_spmv_plain(const DevMesh &m, DevState &s, const DevPlain &p, hipStream_t st) {
@@ -706,20 +762,17 @@ void launch_inject_plain(const DevMesh &m, DevState &s, const DevPlain &p, const
     hipLaunchKernelGGL(k_inject_commit_d, dim3(1), dim3(1), 0, st, s, ip.per_step);
 }
 
-void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool have_prev_q,
-                       bool first, hipStream_t st) {
-    (void)hipMemsetAsync(s.diag, 0, sizeof(DevDiag), st);
+void launch_charge_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, hipStream_t st) {
     hipLaunchKernelGGL(k_charge_init_d, dim3(nb_(m.n0, 256)), dim3(256), 0, st, m, p);
-    if (s.capacity) hipLaunchKernelGGL(k_charge_d, dim3(nb_(s.capacity, 256)), dim3(256), 0, st, m, s, p, k);
-    hipLaunchKernelGGL(k_node_diag_d, dim3(nb_(m.n0, 256)), dim3(256), 0, st, m, s, p, k.qunit, have_prev_q ? 1 : 0,
-                       first ? 1 : 0);
-    const int64_t ne = m.n1 > m.n2 ? m.n1 : m.n2;
-    hipLaunchKernelGGL(k_energy_fields_d, dim3(nb_(ne, 256)), dim3(256), 0, st, m, s, p, k.dt);
-    if (s.capacity) {
-        const int np = 1024;
-        hipLaunchKernelGGL(k_energy_kin_d, dim3(np), dim3(256), 0, st, s, p, k, s.kin_part);
-        hipLaunchKernelGGL(k_energy_kin_final_d, dim3(1), dim3(256), 0, st, s, s.kin_part, np);
-    }
+    if (s.capacity) hipLaunchKernelGGL(k_charge_d, dim3(nb_(s.capacity, kChunkD)), dim3(kWGd), 0, st, m, s, p, k);
+}
+
+void launch_diag_plain(const DevMesh &m, DevState &s, const DevPlain &p, const PlainConst &k, bool in_step,
+                       hipStream_t st) {
+    const int64_t nn = m.n0 > m.n1 ? m.n0 : m.n1;
+    hipLaunchKernelGGL(k_node_diag_d, dim3(nb_(nn, 256)), dim3(256), 0, st, m, s, p, k.qunit, in_step ? 1 : 0,
+                       (int)nb_(m.n2, 256), (int)nb_(m.n1, 256));
+    launch_diag_final(m, s, in_step, true, st);
 }
 
 }  // namespace axp

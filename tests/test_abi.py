@@ -63,7 +63,8 @@ def _c_layout():
                            "spai_energy_drift", "spai_seconds", "n_layer_faces"],
               "axp_diag": ["step", "n_live", "n_absorbed", "walk_overflow", "nan_count", "fixed_overflow",
                            "dce_max_abs", "dce_max_rel", "gauss_max_drift", "gauss_max_abs", "gauss_scale", "W_E",
-                           "W_B", "W_K", "Q_total"]}
+                           "W_B", "W_K", "Q_total", "energy_step", "n_evals", "W_E_now"],
+              "axp_energy": ["step", "n_live", "W_E", "W_B", "W_K", "Q_total"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for st, fs in fields.items():
         lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
@@ -86,7 +87,8 @@ def test_struct_layout_matches_c_compiler():
     import ctypes as C
     import paper_1701_03784_amd.axpic as ax
     lay, fields = _c_layout()
-    for st, cls in (("axp_config", ax.Config), ("axp_info", ax.Info), ("axp_diag", ax.Diag)):
+    for st, cls in (("axp_config", ax.Config), ("axp_info", ax.Info), ("axp_diag", ax.Diag),
+                    ("axp_energy", ax.Energy)):
         assert C.sizeof(cls) == lay[(st, "sizeof")], st
         for f in fields[st]:
             assert getattr(cls, f).offset == lay[(st, f)], (st, f)
@@ -114,3 +116,26 @@ def test_spai_model_train_rejects_bad_arguments_before_any_device_work(tmp_path)
     empty.write_text("# nothing but a comment\n\n")
     assert lib.axp_spai_model_train(str(empty).encode(), str(tmp_path / "x.bin").encode(), 0) == -1
     assert not (tmp_path / "x.bin").exists()
+
+
+def test_network_binding_rejects_unreadable_tensors_before_any_launch():
+    """Mlp.forward / loss_grad refuse host tensors, other dtypes and
+    non-contiguous views with ValueError before anything reaches the library
+    (the kernels read float4 rows from device memory)."""
+    import torch
+    import paper_1701_03784_amd.axpic as ax
+    net = ax.Mlp.__new__(ax.Mlp)          # no device handle: any library call would fail differently
+    net.lib, net.h, net.device = None, None, 0
+    X = torch.zeros(8, 16)
+    y = torch.zeros(8)
+    with pytest.raises(ValueError, match="cuda:0"):
+        net.forward(X, y)
+    with pytest.raises(ValueError, match="cuda:0"):
+        net.loss_grad(X, y, y)
+    with pytest.raises(ValueError):
+        net.forward(X.double(), y)
+    with pytest.raises(ValueError):
+        net.loss_grad(X.t(), y, y)
+    with pytest.raises(ValueError, match="torch tensor"):
+        net.forward(X.numpy(), y)
+    net.h = None
