@@ -1,13 +1,16 @@
 """Throughput benchmark of the axisymmetric EM-PIC step on one MI355X.
 
-Workload (default): rippled-wall BWO slow-wave tube, ~208k faces, 8M
+Headline workload: the rippled-wall BWO slow-wave tube, ~208k faces, 8M
 macro-electrons of a 500 keV annular beam, B_z = 1 T, mixed precision,
-dt = 0.5 x the leapfrog stability limit.  Inputs are seeded and synthetic.
+dt = 0.5 x the leapfrog stability limit, steps replayed from graphs, with the
+diagnostics (nodal charge, Gauss and continuity residuals, energies) at the
+stated cadence inside the timed steps.  Inputs are seeded and synthetic.
 
 Prints one JSON line: particle-steps/s of the whole step (value), the field
-kernels' HBM rate, the dominant kernel's roofline (HIP-event time of the
-particle kernel on the library's stream) and the FP64 CPU oracle timed on a
-bounded slice of the same workload.
+kernels' HBM rate, the dominant kernel's roofline against its algorithmic
+bytes, per-workload legs (cavity, diode, the 64-member batched sweep, a pool
+of small members against the same members stepped one by one), and the FP64
+oracle timed on the host (one thread and OpenMP) beside the legs.
 """
 
 from __future__ import annotations
@@ -15,6 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -24,23 +28,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1701_03784_amd", "csrc", "kernels_mixed.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particles_bwo_traffic.txt")
+QE, ME, C = -1.602176634e-19, 9.1093837015e-31, 299792458.0
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_1701_03784_amd", "csrc", "kernels_mixed.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_particles_bwo_traffic.txt")
-
-
+# ------------------------------------------------------------ byte models
 def particle_bytes(n_live, n_faces):
-    """Algorithmic bytes of one k_particles launch (gather, push, walk and
-    current): 24 B of particle state read and written per particle (48 B),
-    plus once per face the gather tile (32 B), the geometry used by the push
-    (rho of the nodes and the scaled barycentric gradients, 32 B) and the
-    three fixed-point side currents (24 B)."""
-    return 48.0 * n_live + 88.0 * n_faces
+    """Algorithmic bytes of one particle-kernel launch (gather, push, walk,
+    current): the particle state read and written, 2 x 24 B per particle,
+    plus the per-face tables the particles need, 40 B per face (the gather
+    tile's E coefficients and face field, the barycentric gradients and the
+    three side currents, amortised over the particles of a face)."""
+    return 48.0 * n_live + 40.0 * n_faces
+
+
+def field_bytes(n_free_edges, n_faces, spai_nnz):
+    """Algorithmic bytes of the field update per step: Faraday reads three
+    E values and reads and writes B (28 B per face); Ampere with the SPAI
+    reads 8 B per non-zero of M and per free edge reads and writes D (8 B),
+    writes E (4 B) and reads J (8 B).  No padding, no index overhead."""
+    return 28.0 * n_faces + 8.0 * spai_nnz + 20.0 * n_free_edges
 
 
 def kernel_source_hash():
@@ -49,8 +61,8 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per k_particles launch from the committed counter summary, if it
-    was taken on the current kernel source (else None)."""
+    """HBM bytes per particle-kernel launch from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -66,97 +78,176 @@ def measured_traffic():
         return None
 
 
-def field_bytes(n_edges, n_faces, spai_nnz_padded):
-    """Bytes the three field kernels must move once per step:
-    face pass 144 B/face + 4 B/edge; edge pass 44 B/edge + 32 B/face;
-    SpMV 8 B per stored matrix entry + 8 B/edge."""
-    return (144.0 * n_faces + 4.0 * n_edges) + (44.0 * n_edges + 32.0 * n_faces) + \
-        (8.0 * spai_nnz_padded + 8.0 * n_edges)
+# ------------------------------------------------------------ GPU helpers
+def timed(c, steps):
+    """Wall time of `steps` steps enqueued at once (graphs replay them)."""
+    c.sync()
+    t0 = time.perf_counter()
+    c.step(steps)
+    c.sync()
+    return time.perf_counter() - t0
 
 
-def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, pusher=0, diag_every=0):
+def live_steps(c, steps, el):
+    """Particle-steps of the last timed steps from the energy records of
+    their diagnostic steps (live count at each start level), else the live
+    count after them times the steps."""
+    r = c.energies()
+    if len(r) >= steps:
+        return float(r["n_live"][-steps:].sum())
+    return float(c.diag()["n_live"]) * steps
+
+
+def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, pusher=0, diag_every=1):
     import synth
     from synth import configs
     import paper_1701_03784_amd as axp
     t0 = time.perf_counter()
     m = configs.bwo_mesh(seed=seed)
     L = m.meta["length"]
-    log(f"mesh: {m.n_nodes} nodes, {m.n_tris} faces ({time.perf_counter() - t0:.1f} s)")
     kw = {} if precision is None else {"precision": precision}
     c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, pusher=pusher, diag_every=diag_every, **kw)
     info = c.info()
-    log(f"built: {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s "
-        f"(limit {info['dt_cfl']:.3e}), setup {info['setup_seconds']:.1f} s")
     c.set_fields(np.zeros(info["n_edges"]), np.zeros(info["n_faces"]))
     c.set_external_bz(configs.BWO_BZ)
     w = configs.bwo_weight(n_particles, L)
     sp = c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, w)
     zr, u = configs.bwo_beam(n_particles, L, seed=seed)
-    t1 = time.perf_counter()
     c.inject(sp, zr, u)
-    log(f"injected {n_particles} particles (weight {w}) in {time.perf_counter() - t1:.1f} s")
+    log(f"bwo ctx: {m.n_tris} faces, {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s, "
+        f"{n_particles} particles (weight {w}), diag_every {diag_every}, {time.perf_counter() - t0:.1f} s")
     desc = (f"bwo: rippled-wall tube R=1.5+0.25 sin cm, 10 periods of 1.67 cm + drifts, {m.n_tris} faces, "
             f"{info['n_edges']} edges; {n_particles} macro-electrons, 500 keV annular beam, B_z=1 T; "
             f"SPAI level 3 ({info['spai_nnz']} nnz); dt=0.5 CFL")
     return c, m, info, desc
 
 
-def plain_leg(n_particles, steps, warmup, use_graph):
-    """The same workload on the FP64 GPU step: the same kernel structure in
-    FP64, one instance, sort period autotuned the same way; launched eagerly
-    (the reference point of the speedups) or replayed from graphs."""
-    import paper_1701_03784_amd as axp
-    c, m, info, _ = setup_bwo(n_particles, precision=axp.PREC_PLAIN_FP64, use_graph=use_graph)
+def tube_rate(args, precision=None, use_graph=1, pusher=0, diag_every=1, timing=False):
+    """One run of the tube workload: rate of args.steps steps after the
+    warmup; with timing, HIP-event durations of every phase over the same
+    number of steps launched eagerly right after."""
+    c, m, info, desc = setup_bwo(args.particles, precision=precision, use_graph=use_graph, pusher=pusher,
+                                 diag_every=diag_every)
     sp = c.autotune(16)
-    log(f"fp64 step: autotuned sort period {sp}")
-    c.step(warmup)
-    c.sync()
-    steps = max(2 * sp, steps // (2 * sp) * (2 * sp))
-    t0 = time.perf_counter()
-    c.step(steps)
-    c.sync()
-    el = time.perf_counter() - t0
+    c.step(args.warmup)
+    steps = args.steps
+    if use_graph:
+        steps = max(2 * sp, steps // (2 * sp) * (2 * sp))
+    c.energies()                                  # discard the records of setup and warmup
+    el = timed(c, steps)
+    ps = live_steps(c, steps, el)
     d = c.diag()
+    out = {"value": ps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps, "steps": steps,
+           "sort_period": sp, "graphs": bool(use_graph), "diag_every": diag_every, "particles": int(d["n_live"]),
+           "field_dof_steps_per_s": (info["n_edges"] + info["n_faces"]) * steps / el,
+           "walk_overflow": d["walk_overflow"], "nan_count": d["nan_count"]}
+    if diag_every:
+        out["dce_max_abs" if precision is None else "dce_max_rel"] = d["dce_max_abs"] if precision is None \
+            else d["dce_max_rel"]
+        out["gauss_drift_rel"] = d["gauss_max_drift"] / max(d["gauss_scale"], 1e-300)
+    tim = None
+    if timing:
+        c.set_timing(True)
+        c.sync()
+        t1 = time.perf_counter()
+        c.step(steps)
+        c.sync()
+        out["ms_per_step_events"] = (time.perf_counter() - t1) * 1e3 / steps
+        tim = c.get_timing()
     c.close()
-    return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
-            "steps": steps, "precision": "plain fp64", "particles": int(d["n_live"]), "sort_period": sp,
-            "graphs": bool(use_graph)}
+    return out, tim, info, desc
 
 
-def vay_leg(n_particles, steps, warmup):
-    """The headline workload with Vay's pusher in place of the Boris push
-    (mixed precision, graphs, sort period autotuned)."""
-    import paper_1701_03784_amd as axp
-    c, m, info, _ = setup_bwo(n_particles, pusher=axp.PUSH_VAY)
-    sp = c.autotune(16)
-    c.step(warmup)
-    c.sync()
-    steps = max(2 * sp, steps // (2 * sp) * (2 * sp))
-    t0 = time.perf_counter()
-    c.step(steps)
-    c.sync()
-    el = time.perf_counter() - t0
-    d = c.diag()
-    c.close()
-    return {"value": d["n_live"] * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
-            "steps": steps, "precision": "mixed", "pusher": "vay", "particles": int(d["n_live"]), "sort_period": sp,
-            "graphs": True}
-
-
-def batched_leg(n_variants, steps, per_face=25, seed_note=""):
-    """Batched sweep: members 0..n-1 of the seeded BWO variant family (ripple
-    amplitude, period, taper, beam voltage; 20k-300k faces), ~25 particles
-    per face each, pooled into one batch, sort schedule autotuned, steps
-    replayed from graphs."""
+# ------------------------------------------------------------ legs
+def cavity_run(axp, precision, steps, diag_every=1, use_graph=1):
     import synth
     from synth import configs
-    import paper_1701_03784_amd as axp
+    m = configs.cavity_mesh()
+    c = axp.make_ctx(m, dt=configs.CAVITY_DT, precision=precision, diag_every=diag_every, use_graph=use_graph)
+    E0, B0, _ = synth.tm010_fields(m.nodes, m.tris, c.get_edges(), configs.CAVITY_A, 1e6, configs.CAVITY_DT)
+    c.set_fields(E0, B0)
+    zr, u = configs.cavity_beam()
+    c.inject(c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.CAVITY_WEIGHT), zr, u)
+    c.diag()
+    c.energies()
+    el = timed(c, steps)
+    r = c.energies()
+    d = c.diag()
+    E, B = c.get_fields()
+    info = c.info()
+    c.close()
+    return {"ms_per_step": el * 1e3 / steps, "particle_steps_per_s": float(r["n_live"].sum()) / el,
+            "field_dof_steps_per_s": (info["n_edges"] + info["n_faces"]) * steps / el,
+            "dce": d["dce_max_abs"] if precision == axp.PREC_MIXED else d["dce_max_rel"],
+            "gauss_drift_rel": d["gauss_max_drift"] / max(d["gauss_scale"], 1e-300)}, E, B
+
+
+def cavity_leg(axp, steps=1000):
+    """Cavity (TM010 + 10,000 electrons at 0.5 c, ~2k faces), 1,000 steps,
+    diagnostics every step: both precisions, and the field error of each
+    against the oracle's run of the same steps (timed in the cpu legs)."""
+    out = {}
+    for name, prec in (("plain_fp64", axp.PREC_PLAIN_FP64), ("mixed", axp.PREC_MIXED)):
+        out[name], E, B = cavity_run(axp, prec, steps)
+        out[name]["_EB"] = (E, B)
+    return out
+
+
+def diode_leg(axp, steps=5000, per_step=2000):
+    """Diode (gap 1 cm at 100 kV, emitter rho < 2 cm, ~20k faces): 2,000
+    electrons emitted per step at 1 eV, 5,000 steps, mixed precision, graphs,
+    diagnostics every 8 steps (the emission makes the count grow to ~3M)."""
+    import synth
+    from synth import configs
+    EPS0 = 8.8541878128e-12
+    V, d, Re = configs.DIODE_VOLTS, configs.DIODE_GAP, 0.02
+    I_cl = 4 * EPS0 / 9 * np.sqrt(2 * abs(QE) / ME) * V ** 1.5 / d ** 2 * np.pi * Re ** 2
+    m = configs.diode_mesh()
+    c = axp.make_ctx(m, sort_period=8, diag_every=8)
+    info = c.info()
+    e = c.get_edges()
+    phi = V * m.nodes[:, 0] / d
+    c.set_fields(-(phi[e[:, 1]] - phi[e[:, 0]]), np.zeros(info["n_faces"]))
+    w = int(round(2 * I_cl * info["dt"] / (per_step * abs(QE))))
+    sp = c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, w)
+    c.set_injector(sp, per_step, [0.0, 0.0, np.sqrt((1 + 1.0 / 511e3) ** 2 - 1) * C], 0.0, 11)
+    c.diag()
+    c.energies()
+    el = timed(c, steps)
+    r = c.energies()
+    dd = c.diag()
+    # particle-steps: the live count grows by per_step a step until the first
+    # electrons reach the anode; the records give it every 8th level
+    lv = np.interp(np.arange(steps), r["step"], r["n_live"])
+    ps = float(lv.sum())
+    c.close()
+    return {"faces": info["n_faces"], "steps": steps, "ms_per_step": el * 1e3 / steps,
+            "particle_steps_per_s": ps / el, "field_dof_steps_per_s": (info["n_edges"] + info["n_faces"]) * steps / el,
+            "live_at_end": int(dd["n_live"]), "absorbed": int(dd["n_absorbed"]), "dce_max_abs": dd["dce_max_abs"],
+            "gauss_drift_rel": dd["gauss_max_drift"] / max(dd["gauss_scale"], 1e-300)}
+
+
+def _variant(i):
+    from synth import configs
+    m, p = configs.variant_mesh(i)
+    return m, p
+
+
+def batched_leg(axp, n_variants, steps, per_face=25, diag_every=1):
+    """Batched sweep: members 0..n-1 of the seeded BWO variant family (ripple
+    amplitude 1-4 mm, period 1.2-2.0 cm, taper 0-30 %, beam 300-600 keV;
+    20k-300k faces), ~25 particles per face each, pooled into one batch,
+    sort schedule autotuned, steps replayed from graphs."""
+    import multiprocessing as mp
+    import synth
+    from synth import configs
     t0 = time.perf_counter()
-    ctxs = []
-    n_faces = n_part = 0
-    for i in range(n_variants):
-        m, p = configs.variant_mesh(i)
-        c = axp.make_ctx(m, sort_period=4)
+    with mp.get_context("fork").Pool(min(16, max(1, n_variants))) as pool:
+        meshes = pool.map(_variant, range(n_variants))
+    log(f"batch: {n_variants} meshes in {time.perf_counter() - t0:.1f} s")
+    ctxs, n_faces, n_part = [], 0, 0
+    for i, (m, p) in enumerate(meshes):
+        c = axp.make_ctx(m, sort_period=4, diag_every=diag_every)
         info = c.info()
         c.set_fields(np.zeros(info["n_edges"]), np.zeros(info["n_faces"]))
         c.set_external_bz(configs.BWO_BZ)
@@ -169,11 +260,11 @@ def batched_leg(n_variants, steps, per_face=25, seed_note=""):
         n_faces += m.n_tris
         n_part += n
         ctxs.append(c)
-        log(f"batch member {i}: {m.n_tris} faces, {n} particles, {p['kev']:.0f} keV")
+    meshes = None
     b = axp.Batch(ctxs)
-    log(f"batch of {n_variants}: {n_faces} faces, {n_part} particles, setup {time.perf_counter() - t0:.1f} s")
+    setup = time.perf_counter() - t0
+    log(f"batch of {n_variants}: {n_faces} faces, {n_part} particles, setup {setup:.1f} s")
     sp_best = b.autotune(trial_steps=16)
-    log(f"autotuned sort period {sp_best}")
     b.step(2 * sp_best)
     b.sync()
     steps = max(2 * sp_best, steps // (2 * sp_best) * (2 * sp_best))
@@ -188,61 +279,178 @@ def batched_leg(n_variants, steps, per_face=25, seed_note=""):
         c.close()
     return {"value": live * steps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps,
             "steps": steps, "variants": n_variants, "faces": n_faces, "particles": int(live),
-            "sort_period": sp_best, "graphs": True,
+            "sort_period": sp_best, "graphs": True, "diag_every": diag_every, "setup_s": round(setup, 1),
             "field_dof_steps_per_s": (n_faces + n_edges) * steps / el}
 
 
-def cpu_baseline(target_seconds=15.0):
-    """FP64 oracle on a bounded slice of the BWO workload: one ripple period
-    of the same profile and mesh size, the same beam density."""
-    from synth import configs
+def small_pool_leg(axp, n_members=64, steps=64, n_part=10000):
+    """Many small devices: n cavities (meshes seeded 0..n-1, ~2k faces, TM010
+    and 10,000 electrons each), stepped one by one (each from its own graphs)
+    against the same members pooled into one batch (one launch per phase for
+    all of them).  Launch latency dominates the small member's step."""
     import synth
-    from oracle.pic import OracleSim
-    m = configs.bwo_mesh(seed=3, n_periods=1, up=0.0, down=0.0)
-    full_area = 0.217 * 0.015
-    area = m.signed_areas().sum()
-    n = int(8_000_000 * area / full_area)
+    from synth import configs
+
+    def members():
+        out = []
+        for i in range(n_members):
+            m = configs.cavity_mesh(seed=i)
+            c = axp.make_ctx(m, dt=configs.CAVITY_DT, sort_period=4, diag_every=0)
+            E0, B0, _ = synth.tm010_fields(m.nodes, m.tris, c.get_edges(), configs.CAVITY_A, 1e6, configs.CAVITY_DT)
+            c.set_fields(E0, B0)
+            zr, u = configs.cavity_beam(n_part, seed=100 + i)
+            c.inject(c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.CAVITY_WEIGHT), zr, u)
+            out.append(c)
+        return out
+
+    alone = members()
+    for c in alone:
+        c.step(8)
+    for c in alone:
+        c.sync()
     t0 = time.perf_counter()
-    sim = OracleSim(m.nodes, m.tris, m.seg, m.tag)
-    setup = time.perf_counter() - t0
-    sim.bz = configs.BWO_BZ
-    L = m.meta["length"]
-    zr, u = configs.bwo_beam(n, L, seed=3)
-    sp = sim.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.bwo_weight(n, L))
-    sim.inject(sp, zr, u)
-    sim.step(1)
-    steps, el = 0, 0.0
-    while el < target_seconds and steps < 400:
-        t1 = time.perf_counter()
+    for c in alone:
+        c.step(steps)
+    for c in alone:
+        c.sync()
+    el_alone = time.perf_counter() - t0
+    live = sum(c.diag()["n_live"] for c in alone)
+    for c in alone:
+        c.close()
+    pooled = members()
+    b = axp.Batch(pooled)
+    b.step(8)
+    b.sync()
+    t1 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    el_pool = time.perf_counter() - t1
+    live_p = sum(c.info()["n_particles"] for c in pooled)
+    b.close()
+    for c in pooled:
+        c.close()
+    return {"members": n_members, "faces_each": 1992, "particles_each": n_part, "steps": steps,
+            "one_by_one_ms_per_step": el_alone * 1e3 / steps, "pooled_ms_per_step": el_pool * 1e3 / steps,
+            "one_by_one_particle_steps_per_s": live * steps / el_alone,
+            "pooled_particle_steps_per_s": live_p * steps / el_pool, "gain": el_alone / el_pool}
+
+
+# ------------------------------------------------------------ oracle (CPU) legs
+def _cpu_leg(name, openmp, seconds):
+    """Runs one oracle timing leg in a child process (the OpenMP build is
+    chosen per process); returns its JSON result."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", name, "--cpu-seconds", str(seconds)]
+    if openmp:
+        cmd.append("--omp")
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        log(f"cpu leg {name} failed: {r.stderr[-2000:]}")
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_leg_main(name, openmp, seconds):
+    import oracle.pic as op
+    op.use_openmp(openmp)
+    import synth
+    from synth import configs
+    from oracle.pic import OracleSim
+    threads = op.oracle_threads()
+    if name == "tube":
+        # one ripple period of the tube at the full beam density
+        m = configs.bwo_mesh(seed=3, n_periods=1, up=0.0, down=0.0)
+        n = int(8_000_000 * m.signed_areas().sum() / (0.217 * 0.015))
+        t0 = time.perf_counter()
+        sim = OracleSim(m.nodes, m.tris, m.seg, m.tag)
+        setup = time.perf_counter() - t0
+        sim.bz = configs.BWO_BZ
+        L = m.meta["length"]
+        zr, u = configs.bwo_beam(n, L, seed=3)
+        sim.inject(sim.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.bwo_weight(n, L)), zr, u)
         sim.step(1)
-        el += time.perf_counter() - t1
-        steps += 1
-    live = int(sim.palive.sum())
-    rate = live * steps / el
-    return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one ripple period of the bwo profile (1.67 cm, {m.n_tris} faces, h=0.19 mm) with "
-                      f"{live} particles at the full beam density, {steps} steps timed "
-                      f"({el:.1f} s) after {setup:.1f} s of oracle setup; single thread FP64"}
+        steps, el, ps = 0, 0.0, 0
+        while el < seconds and steps < 400:
+            live = int(sim.palive.sum())
+            t1 = time.perf_counter()
+            sim.step(1)
+            el += time.perf_counter() - t1
+            steps += 1
+            ps += live
+        out = {"value": ps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+               "field_dof_steps_per_s": (sim.topo.n1 + sim.topo.n2) * steps / el,
+               "sample": f"one ripple period of the bwo tube (1.67 cm, {m.n_tris} faces, h=0.19 mm) with "
+                         f"{int(sim.palive.sum())} particles at the full beam density, {steps} steps timed "
+                         f"({el:.1f} s) after {setup:.1f} s of oracle setup; FP64, "
+                         f"{'OpenMP' if openmp else 'one thread'}, gcc -O3"}
+    elif name == "cavity":
+        m = configs.cavity_mesh()
+        sim = OracleSim(m.nodes, m.tris, m.seg, m.tag, dt=configs.CAVITY_DT)
+        E0, B0, _ = synth.tm010_fields(m.nodes, m.tris, sim.topo.edges, configs.CAVITY_A, 1e6, sim.dt)
+        sim.set_fields(E0, B0)
+        zr, u = configs.cavity_beam()
+        sim.inject(sim.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, configs.CAVITY_WEIGHT), zr, u)
+        el, ps = 0.0, 0
+        for _ in range(1000):
+            ps += int(sim.palive.sum())
+            t1 = time.perf_counter()
+            sim.step(1)
+            el += time.perf_counter() - t1
+        out = {"particle_steps_per_s": ps / el, "field_dof_steps_per_s": (sim.topo.n1 + sim.topo.n2) * 1000 / el,
+               "steps": 1000, "seconds": el, "cores": threads, "E": sim.E.tolist(), "B": sim.B.tolist()}
+    elif name == "diode":
+        # the first steps of the diode run (the count grows by 2,000 a step)
+        EPS0 = 8.8541878128e-12
+        V, d, Re = configs.DIODE_VOLTS, configs.DIODE_GAP, 0.02
+        I_cl = 4 * EPS0 / 9 * np.sqrt(2 * abs(QE) / ME) * V ** 1.5 / d ** 2 * np.pi * Re ** 2
+        m = configs.diode_mesh()
+        sim = OracleSim(m.nodes, m.tris, m.seg, m.tag)
+        phi = V * m.nodes[:, 0] / d
+        e = sim.topo.edges
+        sim.set_fields(-(phi[e[:, 1]] - phi[e[:, 0]]), np.zeros(sim.topo.n2))
+        w = int(round(2 * I_cl * sim.dt / (2000 * abs(QE))))
+        sp = sim.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, w)
+        sim.set_injector(sp, 2000, [0.0, 0.0, np.sqrt((1 + 1.0 / 511e3) ** 2 - 1) * C], 0.0, 11)
+        steps, el, ps = 0, 0.0, 0
+        while el < seconds and steps < 5000:
+            t1 = time.perf_counter()
+            sim.step(1)
+            el += time.perf_counter() - t1
+            steps += 1
+            ps += int(sim.palive.sum())
+        out = {"particle_steps_per_s": ps / el, "field_dof_steps_per_s": (sim.topo.n1 + sim.topo.n2) * steps / el,
+               "steps": steps, "seconds": el, "cores": threads, "live_at_end": int(sim.palive.sum()),
+               "sample": f"the first {steps} of the 5,000 steps (emission 2,000/step)"}
+    else:
+        raise SystemExit(f"unknown cpu leg {name}")
+    print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--particles", type=int, default=8_000_000)
-    ap.add_argument("--sort-period", type=int, default=0, help="0: chosen by the library's autotuner")
+    ap.add_argument("--diag-every", type=int, default=1,
+                    help="diagnostic steps (charge, Gauss and continuity residuals, energies) every this many steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--plain-steps", type=int, default=20, help="timed steps of the FP64 leg (0: skip)")
+    ap.add_argument("--plain-steps", type=int, default=32, help="timed steps of the FP64 legs (0: skip)")
     ap.add_argument("--vay-steps", type=int, default=32, help="timed steps of the Vay-pusher leg (0: skip)")
-    ap.add_argument("--batch-variants", type=int, default=8, help="members of the batched sweep (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=48)
-    ap.add_argument("--diag-every", type=int, default=0,
-                    help="diagnostic steps (nodal charge, Gauss and continuity residuals, energies) every this many steps")
+    ap.add_argument("--batch-variants", type=int, default=64, help="members of the batched sweep (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=32)
+    ap.add_argument("--small-members", type=int, default=64, help="members of the small-device pool (0: skip)")
+    ap.add_argument("--no-cavity", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (counter calibration)")
+                    help="also run a plain device copy of this size (calibration of the traffic counters)")
+    ap.add_argument("--no-diode", action="store_true")
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--omp", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_leg:
+        cpu_leg_main(args.cpu_leg, args.omp, args.cpu_seconds)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the workload is measured at N=1; the multi-GPU path "
               "(z-slab decomposition, independent batch members per GPU) is a design, not implemented",
@@ -251,46 +459,23 @@ def main():
 
     import paper_1701_03784_amd as axp
     axp.load_library()
-    c, m, info, desc = setup_bwo(args.particles, sort_period=max(1, args.sort_period), diag_every=args.diag_every)
-    sort_period = args.sort_period
-    if sort_period == 0:
-        sort_period = c.autotune(16)
-        log(f"autotuned sort period {sort_period} (steps so far {c.info()['step']})")
-    c.step(args.warmup)
-    c.sync()
-    log(f"warmup {args.warmup} steps done")
-    # timed region: the production mode, steps replayed from graphs
-    t0 = time.perf_counter()
-    c.step(args.steps)
-    c.sync()
-    el = time.perf_counter() - t0
-    d_timed = c.diag()
-    # kernel durations: the next args.steps steps with HIP events around every
-    # phase (eager launches: HIP cannot time event records inside a graph)
-    c.set_timing(True)
-    c.sync()
-    t1 = time.perf_counter()
-    c.step(args.steps)
-    c.sync()
-    el_events = time.perf_counter() - t1
-    tim = c.get_timing()
-    d = c.diag()
-    n_live = d_timed["n_live"]
+    # ---- headline: the tube, mixed precision, graphs, diagnostics at the stated cadence
+    head, tim, info, desc = tube_rate(args, diag_every=args.diag_every, timing=True)
+    log(f"headline: {head['value']:.3e} particle-steps/s, {head['ms_per_step']:.4f} ms/step "
+        f"(sort period {head['sort_period']}, diag_every {args.diag_every})")
     n1, n2 = info["n_edges"], info["n_faces"]
-    ms_step = el * 1e3 / args.steps
-    value = n_live * args.steps / el
-    part_ms, part_n = tim["particles"]
-    part_avg_s = part_ms / part_n / 1e3
+    n_live = head["particles"]
+    steps = head["steps"]
+    per_launch = {k: round(v[0] / max(1, v[1]) * 1e3, 2) for k, v in tim.items() if v[1]}
+    per_step = {k: round(v[0] / steps * 1e3, 2) for k, v in tim.items() if v[1]}
+    part_s = tim["particles"][0] / tim["particles"][1] / 1e3
     pb = particle_bytes(n_live, n2)
-    achieved = pb / part_avg_s / 1e9
-    nnz_pad = info["spai_nnz"] * 1.15
-    fb = field_bytes(n1, n2, nnz_pad)
-    field_ms = sum(tim[k][0] for k in ("face", "edge", "spmv")) / args.steps
-    walk_ms, walk_n = tim["walk"]
+    achieved = pb / part_s / 1e9
+    fb = field_bytes(info["n_free_edges"], n2, info["spai_nnz"])
+    field_ms = sum(tim[k][0] for k in ("face", "edge", "spmv")) / steps
     field_gbs = fb / (field_ms / 1e3) / 1e9
-    per_phase = {k: round(v[0] / max(1, v[1]) * 1e3, 2) for k, v in tim.items() if v[1]}
-    log(f"{args.steps} steps in {el:.3f} s: {ms_step:.3f} ms/step; per-launch us {per_phase}")
-    log(f"diag: live {n_live} absorbed {d['n_absorbed']} overflow {d['walk_overflow']} nan {d['nan_count']}")
+    step_bytes = pb + fb
+    log(f"per-launch us {per_launch}")
 
     if args.copy_probe_mib:
         import torch
@@ -299,68 +484,119 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
         log(f"copy probe: {args.copy_probe_mib} MiB x3")
 
-    c.close()
-    plain = plain_graph = batched = None
+    nodiag = None
+    if args.diag_every:
+        nodiag, tim0, _, _ = tube_rate(args, diag_every=0, timing=True)
+        nodiag["particle_kernel_us"] = tim0["particles"][0] / tim0["particles"][1] * 1e3
+        nodiag["roofline_frac"] = pb / (nodiag["particle_kernel_us"] / 1e6) / 1e9 / HBM_PEAK_GBS
+        nodiag["step_algorithmic_frac"] = step_bytes / (nodiag["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS
+        log(f"without diagnostics: {nodiag['value']:.3e} particle-steps/s, {nodiag['ms_per_step']:.4f} ms/step")
+
+    plain = plain_graph = vay = None
     if args.plain_steps > 0:
-        log("plain FP64 leg (eager) ...")
-        plain = plain_leg(args.particles, args.plain_steps, 4, use_graph=0)
-        log(f"plain: {plain['value']:.3e} particle-steps/s ({plain['ms_per_step']:.3f} ms/step)")
-        log("plain FP64 leg (graphs) ...")
-        plain_graph = plain_leg(args.particles, args.plain_steps, 4, use_graph=1)
-        log(f"plain, graphs: {plain_graph['value']:.3e} particle-steps/s ({plain_graph['ms_per_step']:.3f} ms/step)")
-    vay = None
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps = args.plain_steps
+        a2.warmup = 4
+        # the FP64 reference of the speedup: the same pipeline in FP64, one
+        # instance, launched eagerly; both sides without diagnostic steps
+        plain, _, _, _ = tube_rate(a2, precision=axp.PREC_PLAIN_FP64, use_graph=0, diag_every=0)
+        plain_graph, _, _, _ = tube_rate(a2, precision=axp.PREC_PLAIN_FP64, use_graph=1, diag_every=0)
+        log(f"fp64 step: {plain['value']:.3e} (eager), {plain_graph['value']:.3e} (graphs) particle-steps/s")
     if args.vay_steps > 0:
-        log("Vay pusher leg ...")
-        vay = vay_leg(args.particles, args.vay_steps, 4)
-        log(f"vay: {vay['value']:.3e} particle-steps/s ({vay['ms_per_step']:.3f} ms/step)")
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps = args.vay_steps
+        a2.warmup = 4
+        vay, _, _, _ = tube_rate(a2, pusher=axp.PUSH_VAY, diag_every=args.diag_every)
+        log(f"vay: {vay['value']:.3e} particle-steps/s")
+
+    cavity = diode = batched = small = None
+    if not args.no_cavity:
+        cavity = cavity_leg(axp)
+        log(f"cavity: mixed {cavity['mixed']['ms_per_step']:.4f} ms/step, fp64 {cavity['plain_fp64']['ms_per_step']:.4f}")
+    if not args.no_diode:
+        diode = diode_leg(axp)
+        log(f"diode: {diode['particle_steps_per_s']:.3e} particle-steps/s, {diode['ms_per_step']:.4f} ms/step")
+    if args.small_members > 0:
+        small = small_pool_leg(axp, args.small_members)
+        log(f"small pool: gain {small['gain']:.2f}x ({small['one_by_one_ms_per_step']:.3f} -> "
+            f"{small['pooled_ms_per_step']:.3f} ms/step)")
     if args.batch_variants > 0:
-        log("batched leg ...")
-        batched = batched_leg(args.batch_variants, args.batch_steps)
+        batched = batched_leg(axp, args.batch_variants, args.batch_steps, diag_every=args.diag_every)
         log(f"batched: {batched['value']:.3e} particle-steps/s ({batched['ms_per_step']:.3f} ms/step)")
 
-    cpu = None
+    cpu = cpu1 = cav_cpu = dio_cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(args.cpu_seconds)
-        log(f"cpu baseline: {cpu['value']:.3e} particle-steps/s")
+        cpu = _cpu_leg("tube", True, args.cpu_seconds)
+        cpu1 = _cpu_leg("tube", False, args.cpu_seconds)
+        if cavity is not None:
+            cav_cpu = {"openmp": _cpu_leg("cavity", True, 0), "one_thread": _cpu_leg("cavity", False, 0)}
+            ref = cav_cpu["one_thread"] or cav_cpu["openmp"]
+            if ref:
+                Eo, Bo = np.array(ref.pop("E")), np.array(ref.pop("B"))
+                for k in ("mixed", "plain_fp64"):
+                    E, B = cavity[k].pop("_EB")
+                    cavity[k]["E_rel_l2_vs_oracle"] = float(np.linalg.norm(E - Eo) / np.linalg.norm(Eo))
+                    cavity[k]["B_rel_l2_vs_oracle"] = float(np.linalg.norm(B - Bo) / np.linalg.norm(Bo))
+            for v in cav_cpu.values():
+                if v:
+                    v.pop("E", None)
+                    v.pop("B", None)
+        if diode is not None:
+            dio_cpu = {"openmp": _cpu_leg("diode", True, args.cpu_seconds),
+                       "one_thread": _cpu_leg("diode", False, args.cpu_seconds)}
+        log(f"cpu baseline (oracle): {cpu['value'] if cpu else float('nan'):.3e} particle-steps/s")
+    if cavity is not None:
+        for k in ("mixed", "plain_fp64"):
+            cavity[k].pop("_EB", None)
 
     out = {
         "metric": "particle-steps/s + field HBM GB/s at 1 GPU; batched-mixed vs plain at fixed error",
-        "value": value,
+        "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+i64",
         "data": "synthetic (seeded mesh, beam and fields)",
-        "config": {"workload": desc, "faces": n2, "edges": n1, "particles": int(n_live),
-                   "precision": "mixed", "sort_period": sort_period},
-        "field_dof_steps_per_s": (n1 + n2) * args.steps / el,
-        "timing": "value and ms_per_step: wall clock of the timed steps, replayed from HIP graphs; kernel durations "
-                  "(phase_us_*, roofline): HIP events around every phase over the same number of steps right after, "
-                  f"launched eagerly ({el_events * 1e3 / args.steps:.4f} ms/step with the events)",
+        "config": {"workload": desc, "faces": n2, "edges": n1, "particles": n_live, "precision": "mixed",
+                   "sort_period": head["sort_period"], "diag_every": args.diag_every},
+        "field_dof_steps_per_s": head["field_dof_steps_per_s"],
+        "timing": "value and ms_per_step: wall clock of the timed steps, replayed from HIP graphs, diagnostics "
+                  f"every {args.diag_every} step(s) inside them; kernel durations (phase_us_*, roofline): HIP events "
+                  "around every phase over the same number of steps right after, launched eagerly "
+                  f"({head['ms_per_step_events']:.4f} ms/step with the events)",
         "field_hbm_gbs": field_gbs,
-        "phase_us_per_launch": per_phase,
-        "phase_us_per_step": {k: round(v[0] / args.steps * 1e3, 2) for k, v in tim.items() if v[1]},
+        "field_bytes_per_step": fb,
+        "step_algorithmic_gbs": step_bytes / (head["ms_per_step"] / 1e3) / 1e9,
+        "step_algorithmic_frac": step_bytes / (head["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "phase_us_per_launch": per_launch,
+        "phase_us_per_step": per_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_particles", "bytes_per_launch": pb,
-                     "avg_launch_us": part_avg_s * 1e6,
+                     "kernel": "k_particles" + ("<diag>" if args.diag_every else ""), "bytes_per_launch": pb,
+                     "bytes_model": "48 B per particle + 40 B per face", "avg_launch_us": part_s * 1e6,
                      "kernel_source_sha256_16": kernel_source_hash()},
+        "no_diagnostics": nodiag,
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
         "plain_fp64": plain,
         "plain_fp64_graphs": plain_graph,
         "pusher_vay": vay,
+        "cavity": {"gpu": cavity, "oracle": cav_cpu} if cavity is not None else None,
+        "diode": {"gpu": diode, "oracle": dio_cpu} if diode is not None else None,
+        "small_member_pool": small,
         "batched_mixed": batched,
-        "speedup_mixed_vs_plain": (value / plain["value"]) if plain else None,
-        "speedup_batched_mixed_vs_plain": (batched["value"] / plain["value"]) if (plain and batched) else None,
-        "speedup_mixed_vs_plain_graphs": (value / plain_graph["value"]) if plain_graph else None,
+        "speedup_mixed_vs_plain": ((nodiag or head)["value"] / plain["value"]) if plain else None,
+        "speedup_mixed_vs_plain_graphs": ((nodiag or head)["value"] / plain_graph["value"]) if plain_graph else None,
+        "speedup_note": "mixed and FP64 steps of the tube without diagnostic steps, both at rel-L2 <= 1e-5 against "
+                        "the oracle (cavity leg: mixed and FP64 field errors after 1,000 steps)",
     }
     print(json.dumps(out), flush=True)
 

@@ -506,7 +506,10 @@ axp_status axp_autotune(axp_ctx *ctx, int32_t trial_steps, int32_t *sort_period)
  * contexts are borrowed and must outlive the batch; their own state is
  * stale until axp_batch_sync copies the pooled state back (after which the
  * per-context getters and axp_diag_get see it).  Every member's result is
- * the same, bit for bit, as stepping that context alone. */
+ * the same, bit for bit, as stepping that context alone.  The members must
+ * share their diagnostic cadence (cfg.diag_every, else AXP_E_ARG); the pool's
+ * diagnostic steps evaluate all members together (residual maxima over them,
+ * charges and energies summed). */
 axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out);
 axp_status axp_batch_step(axp_batch *b, int32_t n_steps);
 axp_status axp_batch_sync(axp_batch *b);

@@ -31,24 +31,44 @@ _LIB = os.path.join(_HERE, "_build", "liboracle_pic.so")
 TWO_PI = 2.0 * np.pi
 
 
-def build_oracle(force: bool = False) -> str:
-    """Compile pic_step.c with gcc (plain -O2, FP64, single thread)."""
-    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+_LIB_OMP = os.path.join(_HERE, "_build", "liboracle_pic_omp.so")
+
+
+def build_oracle(force: bool = False, openmp: bool = False) -> str:
+    """Compile pic_step.c with gcc, FP64 without value-changing
+    optimisations: -O3 single thread, or -O3 -fopenmp for timing (particles
+    split statically over the threads, per-thread buffers added in thread
+    order)."""
+    lib = _LIB_OMP if openmp else _LIB
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + f".tmp{os.getpid()}"
+        flags = ["-fopenmp"] if openmp else []
+        subprocess.run(["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", *flags,
                         "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
 
 
+def use_openmp(on: bool = True):
+    """Selects the OpenMP build of the step for this process (timing of the
+    oracle on several cores); must precede the first step."""
+    global _OPENMP
+    if _lib is not None and bool(on) != _OPENMP:
+        raise RuntimeError("the oracle library is already loaded")
+    _OPENMP = bool(on)
+
+
+_OPENMP = False
+
+
 def _load():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build_oracle())
+        _lib = C.CDLL(build_oracle(openmp=_OPENMP))
         vp = C.c_void_p
         _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp, vp] + [vp] * 9
         _lib.oracle_step.restype = None
@@ -59,7 +79,13 @@ def _load():
         _lib.oracle_boris.argtypes = [vp, vp, vp, C.c_double]
         _lib.oracle_vay.argtypes = [vp, vp, vp, C.c_double]
         _lib.oracle_move.argtypes = [C.c_double, C.c_double, vp, C.c_double, vp, vp]
+        _lib.oracle_threads.restype = C.c_int
     return _lib
+
+
+def oracle_threads() -> int:
+    """Threads of the loaded oracle step (1 for the serial build)."""
+    return int(_load().oracle_threads())
 
 
 class _OMesh(C.Structure):

@@ -26,7 +26,11 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define O_PEC 1
 #define O_AXIS 2
@@ -330,29 +334,79 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher
         for (int64_t t = 0; t < m->n2; ++t) wb += Bh[t] * m->H[t] * B[t];
     memset(J, 0, sizeof(double) * m->n1);
 
-    /* 2-4. gather, push, scatter */
-    for (int64_t p = 0; p < P->n; ++p) {
-        if (!P->alive[p]) continue;
-        int64_t t = P->tri[p];
-        int64_t sp = P->species[p];
-        double lam[3], e2[2];
-        bary(m, t, P->z[p], P->rho[p], lam);
-        gather_E(m, t, lam, E, e2);
-        double bphi = 0.5 * (B[t] + Bh[t]) / tri_area(m, t);
-        double Ev[3] = {e2[1], 0.0, e2[0]};          /* (E_rho, E_phi, E_z) */
-        double Bv[3] = {0.0, bphi, bz};               /* (B_rho, B_phi, B_z) */
-        double *u = P->u + 3 * p;
-        /* m w c^2 / (2 pi) of the macro-particle: m w = (q w) / (q / m) */
-        double mwc2 = P->sp_qw[sp] / P->sp_qm[sp] * O_C * O_C / O_TWO_PI;
-        if (energy) k_old += mwc2 * gamma_m1(u);
-        if (pusher == 1) oracle_vay(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
-        else oracle_boris(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
-        if (energy) k_new += mwc2 * gamma_m1(u);
-        double ze, re;
-        oracle_move(P->z[p], P->rho[p], u, dt, &ze, &re);
-        double q_ring = P->sp_qw[sp] / O_TWO_PI;
-        int nseg = walk(m, P, p, ze, re, q_ring / dt, q_ring, J, Qres, stats);
-        if (nseg > 0) stats[0] += nseg;
+    /* 2-4. gather, push, scatter.  Built with OpenMP (the timing form of the
+     *     oracle) the particles are split statically over the threads, each
+     *     with its own current, wall charge, counters and energy sums, added up
+     *     in thread order afterwards: for a given thread count the result does
+     *     not depend on scheduling, and with one thread it is the serial loop. */
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    double *Jt = J, *Qt = Qres, *Kt = NULL;
+    int64_t *St = stats;
+    if (nth > 1) {
+        Jt = (double *)calloc((size_t)nth * m->n1, sizeof(double));
+        Qt = (double *)calloc((size_t)nth * m->n0, sizeof(double));
+        St = (int64_t *)calloc((size_t)nth * 3, sizeof(int64_t));
+    }
+    Kt = (double *)calloc((size_t)nth * 2, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nth)
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *Jl = nth > 1 ? Jt + (size_t)tid * m->n1 : J;
+        double *Ql = nth > 1 ? Qt + (size_t)tid * m->n0 : Qres;
+        int64_t *Sl = nth > 1 ? St + 3 * tid : stats;
+        double kol = 0.0, knl = 0.0;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t p = 0; p < P->n; ++p) {
+            if (!P->alive[p]) continue;
+            int64_t t = P->tri[p];
+            int64_t sp = P->species[p];
+            double lam[3], e2[2];
+            bary(m, t, P->z[p], P->rho[p], lam);
+            gather_E(m, t, lam, E, e2);
+            double bphi = 0.5 * (B[t] + Bh[t]) / tri_area(m, t);
+            double Ev[3] = {e2[1], 0.0, e2[0]};          /* (E_rho, E_phi, E_z) */
+            double Bv[3] = {0.0, bphi, bz};               /* (B_rho, B_phi, B_z) */
+            double *u = P->u + 3 * p;
+            /* m w c^2 / (2 pi) of the macro-particle: m w = (q w) / (q / m) */
+            double mwc2 = P->sp_qw[sp] / P->sp_qm[sp] * O_C * O_C / O_TWO_PI;
+            if (energy) kol += mwc2 * gamma_m1(u);
+            if (pusher == 1) oracle_vay(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
+            else oracle_boris(u, Ev, Bv, P->sp_qm[sp] * dt * 0.5);
+            if (energy) knl += mwc2 * gamma_m1(u);
+            double ze, re;
+            oracle_move(P->z[p], P->rho[p], u, dt, &ze, &re);
+            double q_ring = P->sp_qw[sp] / O_TWO_PI;
+            int nseg = walk(m, P, p, ze, re, q_ring / dt, q_ring, Jl, Ql, Sl);
+            if (nseg > 0) Sl[0] += nseg;
+        }
+        Kt[2 * tid] = kol;
+        Kt[2 * tid + 1] = knl;
+    }
+    for (int th = 0; th < nth; ++th) {
+        k_old += Kt[2 * th];
+        k_new += Kt[2 * th + 1];
+    }
+    free(Kt);
+    if (nth > 1) {
+        for (int th = 0; th < nth; ++th) {
+            const double *Jl = Jt + (size_t)th * m->n1, *Ql = Qt + (size_t)th * m->n0;
+            for (int64_t e = 0; e < m->n1; ++e) J[e] += Jl[e];
+            for (int64_t v = 0; v < m->n0; ++v) Qres[v] += Ql[v];
+            for (int k = 0; k < 3; ++k) stats[k] += St[3 * th + k];
+        }
+        free(Jt);
+        free(Qt);
+        free(St);
     }
 
     /* 5. Ampere: rhs = C^T H B^{n+1/2} - J on free edges; in the absorbing
@@ -427,6 +481,16 @@ void oracle_step(const omesh *m, oparticles *P, double dt, double bz, int pusher
         energy[2] = 0.5 * (k_old + k_new);
         energy[3] = k_new;
     }
+}
+
+/* threads the step uses (1 without OpenMP) */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Nodal charge, eq. (charge): Q_v = sum_p (q/2pi) lam_v(r_p) + Qres_v */

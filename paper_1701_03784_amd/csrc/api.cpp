@@ -53,6 +53,7 @@ struct axp_ctx {
     int64_t step = 0;
     int64_t last_eval_level = -1;  // time level of the last diagnostic evaluation enqueued (-1: none)
     int64_t energy_read = 0;       // energy records already returned by axp_get_energies
+    bool q32 = true;               // every species' charge multiple is 0 or 1 (all members of a pool)
     int64_t n_live_host = 0;
     // continuous injector
     bool inj_on = false;
@@ -600,7 +601,7 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
         PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
-        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, diag, st);
+        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, diag, c->q32, st);
     }
     { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, diag, st); }
     {
@@ -1067,6 +1068,7 @@ axp_status axp_add_species(axp_ctx *c, double q, double m, int64_t weight, int32
         ic.qe[sp] = float(q * c->dt / (2.0 * m * kC));
         ic.qb[sp] = float(q * c->dt / (2.0 * m));
         ic.kq[sp] = int32_t(std::nearbyint(k));
+        if (ic.kq[sp] != 0 && ic.kq[sp] != 1) c->q32 = false;
         ic.mw[sp] = m * double(weight) * kC * kC / kTwoPi;
         ic.jscale = c->q_unit / (kTwoPi * double(kLamOne) * double(kLamOne));   // current unit 2^-46
         ic.qscale = c->q_unit / (kTwoPi * double(kLamOne));                    // charge unit 2^-23
@@ -1802,15 +1804,19 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
         if (c->fs.n_src > 0 || c->fs.probe_face >= 0)
             return fail(c, AXP_E_ARG, "batch members cannot carry point sources or a probe");
         if (c->dl.n) return fail(c, AXP_E_ARG, "batch members cannot carry absorbing layers");
+        if (c->cfg.diag_every != ctxs[0]->cfg.diag_every)
+            return fail(c, AXP_E_ARG, "batch members must share a diagnostic cadence");
     }
+    bool q32 = true;
+    for (int k = 0; k < n; ++k) q32 = q32 && ctxs[k]->q32;
     auto *b = new (std::nothrow) axp_batch();
     if (!b) return AXP_E_OOM;
     auto *p = new (std::nothrow) axp_ctx();
     if (!p) { delete b; return AXP_E_OOM; }
     b->pool = p;
     b->ctxs.assign(ctxs, ctxs + n);
-    p->cfg = ctxs[0]->cfg;
-    p->cfg.diag_every = 0;
+    p->cfg = ctxs[0]->cfg;      // diagnostic steps of the pool evaluate all members together
+    p->q32 = q32;
     p->stream = ctxs[0]->stream;
     const axp_status st = guarded(p, [&]() -> axp_status {
         hcheck(hipSetDevice(p->cfg.device), "hipSetDevice");

@@ -223,8 +223,9 @@ void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const De
 void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const DevLayers &lay, hipStream_t st);
 void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st);
 // gather, push and walk of every particle, with the charge-conserving current
+// (q32: every charge multiple is 0 or 1; the single case implies it)
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
-                      bool diag, hipStream_t st);
+                      bool diag, bool q32, hipStream_t st);
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, bool diag, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);

@@ -121,11 +121,13 @@ __device__ __forceinline__ DiagVals block_reduce_diag(const DiagVals &v) {
     return r;
 }
 
-__device__ __forceinline__ void store_partials(double *out, const DiagVals &r) {
+// Stores a block's partials slot-major (slot k of block b at k * nb + b), so
+// the final reduction reads each slot with coalesced loads.
+__device__ __forceinline__ void store_partials(double *part, int b, int nb, const DiagVals &r) {
 #pragma unroll
-    for (int k = 0; k < kDiagSums; ++k) out[k] = r.sum[k];
+    for (int k = 0; k < kDiagSums; ++k) part[(size_t)k * nb + b] = r.sum[k];
 #pragma unroll
-    for (int k = 0; k < kDiagMaxes; ++k) out[kDiagSums + k] = __longlong_as_double((long long)r.mx[k]);
+    for (int k = 0; k < kDiagMaxes; ++k) part[(size_t)(kDiagSums + k) * nb + b] = __longlong_as_double((long long)r.mx[k]);
 }
 
 }  // namespace axp

@@ -668,7 +668,10 @@ __device__ __forceinline__ double kin_sum(const DevMesh &m, const PushConst &k0,
     return v;
 }
 
-template <bool SINGLE, bool VAY, bool DIAG>
+// Q32: every species' charge multiple is 0 or 1, so the end-position charge
+// of a diagnostic step accumulates in 32-bit LDS words (always so in the
+// single case).
+template <bool SINGLE, bool VAY, bool DIAG, bool Q32>
 __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
                                                                PushConst k0) {
     __shared__ int s_nmv;
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
     __shared__ Mover s_mv[kQCap];
     // diagnostic steps: the end positions' charge window, per wave the
     // kinetic energy and live count, the block's absorbed count
-    using QA = typename std::conditional<SINGLE, unsigned, unsigned long long>::type;
+    using QA = typename std::conditional<SINGLE || Q32, unsigned, unsigned long long>::type;
     __shared__ QA s_ql[DIAG ? 3 * kWin : 1];
     __shared__ double s_wk[kWG / 64];
     __shared__ int s_nl[kWG / 64];
@@ -1248,7 +1251,7 @@ __global__ __launch_bounds__(256) void k_node_diag(DevMesh m, DevState s, int in
     if (i < m.n1) v.sum[1] = 0.5 * (double)s.E[i] * s.D[i];
     fold_slices(s, v, in_step, nb_face, nb_edge);
     const DiagVals r = block_reduce_diag(v);
-    if (threadIdx.x == 0) store_partials(s.part_node + (size_t)kDiagSlots * blockIdx.x, r);
+    if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, gridDim.x, r);
 }
 
 // Reduces the node-pass partials of an evaluation at level n = ctr->step in
@@ -1260,34 +1263,47 @@ constexpr int kFinalThreads = 64 * kDiagSlots;      // one wave per slot
 
 __global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb_node, int in_step, int plain) {
     __shared__ double res[kDiagSlots];
+    __shared__ unsigned long long cur[7];     // the counters and running values thread 0 updates
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;   // wave w reduces slot w over the node-pass blocks
+    if (w == kDiagSlots - 1 && l < 7) {       // fetched in parallel, overlapping the reduction
+        const unsigned long long *src[7] = {&s.ctr->step, &s.ctr->diag_level1, &s.ctr->energy_count,
+                                            &s.diag->gauss_drift_max_bits, &s.diag->dce_max,
+                                            &s.diag->dce_rel_max_bits, &s.diag->n_evals};
+        cur[l] = *src[l];
+    }
+    const double *p = s.part_node + (size_t)w * nb_node;   // slot w of every node-pass block
+    // four independent accumulators per lane (loads in flight together), combined in order
     if (w < kDiagSums) {
-        double x = 0.0;
-        for (int b = l; b < nb_node; b += 64) x += s.part_node[(size_t)kDiagSlots * b + w];
-        x = wave_sum64d(x);
-        if (l == 0) res[w] = x;
+        double x[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = l; b < nb_node; b += 256)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + 64 * q < nb_node) x[q] += p[b + 64 * q];
+        const double t = wave_sum64d(((x[0] + x[1]) + x[2]) + x[3]);
+        if (l == 0) res[w] = t;
     } else if (w < kDiagSums + kDiagMaxes) {
         unsigned long long x = 0;
-        for (int b = l; b < nb_node; b += 64) {
-            const unsigned long long y = dbits(s.part_node[(size_t)kDiagSlots * b + w]);
-            x = y > x ? y : x;
-        }
+        for (int b = l; b < nb_node; b += 256)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + 64 * q < nb_node) {
+                    const unsigned long long y = dbits(p[b + 64 * q]);
+                    x = y > x ? y : x;
+                }
         x = wave_max64(x);
         if (l == 0) res[w] = __longlong_as_double((long long)x);
     }
     __syncthreads();
-    DiagVals r{};
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < kDiagSums; ++k) r.sum[k] = res[k];
-#pragma unroll
-        for (int k = 0; k < kDiagMaxes; ++k) r.mx[k] = dbits(res[kDiagSums + k]);
-    }
     if (threadIdx.x != 0) return;
+    DiagVals r{};
+#pragma unroll
+    for (int k = 0; k < kDiagSums; ++k) r.sum[k] = res[k];
+#pragma unroll
+    for (int k = 0; k < kDiagMaxes; ++k) r.mx[k] = dbits(res[kDiagSums + k]);
     DevCounters &ctr = *s.ctr;
     DevDiag &d = *s.diag;
-    const unsigned long long n = ctr.step;
-    const bool have_prev = ctr.diag_level1 == n && n > 0;
+    const unsigned long long n = cur[0];
+    const bool have_prev = cur[1] == n && n > 0;
     d.level = (long long)n;
     d.n_live = (long long)r.sum[kSumLiveNow];
     d.q_total = r.sum[kSumQ];
@@ -1296,19 +1312,19 @@ __global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb
     d.gauss_scale = __longlong_as_double((long long)r.mx[2]);
     const double qmax = __longlong_as_double((long long)r.mx[4]);
     d.qmax = qmax;
-    if (r.mx[0] > d.gauss_drift_max_bits) d.gauss_drift_max_bits = r.mx[0];
+    if (r.mx[0] > cur[3]) d.gauss_drift_max_bits = r.mx[0];
     if (have_prev) {
         const unsigned long long x = r.mx[3];
         d.dce_last = (long long)x;
-        if (x > d.dce_max) d.dce_max = x;
+        if (x > cur[4]) d.dce_max = x;
         if (plain) {
             const double rel = __longlong_as_double((long long)x) / (qmax > 0.0 ? qmax : 1.0);
-            if (dbits(rel) > d.dce_rel_max_bits) d.dce_rel_max_bits = dbits(rel);
+            if (dbits(rel) > cur[5]) d.dce_rel_max_bits = dbits(rel);
         }
     } else {
         d.dce_last = -1;
     }
-    d.n_evals += 1;
+    d.n_evals = cur[6] + 1;
     if (in_step) {
         DevEnergy e;
         e.level = (long long)n - 1;
@@ -1317,8 +1333,8 @@ __global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb
         e.WB = r.sum[kSumWB];
         e.WK = r.sum[kSumWK];
         e.Qtot = 0.0;
-        s.energy[ctr.energy_count % kEnergyRing] = e;
-        ctr.energy_count += 1;
+        s.energy[cur[2] % kEnergyRing] = e;
+        ctr.energy_count = cur[2] + 1;
         d.energy = e;
     }
     ctr.diag_level1 = n + 1;
@@ -1399,24 +1415,26 @@ void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const De
 // per-particle table lookup.
 template <bool SINGLE, bool VAY>
 static void launch_particles_t(const DevMesh &m, DevState &s, int max_walk, int dc, PushConst k0, bool diag,
-                               dim3 grid, hipStream_t st) {
-    if (diag) hipLaunchKernelGGL((k_particles<SINGLE, VAY, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
-    else hipLaunchKernelGGL((k_particles<SINGLE, VAY, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+                               bool q32, dim3 grid, hipStream_t st) {
+    if (!diag) hipLaunchKernelGGL((k_particles<SINGLE, VAY, false, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+    else if (SINGLE || q32)
+        hipLaunchKernelGGL((k_particles<SINGLE, VAY, true, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+    else hipLaunchKernelGGL((k_particles<SINGLE, VAY, true, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
 }
 
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
-                      bool diag, hipStream_t st) {
+                      bool diag, bool q32, hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nblk(s.capacity, kChunk));
     const int dc = count ? 1 : 0;
     if (single) {
         const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1, 1.0f};
-        if (vay) launch_particles_t<true, true>(m, s, max_walk, dc, k0, diag, grid, st);
-        else launch_particles_t<true, false>(m, s, max_walk, dc, k0, diag, grid, st);
+        if (vay) launch_particles_t<true, true>(m, s, max_walk, dc, k0, diag, true, grid, st);
+        else launch_particles_t<true, false>(m, s, max_walk, dc, k0, diag, true, grid, st);
     } else {
         const PushConst k0{0.f, 0.f, 0.f, 0.f, 1, 1.0f};
-        if (vay) launch_particles_t<false, true>(m, s, max_walk, dc, k0, diag, grid, st);
-        else launch_particles_t<false, false>(m, s, max_walk, dc, k0, diag, grid, st);
+        if (vay) launch_particles_t<false, true>(m, s, max_walk, dc, k0, diag, q32, grid, st);
+        else launch_particles_t<false, false>(m, s, max_walk, dc, k0, diag, q32, grid, st);
     }
 }
 

@@ -686,7 +686,7 @@ __global__ __launch_bounds__(256) void k_node_diag_d(DevMesh m, DevState s, DevP
     if (v < m.n1) d.sum[kSumWEnow] = 0.5 * p.E[v] * s.D[v];
     fold_slices(s, d, in_step, nb_face, nb_edge);
     const DiagVals r = block_reduce_diag(d);
-    if (threadIdx.x == 0) store_partials(s.part_node + (size_t)kDiagSlots * blockIdx.x, r);
+    if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, gridDim.x, r);
 }
 
 // emission: as the mixed step, with FP64 coordinates and wall charge

@@ -120,6 +120,34 @@ def test_batch_matches_members_run_alone(axp):
     b.close()
 
 
+def test_batch_with_diagnostic_steps_matches_members_alone(axp):
+    """Members with a diagnostic step every step, pooled (the pool's
+    diagnostic steps take the 32-bit charge window of single-charge species):
+    the state after 24 steps equals each member stepped alone, with exact
+    continuity, and a pool refuses members of different cadences."""
+    print("[gpu] batch with diagnostics vs alone", flush=True)
+
+    def members():
+        return [_cavity_member(axp, diag_every=1), _cavity_member(axp, n_part=2000, seed=12, diag_every=1),
+                _tube_member(axp, diag_every=1)]
+
+    alone = members()
+    for c in alone:
+        c.step(24)
+    ref = [_state(c) for c in alone]
+    pooled = members()
+    b = axp.Batch(pooled)
+    b.step(24)
+    b.sync()
+    for k, c in enumerate(pooled):
+        _assert_same(ref[k], _state(c), f"member {k}")
+        d = c.diag()
+        assert d["dce_max_abs"] == 0 and d["walk_overflow"] == 0
+    b.close()
+    with pytest.raises(axp.AxpError):
+        axp.Batch([_cavity_member(axp, diag_every=1), _cavity_member(axp, diag_every=2)])
+
+
 def test_autotune_keeps_results(axp):
     print("[gpu] autotune vs fixed schedule", flush=True)
     a = _tube_member(axp, use_graph=1)
