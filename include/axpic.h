@@ -434,6 +434,31 @@ axp_status axp_mlp_forward(axp_mlp *net, const float *X, int64_t n, float *y);
  * are host outputs and may be NULL (then nothing is synchronised). */
 axp_status axp_mlp_loss_grad(axp_mlp *net, const float *X, const float *y, const float *w, int64_t n, double *loss,
                              float *grad);
+/* Allocation-free variant of axp_mlp_loss_grad, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc.  Same kernels and
+ * arithmetic as axp_mlp_loss_grad, so the same results bit for bit.
+ *   X[n][16], y[n], w[n]   DEVICE inputs (FP32), as for axp_mlp_loss_grad
+ *   loss_dev[2]            DEVICE output (FP64): weighted mean squared error,
+ *                          then the sum of the weights (when that sum is not
+ *                          positive, loss_dev[0] and grad_dev are 0)
+ *   grad_dev[n_params]     DEVICE output (FP32): d loss / d parameters
+ * Enqueued on the network's stream; nothing is synchronised or copied to the
+ * host, and the network's own gradient (the one axp_mlp_adam_step uses) is
+ * left as it was.  No device or host memory is allocated: the intermediate
+ * activations, deltas and partial sums live in one static device array of
+ * 32 MiB per device (held until the process ends), which a call of n samples
+ * uses as 256-byte aligned pieces of 8 L H n, 4 n, 4 n, 16 ceil(n/256) and
+ * 4 n_params ceil(n/512) bytes (L hidden layers of width H); at most
+ * 31,234 samples at H = 64, L = 2 and 15,497 at H = 64, L = 4.  A call needing
+ * more returns AXP_E_ARG before any launch (axp_mlp_last_error gives the
+ * size).  Every byte a call reads from the array it has written first, but
+ * all calls on one device share the array: calls that may overlap on one
+ * device (other streams, other threads, other networks) race and must be
+ * ordered by the caller.  AXP_E_ARG for null pointers or n < 1; AXP_E_HIP if
+ * the launch fails. */
+axp_status axp_mlp_loss_grad_noalloc(axp_mlp *net, const float *X, const float *y, const float *w, int64_t n,
+                                     double *loss_dev, float *grad_dev);
 /* One Adam step (bias-corrected) with the gradient of the last loss_grad call. */
 axp_status axp_mlp_adam_step(axp_mlp *net, double lr, double beta1, double beta2, double eps);
 axp_status axp_mlp_info(const axp_mlp *net, int32_t *n_in, int32_t *n_hidden, int32_t *n_layers, int32_t *spai_level,

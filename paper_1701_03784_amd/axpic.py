@@ -80,7 +80,7 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_batch_destroy", "axp_set_timing", "axp_get_timing", "axp_autotune", "axp_batch_autotune",
            "axp_batch_set_timing", "axp_batch_get_timing", "axp_batch_info", "axp_batch_last_error",
            "axp_mlp_create", "axp_mlp_n_params", "axp_mlp_set_params", "axp_mlp_get_params", "axp_mlp_forward",
-           "axp_mlp_loss_grad", "axp_mlp_adam_step", "axp_mlp_info", "axp_mlp_save", "axp_mlp_load",
+           "axp_mlp_loss_grad", "axp_mlp_loss_grad_noalloc", "axp_mlp_adam_step", "axp_mlp_info", "axp_mlp_save", "axp_mlp_load",
            "axp_mlp_last_error", "axp_mlp_destroy", "axp_set_spai_model", "axp_spai_pairs",
            "axp_spai_model_load", "axp_spai_model_train"]
 PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject", "walk"]
@@ -152,6 +152,7 @@ def load_library(path: str = LIB_PATH):
         "axp_mlp_get_params": (i32, [vp, vp]),
         "axp_mlp_forward": (i32, [vp, vp, i64, vp]),
         "axp_mlp_loss_grad": (i32, [vp, vp, vp, vp, i64, C.POINTER(dbl), vp]),
+        "axp_mlp_loss_grad_noalloc": (i32, [vp, vp, vp, vp, i64, vp, vp]),
         "axp_mlp_adam_step": (i32, [vp, dbl, dbl, dbl, dbl]),
         "axp_mlp_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]),
         "axp_mlp_save": (i32, [vp, C.c_char_p]),
@@ -486,16 +487,17 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def _check_dev(name, t, device, shape):
+def _check_dev(name, t, device, shape, dtype="float32"):
     """Rejects what the network kernels cannot read: host or other-device
-    tensors, dtypes other than float32, non-contiguous views, wrong shapes."""
+    tensors, other dtypes (float32 unless stated), non-contiguous views,
+    wrong shapes."""
     import torch
     if not isinstance(t, torch.Tensor):
         raise ValueError(f"{name}: a torch tensor is required")
     if not t.is_cuda or t.device.index != device:
         raise ValueError(f"{name}: must live on cuda:{device} (got {t.device})")
-    if t.dtype != torch.float32:
-        raise ValueError(f"{name}: float32 required (got {t.dtype})")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name}: {dtype} required (got {t.dtype})")
     if not t.is_contiguous():
         raise ValueError(f"{name}: must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -577,6 +579,22 @@ class Mlp:
         self._check(self.lib.axp_mlp_loss_grad(self.h, _dptr(X), _dptr(y), _dptr(w), n, C.byref(loss),
                                                _ptr(g)))
         return (loss.value, g) if want_grad else loss.value
+
+    def loss_grad_noalloc(self, X, y, w, loss_out, grad_out):
+        """Allocation-free loss and gradient (axp_mlp_loss_grad_noalloc):
+        X (n, n_in), y and w (n,) float32, loss_out (2,) float64 and
+        grad_out (n_params,) float32, all contiguous on the network's device.
+        Enqueued on the network's stream; nothing is synchronised."""
+        for name, t in (("X", X), ("y", y), ("w", w), ("grad_out", grad_out)):
+            _check_dev(name, t, self.device, None)
+        _check_dev("loss_out", loss_out, self.device, (2,), dtype="float64")
+        n = int(X.shape[0]) if X.dim() == 2 else -1
+        _check_dev("X", X, self.device, (n, self._n_in()))
+        _check_dev("y", y, self.device, (n,))
+        _check_dev("w", w, self.device, (n,))
+        _check_dev("grad_out", grad_out, self.device, (self.n_params(),))
+        self._check(self.lib.axp_mlp_loss_grad_noalloc(self.h, _dptr(X), _dptr(y), _dptr(w), n, _dptr(loss_out),
+                                                       _dptr(grad_out)))
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self._check(self.lib.axp_mlp_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))

@@ -28,6 +28,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpWG = 256;
+static_assert(kMlpWG == kMlpLossBlock, "one loss partial per workgroup");
 
 template <int NIN, int H>
 __device__ __forceinline__ int out_offset(int L) {

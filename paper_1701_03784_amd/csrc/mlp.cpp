@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -24,6 +25,7 @@ struct axp_mlp {
     float *params = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     double *loss = nullptr;
     MlpScratch k;
+    void *static_scratch = nullptr;   // this device's copy of `scratch` (device address)
     int64_t t = 0;            // Adam steps taken
     std::string err;
 };
@@ -51,7 +53,7 @@ int ensure_scratch(axp_mlp *net, int64_t n) {
     if (n <= net->k.cap) return AXP_OK;
     free_scratch(net->k);
     const int64_t cap = std::max<int64_t>(n, 1024);
-    const int64_t nb = (cap + 255) / 256, nc = (cap + kMlpChunk - 1) / kMlpChunk;
+    const int64_t nb = (cap + kMlpLossBlock - 1) / kMlpLossBlock, nc = (cap + kMlpChunk - 1) / kMlpChunk;
     MlpScratch &k = net->k;
     const size_t ah = sizeof(float) * size_t(net->s.L) * size_t(cap) * size_t(net->s.H);
     MLP_HIP(net, hipMalloc(&k.act, ah), "hipMalloc");
@@ -65,6 +67,60 @@ int ensure_scratch(axp_mlp *net, int64_t n) {
 }
 
 const char kMagic[8] = {'A', 'X', 'P', 'M', 'L', 'P', '1', '\0'};
+
+// ---- static scratch of axp_mlp_loss_grad_noalloc
+// One array per device, held until the process ends.  In host code
+// `scratch` only stands for the symbol: its device address on a given device
+// comes from hipGetSymbolAddress with that device current, done once per
+// device when the first network is created there.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// The calling thread's current device must be net->device.
+int resolve_static_scratch(axp_mlp *net) {
+    if (net->device >= kMaxDevices) {
+        net->err = "device ordinal beyond the static-scratch table";
+        return AXP_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[net->device]) {
+        void *p = nullptr;
+        MLP_HIP(net, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) {
+            net->err = "hipGetSymbolAddress(scratch) returned a null address";
+            return AXP_E_HIP;
+        }
+        g_scratch_addr[net->device] = p;
+    }
+    net->static_scratch = g_scratch_addr[net->device];
+    return AXP_OK;
+}
+
+// Places the loss/gradient scratch of n samples at base (256-byte aligned
+// pieces, the layout ensure_scratch allocates) and returns the bytes used.
+size_t carve_scratch(const MlpShape &s, int64_t n, unsigned char *base, MlpScratch &k) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = base + off;
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    const size_t nn = size_t(n);
+    const size_t nb = (nn + kMlpLossBlock - 1) / kMlpLossBlock, nc = (nn + kMlpChunk - 1) / kMlpChunk;
+    const size_t ah = sizeof(float) * size_t(s.L) * nn * size_t(s.H);
+    k.cap = n;
+    k.act = reinterpret_cast<float *>(take(ah));
+    k.delta = reinterpret_cast<float *>(take(ah));
+    k.pred = reinterpret_cast<float *>(take(sizeof(float) * nn));
+    k.dout = reinterpret_cast<float *>(take(sizeof(float) * nn));
+    k.loss_part = reinterpret_cast<double *>(take(sizeof(double) * 2 * nb));
+    k.part = reinterpret_cast<float *>(take(sizeof(float) * nc * size_t(s.np)));
+    return off;
+}
 
 }  // namespace
 
@@ -83,6 +139,10 @@ axp_status axp_mlp_create(int32_t device, void *hip_stream, int32_t n_in, int32_
     net->level = spai_level;
     net->s.n_in = n_in; net->s.H = n_hidden; net->s.L = n_layers;
     net->s.np = mlp_param_count(n_in, n_hidden, n_layers);
+    if (resolve_static_scratch(net) != AXP_OK) {
+        axp_mlp_destroy(net);
+        return AXP_E_HIP;
+    }
     const size_t pb = sizeof(float) * net->s.np;
     if (hipMalloc(&net->params, pb) != hipSuccess || hipMalloc(&net->grad, pb) != hipSuccess ||
         hipMalloc(&net->m, pb) != hipSuccess || hipMalloc(&net->v, pb) != hipSuccess ||
@@ -157,6 +217,31 @@ axp_status axp_mlp_loss_grad(axp_mlp *net, const float *X, const float *y, const
         if (loss) *loss = l[0];
         if (!(l[1] > 0)) { net->err = "sum of sample weights is not positive"; return AXP_E_ARG; }
     }
+    return AXP_OK;
+}
+
+axp_status axp_mlp_loss_grad_noalloc(axp_mlp *net, const float *X, const float *y, const float *w, int64_t n,
+                                     double *loss_dev, float *grad_dev) {
+    if (!net || n < 1 || !X || !y || !w || !loss_dev || !grad_dev) return AXP_E_ARG;
+    if (!net->static_scratch) {
+        net->err = "the static scratch of this device was not resolved";
+        return AXP_E_STATE;
+    }
+    // every sample takes more than one byte, so this bound keeps the size arithmetic in range
+    if (n > int64_t(kStaticScratchBytes)) {
+        net->err = "n = " + std::to_string(n) + " samples exceed the " + std::to_string(kStaticScratchBytes) +
+                   "-byte static scratch";
+        return AXP_E_ARG;
+    }
+    MlpScratch k;
+    const size_t need = carve_scratch(net->s, n, static_cast<unsigned char *>(net->static_scratch), k);
+    if (need > kStaticScratchBytes) {
+        net->err = "n = " + std::to_string(n) + " samples need " + std::to_string(need) +
+                   " bytes of scratch; the static scratch holds " + std::to_string(kStaticScratchBytes);
+        return AXP_E_ARG;
+    }
+    launch_mlp_loss_grad(net->s, X, y, w, n, net->params, k, grad_dev, loss_dev, net->stream);
+    MLP_HIP(net, hipGetLastError(), "loss/grad launch");
     return AXP_OK;
 }
 

@@ -7,6 +7,7 @@
 namespace axp {
 
 constexpr int kMlpChunk = 512;     // samples per partial-gradient chunk
+constexpr int kMlpLossBlock = 256; // samples per loss partial (one workgroup)
 
 struct MlpShape {
     int n_in = 16, H = 64, L = 2;  // inputs, hidden width, hidden layers
