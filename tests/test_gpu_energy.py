@@ -8,10 +8,15 @@ test_oracle_energy.py), and evaluates its end level n+1 inside the step's
 kernels: the nodal charge, the Gauss residual's drift (Sec. 3.5.2) and the
 continuity residual (Sec. 3.5.1).
 
-Bounds: the FP64 step matches the oracle's energies to 1e-10 of the field
-energy; the mixed step's fields carry FP32 rounding (rel-L2 <= 1e-5 after
-1,000 steps), which enters an energy twice, so 5e-5 of the field energy and
-2e-5 of the kinetic energy; live counts and the total charge are exact.
+Bounds: the FP64 step matches the oracle's energies to 1e-12 (field
+energies relative to the field energy, W_K relative to itself; measured
+4e-15 and 1e-13).  The mixed step's fields carry FP32 rounding (rel-L2
+<= 1e-5 after 1,000 steps), which enters a quadratic energy as a product of
+two such fields whose errors largely cancel in the sum over edges: 1e-6 of
+the field energy (measured 2e-8).  Its momenta are FP32 and each push adds a
+relative rounding of ~6e-8 that accumulates over the 1,000 steps of a
+particle's life, so W_K is held to 2e-5 (measured 7e-6).  Live counts and
+the total charge are exact.
 Diagnostic steps observe only: the state after them is bit-identical to the
 state after plain steps, and graph replays reproduce eager steps bit for bit.
 The counting sort places the particles of one face in an order that varies
@@ -110,8 +115,8 @@ def test_energy_records_match_oracle(axp, cavity, oracle_run, prec):
     k = (wk > 0) & (diff == 0)           # the same particles pushed in the step
     dwk = (np.abs(r["W_K"][k] - wk[k]) / wk[k]).max()
     print(f"[gpu] {prec}: max |dW_E| {dwe:.2e}, |dW_B| {dwb:.2e} of the field energy; |dW_K| {dwk:.2e}", flush=True)
-    assert dwe <= (1e-10 if tight else 5e-5)
-    assert dwb <= (1e-10 if tight else 5e-5)
+    assert dwe <= (1e-12 if tight else 1e-6)
+    assert dwb <= (1e-12 if tight else 1e-6)
     assert dwk <= (1e-12 if tight else 2e-5)
     assert np.all(r["W_K"][wk == 0] == 0.0)
     # total charge (particles + wall): fixed point keeps it exactly, FP64 to rounding
