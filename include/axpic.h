@@ -94,7 +94,8 @@ enum {
 enum {
     AXP_SPAI_PLAIN = 0,            /* least squares per column (Sec. 3.1) */
     AXP_SPAI_LEARNED = 1,          /* network guess + refinement, least-squares fallback per column */
-    AXP_SPAI_LEARNED_REJECTED = 2  /* learned matrix failed the energy guard: plain SPAI used */
+    AXP_SPAI_LEARNED_REJECTED = 2, /* learned matrix failed the energy guard: plain SPAI used */
+    AXP_SPAI_LEARNED_REVERTED = 3  /* learned matrix tripped the run-time energy guard: plain SPAI since */
 };
 
 typedef struct axp_mlp axp_mlp;
@@ -143,6 +144,11 @@ typedef struct {
     double spai_energy_drift;        /* learned SPAI: relative energy drift of the guard run */
     double spai_seconds;             /* host time of the SPAI construction */
     int64_t n_layer_faces;           /* faces of the absorbing layers (axp_set_layers) */
+    int64_t spai_guard_trip_step;    /* level at which the run-time guard tripped (-1: never) */
+    double spai_run_drift;           /* largest total-energy drift the run-time guard has seen */
+    double spai_feature_seconds;     /* learned SPAI: pair features (host) */
+    double spai_infer_seconds;       /* learned SPAI: network inference (device, copies included) */
+    double spai_solve_seconds;       /* least squares (plain); refinement, fallback and assembly (learned) */
 } axp_info;
 
 typedef struct {
@@ -479,6 +485,28 @@ void axp_mlp_destroy(axp_mlp *net);
  * energy_drift_tol (relative), else the plain SPAI is used
  * (AXP_SPAI_LEARNED_REJECTED).  The network is borrowed during axp_build. */
 axp_status axp_set_spai_model(axp_ctx *ctx, axp_mlp *net, double row_tol, double energy_drift_tol, int32_t iters);
+
+/* Run-time energy guard of the learned SPAI: the plain SPAI (Sec. 3.1) is
+ * the fallback when the run's energy drifts.  Needs a context built with a
+ * learned SPAI that the setup guard kept (AXP_SPAI_LEARNED) and diagnostic
+ * steps (diag_every > 0); AXP_E_STATE otherwise.  drift_tol >= 0 arms the
+ * guard, drift_tol < 0 disarms it.  While armed, axp_step works in chunks of
+ * at most 2048 diagnostic steps: it first copies the state (fields, sources,
+ * particles, counters; on the device, in memory allocated once and grown
+ * with the particle buffers) as the chunk's checkpoint, runs the chunk, and
+ * reads the energy records it produced.  The first record after arming sets
+ * the reference W_ref of the total energy W = W_E + W_B + W_K; when a record
+ * has |W - W_ref| > drift_tol |W_ref|, the context rebuilds M with the plain
+ * SPAI, restores the checkpoint, keeps D (so Gauss's law and the continuity
+ * equation carry over unchanged), sets E = M D with the new M, and runs the
+ * chunk again.  The guard is then off, axp_info reports
+ * AXP_SPAI_LEARNED_REVERTED and the level that tripped it.  Emission and
+ * absorption exchange energy with the outside, so drift_tol must exceed what
+ * the run's physics moves; the guard is meant for the growth of an unstable
+ * M.  AXP_E_UNSTABLE (the state restored to the checkpoint, the learned M
+ * kept) if dt exceeds the plain SPAI's stability limit.  A context with an
+ * armed guard cannot join a batch. */
+axp_status axp_set_spai_run_guard(axp_ctx *ctx, double drift_tol);
 
 /* Loads a network saved by axp_mlp_save or axp_spai_model_train and uses it
  * for this context's SPAI as axp_set_spai_model does, with row_tol 0.01,

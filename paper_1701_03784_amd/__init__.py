@@ -9,5 +9,5 @@ from .axpic import (  # noqa: F401
     Ctx, Batch, Mlp, AxpError, make_ctx, default_spai_model, load_library, EXPORTS, LIB_PATH,
     write_mesh, spai_model_train,
     BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN, PREC_MIXED, PREC_PLAIN_FP64, PUSH_BORIS, PUSH_VAY,
-    SPAI_PLAIN, SPAI_LEARNED, SPAI_LEARNED_REJECTED,
+    SPAI_PLAIN, SPAI_LEARNED, SPAI_LEARNED_REJECTED, SPAI_LEARNED_REVERTED,
 )

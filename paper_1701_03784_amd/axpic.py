@@ -23,7 +23,7 @@ ERRORS = {-1: "AXP_E_ARG", -2: "AXP_E_MESH", -3: "AXP_E_SPAI", -4: "AXP_E_UNSTAB
 BC_PEC, BC_AXIS, BC_EMITTER, BC_OPEN = 1, 2, 3, 4
 PREC_PLAIN_FP64, PREC_MIXED = 0, 1
 PUSH_BORIS, PUSH_VAY = 0, 1
-SPAI_PLAIN, SPAI_LEARNED, SPAI_LEARNED_REJECTED = 0, 1, 2
+SPAI_PLAIN, SPAI_LEARNED, SPAI_LEARNED_REJECTED, SPAI_LEARNED_REVERTED = 0, 1, 2, 3
 SPAI_FEATURES = 16
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -53,7 +53,9 @@ class Info(C.Structure):
                 ("precision", C.c_int32), ("n_species", C.c_int32), ("spai_mode", C.c_int32), ("pad_", C.c_int32),
                 ("spai_fallback_columns", C.c_int64), ("spai_pred_resid_mean", C.c_double),
                 ("spai_kept_resid_mean", C.c_double), ("spai_energy_drift", C.c_double), ("spai_seconds", C.c_double),
-                ("n_layer_faces", C.c_int64)]
+                ("n_layer_faces", C.c_int64), ("spai_guard_trip_step", C.c_int64), ("spai_run_drift", C.c_double),
+                ("spai_feature_seconds", C.c_double), ("spai_infer_seconds", C.c_double),
+                ("spai_solve_seconds", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -81,7 +83,7 @@ EXPORTS = ["axp_config_default", "axp_create", "axp_set_mesh", "axp_set_boundary
            "axp_batch_set_timing", "axp_batch_get_timing", "axp_batch_info", "axp_batch_last_error",
            "axp_mlp_create", "axp_mlp_n_params", "axp_mlp_set_params", "axp_mlp_get_params", "axp_mlp_forward",
            "axp_mlp_loss_grad", "axp_mlp_loss_grad_noalloc", "axp_mlp_adam_step", "axp_mlp_info", "axp_mlp_save", "axp_mlp_load",
-           "axp_mlp_last_error", "axp_mlp_destroy", "axp_set_spai_model", "axp_spai_pairs",
+           "axp_mlp_last_error", "axp_mlp_destroy", "axp_set_spai_model", "axp_set_spai_run_guard", "axp_spai_pairs",
            "axp_spai_model_load", "axp_spai_model_train"]
 PHASES = ["face", "particles", "edge", "spmv", "sort", "diag", "inject", "walk"]
 
@@ -160,6 +162,7 @@ def load_library(path: str = LIB_PATH):
         "axp_mlp_last_error": (C.c_char_p, [vp]),
         "axp_mlp_destroy": (None, [vp]),
         "axp_set_spai_model": (i32, [vp, vp, dbl, dbl, i32]),
+        "axp_set_spai_run_guard": (i32, [vp, dbl]),
         "axp_spai_pairs": (i32, [vp, i64, C.POINTER(i64), vp, vp, vp]),
         "axp_spai_model_load": (i32, [vp, C.c_char_p]),
         "axp_spai_model_train": (i32, [C.c_char_p, C.c_char_p, C.c_uint64]),
@@ -376,6 +379,11 @@ class Ctx:
         self._spai_model = net
         self._check(self.lib.axp_set_spai_model(self.h, net.h if net is not None else None, float(row_tol),
                                                 float(energy_drift_tol), int(iters)))
+
+    def set_spai_run_guard(self, drift_tol):
+        """Arms (drift_tol >= 0) or disarms (< 0) the run-time energy guard
+        of the learned SPAI (axp_set_spai_run_guard)."""
+        self._check(self.lib.axp_set_spai_run_guard(self.h, float(drift_tol)))
 
     def spai_model_load(self, path):
         """Learned SPAI for the next build from a saved network file

@@ -73,6 +73,14 @@ struct axp_ctx {
     int spai_mode_used = AXP_SPAI_PLAIN;
     LearnedSpaiStats spai_stats;
     double spai_energy_drift = 0, spai_seconds = 0;
+    double spai_feature_s = 0, spai_infer_s = 0, spai_solve_s = 0;
+    // run-time energy guard of the learned SPAI (axp_set_spai_run_guard)
+    double guard_tol = -1.0;            // < 0: off
+    bool guard_ref_set = false;
+    double guard_wref = 0.0, guard_drift = 0.0;
+    int64_t guard_trip_step = -1;
+    void *snap = nullptr;               // device copy of the state at the last checkpoint
+    size_t snap_bytes = 0;
     // step graphs (one per particle buffer), replayed on stream
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -685,6 +693,176 @@ void run_steps(axp_ctx *c, int n_steps) {
     hcheck(hipGetLastError(), "step launch");
 }
 
+// ---- run-time energy guard of the learned SPAI
+
+// Device regions a step reads and writes (fields, sources, the particle
+// buffer in use up to n_slots, counters and diagnostic state).
+std::vector<std::pair<void *, size_t>> state_regions(axp_ctx *c, int64_t n_slots) {
+    const DevState &s = c->ds;
+    const size_t n0 = c->hm.n0, n1 = c->hm.n1, n2 = c->hm.n2, np = size_t(n_slots);
+    const int b = s.cur;
+    std::vector<std::pair<void *, size_t>> r = {
+        {s.B, 8 * n2}, {s.Bprev, 8 * n2}, {s.D, 8 * n1}, {s.g0, 8 * n0}, {s.cell[b], 4 * np},
+        {s.ctr, sizeof(DevCounters)}, {s.diag, sizeof(DevDiag)}};
+    if (c->plain) {
+        const DevPlain &p = c->dp;
+        for (void *q : {(void *)p.E, (void *)p.Jfx}) r.push_back({q, 8 * n1});
+        for (void *q : {(void *)p.Qres, (void *)p.Q, (void *)p.Qprev}) r.push_back({q, 8 * n0});
+        for (void *q : {(void *)p.l0[b], (void *)p.l1[b], (void *)p.ur[b], (void *)p.up[b], (void *)p.uz[b]})
+            r.push_back({q, 8 * np});
+    } else {
+        r.push_back({s.E, 4 * n1});
+        r.push_back({s.D32, 4 * n1});
+        r.push_back({s.Jfx, 8 * n1});
+        for (void *q : {(void *)s.Qres, (void *)s.Qfx, (void *)s.Qprev}) r.push_back({q, 8 * n0});
+        for (void *q : {(void *)s.L0[b], (void *)s.L1[b], (void *)s.ur[b], (void *)s.up[b], (void *)s.uz[b]})
+            r.push_back({q, 4 * np});
+    }
+    return r;
+}
+
+struct Checkpoint {
+    std::vector<std::pair<void *, size_t>> regions;
+    int64_t step = 0, last_eval_level = -1, n_live_host = 0;
+    int cur = 0;
+    uint64_t energy_count = 0;
+};
+
+// Device copy of the state into c->snap (grown as needed); the copies are
+// enqueued on the context's stream.
+Checkpoint take_checkpoint(axp_ctx *c) {
+    const DevCounters h = read_counters(c);
+    Checkpoint k;
+    k.regions = state_regions(c, int64_t(h.n_slots));
+    size_t total = 0;
+    for (auto &r : k.regions) total += (r.second + 255) & ~size_t(255);
+    if (total > c->snap_bytes) {
+        if (c->snap) dfree(c, c->snap);
+        c->snap = nullptr;
+        c->snap_bytes = 0;
+        c->snap = dalloc(c, total);
+        c->snap_bytes = total;
+    }
+    size_t off = 0;
+    for (auto &r : k.regions) {
+        if (r.second)
+            hcheck(hipMemcpyAsync(static_cast<char *>(c->snap) + off, r.first, r.second, hipMemcpyDeviceToDevice,
+                                  c->stream), "checkpoint");
+        off += (r.second + 255) & ~size_t(255);
+    }
+    k.step = c->step;
+    k.last_eval_level = c->last_eval_level;
+    k.n_live_host = c->n_live_host;
+    k.cur = c->ds.cur;
+    k.energy_count = h.energy_count;
+    return k;
+}
+
+void restore_checkpoint(axp_ctx *c, const Checkpoint &k) {
+    size_t off = 0;
+    for (auto &r : k.regions) {
+        if (r.second)
+            hcheck(hipMemcpyAsync(r.first, static_cast<char *>(c->snap) + off, r.second, hipMemcpyDeviceToDevice,
+                                  c->stream), "restore");
+        off += (r.second + 255) & ~size_t(255);
+    }
+    c->step = k.step;
+    c->last_eval_level = k.last_eval_level;
+    c->n_live_host = k.n_live_host;
+    c->ds.cur = k.cur;
+    hcheck(hipStreamSynchronize(c->stream), "sync");
+}
+
+// Replaces the learned M by the plain SPAI (host least squares, then the
+// sliced ELL upload).  Throws AXP_E_UNSTABLE, the learned M kept, if the run's
+// dt exceeds the plain SPAI's stability limit.
+void revert_to_plain_spai(axp_ctx *c) {
+    HostMesh &m = c->hm;
+    Csr learned = m.M;
+    const double fro = m.spai_fro, mx = m.spai_max_col;
+    const int64_t nnz = m.spai_nnz;
+    const int nt = int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+    const double cfl = cfl_dt(m, 400);
+    if (!(c->dt <= cfl * (1.0 + 1e-9))) {
+        m.M = std::move(learned);
+        m.spai_fro = fro; m.spai_max_col = mx; m.spai_nnz = nnz;
+        throw ApiError{AXP_E_UNSTABLE, "the run-time guard tripped, but dt " + std::to_string(c->dt) +
+                                           " exceeds the plain SPAI's stability limit " + std::to_string(cfl)};
+    }
+    std::vector<int64_t> sptr;
+    std::vector<int32_t> slen, mcol;
+    std::vector<float> mval;
+    std::vector<double> mvald;
+    build_sell(m.M, m.n1, sptr, slen, mval, c->plain ? &mvald : nullptr, mcol);
+    hcheck(hipStreamSynchronize(c->stream), "sync");
+    DevMesh &d = c->dm;
+    dfree(c, (void *)d.m_sptr); dfree(c, (void *)d.m_slen); dfree(c, (void *)d.m_col);
+    d.m_sptr = upload(c, sptr); d.m_slen = upload(c, slen); d.m_col = upload(c, mcol);
+    if (c->plain) {
+        dfree(c, (void *)c->dp.m_val);
+        c->dp.m_val = upload(c, mvald);
+    } else {
+        dfree(c, (void *)d.m_val);
+        d.m_val = upload(c, mval);
+    }
+    c->dt_cfl = cfl;
+    drop_graphs(c);
+    c->spai_mode_used = AXP_SPAI_LEARNED_REVERTED;
+}
+
+// Steps with the guard armed: chunks that fit the energy ring, each with a
+// checkpoint before it and a look at its energy records after it.
+void guarded_steps(axp_ctx *c, int n_steps) {
+    const int de = c->cfg.diag_every;
+    const int chunk_max = std::max(1, (kEnergyRing / 2) * de);
+    for (int done = 0; done < n_steps;) {
+        const int n = std::min(n_steps - done, chunk_max);
+        if (c->inj_on) {
+            // grow first: the checkpoint must cover the buffers the steps use
+            const DevCounters h = read_counters(c);
+            grow_particles(c, int64_t(h.n_slots) + int64_t(n) * c->inj.per_step);
+        }
+        const Checkpoint ck = take_checkpoint(c);
+        run_steps(c, n);
+        const DevCounters h = read_counters(c);
+        const int64_t k = int64_t(h.energy_count) - int64_t(ck.energy_count);
+        int64_t trip = -1;
+        if (k > 0) {
+            std::vector<DevEnergy> ring(kEnergyRing);
+            hcheck(hipMemcpyAsync(ring.data(), c->ds.energy, sizeof(DevEnergy) * kEnergyRing, hipMemcpyDeviceToHost,
+                                  c->stream), "energies");
+            hcheck(hipStreamSynchronize(c->stream), "sync");
+            for (int64_t i = 0; i < k; ++i) {
+                const DevEnergy &e = ring[size_t((ck.energy_count + uint64_t(i)) % kEnergyRing)];
+                const double w = e.WE + e.WB + e.WK;
+                if (!c->guard_ref_set) {
+                    if (w != 0.0 && std::isfinite(w)) { c->guard_wref = w; c->guard_ref_set = true; }
+                    continue;
+                }
+                const double drift = std::fabs(w - c->guard_wref) / std::fabs(c->guard_wref);
+                if (!(drift <= c->guard_drift)) c->guard_drift = std::isfinite(drift) ? drift : INFINITY;
+                if (!(drift <= c->guard_tol)) { trip = e.level; break; }
+            }
+        }
+        if (trip >= 0) {
+            revert_to_plain_spai(c);
+            restore_checkpoint(c, ck);
+            // D is the state: Gauss's law and continuity carry over; E = M D with the new M
+            if (c->plain) launch_spmv_plain(c->dm, c->ds, c->dp, c->stream);
+            else launch_spmv(c->dm, c->ds, c->stream);
+            hcheck(hipGetLastError(), "spmv launch");
+            c->guard_trip_step = trip;
+            c->guard_tol = -1.0;
+            run_steps(c, n);
+            done += n;
+            if (done < n_steps) run_steps(c, n_steps - done);
+            return;
+        }
+        done += n;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -766,17 +944,23 @@ axp_status axp_build(axp_ctx *c) {
             scaled_hodge(m, h);
             PairSet ps;
             spai_pair_features(m, h, c->cfg.spai_level, nt, ps);
+            const auto tf = std::chrono::steady_clock::now();
             std::vector<float> pred(ps.j.size());
             std::string err;
             const int st = mlp_predict_host(c->spai_model, ps.X.data(), int64_t(ps.j.size()), pred.data(), err);
             if (st != AXP_OK) throw ApiError{st, err};
             ps.X.clear();
             ps.X.shrink_to_fit();
+            const auto ti = std::chrono::steady_clock::now();
             learned_spai(m, h, ps, pred.data(), c->cfg.spai_level, c->cfg.spai_drop_tol, c->spai_iters, c->spai_row_tol,
                          nt, c->spai_stats);
             c->spai_mode_used = AXP_SPAI_LEARNED;
+            c->spai_feature_s = std::chrono::duration<double>(tf - ts).count();
+            c->spai_infer_s = std::chrono::duration<double>(ti - tf).count();
+            c->spai_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - ti).count();
         } else {
             build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+            c->spai_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
         }
         c->spai_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
         c->dt_cfl = cfl_dt(m, 400);
@@ -787,7 +971,9 @@ axp_status axp_build(axp_ctx *c) {
                                        ? leapfrog_energy_drift(m, c->dt, 64, 12345)
                                        : INFINITY;
             if (!(c->spai_energy_drift <= c->spai_energy_tol)) {
+                const auto tr = std::chrono::steady_clock::now();
                 build_spai(m, c->cfg.spai_level, c->cfg.spai_drop_tol, nt);
+                c->spai_solve_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tr).count();
                 c->spai_mode_used = AXP_SPAI_LEARNED_REJECTED;
                 c->dt_cfl = cfl_dt(m, 400);
                 c->dt = c->cfg.dt > 0 ? c->cfg.dt : c->cfg.cfl_fraction * c->dt_cfl;
@@ -835,6 +1021,11 @@ axp_status axp_info_get(const axp_ctx *c, axp_info *out) {
     out->spai_energy_drift = c->spai_energy_drift;
     out->spai_seconds = c->spai_seconds;
     out->n_layer_faces = int64_t(c->hl.face.size());
+    out->spai_guard_trip_step = c->guard_trip_step;
+    out->spai_run_drift = c->guard_drift;
+    out->spai_feature_seconds = c->spai_feature_s;
+    out->spai_infer_seconds = c->spai_infer_s;
+    out->spai_solve_seconds = c->spai_solve_s;
     return c->built ? AXP_OK : AXP_E_STATE;
 }
 
@@ -1238,7 +1429,8 @@ axp_status axp_step(axp_ctx *c, int32_t n_steps) {
     if (!c || n_steps < 0) return AXP_E_ARG;
     return guarded(c, [&]() -> axp_status {
         require_built(c);
-        run_steps(c, n_steps);
+        if (c->guard_tol >= 0.0) guarded_steps(c, n_steps);
+        else run_steps(c, n_steps);
         return AXP_OK;
     });
 }
@@ -1660,6 +1852,20 @@ axp_status axp_set_spai_model(axp_ctx *c, axp_mlp *net, double row_tol, double e
     return AXP_OK;
 }
 
+axp_status axp_set_spai_run_guard(axp_ctx *c, double drift_tol) {
+    if (!c || std::isnan(drift_tol)) return AXP_E_ARG;
+    if (!c->built) return fail(c, AXP_E_STATE, "axp_build first");
+    if (drift_tol < 0.0) { c->guard_tol = -1.0; return AXP_OK; }
+    if (c->spai_mode_used != AXP_SPAI_LEARNED)
+        return fail(c, AXP_E_STATE, "the run-time guard needs a learned SPAI in use");
+    if (c->cfg.diag_every <= 0) return fail(c, AXP_E_STATE, "the run-time guard needs diagnostic steps (diag_every > 0)");
+    c->guard_tol = drift_tol;
+    c->guard_ref_set = false;
+    c->guard_wref = 0.0;
+    c->guard_drift = 0.0;
+    return AXP_OK;
+}
+
 axp_status axp_spai_model_load(axp_ctx *c, const char *model_path) {
     if (!c || !model_path) return AXP_E_ARG;
     if (c->built) return fail(c, AXP_E_STATE, "load the SPAI model before axp_build");
@@ -1806,6 +2012,7 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
         if (c->dl.n) return fail(c, AXP_E_ARG, "batch members cannot carry absorbing layers");
         if (c->cfg.diag_every != ctxs[0]->cfg.diag_every)
             return fail(c, AXP_E_ARG, "batch members must share a diagnostic cadence");
+        if (c->guard_tol >= 0.0) return fail(c, AXP_E_ARG, "batch members cannot carry an armed SPAI run-time guard");
     }
     bool q32 = true;
     for (int k = 0; k < n; ++k) q32 = q32 && ctxs[k]->q32;

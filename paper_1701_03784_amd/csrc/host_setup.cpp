@@ -443,69 +443,115 @@ void spai_ls_columns(const ScaledHodge &h, int level, double drop_tol, const std
     for (auto &v : per_thread) out.insert(out.end(), v.begin(), v.end());
 }
 
-void finish_spai(HostMesh &m, const ScaledHodge &h, std::vector<SpaiEntry> &entries) {
+void finish_spai(HostMesh &m, const ScaledHodge &h, std::vector<SpaiEntry> &entries, int n_threads) {
     const int nf = int(h.fedge.size());
-    // symmetric average (M^ + M^T)/2 and unscaling, into CSR over internal edges
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(nf);
-    for (auto &e : entries) {
-        rows[e.row].push_back({e.col, 0.5 * e.v});
-        rows[e.col].push_back({e.row, 0.5 * e.v});
-    }
+    // symmetric average (M^ + M^T)/2: both halves of every entry, bucketed by
+    // row (in any order: each row is sorted below)
+    const int64_t ne = int64_t(entries.size());
+    std::vector<std::atomic<int64_t>> slot(size_t(nf) + 1);
+    for (auto &a : slot) a.store(0, std::memory_order_relaxed);
+    auto over_entries = [&](auto &&body) {
+        std::atomic<int64_t> next{0};
+        parallel(n_threads, [&](int) {
+            for (;;) {
+                const int64_t q0 = next.fetch_add(65536);
+                if (q0 >= ne) break;
+                for (int64_t q = q0; q < std::min(ne, q0 + 65536); ++q) body(entries[size_t(q)]);
+            }
+        });
+    };
+    over_entries([&](const SpaiEntry &e) {
+        slot[size_t(e.row) + 1].fetch_add(1, std::memory_order_relaxed);
+        slot[size_t(e.col) + 1].fetch_add(1, std::memory_order_relaxed);
+    });
+    std::vector<int64_t> start(size_t(nf) + 1, 0);
+    for (int i = 0; i < nf; ++i) start[i + 1] = start[i] + slot[size_t(i) + 1].load(std::memory_order_relaxed);
+    for (int i = 0; i < nf; ++i) slot[i].store(start[i], std::memory_order_relaxed);
+    std::vector<std::pair<int32_t, double>> pairs(static_cast<size_t>(start[nf]));
+    over_entries([&](const SpaiEntry &e) {
+        pairs[size_t(slot[e.row].fetch_add(1, std::memory_order_relaxed))] = {e.col, 0.5 * e.v};
+        pairs[size_t(slot[e.col].fetch_add(1, std::memory_order_relaxed))] = {e.row, 0.5 * e.v};
+    });
     entries.clear();
     entries.shrink_to_fit();
+    // per row: sort by column and add the halves that meet (a + b: the sum
+    // does not depend on the order the columns were solved in)
+    std::vector<int64_t> cnt(nf, 0);
+    {
+        std::atomic<int> next{0};
+        parallel(n_threads, [&](int) {
+            for (;;) {
+                const int i0 = next.fetch_add(1024);
+                if (i0 >= nf) break;
+                for (int i = i0; i < std::min(nf, i0 + 1024); ++i) {
+                    const int64_t b = start[i], e = start[i + 1];
+                    std::sort(pairs.begin() + b, pairs.begin() + e);
+                    int64_t w = b;
+                    for (int64_t q = b; q < e; ++q) {
+                        if (w > b && pairs[size_t(w - 1)].first == pairs[size_t(q)].first)
+                            pairs[size_t(w - 1)].second += pairs[size_t(q)].second;
+                        else
+                            pairs[size_t(w++)] = pairs[size_t(q)];
+                    }
+                    cnt[i] = w - b;
+                }
+            }
+        });
+    }
+    // CSR over internal edges, unscaled
     m.M = Csr{};
     m.M.n = m.n1;
-    m.M.ptr.assign(m.n1 + 1, 0);
-    std::vector<std::vector<std::pair<int32_t, double>>> merged(nf);
-    for (int i = 0; i < nf; ++i) {
-        auto &r = rows[i];
-        std::sort(r.begin(), r.end());
-        for (auto &p : r) {
-            if (!merged[i].empty() && merged[i].back().first == p.first) merged[i].back().second += p.second;
-            else merged[i].push_back(p);
-        }
-        rows[i].clear();
-        rows[i].shrink_to_fit();
-    }
+    m.M.ptr.assign(size_t(m.n1) + 1, 0);
     for (int e = 0; e < m.n1; ++e) {
-        int i = h.fidx[e];
-        m.M.ptr[e + 1] = m.M.ptr[e] + (i >= 0 ? int64_t(merged[i].size()) : 0);
+        const int i = h.fidx[e];
+        m.M.ptr[e + 1] = m.M.ptr[e] + (i >= 0 ? cnt[i] : 0);
     }
-    m.M.col.resize(m.M.ptr[m.n1]);
-    m.M.val.resize(m.M.ptr[m.n1]);
-    for (int e = 0; e < m.n1; ++e) {
-        int i = h.fidx[e];
-        if (i < 0) continue;
-        int64_t o = m.M.ptr[e];
-        for (auto &p : merged[i]) {
-            m.M.col[o] = h.fedge[p.first];
-            m.M.val[o] = h.s[i] * p.second * h.s[p.first];
-            ++o;
-        }
+    m.M.col.resize(size_t(m.M.ptr[m.n1]));
+    m.M.val.resize(size_t(m.M.ptr[m.n1]));
+    std::vector<double> col2(m.n1, 0.0);
+    {
+        std::atomic<int> next{0};
+        parallel(n_threads, [&](int) {
+            std::vector<double> acc(m.n1, 0.0);
+            std::vector<int32_t> touched;
+            for (;;) {
+                const int e0 = next.fetch_add(1024);
+                if (e0 >= m.n1) break;
+                for (int e = e0; e < std::min(m.n1, e0 + 1024); ++e) {
+                    const int i = h.fidx[e];
+                    if (i < 0) continue;
+                    int64_t o = m.M.ptr[e];
+                    for (int64_t q = start[i]; q < start[i] + cnt[i]; ++q, ++o) {
+                        const auto &p = pairs[size_t(q)];
+                        m.M.col[o] = h.fedge[p.first];
+                        m.M.val[o] = h.s[i] * p.second * h.s[p.first];
+                    }
+                    // residual of the column: A m_e - e_e (M symmetric: column e = row e)
+                    touched.clear();
+                    for (int64_t j = m.M.ptr[e]; j < m.M.ptr[e + 1]; ++j) {
+                        const int c = m.M.col[j];
+                        for (int64_t q = m.A.ptr[c]; q < m.A.ptr[c + 1]; ++q) {
+                            const int r = m.A.col[q];
+                            if (!m.efree[r]) continue;
+                            if (acc[r] == 0.0) touched.push_back(r);
+                            acc[r] += m.A.val[q] * m.M.val[j];
+                        }
+                    }
+                    acc[e] -= 1.0;
+                    if (std::find(touched.begin(), touched.end(), e) == touched.end()) touched.push_back(e);
+                    double s2 = 0;
+                    for (int r : touched) { s2 += acc[r] * acc[r]; acc[r] = 0.0; }
+                    col2[e] = s2;
+                }
+            }
+        });
     }
     m.spai_nnz = m.M.ptr[m.n1];
-    // residual of each column: A m_k - e_k (M symmetric: column k = row k)
     double fro = 0, mxc = 0;
-    std::vector<double> acc(m.n1, 0.0);
-    std::vector<int32_t> touched;
-    for (int e = 0; e < m.n1; ++e) {
+    for (int e = 0; e < m.n1; ++e) {        // in edge order, whatever the thread count
         if (!m.efree[e]) continue;
-        touched.clear();
-        for (int64_t j = m.M.ptr[e]; j < m.M.ptr[e + 1]; ++j) {
-            int c = m.M.col[j];
-            for (int64_t q = m.A.ptr[c]; q < m.A.ptr[c + 1]; ++q) {
-                int r = m.A.col[q];
-                if (!m.efree[r]) continue;
-                if (acc[r] == 0.0) touched.push_back(r);
-                acc[r] += m.A.val[q] * m.M.val[j];
-            }
-        }
-        acc[e] -= 1.0;
-        if (std::find(touched.begin(), touched.end(), e) == touched.end()) touched.push_back(e);
-        double col2 = 0;
-        for (int r : touched) { col2 += acc[r] * acc[r]; acc[r] = 0.0; }
-        fro += col2;
-        mxc = std::max(mxc, std::sqrt(col2));
+        fro += col2[e];
+        mxc = std::max(mxc, std::sqrt(col2[e]));
     }
     m.spai_fro = std::sqrt(fro / std::max(1, nf));
     m.spai_max_col = mxc;
@@ -516,7 +562,7 @@ void build_spai(HostMesh &m, int level, double drop_tol, int n_threads) {
     scaled_hodge(m, h);
     std::vector<SpaiEntry> entries;
     spai_ls_columns(h, level, drop_tol, nullptr, n_threads, entries);
-    finish_spai(m, h, entries);
+    finish_spai(m, h, entries, n_threads);
 }
 
 // ------------------------------------------------------- learned SPAI
@@ -721,7 +767,7 @@ void learned_spai(HostMesh &m, const ScaledHodge &h, const PairSet &ps, const fl
     st.pred_resid_mean = nf ? r0 / nf : 0.0;
     st.kept_resid_mean = (nf - st.n_fallback) > 0 ? r1 / double(nf - st.n_fallback) : 0.0;
     if (!fb.empty()) spai_ls_columns(h, level, drop_tol, &fb, n_threads, entries);
-    finish_spai(m, h, entries);
+    finish_spai(m, h, entries, n_threads);
 }
 
 // Source-free leapfrog in the D-form with the current M from a seeded random

@@ -134,7 +134,7 @@ void scaled_hodge(const HostMesh &m, ScaledHodge &h);
 void spai_ls_columns(const ScaledHodge &h, int level, double drop_tol, const std::vector<int32_t> *cols, int n_threads,
                      std::vector<SpaiEntry> &out);
 // symmetric average, unscaling into m.M, residual statistics
-void finish_spai(HostMesh &m, const ScaledHodge &h, std::vector<SpaiEntry> &entries);
+void finish_spai(HostMesh &m, const ScaledHodge &h, std::vector<SpaiEntry> &entries, int n_threads);
 void spai_pair_features(const HostMesh &m, const ScaledHodge &h, int level, int n_threads, PairSet &ps);
 void learned_spai(HostMesh &m, const ScaledHodge &h, const PairSet &ps, const float *pred, int level, double drop_tol,
                   int iters, double row_tol, int n_threads, LearnedSpaiStats &st);

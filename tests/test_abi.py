@@ -60,7 +60,8 @@ def _c_layout():
                            "spai_fro_residual", "spai_max_col_residual", "dt", "dt_cfl", "setup_seconds",
                            "particle_capacity", "n_particles", "step", "precision", "n_species", "spai_mode",
                            "spai_fallback_columns", "spai_pred_resid_mean", "spai_kept_resid_mean",
-                           "spai_energy_drift", "spai_seconds", "n_layer_faces"],
+                           "spai_energy_drift", "spai_seconds", "n_layer_faces", "spai_guard_trip_step",
+                           "spai_run_drift", "spai_feature_seconds", "spai_infer_seconds", "spai_solve_seconds"],
               "axp_diag": ["step", "n_live", "n_absorbed", "walk_overflow", "nan_count", "fixed_overflow",
                            "dce_max_abs", "dce_max_rel", "gauss_max_drift", "gauss_max_abs", "gauss_scale", "W_E",
                            "W_B", "W_K", "Q_total", "energy_step", "n_evals", "W_E_now"],
@@ -101,6 +102,7 @@ def test_spai_enum_values():
     assert val["AXP_SPAI_PLAIN"] == ax.SPAI_PLAIN
     assert val["AXP_SPAI_LEARNED"] == ax.SPAI_LEARNED
     assert val["AXP_SPAI_LEARNED_REJECTED"] == ax.SPAI_LEARNED_REJECTED
+    assert val["AXP_SPAI_LEARNED_REVERTED"] == ax.SPAI_LEARNED_REVERTED
 
 
 def test_spai_model_train_rejects_bad_arguments_before_any_device_work(tmp_path):
