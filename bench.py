@@ -472,8 +472,6 @@ def main():
     pb = particle_bytes(n_live, n2)
     achieved = pb / part_s / 1e9
     fb = field_bytes(info["n_free_edges"], n2, info["spai_nnz"])
-    field_ms = sum(tim[k][0] for k in ("face", "edge", "spmv")) / steps
-    field_gbs = fb / (field_ms / 1e3) / 1e9
     step_bytes = pb + fb
     log(f"per-launch us {per_launch}")
 
@@ -494,6 +492,11 @@ def main():
         nodiag["roofline_frac"] = pb / (nodiag["particle_kernel_us"] / 1e6) / 1e9 / HBM_PEAK_GBS
         nodiag["step_algorithmic_frac"] = step_bytes / (nodiag["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS
         log(f"without diagnostics: {nodiag['value']:.3e} particle-steps/s, {nodiag['ms_per_step']:.4f} ms/step")
+    # field kernels alone: from the steps without diagnostics (with them, the
+    # SpMV launch also carries the node pass of the evaluation)
+    ft = tim0 if args.diag_every else tim
+    field_ms = sum(ft[k][0] / max(1, ft[k][1]) for k in ("face", "edge", "spmv"))
+    field_gbs = fb / (field_ms / 1e3) / 1e9
 
     plain = plain_graph = vay = None
     if args.plain_steps > 0:

@@ -474,6 +474,7 @@ void upload_tables(axp_ctx *c, const HostTables &h, bool pooled, int n_inst) {
     s.part_edge = zeros<double>(c, (size_t(h.n1) + 255) / 256);
     s.part_node = zeros<double>(c, size_t(kDiagSlots) * ((size_t(std::max(h.n0, h.n1)) + 255) / 256));
     s.part_kin = zeros<double>(c, 3);
+    s.part_wenow = zeros<double>(c, (size_t(h.n1) + 255) / 256);
     s.energy = zeros<DevEnergy>(c, kEnergyRing);
     s.capacity = 0;
     s.cur = 0;
@@ -612,12 +613,18 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
         launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, diag, c->q32, st);
     }
     { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, diag, st); }
-    {
+    if (diag && !c->dl.n) {
+        // one launch: E = M D beside the evaluation of the new level
         PhaseScope ps(c, AXP_PHASE_SPMV, st);
-        launch_spmv(m, s, st);
-        launch_layers_post(m, s, (const float *)s.E, c->dl, st);
+        launch_spmv_diag(m, s, st);
+    } else {
+        {
+            PhaseScope ps(c, AXP_PHASE_SPMV, st);
+            launch_spmv(m, s, st);
+            launch_layers_post(m, s, (const float *)s.E, c->dl, st);
+        }
+        if (diag) { PhaseScope ps(c, AXP_PHASE_DIAG, st); launch_diag_in_step(m, s, st); }
     }
-    if (diag) { PhaseScope ps(c, AXP_PHASE_DIAG, st); launch_diag_in_step(m, s, st); }
     ++c->step;
     if (diag) c->last_eval_level = c->step;
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort(m, s, true, st); }

@@ -168,6 +168,7 @@ struct DevState {
     double *part_edge = nullptr;   // W_E per edge-pass block
     double *part_node = nullptr;   // kDiagSlots per node-pass block
     double *part_kin = nullptr;    // per particle block: W_K, live at the start, live at the end
+    double *part_wenow = nullptr;  // 1/2 E D of the new level per block of the fused SpMV
     DevEnergy *energy = nullptr;   // kEnergyRing records
 };
 
@@ -234,6 +235,10 @@ void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st);
 // the edge pass ran with diag on): the evaluation of its end level n + 1 and
 // the energy record of its start level n, launched after the field update.
 void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st);
+// E = M D of a diagnostic step (no absorbing layers) with the energy of the
+// new level per block of rows, then the node pass over the nodes alone and
+// the final reduction
+void launch_spmv_diag(const DevMesh &m, DevState &s, hipStream_t st);
 // Diagnostics of the current state (level = steps taken), on demand.
 void launch_diag_now(const DevMesh &m, DevState &s, hipStream_t st);
 // clears the face-corner charge accumulators (a fill kernel, graph-safe)

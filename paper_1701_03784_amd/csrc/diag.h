@@ -37,8 +37,8 @@ struct DiagVals {
 // Adds this block's slices of the particle partials (3 per particle block:
 // W_K, live at the start, live at the end; on demand only the last is
 // written), the face partials and the edge partials to v.
-__device__ __forceinline__ void fold_slices(const DevState &s, DiagVals &v, int in_step, int nb_face, int nb_edge) {
-    const int nb_node = gridDim.x;
+__device__ __forceinline__ void fold_slices(const DevState &s, DiagVals &v, int in_step, int nb_face, int nb_edge,
+                                            int nb_node) {
     const long long ns = (long long)s.ctr->n_slots;
     const int nb_part = (int)((ns + 1023) / 1024);
     const int kp = (nb_part + nb_node - 1) / nb_node;

@@ -212,32 +212,77 @@ __device__ __forceinline__ void win_add_c(const Win &w, int *cnt, int t, int v) 
 // each run adds the run's total.  Cost is independent of how many faces the
 // wave holds.  Lanes with t < 0 hold nothing.  All lanes of the wave must
 // call this together.
+//
+// The scan moves values between lanes with DPP (data-parallel primitives of
+// the VALU, no LDS round trip): shifts by 1, 2, 4 and 8 lanes within each
+// row of 16, then the last lane of a row broadcast into the next row
+// (row_bcast:15, rows 1 and 3) and lane 31 into the upper half (row_bcast:31,
+// rows 2 and 3).  A lane adds what arrives only from a lane of its own run;
+// lanes outside a move's source range receive 0, which is no run.
+// GFX9 DPP controls: row_shr:n = 0x110 + n, wave_shl:1 = 0x130,
+// wave_shr:1 = 0x138, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_mov(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_mov(unsigned v) {
+    return (unsigned)dpp_mov<CTRL, ROWS>((int)v);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_mov(long long v) {
+    const unsigned lo = (unsigned)dpp_mov<CTRL, ROWS>((int)(unsigned)v);
+    const unsigned hi = (unsigned)dpp_mov<CTRL, ROWS>((int)(unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_mov(unsigned long long v) {
+    return (unsigned long long)dpp_mov<CTRL, ROWS>((long long)v);
+}
+
 __device__ __forceinline__ int lane_run(int t) {
     const int lane = threadIdx.x & 63;
-    const int tp = __shfl_up(t, 1, 64);
+    const int tp = dpp_mov<0x138, 0xF>(t);                   // lane - 1 (lane 0: head anyway)
     const unsigned long long heads = __ballot(lane == 0 || tp != t);
     return __popcll(heads & ((2ull << lane) - 1ull));       // 1-based index of the lane's run
 }
 
 __device__ __forceinline__ bool run_tail(int t) {
     const int lane = threadIdx.x & 63;
-    const int tn = __shfl_down(t, 1, 64);
+    const int tn = dpp_mov<0x130, 0xF>(t);                   // lane + 1 (lane 63: tail anyway)
     return lane == 63 || tn != t;
+}
+
+template <int CTRL, int ROWS, class V, int N>
+__device__ __forceinline__ void seg_step(int run, V (&a)[N]) {
+    const int ro = dpp_mov<CTRL, ROWS>(run);
+    V b[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) b[k] = dpp_mov<CTRL, ROWS>(a[k]);
+    if (ro == run)
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] += b[k];
+}
+
+// Inclusive sums of a[] over the lane's run (run: 1-based run index).
+template <class V, int N>
+__device__ __forceinline__ void seg_scan(int run, V (&a)[N]) {
+    seg_step<0x111, 0xF>(run, a);
+    seg_step<0x112, 0xF>(run, a);
+    seg_step<0x114, 0xF>(run, a);
+    seg_step<0x118, 0xF>(run, a);
+    seg_step<0x142, 0xA>(run, a);
+    seg_step<0x143, 0xC>(run, a);
 }
 
 __device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0, long long a1,
                                              long long a2) {
-    const int lane = threadIdx.x & 63;
-    const int run = lane_run(t);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ro = __shfl_up(run, off, 64);
-        const long long b0 = __shfl_up(a0, off, 64);
-        const long long b1 = __shfl_up(a1, off, 64);
-        const long long b2 = __shfl_up(a2, off, 64);
-        if (lane >= off && ro == run) { a0 += b0; a1 += b1; a2 += b2; }
-    }
-    if (run_tail(t) && t >= 0) win_add_j(w, J, t, a0, a1, a2);
+    long long a[3] = {a0, a1, a2};
+    seg_scan<long long, 3>(lane_run(t), a);
+    if (run_tail(t) && t >= 0) win_add_j(w, J, t, a[0], a[1], a[2]);
 }
 
 // Charge of the particles' end positions in a diagnostic step (eq. charge):
@@ -277,42 +322,11 @@ __device__ __forceinline__ void qwin_add3(const QWinL<QA> &w, unsigned long long
     }
 }
 
-// wave_deposit of a diagnostic step: the stayers' currents and end-position
-// charges (the same faces) share one segmented scan
-template <class QA>
-__device__ __forceinline__ void wave_deposit_q(const Win &w, unsigned long long *J, const QWinL<QA> &qw,
-                                               unsigned long long *Qloc, int t, long long a0, long long a1,
-                                               long long a2, QA q0, QA q1, QA q2) {
-    const int lane = threadIdx.x & 63;
-    const int run = lane_run(t);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ro = __shfl_up(run, off, 64);
-        const long long b0 = __shfl_up(a0, off, 64);
-        const long long b1 = __shfl_up(a1, off, 64);
-        const long long b2 = __shfl_up(a2, off, 64);
-        const QA c0 = __shfl_up(q0, off, 64);
-        const QA c1 = __shfl_up(q1, off, 64);
-        const QA c2 = __shfl_up(q2, off, 64);
-        if (lane >= off && ro == run) { a0 += b0; a1 += b1; a2 += b2; q0 += c0; q1 += c1; q2 += c2; }
-    }
-    if (run_tail(t) && t >= 0) {
-        win_add_j(w, J, t, a0, a1, a2);
-        qwin_add3(qw, Qloc, t, (long long)q0, (long long)q1, (long long)q2);
-    }
-}
-
 // Same for a count per face (histogram of the counting sort).
 __device__ __forceinline__ void wave_count(const Win &w, int *cnt, int t, int c) {
-    const int lane = threadIdx.x & 63;
-    const int run = lane_run(t);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ro = __shfl_up(run, off, 64);
-        const int b = __shfl_up(c, off, 64);
-        if (lane >= off && ro == run) c += b;
-    }
-    if (run_tail(t) && t >= 0 && c) win_add_c(w, cnt, t, c);
+    int a[1] = {c};
+    seg_scan<int, 1>(lane_run(t), a);
+    if (run_tail(t) && t >= 0 && a[0]) win_add_c(w, cnt, t, a[0]);
 }
 
 __device__ __forceinline__ void win_zero(const Win &w) {
@@ -452,9 +466,9 @@ struct Mover {
 // edge (its charge kept on the wall nodes), stops on the axis, or hits the
 // piece cap.  mv holds the start (face, coordinates, remaining
 // displacement) and receives the final cell word and coordinates.
-template <bool SINGLE, bool DIAG, class QA>
+template <bool SINGLE, bool DIAG>
 __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const PushConst &k0,
-                                           int max_walk, const QWinL<QA> &qw, int *nabs, Mover &mv) {
+                                           int max_walk, int *nabs, Mover &mv) {
     int t = mv.cell & kCellMask;
     const int sp = (mv.cell >> kCellBits) & 15;
     const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
@@ -538,8 +552,6 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
     mv.cell = newcell;
     mv.L0 = L0;
     mv.L1 = L1;
-    if (DIAG && newcell >= 0)        // the end position's charge (level n+1)
-        qwin_add3(qw, s.Qloc, t, (long long)kq * L0, (long long)kq * L1, (long long)kq * (kS - L0 - L1));
 }
 
 // Inclusive sum of N values over runs of consecutive lanes holding the same
@@ -547,18 +559,7 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
 // lanes of the wave must call it together.
 template <class V, int N>
 __device__ __forceinline__ void wave_run_sums(int t, V (&a)[N]) {
-    const int lane = threadIdx.x & 63;
-    const int run = lane_run(t);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int ro = __shfl_up(run, off, 64);
-        V b[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) b[k] = __shfl_up(a[k], off, 64);
-        if (lane >= off && ro == run)
-#pragma unroll
-            for (int k = 0; k < N; ++k) a[k] += b[k];
-    }
+    seg_scan<V, N>(lane_run(t), a);
 }
 
 __device__ __forceinline__ void corner_add(unsigned long long *Qloc, int t, long long q0, long long q1, long long q2) {
@@ -668,21 +669,58 @@ __device__ __forceinline__ double kin_sum(const DevMesh &m, const PushConst &k0,
     return v;
 }
 
+// Charge of the particles' end positions (level n+1, eq. charge) in a
+// diagnostic step: the thread folds its particles face by face, the wave
+// sums runs of lanes holding the same face, and each run's last lane adds
+// the three corner sums kq Lambda_k to the block's charge window.  Done after
+// the walk, when the push's registers are free.  With QA = 32-bit words a
+// wave's sums stay below 2^32 (256 particles of at most 2^23 each).
+template <bool SINGLE, class QA>
+__device__ __forceinline__ void end_charge(const DevMesh &m, const PushConst &k0, const QWinL<QA> &qw,
+                                           unsigned long long *Qloc, const Particle (&P)[kPPT]) {
+    int qt = -1;
+    QA q[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j) {
+        if (P[j].cell < 0) continue;
+        const int T = P[j].cell & kCellMask;
+        if (T != qt) {
+            if (qt >= 0) qwin_add3(qw, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
+            qt = T;
+            q[0] = q[1] = q[2] = 0;
+        }
+        const QA L0 = (QA)P[j].L0, L1 = (QA)P[j].L1, L2 = (QA)kS - L0 - L1;
+        if (SINGLE) {
+            q[0] += L0; q[1] += L1; q[2] += L2;
+        } else {
+            const QA kq = (QA)(long long)push_const<SINGLE>(m, k0, T, (P[j].cell >> kCellBits) & 15).kq;
+            q[0] += kq * L0; q[1] += kq * L1; q[2] += kq * L2;
+        }
+    }
+    wave_run_sums<QA, 3>(qt, q);
+    if (run_tail(qt) && qt >= 0) qwin_add3(qw, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
+}
+
 // Q32: every species' charge multiple is 0 or 1, so the end-position charge
 // of a diagnostic step accumulates in 32-bit LDS words (always so in the
 // single case).
 template <bool SINGLE, bool VAY, bool DIAG, bool Q32>
-__global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
+__global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
                                                                PushConst k0) {
     __shared__ int s_nmv;
     __shared__ int s_base;
     __shared__ unsigned long long s_jl[3 * kWin];
     __shared__ int s_cl[kWin];
-    __shared__ Mover s_mv[kQCap];
-    // diagnostic steps: the end positions' charge window, per wave the
-    // kinetic energy and live count, the block's absorbed count
+    // diagnostic steps: the end positions' charge window (32-bit words: in
+    // the walk queue's LDS once the walk is over, so that the block keeps
+    // the LDS footprint that allows 6 blocks per CU), per wave the kinetic
+    // energy and live count, the block's absorbed count
     using QA = typename std::conditional<SINGLE || Q32, unsigned, unsigned long long>::type;
-    __shared__ QA s_ql[DIAG ? 3 * kWin : 1];
+    constexpr bool kQInQueue = sizeof(QA) * 3 * kWin <= sizeof(Mover) * kQCap;
+    __shared__ __align__(16) unsigned char s_queue[sizeof(Mover) * kQCap];
+    __shared__ QA s_qown[DIAG && !kQInQueue ? 3 * kWin : 1];
+    Mover *const s_mv = reinterpret_cast<Mover *>(s_queue);
+    QA *const s_ql = kQInQueue ? reinterpret_cast<QA *>(s_queue) : s_qown;
     __shared__ double s_wk[kWG / 64];
     __shared__ int s_nl[kWG / 64];
     __shared__ int s_nabs;
@@ -723,26 +761,17 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
     }
     Win w{s_jl, s_cl, 0};
     win_zero(w);
-    unsigned live0 = 0;              // particles live at the start (diagnostic steps)
-    if (DIAG) {
-        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
-        // level n: live count and the kinetic energy of u^{n-1/2}
-#pragma unroll
-        for (int j = 0; j < kPPT; ++j) live0 |= (P[j].cell >= 0 ? 1u : 0u) << j;
-        const double v = wave_sum_d(kin_sum<SINGLE>(m, k0, P, live0));
-        const int nl = wave_sum_i(__popc(live0));
-        if ((threadIdx.x & 63) == 0) { s_wk[threadIdx.x >> 6] = v; s_nl[threadIdx.x >> 6] = nl; }
-    }
     __syncthreads();
     w.base = s_base;
     const QWinL<QA> qw{s_ql, s_base};
-    QA q0 = 0, q1 = 0, q2 = 0;       // end-position charge of the stayers of face acc_t
     // ---- phase 1: push
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
     int ct = -1, cc = 0;             // run-length count of the new faces (stayers only)
     bool mover[kPPT];
     float mfz[kPPT], mfr[kPPT];
+    double kin = 0.0;                // diagnostic steps: sum of mw (gamma - 1) at n-1/2 and n+1/2
+    int nlive = 0;                   // and the particles pushed
     int Tc = -1;                     // face data cached across the thread's particles
     float4 cf0 = make_float4(0.f, 0.f, 0.f, 0.f), cf1 = cf0, cr4 = cf0, cg = cf0;
     int ic_key = -1;                 // cell word (face, species) the constants below belong to
@@ -764,7 +793,12 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
         }
         const int L0 = (int)P[j].L0, L1 = (int)P[j].L1, L2 = kS - L0 - L1;
         float fz, fr;
+        if (DIAG) {                  // W_K = 1/2 (K^{n-1/2} + K^{n+1/2}), absorbed particles included
+            kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
+            ++nlive;
+        }
         push<VAY>(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
+        if (DIAG) kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
         int d0, d1, d2;
         lam_change(cg, fz, fr, d0, d1, d2);
         const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
@@ -772,18 +806,10 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
             long long c0, c1, c2;
             piece_current(L0, L1, L2, e0, e1, e2, SINGLE ? 1 : ic.kq, c0, c1, c2);
             if (T != acc_t) {
-                if (acc_t >= 0) {
-                    win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
-                    if (DIAG) qwin_add3(qw, s.Qloc, acc_t, (long long)q0, (long long)q1, (long long)q2);
-                }
+                if (acc_t >= 0) win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
                 acc_t = T; a0 = a1 = a2 = 0;
-                q0 = q1 = q2 = 0;
             }
             a0 += c0; a1 += c1; a2 += c2;
-            if (DIAG) {
-                const QA kq = SINGLE ? (QA)1 : (QA)(long long)ic.kq;
-                q0 += kq * (QA)e0; q1 += kq * (QA)e1; q2 += kq * (QA)e2;
-            }
             P[j].L0 = (uint32_t)e0;
             P[j].L1 = (uint32_t)e1;
             if (do_count) {
@@ -799,13 +825,11 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
             mfr[j] = fr;
         }
     }
+    wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
     if (DIAG) {
-        wave_deposit_q<QA>(w, s.Jloc, qw, s.Qloc, acc_t, a0, a1, a2, q0, q1, q2);
-        // kinetic energy of u^{n+1/2} of every particle pushed (absorbed ones included)
-        const double v = wave_sum_d(kin_sum<SINGLE>(m, k0, P, live0));
-        if ((threadIdx.x & 63) == 0) s_wk[threadIdx.x >> 6] += v;
-    } else {
-        wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
+        const double v = wave_sum_d(kin);
+        const int nl = wave_sum_i(nlive);
+        if ((threadIdx.x & 63) == 0) { s_wk[threadIdx.x >> 6] = v; s_nl[threadIdx.x >> 6] = nl; }
     }
     if (do_count) wave_count(w, s.cnt, ct, cc);
     // queue the movers in LDS (one LDS atomic per wave and particle slot)
@@ -836,14 +860,14 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
         for (int j = 0; j < kPPT; ++j)
             if (slot[j] == -2) {
                 Mover mv{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
-                walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, qw, &s_nabs, mv);
+                walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, &s_nabs, mv);
                 P[j].cell = mv.cell; P[j].L0 = (uint32_t)mv.L0; P[j].L1 = (uint32_t)mv.L1;
                 if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
             }
     }
     for (int i = threadIdx.x; i < nmv; i += kWG) {
         Mover mv = s_mv[i];
-        walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, qw, &s_nabs, mv);
+        walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, &s_nabs, mv);
         s_mv[i] = mv;
         if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
     }
@@ -856,6 +880,14 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 1) void k_particles(DevMesh m, DevS
             P[j].L0 = (uint32_t)s_mv[slot[j]].L0;
             P[j].L1 = (uint32_t)s_mv[slot[j]].L1;
         }
+    if (DIAG) {
+        // level n+1: the end positions' charge (absorbed particles, cell -1, hold none)
+        __syncthreads();             // the owners have read the queue: its LDS becomes the charge window
+        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
+        __syncthreads();
+        end_charge<SINGLE, QA>(m, k0, qw, s.Qloc, P);
+        __syncthreads();
+    }
     win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
     if (DIAG) {                      // the charge window, and the block's partials of level n and n+1
         for (int i = threadIdx.x; i < 3 * kWin; i += kWG) {
@@ -933,9 +965,8 @@ __global__ __launch_bounds__(256) void k_edge_pass(DevMesh m, DevState s, int ke
 }
 
 // ------------------------------------------------------------------- SpMV
-__global__ __launch_bounds__(256) void k_spmv(DevMesh m, DevState s) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.n1) return;
+// Row i of E = M D in the sliced ELL layout (FP32, D read as its FP32 copy).
+__device__ __forceinline__ float spmv_row(const DevMesh &m, const DevState &s, int i) {
     const int sl = i >> 6, lane = i & 63;
     const int64_t beg = m.m_sptr[sl];
     const int len = m.m_slen[sl];
@@ -954,7 +985,13 @@ __global__ __launch_bounds__(256) void k_spmv(DevMesh m, DevState s) {
         acc = fmaf(v3, x3, acc);
     }
     for (; j < len; ++j) acc = fmaf(v[64 * j], s.D32[c[64 * j]], acc);
-    s.E[i] = acc;
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void k_spmv(DevMesh m, DevState s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n1) return;
+    s.E[i] = spmv_row(m, s, i);
 }
 
 // ------------------------------------------------------------------- sort
@@ -1213,88 +1250,59 @@ __global__ __launch_bounds__(kWG) void k_charge_now(DevMesh m, DevState s) {
 // was evaluated, the total charge; per edge 1/2 E^n D^n (W_E with the
 // scheme's [*eps]_a).  Each block also folds its slice of the step's
 // particle, face and edge partials (in_step).
+// Node i of an evaluation at level n = ctr->step: nodal charge (wall charge
+// plus the corners of its faces), the Gauss residual against its reference
+// and its scale, the continuity residual against the last evaluated level,
+// and the charge in charge units.
+__device__ __forceinline__ void node_vals(const DevMesh &m, DevState &s, int i, bool have_prev, bool first,
+                                          DiagVals &v) {
+    const int inst = m.ninst ? m.ninst[i] : 0;
+    long long Q = s.Qres[i];
+    for (int k = m.ncptr[i]; k < m.ncptr[i + 1]; ++k) Q += (long long)s.Qloc[m.ncorner[k]];
+    double div = 0.0, mag = 0.0;
+    long long divj = 0;
+    for (int k = m.nptr[i]; k < m.nptr[i + 1]; ++k) {
+        const int e = m.nedge[k];
+        const double d = s.D[e];
+        div += m.nsign[k] > 0 ? d : -d;
+        mag += fabs(d);
+        divj += m.nsign[k] > 0 ? s.Jfx[e] : -s.Jfx[e];
+    }
+    const double q = (double)Q * m.inst[inst].qscale;
+    if (have_prev) {
+        const long long r = (long long)kS * (Q - s.Qprev[i]) + divj;
+        v.mx[3] = (unsigned long long)(r < 0 ? -r : r);
+    }
+    s.Qprev[i] = Q;
+    s.Qfx[i] = Q;
+    if (m.nfree[i]) {
+        const double g = div - q;
+        if (first) s.g0[i] = g;
+        v.mx[0] = dbits(fabs(g - s.g0[i]));
+        v.mx[1] = dbits(fabs(g));
+        v.mx[2] = dbits(mag);
+    }
+    v.sum[0] = q;
+}
+
 __global__ __launch_bounds__(256) void k_node_diag(DevMesh m, DevState s, int in_step, int nb_face, int nb_edge) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long n = s.ctr->step;
     const bool have_prev = s.ctr->diag_level1 == n && n > 0;
     const bool first = s.ctr->g0_set == 0;
     DiagVals v{};
-    if (i < m.n0) {
-        const int inst = m.ninst ? m.ninst[i] : 0;
-        long long Q = s.Qres[i];
-        for (int k = m.ncptr[i]; k < m.ncptr[i + 1]; ++k) Q += (long long)s.Qloc[m.ncorner[k]];
-        double div = 0.0, mag = 0.0;
-        long long divj = 0;
-        for (int k = m.nptr[i]; k < m.nptr[i + 1]; ++k) {
-            const int e = m.nedge[k];
-            const double d = s.D[e];
-            div += m.nsign[k] > 0 ? d : -d;
-            mag += fabs(d);
-            divj += m.nsign[k] > 0 ? s.Jfx[e] : -s.Jfx[e];
-        }
-        const double q = (double)Q * m.inst[inst].qscale;
-        if (have_prev) {
-            const long long r = (long long)kS * (Q - s.Qprev[i]) + divj;
-            v.mx[3] = (unsigned long long)(r < 0 ? -r : r);
-        }
-        s.Qprev[i] = Q;
-        s.Qfx[i] = Q;
-        if (m.nfree[i]) {
-            const double g = div - q;
-            if (first) s.g0[i] = g;
-            v.mx[0] = dbits(fabs(g - s.g0[i]));
-            v.mx[1] = dbits(fabs(g));
-            v.mx[2] = dbits(mag);
-        }
-        v.sum[0] = q;
-    }
+    if (i < m.n0) node_vals(m, s, i, have_prev, first, v);
     if (i < m.n1) v.sum[1] = 0.5 * (double)s.E[i] * s.D[i];
-    fold_slices(s, v, in_step, nb_face, nb_edge);
+    fold_slices(s, v, in_step, nb_face, nb_edge, gridDim.x);
     const DiagVals r = block_reduce_diag(v);
     if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, gridDim.x, r);
 }
 
-// Reduces the node-pass partials of an evaluation at level n = ctr->step in
-// a fixed order into DevDiag; in a step (whose start level is n - 1),
-// appends the energy record of level n - 1 to the ring.  Sets the reference
-// flags of the next evaluation.  plain: the FP64 step's continuity residual
-// is a double (|dQ + Ddiv J| in charge units) judged against max |Q|.
-constexpr int kFinalThreads = 64 * kDiagSlots;      // one wave per slot
-
-__global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb_node, int in_step, int plain) {
-    __shared__ double res[kDiagSlots];
-    __shared__ unsigned long long cur[7];     // the counters and running values thread 0 updates
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;   // wave w reduces slot w over the node-pass blocks
-    if (w == kDiagSlots - 1 && l < 7) {       // fetched in parallel, overlapping the reduction
-        const unsigned long long *src[7] = {&s.ctr->step, &s.ctr->diag_level1, &s.ctr->energy_count,
-                                            &s.diag->gauss_drift_max_bits, &s.diag->dce_max,
-                                            &s.diag->dce_rel_max_bits, &s.diag->n_evals};
-        cur[l] = *src[l];
-    }
-    const double *p = s.part_node + (size_t)w * nb_node;   // slot w of every node-pass block
-    // four independent accumulators per lane (loads in flight together), combined in order
-    if (w < kDiagSums) {
-        double x[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = l; b < nb_node; b += 256)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + 64 * q < nb_node) x[q] += p[b + 64 * q];
-        const double t = wave_sum64d(((x[0] + x[1]) + x[2]) + x[3]);
-        if (l == 0) res[w] = t;
-    } else if (w < kDiagSums + kDiagMaxes) {
-        unsigned long long x = 0;
-        for (int b = l; b < nb_node; b += 256)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + 64 * q < nb_node) {
-                    const unsigned long long y = dbits(p[b + 64 * q]);
-                    x = y > x ? y : x;
-                }
-        x = wave_max64(x);
-        if (l == 0) res[w] = __longlong_as_double((long long)x);
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
+// The bookkeeping of an evaluation (one thread): res holds the kDiagSums
+// sums and the kDiagMaxes maxima (bit patterns as doubles), cur the step,
+// the continuity reference, the energy count and the running maxima.
+__device__ __forceinline__ void finish_eval(DevState s, const double *res, const unsigned long long *cur, int in_step,
+                                         int plain) {
     DiagVals r{};
 #pragma unroll
     for (int k = 0; k < kDiagSums; ++k) r.sum[k] = res[k];
@@ -1339,6 +1347,88 @@ __global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb
     }
     ctr.diag_level1 = n + 1;
     ctr.g0_set = 1;
+}
+
+__device__ __forceinline__ void load_eval_state(const DevState &s, int l, unsigned long long *cur) {
+    const unsigned long long *src[7] = {&s.ctr->step, &s.ctr->diag_level1, &s.ctr->energy_count,
+                                        &s.diag->gauss_drift_max_bits, &s.diag->dce_max, &s.diag->dce_rel_max_bits,
+                                        &s.diag->n_evals};
+    cur[l] = *src[l];
+}
+
+// Reduces the node-pass partials of an evaluation at level n = ctr->step in
+// a fixed order into DevDiag; in a step (whose start level is n - 1),
+// appends the energy record of level n - 1 to the ring.  Sets the reference
+// flags of the next evaluation.  plain: the FP64 step's continuity residual
+// is a double (|dQ + Ddiv J| in charge units) judged against max |Q|.
+constexpr int kFinalThreads = 64 * kDiagSlots;      // one wave per slot
+
+__global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb_node, int in_step, int plain,
+                                                               int nb_we) {
+    __shared__ double res[kDiagSlots];
+    __shared__ unsigned long long cur[7];     // the counters and running values thread 0 updates
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;   // wave w reduces slot w over the node-pass blocks
+    if (w == kDiagSlots - 1 && l < 7) load_eval_state(s, l, cur);   // in parallel with the reduction
+    // slot w of every node-pass block; with nb_we > 0 the energy of the new
+    // level comes from the SpMV blocks' partials instead
+    const bool we = w == kSumWEnow && nb_we > 0;
+    const double *p = we ? s.part_wenow : s.part_node + (size_t)w * nb_node;
+    const int nb = we ? nb_we : nb_node;
+    // four independent accumulators per lane (loads in flight together), combined in order
+    if (w < kDiagSums) {
+        double x[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = l; b < nb; b += 256)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + 64 * q < nb) x[q] += p[b + 64 * q];
+        const double t = wave_sum64d(((x[0] + x[1]) + x[2]) + x[3]);
+        if (l == 0) res[w] = t;
+    } else if (w < kDiagSums + kDiagMaxes) {
+        unsigned long long x = 0;
+        for (int b = l; b < nb_node; b += 256)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + 64 * q < nb_node) {
+                    const unsigned long long y = dbits(p[b + 64 * q]);
+                    x = y > x ? y : x;
+                }
+        x = wave_max64(x);
+        if (l == 0) res[w] = __longlong_as_double((long long)x);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) finish_eval(s, res, cur, in_step, plain);
+}
+
+// E = M D of a diagnostic step, with 1/2 E D of the new level summed per
+// block of rows (the energy the evaluation reports for that level).
+__global__ __launch_bounds__(256) void k_spmv_we(DevMesh m, DevState s) {
+    __shared__ double wsum[4];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int i = blockIdx.x * 256 + t;
+    double we = 0.0;
+    if (i < m.n1) {
+        const float e = spmv_row(m, s, i);
+        s.E[i] = e;
+        we = 0.5 * (double)e * s.D[i];
+    }
+    we = wave_sum64d(we);
+    if (l == 0) wsum[w] = we;
+    __syncthreads();
+    if (t == 0) s.part_wenow[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
+// The node pass of a diagnostic step: one thread per node only (the energy
+// of the new level comes from the SpMV blocks).
+__global__ __launch_bounds__(256) void k_node_step(DevMesh m, DevState s, int nb_face, int nb_edge) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long n = s.ctr->step;
+    const bool have_prev = s.ctr->diag_level1 == n && n > 0;
+    const bool first = s.ctr->g0_set == 0;
+    DiagVals v{};
+    if (i < m.n0) node_vals(m, s, i, have_prev, first, v);
+    fold_slices(s, v, 1, nb_face, nb_edge, gridDim.x);
+    const DiagVals r = block_reduce_diag(v);
+    if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, gridDim.x, r);
 }
 
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
@@ -1538,13 +1628,20 @@ static int node_blocks(const DevMesh &m) { return (int)nblk(m.n0 > m.n1 ? m.n0 :
 
 void launch_diag_final(const DevMesh &m, DevState &s, bool in_step, bool plain, hipStream_t st) {
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kFinalThreads), 0, st, s, node_blocks(m), in_step ? 1 : 0,
-                       plain ? 1 : 0);
+                       plain ? 1 : 0, 0);
 }
 
 void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st) {
     hipLaunchKernelGGL(k_node_diag, dim3(node_blocks(m)), dim3(256), 0, st, m, s, 1, (int)nblk(m.n2, 256),
                        (int)nblk(m.n1, 256));
     launch_diag_final(m, s, true, false, st);
+}
+
+void launch_spmv_diag(const DevMesh &m, DevState &s, hipStream_t st) {
+    const int nb_node = (int)nblk(m.n0, 256), nb_spmv = (int)nblk(m.n1, 256);
+    hipLaunchKernelGGL(k_spmv_we, dim3(nb_spmv), dim3(256), 0, st, m, s);
+    hipLaunchKernelGGL(k_node_step, dim3(nb_node), dim3(256), 0, st, m, s, (int)nblk(m.n2, 256), nb_spmv);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kFinalThreads), 0, st, s, nb_node, 1, 0, nb_spmv);
 }
 
 void launch_diag_now(const DevMesh &m, DevState &s, hipStream_t st) {

@@ -684,7 +684,7 @@ __global__ __launch_bounds__(256) void k_node_diag_d(DevMesh m, DevState s, DevP
         d.sum[kSumQ] = Qv * qunit;
     }
     if (v < m.n1) d.sum[kSumWEnow] = 0.5 * p.E[v] * s.D[v];
-    fold_slices(s, d, in_step, nb_face, nb_edge);
+    fold_slices(s, d, in_step, nb_face, nb_edge, gridDim.x);
     const DiagVals r = block_reduce_diag(d);
     if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, gridDim.x, r);
 }
