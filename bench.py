@@ -138,7 +138,8 @@ def tube_rate(args, precision=None, use_graph=1, pusher=0, diag_every=1, timing=
     ps = live_steps(c, steps, el)
     d = c.diag()
     out = {"value": ps / el, "unit": "particle-steps/s", "ms_per_step": el * 1e3 / steps, "steps": steps,
-           "sort_period": sp, "graphs": bool(use_graph), "diag_every": diag_every, "particles": int(d["n_live"]),
+           "sort_period": sp, "window_lead": c.info()["window_lead"], "graphs": bool(use_graph),
+           "diag_every": diag_every, "particles": int(d["n_live"]),
            "field_dof_steps_per_s": (info["n_edges"] + info["n_faces"]) * steps / el,
            "walk_overflow": d["walk_overflow"], "nan_count": d["nan_count"]}
     if diag_every:
@@ -569,7 +570,8 @@ def main():
         "dtype": "f32+i64",
         "data": "synthetic (seeded mesh, beam and fields)",
         "config": {"workload": desc, "faces": n2, "edges": n1, "particles": n_live, "precision": "mixed",
-                   "sort_period": head["sort_period"], "diag_every": args.diag_every},
+                   "sort_period": head["sort_period"], "window_lead": head["window_lead"],
+                   "diag_every": args.diag_every},
         "field_dof_steps_per_s": head["field_dof_steps_per_s"],
         "timing": "value and ms_per_step: wall clock of the timed steps, replayed from HIP graphs, diagnostics "
                   f"every {args.diag_every} step(s) inside them; kernel durations (phase_us_*, roofline): HIP events "

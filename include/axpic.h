@@ -149,6 +149,8 @@ typedef struct {
     double spai_feature_seconds;     /* learned SPAI: pair features (host) */
     double spai_infer_seconds;       /* learned SPAI: network inference (device, copies included) */
     double spai_solve_seconds;       /* least squares (plain); refinement, fallback and assembly (learned) */
+    int32_t sort_period;             /* sort period in use (axp_config, or the autotuner's) */
+    int32_t window_lead;             /* particle kernel's accumulation window: faces before a block's first */
 } axp_info;
 
 typedef struct {
@@ -539,13 +541,21 @@ axp_status axp_spai_model_train(const char *mesh_list, const char *out_model, ui
  * capacity). */
 axp_status axp_spai_pairs(axp_ctx *ctx, int64_t capacity, int64_t *n, float *X, float *y, int32_t *kj);
 
-/* Sort schedule autotuner: runs about trial_steps real steps under each of
- * the sort periods 1, 2, 4, 8, 16 (plus one settling window each), times
- * them with HIP events and keeps the fastest in the context's configuration
- * (*sort_period receives it; may be NULL).  The state advances by those
- * steps; since the current is summed in fixed point, the fields and
- * particles after them do not depend on the schedule (bit for bit; only the
- * storage order of the particles does). */
+/* Autotuner of two knobs of the step: runs about trial_steps real steps
+ * (plus one settling window) under each of the sort periods 1, 2, 4, 8, 16,
+ * keeps the fastest, then under each accumulation-window lead 64, 128, 192,
+ * 256, 320 of the particle kernel (faces of the window before a block's first
+ * particle's face) at that period, and keeps the fastest; timed with HIP
+ * events (*sort_period receives the period, axp_info both).  The state
+ * advances by those steps; since the current and the diagnostic charge are
+ * summed in fixed point, the fields and particles after them do not depend
+ * on the knobs (bit for bit; only the storage order of the particles does).
+ * Cache: when the environment variable AXP_AUTOTUNE_CACHE names a file, a
+ * line "key sort_period window_lead ms_per_step" is appended after the
+ * trials, and a later call whose key (mesh, particle count to the nearest
+ * power of two, precision, diagnostic cadence, pusher, GPU architecture)
+ * is found there takes the knobs from the file's last such line and runs
+ * no steps at all. */
 axp_status axp_autotune(axp_ctx *ctx, int32_t trial_steps, int32_t *sort_period);
 
 /* ---- batched sweep: many independent devices advanced together ---------

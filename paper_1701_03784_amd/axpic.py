@@ -55,7 +55,7 @@ class Info(C.Structure):
                 ("spai_kept_resid_mean", C.c_double), ("spai_energy_drift", C.c_double), ("spai_seconds", C.c_double),
                 ("n_layer_faces", C.c_int64), ("spai_guard_trip_step", C.c_int64), ("spai_run_drift", C.c_double),
                 ("spai_feature_seconds", C.c_double), ("spai_infer_seconds", C.c_double),
-                ("spai_solve_seconds", C.c_double)]
+                ("spai_solve_seconds", C.c_double), ("sort_period", C.c_int32), ("window_lead", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -401,7 +401,9 @@ class Ctx:
         return X, y, kj
 
     def autotune(self, trial_steps=16):
-        """Chooses the sort period by timing real steps; returns it."""
+        """Chooses the sort period, then the particle kernel's window lead, by
+        timing real steps (or from the AXP_AUTOTUNE_CACHE file); returns the
+        period (info() has both)."""
         sp = C.c_int32()
         self._check(self.lib.axp_autotune(self.h, int(trial_steps), C.byref(sp)))
         return sp.value

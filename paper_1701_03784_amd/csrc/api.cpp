@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -54,6 +55,8 @@ struct axp_ctx {
     int64_t last_eval_level = -1;  // time level of the last diagnostic evaluation enqueued (-1: none)
     int64_t energy_read = 0;       // energy records already returned by axp_get_energies
     bool q32 = true;               // every species' charge multiple is 0 or 1 (all members of a pool)
+    int win_lead = 192;            // accumulation window lead of the particle kernel (tuning knob)
+    uint64_t shape_hash = 0;       // mesh identity for the autotune cache (a pool: its members')
     int64_t n_live_host = 0;
     // continuous injector
     bool inj_on = false;
@@ -95,6 +98,8 @@ struct axp_ctx {
 };
 
 namespace {
+
+uint64_t mesh_hash(const axp_ctx *c);
 
 struct ApiError {
     int code;
@@ -610,7 +615,8 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
         PhaseScope ps(c, AXP_PHASE_PARTICLES, st);
-        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, diag, c->q32, st);
+        launch_particles(m, s, c->cfg.max_walk, sort_now, k0, c->cfg.pusher == AXP_PUSH_VAY, diag, c->q32, c->win_lead,
+                         st);
     }
     { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, diag, st); }
     if (diag && !c->dl.n) {
@@ -1003,6 +1009,7 @@ axp_status axp_build(axp_ctx *c) {
                                                std::to_string(c->dt_cfl)};
         build_locator(m);
         c->hm = std::move(m);
+        c->shape_hash = mesh_hash(c);
         if (hipSetDevice(c->cfg.device) != hipSuccess) throw ApiError{AXP_E_HIP, "hipSetDevice"};
         build_device(c);
         c->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1033,6 +1040,8 @@ axp_status axp_info_get(const axp_ctx *c, axp_info *out) {
     out->spai_feature_seconds = c->spai_feature_s;
     out->spai_infer_seconds = c->spai_infer_s;
     out->spai_solve_seconds = c->spai_solve_s;
+    out->sort_period = c->cfg.sort_period;
+    out->window_lead = c->win_lead;
     return c->built ? AXP_OK : AXP_E_STATE;
 }
 
@@ -1663,6 +1672,55 @@ uint64_t mesh_hash(const axp_ctx *c) {
     return h;
 }
 
+// Autotune cache key: the mesh (a pool: its members'), the particle count
+// to the nearest power of two, the precision, the diagnostic cadence, the
+// pusher and the GPU architecture.
+std::string tune_key(const axp_ctx *c) {
+    const DevCounters h = read_counters(const_cast<axp_ctx *>(c));
+    const double n = double(h.n_slots);
+    const int lg = n > 0 ? int(std::lround(std::log2(n))) : -1;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->cfg.device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%016llx/p2^%d/prec%d/diag%d/push%d/%s",
+                  (unsigned long long)c->shape_hash, lg, int(c->cfg.precision), int(c->cfg.diag_every),
+                  int(c->cfg.pusher), arch.c_str());
+    return buf;
+}
+
+// The last line of the cache file with this key: "key sort_period window_lead ms_per_step".
+bool cache_lookup(const char *path, const std::string &key, int &sp, int &wl) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[256];
+        int a = 0, b = 0;
+        double ms = 0;
+        if (std::sscanf(line, "%255s %d %d %lf", k, &a, &b, &ms) == 4 && key == k && a >= 1 && a <= 1024 && b >= 0 &&
+            b < 512) {
+            sp = a;
+            wl = b;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int sp, int wl, double ms) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;                 // an unwritable cache only costs the next run its trials
+    char line[512];
+    const int len = std::snprintf(line, sizeof(line), "%s %d %d %.6f\n", key.c_str(), sp, wl, ms);
+    if (len > 0) std::fwrite(line, 1, size_t(len), f);     // one write: appends from several processes stay whole
+    std::fclose(f);
+}
+
 struct CkptHeader {
     char magic[8];
     uint64_t mesh;
@@ -1928,14 +1986,22 @@ axp_status axp_autotune(axp_ctx *c, int32_t trial_steps, int32_t *sort_period) {
     return guarded(c, [&]() -> axp_status {
         require_built(c);
         if (c->timing) throw ApiError{AXP_E_STATE, "turn timing off before autotuning"};
-        const int cand[] = {1, 2, 4, 8, 16};
+        const std::string key = tune_key(c);
+        const char *cache = std::getenv("AXP_AUTOTUNE_CACHE");
+        int sp_c = 0, wl_c = 0;
+        if (cache && *cache && cache_lookup(cache, key, sp_c, wl_c)) {
+            c->cfg.sort_period = sp_c;
+            c->win_lead = wl_c;
+            drop_graphs(c);
+            if (sort_period) *sort_period = sp_c;
+            return AXP_OK;
+        }
         hipEvent_t e0, e1;
         hcheck(hipEventCreate(&e0), "event");
         hcheck(hipEventCreate(&e1), "event");
-        double best = 1e300;
-        int best_sp = c->cfg.sort_period;
-        for (int sp : cand) {
-            c->cfg.sort_period = sp;
+        // time trial_steps real steps (whole graph windows) under the current knobs
+        auto trial = [&]() {
+            const int sp = c->cfg.sort_period;
             drop_graphs(c);
             // align to the sort period, then one window to build the graph and settle the order
             const int align = int((sp - c->step % sp) % sp);
@@ -1947,13 +2013,30 @@ axp_status axp_autotune(axp_ctx *c, int32_t trial_steps, int32_t *sort_period) {
             hcheck(hipEventSynchronize(e1), "event sync");
             float ms = 0.f;
             hcheck(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-            const double per = double(ms) / n;
+            return double(ms) / n;
+        };
+        // knob 1: the sort period; knob 2, at the best period: the lead of the
+        // particle kernel's accumulation window
+        double best = 1e300;
+        int best_sp = c->cfg.sort_period;
+        for (int sp : {1, 2, 4, 8, 16}) {
+            c->cfg.sort_period = sp;
+            const double per = trial();
             if (per < best) { best = per; best_sp = sp; }
         }
+        c->cfg.sort_period = best_sp;
+        int best_wl = c->win_lead;
+        best = 1e300;
+        for (int wl : {64, 128, 192, 256, 320}) {
+            c->win_lead = wl;
+            const double per = trial();
+            if (per < best) { best = per; best_wl = wl; }
+        }
+        c->win_lead = best_wl;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        c->cfg.sort_period = best_sp;
         drop_graphs(c);
+        if (cache && *cache) cache_store(cache, key, best_sp, best_wl, best);
         if (sort_period) *sort_period = best_sp;
         return AXP_OK;
     });
@@ -2030,6 +2113,13 @@ axp_status axp_batch_create(axp_ctx *const *ctxs, int32_t n, axp_batch **out) {
     b->pool = p;
     b->ctxs.assign(ctxs, ctxs + n);
     p->cfg = ctxs[0]->cfg;      // diagnostic steps of the pool evaluate all members together
+    p->shape_hash = 1469598103934665603ull;
+    for (int k = 0; k < n; ++k) {
+        for (int q = 0; q < 8; ++q) {
+            p->shape_hash ^= (ctxs[k]->shape_hash >> (8 * q)) & 0xFFull;
+            p->shape_hash *= 1099511628211ull;
+        }
+    }
     p->q32 = q32;
     p->stream = ctxs[0]->stream;
     const axp_status st = guarded(p, [&]() -> axp_status {

@@ -225,8 +225,10 @@ void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const Dev
 void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st);
 // gather, push and walk of every particle, with the charge-conserving current
 // (q32: every charge multiple is 0 or 1; the single case implies it)
+// (win_lead: faces of the accumulation window before the block's first face,
+// a tuning knob that changes where sums land, never their values)
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
-                      bool diag, bool q32, hipStream_t st);
+                      bool diag, bool q32, int win_lead, hipStream_t st);
 void launch_sort_zero(const DevMesh &m, DevState &s, hipStream_t st);
 void launch_edge_pass(const DevMesh &m, DevState &s, bool keep_j, bool diag, hipStream_t st);
 void launch_spmv(const DevMesh &m, DevState &s, hipStream_t st);

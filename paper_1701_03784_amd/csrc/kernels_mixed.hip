@@ -178,7 +178,7 @@ __device__ __forceinline__ long long wave_sum64(long long v) {
 // a sort.  With the walk queue that is 24.6 KB of LDS per block, which keeps
 // the 6 waves per SIMD the registers allow.
 constexpr int kWin = 512;
-constexpr int kWinLead = 192;    // window starts this many faces before the block's first face
+constexpr int kWinLead = 192;    // default: the window starts this many faces before the block's first face
 
 struct Win {
     unsigned long long *jl;      // LDS, 3 * kWin
@@ -706,7 +706,7 @@ __device__ __forceinline__ void end_charge(const DevMesh &m, const PushConst &k0
 // single case).
 template <bool SINGLE, bool VAY, bool DIAG, bool Q32>
 __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
-                                                               PushConst k0) {
+                                                      PushConst k0, int win_lead) {
     __shared__ int s_nmv;
     __shared__ int s_base;
     __shared__ unsigned long long s_jl[3 * kWin];
@@ -757,7 +757,7 @@ __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int
     if (threadIdx.x == 0) {
         s_nmv = 0;
         s_nabs = 0;
-        s_base = (P[0].cell >= 0 ? (P[0].cell & kCellMask) : 0) - kWinLead;
+        s_base = (P[0].cell >= 0 ? (P[0].cell & kCellMask) : 0) - win_lead;
     }
     Win w{s_jl, s_cl, 0};
     win_zero(w);
@@ -1258,15 +1258,43 @@ __device__ __forceinline__ void node_vals(const DevMesh &m, DevState &s, int i, 
                                           DiagVals &v) {
     const int inst = m.ninst ? m.ninst[i] : 0;
     long long Q = s.Qres[i];
-    for (int k = m.ncptr[i]; k < m.ncptr[i + 1]; ++k) Q += (long long)s.Qloc[m.ncorner[k]];
+    // four incident corners and edges at a time: their index loads, then their
+    // value loads, are in flight together; the sums keep the list order
+    const int c0 = m.ncptr[i], c1 = m.ncptr[i + 1];
+    for (int k = c0; k < c1; k += 4) {
+        int idx[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) idx[q] = k + q < c1 ? m.ncorner[k + q] : -1;
+        long long v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = idx[q] >= 0 ? (long long)s.Qloc[idx[q]] : 0ll;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Q += v[q];
+    }
     double div = 0.0, mag = 0.0;
     long long divj = 0;
-    for (int k = m.nptr[i]; k < m.nptr[i + 1]; ++k) {
-        const int e = m.nedge[k];
-        const double d = s.D[e];
-        div += m.nsign[k] > 0 ? d : -d;
-        mag += fabs(d);
-        divj += m.nsign[k] > 0 ? s.Jfx[e] : -s.Jfx[e];
+    const int e0 = m.nptr[i], e1 = m.nptr[i + 1];
+    for (int k = e0; k < e1; k += 4) {
+        int e[4], sg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            e[q] = k + q < e1 ? m.nedge[k + q] : -1;
+            sg[q] = k + q < e1 ? m.nsign[k + q] : 0;
+        }
+        double d[4];
+        long long j[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d[q] = e[q] >= 0 ? s.D[e[q]] : 0.0;
+            j[q] = e[q] >= 0 ? s.Jfx[e[q]] : 0ll;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (e[q] >= 0) {
+                div += sg[q] > 0 ? d[q] : -d[q];
+                mag += fabs(d[q]);
+                divj += sg[q] > 0 ? j[q] : -j[q];
+            }
     }
     const double q = (double)Q * m.inst[inst].qscale;
     if (have_prev) {
@@ -1505,26 +1533,28 @@ void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const De
 // per-particle table lookup.
 template <bool SINGLE, bool VAY>
 static void launch_particles_t(const DevMesh &m, DevState &s, int max_walk, int dc, PushConst k0, bool diag,
-                               bool q32, dim3 grid, hipStream_t st) {
-    if (!diag) hipLaunchKernelGGL((k_particles<SINGLE, VAY, false, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+                               bool q32, int wl, dim3 grid, hipStream_t st) {
+    if (!diag)
+        hipLaunchKernelGGL((k_particles<SINGLE, VAY, false, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0, wl);
     else if (SINGLE || q32)
-        hipLaunchKernelGGL((k_particles<SINGLE, VAY, true, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
-    else hipLaunchKernelGGL((k_particles<SINGLE, VAY, true, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0);
+        hipLaunchKernelGGL((k_particles<SINGLE, VAY, true, true>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0, wl);
+    else hipLaunchKernelGGL((k_particles<SINGLE, VAY, true, false>), grid, dim3(kWG), 0, st, m, s, max_walk, dc, k0, wl);
 }
 
 void launch_particles(const DevMesh &m, DevState &s, int max_walk, bool count, const InstConst *single, bool vay,
-                      bool diag, bool q32, hipStream_t st) {
+                      bool diag, bool q32, int win_lead, hipStream_t st) {
     if (s.capacity == 0) return;
     const dim3 grid(nblk(s.capacity, kChunk));
     const int dc = count ? 1 : 0;
+    const int wl = win_lead < 0 ? 0 : (win_lead >= kWin ? kWin - 1 : win_lead);
     if (single) {
         const PushConst k0{single->qe[0], single->qb[0], single->cdt, single->bz, 1, 1.0f};
-        if (vay) launch_particles_t<true, true>(m, s, max_walk, dc, k0, diag, true, grid, st);
-        else launch_particles_t<true, false>(m, s, max_walk, dc, k0, diag, true, grid, st);
+        if (vay) launch_particles_t<true, true>(m, s, max_walk, dc, k0, diag, true, wl, grid, st);
+        else launch_particles_t<true, false>(m, s, max_walk, dc, k0, diag, true, wl, grid, st);
     } else {
         const PushConst k0{0.f, 0.f, 0.f, 0.f, 1, 1.0f};
-        if (vay) launch_particles_t<false, true>(m, s, max_walk, dc, k0, diag, q32, grid, st);
-        else launch_particles_t<false, false>(m, s, max_walk, dc, k0, diag, q32, grid, st);
+        if (vay) launch_particles_t<false, true>(m, s, max_walk, dc, k0, diag, q32, wl, grid, st);
+        else launch_particles_t<false, false>(m, s, max_walk, dc, k0, diag, q32, wl, grid, st);
     }
 }
 

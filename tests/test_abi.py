@@ -61,7 +61,8 @@ def _c_layout():
                            "particle_capacity", "n_particles", "step", "precision", "n_species", "spai_mode",
                            "spai_fallback_columns", "spai_pred_resid_mean", "spai_kept_resid_mean",
                            "spai_energy_drift", "spai_seconds", "n_layer_faces", "spai_guard_trip_step",
-                           "spai_run_drift", "spai_feature_seconds", "spai_infer_seconds", "spai_solve_seconds"],
+                           "spai_run_drift", "spai_feature_seconds", "spai_infer_seconds", "spai_solve_seconds",
+                           "sort_period", "window_lead"],
               "axp_diag": ["step", "n_live", "n_absorbed", "walk_overflow", "nan_count", "fixed_overflow",
                            "dce_max_abs", "dce_max_rel", "gauss_max_drift", "gauss_max_abs", "gauss_scale", "W_E",
                            "W_B", "W_K", "Q_total", "energy_step", "n_evals", "W_E_now"],

@@ -148,15 +148,44 @@ def test_batch_with_diagnostic_steps_matches_members_alone(axp):
         axp.Batch([_cavity_member(axp, diag_every=1), _cavity_member(axp, diag_every=2)])
 
 
-def test_autotune_keeps_results(axp):
+def test_autotune_keeps_results(axp, monkeypatch):
+    """Both knobs (sort period, window lead) change where sums land, never
+    their values: the tuned run equals a run with the default knobs."""
     print("[gpu] autotune vs fixed schedule", flush=True)
-    a = _tube_member(axp, use_graph=1)
+    monkeypatch.delenv("AXP_AUTOTUNE_CACHE", raising=False)
+    a = _tube_member(axp, use_graph=1, diag_every=1)
     sp = a.autotune(trial_steps=8)
-    assert sp in (1, 2, 4, 8, 16)
-    n = a.info()["step"]
-    b = _tube_member(axp, use_graph=0)
+    info = a.info()
+    assert sp in (1, 2, 4, 8, 16) and info["sort_period"] == sp
+    assert info["window_lead"] in (64, 128, 192, 256, 320)
+    n = info["step"]
+    assert n >= 10 * 8                                 # ten trials ran
+    b = _tube_member(axp, use_graph=0, diag_every=1)
+    assert b.info()["window_lead"] == 192
     b.step(n)
     _assert_same(_state(a), _state(b), "autotuned")
+    da, db = a.diag(), b.diag()
+    assert da["dce_max_abs"] == db["dce_max_abs"] == 0 and da["Q_total"] == db["Q_total"]
+
+
+def test_autotune_cache(axp, tmp_path, monkeypatch):
+    """A cache hit applies the stored knobs and runs no step; another
+    particle count (two powers of two away) is another key."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("AXP_AUTOTUNE_CACHE", str(path))
+    print("[gpu] autotune cache", flush=True)
+    a = _tube_member(axp, use_graph=1)
+    sp = a.autotune(trial_steps=4)
+    wl = a.info()["window_lead"]
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:3] == [str(sp), str(wl)]
+    assert "gfx950" in lines[0].split()[0]
+    b = _tube_member(axp, use_graph=1)
+    assert b.autotune(trial_steps=4) == sp
+    assert b.info()["window_lead"] == wl and b.info()["step"] == 0
+    c = _tube_member(axp, n_part=24000, use_graph=1)
+    c.autotune(trial_steps=4)
+    assert c.info()["step"] > 0 and len(path.read_text().splitlines()) == 2
 
 
 def test_batch_rejects_plain_members(axp):
