@@ -68,7 +68,9 @@ _OPENMP = False
 def _load():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build_oracle(openmp=_OPENMP))
+        # ORACLE_PIC_LIBRARY: another build of pic_step.c (the sanitizer test's)
+        alt = os.environ.get("ORACLE_PIC_LIBRARY")
+        _lib = C.CDLL(alt if alt else build_oracle(openmp=_OPENMP))
         vp = C.c_void_p
         _lib.oracle_step.argtypes = [vp, vp, C.c_double, C.c_double, C.c_int, C.c_int64, vp, vp, vp] + [vp] * 9
         _lib.oracle_step.restype = None
