@@ -103,7 +103,7 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, p
     from synth import configs
     import paper_1701_03784_amd as axp
     t0 = time.perf_counter()
-    m = configs.bwo_mesh(seed=seed)
+    m = configs.bwo_mesh(seed=seed, emitter=(0.009, 0.011))
     L = m.meta["length"]
     kw = {} if precision is None else {"precision": precision}
     c = axp.make_ctx(m, sort_period=sort_period, use_graph=use_graph, pusher=pusher, diag_every=diag_every, **kw)
@@ -114,10 +114,17 @@ def setup_bwo(n_particles, seed=3, sort_period=4, precision=None, use_graph=1, p
     sp = c.add_species(synth.ELECTRON_CHARGE, synth.ELECTRON_MASS, w)
     zr, u = configs.bwo_beam(n_particles, L, seed=seed)
     c.inject(sp, zr, u)
+    # replenishment from the upstream plate's annulus at the beam's current
+    # (1.5 kA): balances what the collector absorbs
+    g, b = configs.gamma_beta_from_kev(configs.BWO_KEV)
+    per_step = int(round(1500.0 * info["dt"] / (w * abs(synth.ELECTRON_CHARGE))))
+    c.set_injector(sp, per_step, [0.0, 0.0, g * b * C], 0.0, seed + 100)
     log(f"bwo ctx: {m.n_tris} faces, {info['n_edges']} edges, SPAI nnz {info['spai_nnz']}, dt {info['dt']:.3e} s, "
-        f"{n_particles} particles (weight {w}), diag_every {diag_every}, {time.perf_counter() - t0:.1f} s")
+        f"{n_particles} particles (weight {w}, {per_step} emitted per step), diag_every {diag_every}, "
+        f"{time.perf_counter() - t0:.1f} s")
     desc = (f"bwo: rippled-wall tube R=1.5+0.25 sin cm, 10 periods of 1.67 cm + drifts, {m.n_tris} faces, "
-            f"{info['n_edges']} edges; {n_particles} macro-electrons, 500 keV annular beam, B_z=1 T; "
+            f"{info['n_edges']} edges; {n_particles} macro-electrons preloaded, {per_step} emitted per step from "
+            f"the upstream plate's annulus (1.5 kA), 500 keV annular beam, B_z=1 T; "
             f"SPAI level 3 ({info['spai_nnz']} nnz); dt=0.5 CFL")
     return c, m, info, desc
 

@@ -580,7 +580,9 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     const bool diag = diag_step(c, c->step);
     DevMesh &m = c->dm;
     DevState &s = c->ds;
-    if (c->inj_on) {
+    // the mixed step's emission rides in the face pass when it fits one block
+    const bool emit_in_face = c->inj_on && !c->plain && emission_fits_face_pass(c->inj);
+    if (c->inj_on && !emit_in_face) {
         PhaseScope ps(c, AXP_PHASE_INJECT, st);
         if (c->plain) launch_inject_plain(m, s, c->dp, c->inj_edges, c->inj, st);
         else launch_inject(m, s, c->inj_edges, c->inj, st);
@@ -611,7 +613,10 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     }
     const bool single = m.tinst == nullptr && c->ic.n_species == 1 && c->ic.kq[0] == 1;
     const InstConst *k0 = single ? &c->ic : nullptr;
-    { PhaseScope ps(c, AXP_PHASE_FACE, st); launch_tri_pass(m, s, c->fs, c->dl, diag, st); }
+    {
+        PhaseScope ps(c, AXP_PHASE_FACE, st);
+        launch_tri_pass(m, s, c->fs, c->dl, diag, c->inj_edges, emit_in_face ? &c->inj : nullptr, st);
+    }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
         PhaseScope ps(c, AXP_PHASE_PARTICLES, st);

@@ -218,8 +218,11 @@ struct DevPlain {
 };
 
 // ---- launchers (kernels_mixed.hip) ----
+// the face pass; with emit (1 to 4096 per step from an emitter of at most 1024
+// edges) its last block also does the step's emission
+bool emission_fits_face_pass(const InjParams &p);
 void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
-                     hipStream_t st);
+                     const EmitEdge *ee, const InjParams *emit, hipStream_t st);
 // layer update after E^{n+1}: q, eprev and the corrections of D (E: FP32 or FP64 edge values)
 void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const DevLayers &lay, hipStream_t st);
 void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st);

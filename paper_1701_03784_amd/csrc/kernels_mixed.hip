@@ -126,7 +126,60 @@ __device__ __forceinline__ double tri_pass_face(const DevMesh &m, const DevState
 // Faraday update of every face (and its gather tile).  diag: the step
 // evaluates the diagnostics of its start level; the face pass then clears
 // the corner charges and leaves one partial of W_B per block.
-__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay, int diag) {
+// Emission of one step by one block (the step's count n_slots, the draws'
+// counter inj_step): particle n_slots + i at its emission point on an
+// emitter edge (the face's third coordinate 0), its charge taken from the
+// edge's tail and head nodes' wall charge in fixed point (the nodal charge
+// is unchanged), summed per edge end in LDS (s_q, 2 per edge) and added with
+// one atomic per edge end; then the block commits the count.
+constexpr int kInjMaxEdges = 1024;
+
+__device__ __forceinline__ void inject_block(const DevState &s, const EmitEdge *ee, const InjParams &p,
+                                             unsigned long long *s_q) {
+    for (int k = threadIdx.x; k < 2 * p.n_edges; k += blockDim.x) s_q[k] = 0ull;
+    const unsigned long long step = s.ctr->inj_step;
+    const long long base = (long long)s.ctr->n_slots;
+    __syncthreads();
+    const int c = s.cur;
+    for (int i = threadIdx.x; i < p.per_step; i += blockDim.x) {
+        const long long q = base + i;
+        const Emission em = sample_emission(ee, p, step, i);
+        const EmitEdge E = ee[em.e];
+        int La = (int)rint((1.0 - em.s) * (double)kS);
+        La = La < 0 ? 0 : (La > kS ? kS : La);
+        const int Lb = kS - La;
+        const int L0 = E.ka == 0 ? La : (E.kb == 0 ? Lb : 0);
+        const int L1 = E.ka == 1 ? La : (E.kb == 1 ? Lb : 0);
+        s.cell[c][q] = E.face | (p.species << kCellBits);
+        s.L0[c][q] = (uint32_t)L0;
+        s.L1[c][q] = (uint32_t)L1;
+        s.ur[c][q] = (float)em.ur;
+        s.up[c][q] = (float)em.up;
+        s.uz[c][q] = (float)em.uz;
+        atomicAdd(&s_q[2 * em.e], (unsigned long long)(-(long long)La * p.kq));
+        atomicAdd(&s_q[2 * em.e + 1], (unsigned long long)(-(long long)Lb * p.kq));
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 2 * p.n_edges; k += blockDim.x)
+        if (s_q[k]) {
+            const EmitEdge &E = ee[k >> 1];
+            atomicAdd((unsigned long long *)&s.Qres[(k & 1) ? E.nb : E.na], s_q[k]);
+        }
+    if (threadIdx.x == 0) {
+        s.ctr->n_slots = (unsigned long long)base + (unsigned long long)p.per_step;
+        s.ctr->inj_step = step + 1ull;
+    }
+}
+
+// The face pass; with ip.per_step > 0 its last block is the step's emission
+// (independent of the faces, so it overlaps them and costs no launch).
+__global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay, int diag,
+                                                  const EmitEdge *ee, InjParams ip) {
+    if (ip.per_step > 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
+        __shared__ unsigned long long s_q[2 * kInjMaxEdges];
+        inject_block(s, ee, ip, s_q);
+        return;
+    }
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const double wb = t < m.n2 ? tri_pass_face(m, s, fs, lay, t, diag != 0) : 0.0;
     if (!diag) return;                          // uniform across the grid
@@ -724,10 +777,14 @@ __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int
     __shared__ double s_wk[kWG / 64];
     __shared__ int s_nl[kWG / 64];
     __shared__ int s_nabs;
-    const int chunk = xcd_block(blockIdx.x, gridDim.x);
+    // The grid covers the buffer's capacity (a graph replays one launch
+    // while emission and sorts change the count): only the first nbv blocks
+    // have particles, and they are spread over all XCDs in contiguous chunks.
     const long long n = (long long)s.ctr->n_slots;
+    const int nbv = (int)((n + kChunk - 1) / kChunk);
+    if ((int)blockIdx.x >= nbv) return;                     // whole block past the end
+    const int chunk = xcd_block(blockIdx.x, nbv);
     const long long p0 = ((long long)chunk * kWG + threadIdx.x) * kPPT;
-    if ((long long)chunk * kChunk >= n) return;             // whole block past the end
     const int c = s.cur;
     int32_t *cell = s.cell[c];
     uint32_t *L0a = s.L0[c], *L1a = s.L1[c];
@@ -1507,10 +1564,17 @@ __global__ __launch_bounds__(256) void k_layer_edges(DevMesh m, DevState s, DevL
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+bool emission_fits_face_pass(const InjParams &p) {
+    return p.per_step > 0 && p.per_step <= 4096 && p.n_edges <= kInjMaxEdges;
+}
+
 void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
-                     hipStream_t st) {
+                     const EmitEdge *ee, const InjParams *emit, hipStream_t st) {
     if (m.n2 == 0) return;
-    hipLaunchKernelGGL(k_tri_pass, dim3(nblk(m.n2, 256)), dim3(256), 0, st, m, s, fs, lay, diag ? 1 : 0);
+    InjParams ip{};
+    if (emit && emission_fits_face_pass(*emit)) ip = *emit;
+    const unsigned nb = (unsigned)nblk(m.n2, 256) + (ip.per_step > 0 ? 1u : 0u);
+    hipLaunchKernelGGL(k_tri_pass, dim3(nb), dim3(256), 0, st, m, s, fs, lay, diag ? 1 : 0, ee, ip);
 }
 
 template <class T>
@@ -1633,8 +1697,21 @@ __global__ void k_inject_commit(DevState s, int per_step) {
     s.ctr->inj_step += 1ull;
 }
 
+// The emission alone, in one block (sizes too large for the face pass's
+// block take the multi-block kernel and the commit above).
+constexpr int kInjBlock = 1024, kInjMaxOne = 16 * kInjBlock;
+
+__global__ __launch_bounds__(kInjBlock) void k_inject_one(DevMesh m, DevState s, const EmitEdge *ee, InjParams p) {
+    __shared__ unsigned long long s_q[2 * kInjMaxEdges];
+    inject_block(s, ee, p, s_q);
+}
+
 void launch_inject(const DevMesh &m, DevState &s, const EmitEdge *ee, const InjParams &p, hipStream_t st) {
     if (p.per_step <= 0) return;
+    if (p.per_step <= kInjMaxOne && p.n_edges <= kInjMaxEdges) {
+        hipLaunchKernelGGL(k_inject_one, dim3(1), dim3(kInjBlock), 0, st, m, s, ee, p);
+        return;
+    }
     hipLaunchKernelGGL(k_inject, dim3(nblk(p.per_step, 256)), dim3(256), 0, st, m, s, ee, p);
     hipLaunchKernelGGL(k_inject_commit, dim3(1), dim3(1), 0, st, s, p.per_step);
 }

@@ -72,10 +72,23 @@ def bwo_radius_fn(amp=0.0025, period=0.0167, n_periods=10, r0=0.015, up=0.02, ta
     return R, z1
 
 
-def bwo_mesh(seed=3, h=0.19e-3, amp=0.0025, period=0.0167, n_periods=10, taper=0.0, up=0.02, down=0.03):
+def bwo_mesh(seed=3, h=0.19e-3, amp=0.0025, period=0.0167, n_periods=10, taper=0.0, up=0.02, down=0.03,
+             emitter=None):
+    """The rippled-wall tube; emitter=(r_in, r_out) tags that annulus of the
+    upstream end plate as an emitting conductor (the beam's replenishment)."""
     R, z1 = bwo_radius_fn(amp, period, n_periods, 0.015, up, taper)
     L = z1 + down
-    return rippled_mesh(R, 0.0, L, h, seed=seed,
+    tags = None
+    if emitter is not None:
+        r_in, r_out = emitter
+
+        def tags(side, z, rho):
+            if side == "bottom":
+                return BC_AXIS
+            if side == "left" and r_in <= rho <= r_out:
+                return BC_EMITTER
+            return BC_PEC
+    return rippled_mesh(R, 0.0, L, h, seed=seed, tags=tags,
                         meta=dict(amp=amp, period=period, n_periods=n_periods, taper=taper, length=L))
 
 
