@@ -758,7 +758,10 @@ __device__ __forceinline__ void end_charge(const DevMesh &m, const PushConst &k0
 // of a diagnostic step accumulates in 32-bit LDS words (always so in the
 // single case).
 template <bool SINGLE, bool VAY, bool DIAG, bool Q32>
-__global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
+// Occupancy: 6 waves per SIMD (80 VGPRs) for the plain step; the diagnostic
+// step's extra live values would spill at 80 (scratch traffic measured 1.2x
+// the kernel's bytes and 20 % slower), so it takes 5 waves (96 VGPRs).
+__global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
                                                       PushConst k0, int win_lead) {
     __shared__ int s_nmv;
     __shared__ int s_base;
@@ -818,6 +821,12 @@ __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int
     }
     Win w{s_jl, s_cl, 0};
     win_zero(w);
+    if (DIAG) {                      // particles pushed in the step (live at its start), per wave
+        int nl = 0;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j) nl += __popcll(__ballot(P[j].cell >= 0));
+        if ((threadIdx.x & 63) == 0) s_nl[threadIdx.x >> 6] = nl;
+    }
     __syncthreads();
     w.base = s_base;
     const QWinL<QA> qw{s_ql, s_base};
@@ -828,7 +837,6 @@ __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int
     bool mover[kPPT];
     float mfz[kPPT], mfr[kPPT];
     double kin = 0.0;                // diagnostic steps: sum of mw (gamma - 1) at n-1/2 and n+1/2
-    int nlive = 0;                   // and the particles pushed
     int Tc = -1;                     // face data cached across the thread's particles
     float4 cf0 = make_float4(0.f, 0.f, 0.f, 0.f), cf1 = cf0, cr4 = cf0, cg = cf0;
     int ic_key = -1;                 // cell word (face, species) the constants below belong to
@@ -852,7 +860,6 @@ __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int
         float fz, fr;
         if (DIAG) {                  // W_K = 1/2 (K^{n-1/2} + K^{n+1/2}), absorbed particles included
             kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
-            ++nlive;
         }
         push<VAY>(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
         if (DIAG) kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
@@ -885,8 +892,7 @@ __global__ __launch_bounds__(kWG, 6) void k_particles(DevMesh m, DevState s, int
     wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
     if (DIAG) {
         const double v = wave_sum_d(kin);
-        const int nl = wave_sum_i(nlive);
-        if ((threadIdx.x & 63) == 0) { s_wk[threadIdx.x >> 6] = v; s_nl[threadIdx.x >> 6] = nl; }
+        if ((threadIdx.x & 63) == 0) s_wk[threadIdx.x >> 6] = v;
     }
     if (do_count) wave_count(w, s.cnt, ct, cc);
     // queue the movers in LDS (one LDS atomic per wave and particle slot)
