@@ -53,6 +53,7 @@ struct axp_ctx {
     double q_unit = 0;
     int64_t step = 0;
     int64_t last_eval_level = -1;  // time level of the last diagnostic evaluation enqueued (-1: none)
+    bool final_pending = false;    // a diagnostic step's final reduction waits for the next face pass
     int64_t energy_read = 0;       // energy records already returned by axp_get_energies
     bool q32 = true;               // every species' charge multiple is 0 or 1 (all members of a pool)
     int win_lead = 192;            // accumulation window lead of the particle kernel (tuning knob)
@@ -423,6 +424,29 @@ void build_sell(const Csr &M, int32_t n1, std::vector<int64_t> &sptr, std::vecto
         }
 }
 
+// The node lists of h as column-major slices of 64 nodes, each list padded to
+// the longest of the mesh (the node pass loads all of a node's entries at once).
+void build_node_ell(const HostTables &h, std::vector<int32_t> &corner, int32_t &wc, std::vector<int32_t> &edge,
+                    int32_t &we) {
+    wc = we = 0;
+    for (int v = 0; v < h.n0; ++v) {
+        wc = std::max(wc, h.ncptr[v + 1] - h.ncptr[v]);
+        we = std::max(we, h.nptr[v + 1] - h.nptr[v]);
+    }
+    const size_t ns = (size_t(h.n0) + 63) / 64;
+    corner.assign(ns * size_t(wc) * 64, -1);
+    edge.assign(ns * size_t(we) * 64, 0);
+    for (int v = 0; v < h.n0; ++v) {
+        const size_t sl = size_t(v) / 64, l = size_t(v) % 64;
+        for (int32_t j = 0; j < h.ncptr[v + 1] - h.ncptr[v]; ++j)
+            corner[(sl * wc + j) * 64 + l] = h.ncorner[h.ncptr[v] + j];
+        for (int32_t j = 0; j < h.nptr[v + 1] - h.nptr[v]; ++j) {
+            const int32_t q = h.nptr[v] + j;
+            edge[(sl * we + j) * 64 + l] = h.nsign[q] > 0 ? h.nedge[q] + 1 : -(h.nedge[q] + 1);
+        }
+    }
+}
+
 // Uploads the tables and allocates the field state of a context (one
 // instance: pooled = false; a batch pool: per-face / per-node instance ids).
 void upload_tables(axp_ctx *c, const HostTables &h, bool pooled, int n_inst) {
@@ -440,6 +464,11 @@ void upload_tables(axp_ctx *c, const HostTables &h, bool pooled, int n_inst) {
     d.nptr = upload(c, h.nptr); d.nedge = upload(c, h.nedge); d.nsign = upload(c, h.nsign);
     d.nfree = upload(c, h.nfree); d.ninst = pooled ? upload(c, h.ninst) : nullptr;
     d.ncptr = upload(c, h.ncptr); d.ncorner = upload(c, h.ncorner);
+    {
+        std::vector<int32_t> ce, ee;
+        build_node_ell(h, ce, d.nwc, ee, d.nwe);
+        d.ncorner_ell = upload(c, ce); d.nedge_ell = upload(c, ee);
+    }
     d.m_sptr = upload(c, sptr); d.m_slen = upload(c, slen); d.m_col = upload(c, mcol);
     d.m_val = c->plain ? nullptr : upload(c, mval);
     d.a_ptr = upload(c, h.A.ptr); d.a_col = upload(c, h.A.col); d.a_val = upload(c, h.A.val);
@@ -615,7 +644,9 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     const InstConst *k0 = single ? &c->ic : nullptr;
     {
         PhaseScope ps(c, AXP_PHASE_FACE, st);
-        launch_tri_pass(m, s, c->fs, c->dl, diag, c->inj_edges, emit_in_face ? &c->inj : nullptr, st);
+        launch_tri_pass(m, s, c->fs, c->dl, diag, c->inj_edges, emit_in_face ? &c->inj : nullptr, c->final_pending,
+                        st);
+        c->final_pending = false;
     }
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort_zero(m, s, st); }
     {
@@ -625,9 +656,11 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     }
     { PhaseScope ps(c, AXP_PHASE_EDGE, st); launch_edge_pass(m, s, true, diag, st); }
     if (diag && !c->dl.n) {
-        // one launch: E = M D beside the evaluation of the new level
+        // one launch: E = M D beside the evaluation of the new level; its final
+        // reduction rides in the next face pass (or flush_final)
         PhaseScope ps(c, AXP_PHASE_SPMV, st);
         launch_spmv_diag(m, s, st);
+        c->final_pending = true;
     } else {
         {
             PhaseScope ps(c, AXP_PHASE_SPMV, st);
@@ -639,6 +672,14 @@ void enqueue_step(axp_ctx *c, hipStream_t st) {
     ++c->step;
     if (diag) c->last_eval_level = c->step;
     if (sort_now) { PhaseScope ps(c, AXP_PHASE_SORT, st); launch_sort(m, s, true, st); }
+}
+
+// The final reduction of the last diagnostic step, if no face pass has done it yet.
+void flush_final(axp_ctx *c, hipStream_t st) {
+    if (!c->final_pending) return;
+    PhaseScope ps(c, AXP_PHASE_DIAG, st);
+    launch_step_final(c->dm, c->ds, st);
+    c->final_pending = false;
 }
 
 void drop_graphs(axp_ctx *c) {
@@ -655,13 +696,16 @@ void launch_graph(axp_ctx *c, int W) {
         if (!c->cap_stream) hcheck(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream");
         const DevState saved = c->ds;
         const int64_t saved_step = c->step, saved_eval = c->last_eval_level;
+        const bool saved_pending = c->final_pending;
         hcheck(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
         for (int k = 0; k < W; ++k) enqueue_step(c, c->cap_stream);
+        flush_final(c, c->cap_stream);   // the window leaves no reduction pending
         hipGraph_t g = nullptr;
         const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
         c->ds = saved;              // the captured launches have not run
         c->step = saved_step;
         c->last_eval_level = saved_eval;
+        c->final_pending = saved_pending;
         hcheck(e1, "end capture");
         const hipError_t e2 = hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -700,6 +744,7 @@ void run_steps(axp_ctx *c, int n_steps) {
         }
         if (graph && c->graph_window != 0 && c->graph_window != W) drop_graphs(c);
         if (graph) {
+            flush_final(c, c->stream);   // windows start with no reduction pending
             launch_graph(c, W);
             i += W;
             continue;
@@ -708,6 +753,7 @@ void run_steps(axp_ctx *c, int n_steps) {
         ++i;
         if (c->ev.size() > 4096) collect_timing(c);
     }
+    flush_final(c, c->stream);
     hcheck(hipGetLastError(), "step launch");
 }
 

@@ -45,6 +45,11 @@ struct DevMesh {
     const int8_t *nsign = nullptr;
     const uint8_t *nfree = nullptr;
     const int32_t *ninst = nullptr; // instance of each node, or null
+    // the same two lists in slices of 64 nodes, column-major (entry j of node
+    // 64 s + l at (s * w + j) * 64 + l, w the longest list of the mesh): corner
+    // ids with -1 as padding; edges as +-(e + 1) by divergence sign, 0 as padding
+    const int32_t *ncorner_ell = nullptr, *nedge_ell = nullptr;
+    int32_t nwc = 0, nwe = 0;
     // SPAI M in sliced-ELL (slices of 64 rows, column-major inside a slice)
     const int64_t *m_sptr = nullptr;
     const int32_t *m_slen = nullptr;
@@ -219,10 +224,12 @@ struct DevPlain {
 
 // ---- launchers (kernels_mixed.hip) ----
 // the face pass; with emit (1 to 4096 per step from an emitter of at most 1024
-// edges) its last block also does the step's emission
+// edges) its last block also does the step's emission; with final_prev one
+// more block does the final reduction the last diagnostic step's node pass
+// left (launch_spmv_diag)
 bool emission_fits_face_pass(const InjParams &p);
 void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
-                     const EmitEdge *ee, const InjParams *emit, hipStream_t st);
+                     const EmitEdge *ee, const InjParams *emit, bool final_prev, hipStream_t st);
 // layer update after E^{n+1}: q, eprev and the corrections of D (E: FP32 or FP64 edge values)
 void launch_layers_post(const DevMesh &m, DevState &s, const float *E, const DevLayers &lay, hipStream_t st);
 void launch_layers_post(const DevMesh &m, DevState &s, const double *E, const DevLayers &lay, hipStream_t st);
@@ -241,9 +248,11 @@ void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st);
 // the energy record of its start level n, launched after the field update.
 void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st);
 // E = M D of a diagnostic step (no absorbing layers) with the energy of the
-// new level per block of rows, then the node pass over the nodes alone and
-// the final reduction
+// new level per block of rows, then the node pass over the nodes alone.  Its
+// final reduction is left to the next face pass (final_prev) or to
+// launch_step_final, which must run before anything reads the diagnostics.
 void launch_spmv_diag(const DevMesh &m, DevState &s, hipStream_t st);
+void launch_step_final(const DevMesh &m, DevState &s, hipStream_t st);
 // Diagnostics of the current state (level = steps taken), on demand.
 void launch_diag_now(const DevMesh &m, DevState &s, hipStream_t st);
 // clears the face-corner charge accumulators (a fill kernel, graph-safe)

@@ -173,11 +173,18 @@ __device__ __forceinline__ void inject_block(const DevState &s, const EmitEdge *
 
 // The face pass; with ip.per_step > 0 its last block is the step's emission
 // (independent of the faces, so it overlaps them and costs no launch).
+// final reduction of a diagnostic step's evaluation by one block (defined with the diagnostics)
+__device__ void final_block(DevState s, int nb_node, int nb_we);
+
 __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay, int diag,
-                                                  const EmitEdge *ee, InjParams ip) {
+                                                  const EmitEdge *ee, InjParams ip, int fin_nb_node, int fin_nb_we) {
     if (ip.per_step > 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
         __shared__ unsigned long long s_q[2 * kInjMaxEdges];
         inject_block(s, ee, ip, s_q);
+        return;
+    }
+    if (fin_nb_node > 0 && (int)blockIdx.x == (m.n2 + 255) / 256) {
+        final_block(s, fin_nb_node, fin_nb_we);
         return;
     }
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -331,6 +338,34 @@ __device__ __forceinline__ void seg_scan(int run, V (&a)[N]) {
     seg_step<0x143, 0xC>(run, a);
 }
 
+// The same over two arrays at once (one run exchange per step).
+template <int CTRL, int ROWS, class V, int N, class U, int K>
+__device__ __forceinline__ void seg_step2(int run, V (&a)[N], U (&b)[K]) {
+    const int ro = dpp_mov<CTRL, ROWS>(run);
+    V x[N];
+    U y[K];
+#pragma unroll
+    for (int k = 0; k < N; ++k) x[k] = dpp_mov<CTRL, ROWS>(a[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) y[k] = dpp_mov<CTRL, ROWS>(b[k]);
+    if (ro == run) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] += x[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[k] += y[k];
+    }
+}
+
+template <class V, int N, class U, int K>
+__device__ __forceinline__ void seg_scan2(int run, V (&a)[N], U (&b)[K]) {
+    seg_step2<0x111, 0xF>(run, a, b);
+    seg_step2<0x112, 0xF>(run, a, b);
+    seg_step2<0x114, 0xF>(run, a, b);
+    seg_step2<0x118, 0xF>(run, a, b);
+    seg_step2<0x142, 0xA>(run, a, b);
+    seg_step2<0x143, 0xC>(run, a, b);
+}
+
 __device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0, long long a1,
                                              long long a2) {
     long long a[3] = {a0, a1, a2};
@@ -372,6 +407,22 @@ __device__ __forceinline__ void qwin_add3(const QWinL<QA> &w, unsigned long long
         if (q0) atomicAdd(&Qloc[3 * t], (unsigned long long)q0);
         if (q1) atomicAdd(&Qloc[3 * t + 1], (unsigned long long)q1);
         if (q2) atomicAdd(&Qloc[3 * t + 2], (unsigned long long)q2);
+    }
+}
+
+// A diagnostic step's stayers: their side currents and the corner charges of
+// their end positions (eq. charge, kq Lambda_k per corner), reduced over the
+// same runs of lanes.
+template <class QA>
+__device__ __forceinline__ void wave_deposit_q(const Win &w, unsigned long long *J, const QWinL<QA> &qw,
+                                               unsigned long long *Qloc, int t, long long a0, long long a1,
+                                               long long a2, QA q0, QA q1, QA q2) {
+    long long a[3] = {a0, a1, a2};
+    QA q[3] = {q0, q1, q2};
+    seg_scan2<long long, 3, QA, 3>(lane_run(t), a, q);
+    if (run_tail(t) && t >= 0) {
+        win_add_j(w, J, t, a[0], a[1], a[2]);
+        qwin_add3(qw, Qloc, t, (long long)q[0], (long long)q[1], (long long)q[2]);
     }
 }
 
@@ -518,10 +569,12 @@ struct Mover {
 // the path ends inside a face, is absorbed by a conductor or open boundary
 // edge (its charge kept on the wall nodes), stops on the axis, or hits the
 // piece cap.  mv holds the start (face, coordinates, remaining
-// displacement) and receives the final cell word and coordinates.
-template <bool SINGLE, bool DIAG>
-__device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const PushConst &k0,
-                                           int max_walk, int *nabs, Mover &mv) {
+// displacement) and receives the final cell word and coordinates.  In a
+// diagnostic step a particle still live at the end adds the corner charges
+// of its end position (eq. charge) to the charge window qw.
+template <bool SINGLE, bool DIAG, class QA>
+__device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const QWinL<QA> &qw,
+                                           const PushConst &k0, int max_walk, int *nabs, Mover &mv) {
     int t = mv.cell & kCellMask;
     const int sp = (mv.cell >> kCellBits) & 15;
     const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
@@ -602,6 +655,8 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
         }
         win_add_j(w, s.Jloc, tf, c0, c1, c2);
     }
+    if (DIAG && newcell >= 0)
+        qwin_add3(qw, s.Qloc, t, (long long)kq * L0, (long long)kq * L1, (long long)kq * L2);
     mv.cell = newcell;
     mv.L0 = L0;
     mv.L1 = L1;
@@ -705,55 +760,6 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v;
 }
 
-// (gamma - 1) m w c^2 / (2 pi) summed over the particles of mask in P, in
-// units of the species' mw when SINGLE (FP64 sums of FP32 terms: the storage
-// order within a face changes only their rounding)
-template <bool SINGLE>
-__device__ __forceinline__ double kin_sum(const DevMesh &m, const PushConst &k0, const Particle (&P)[kPPT],
-                                          unsigned mask) {
-    double v = 0.0;
-#pragma unroll
-    for (int j = 0; j < kPPT; ++j)
-        if (mask >> j & 1u) {
-            const int T = P[j].cell & kCellMask;
-            const float mw = SINGLE ? 1.0f : push_const<SINGLE>(m, k0, T, (P[j].cell >> kCellBits) & 15).mw;
-            v += (double)(mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
-        }
-    return v;
-}
-
-// Charge of the particles' end positions (level n+1, eq. charge) in a
-// diagnostic step: the thread folds its particles face by face, the wave
-// sums runs of lanes holding the same face, and each run's last lane adds
-// the three corner sums kq Lambda_k to the block's charge window.  Done after
-// the walk, when the push's registers are free.  With QA = 32-bit words a
-// wave's sums stay below 2^32 (256 particles of at most 2^23 each).
-template <bool SINGLE, class QA>
-__device__ __forceinline__ void end_charge(const DevMesh &m, const PushConst &k0, const QWinL<QA> &qw,
-                                           unsigned long long *Qloc, const Particle (&P)[kPPT]) {
-    int qt = -1;
-    QA q[3] = {0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < kPPT; ++j) {
-        if (P[j].cell < 0) continue;
-        const int T = P[j].cell & kCellMask;
-        if (T != qt) {
-            if (qt >= 0) qwin_add3(qw, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
-            qt = T;
-            q[0] = q[1] = q[2] = 0;
-        }
-        const QA L0 = (QA)P[j].L0, L1 = (QA)P[j].L1, L2 = (QA)kS - L0 - L1;
-        if (SINGLE) {
-            q[0] += L0; q[1] += L1; q[2] += L2;
-        } else {
-            const QA kq = (QA)(long long)push_const<SINGLE>(m, k0, T, (P[j].cell >> kCellBits) & 15).kq;
-            q[0] += kq * L0; q[1] += kq * L1; q[2] += kq * L2;
-        }
-    }
-    wave_run_sums<QA, 3>(qt, q);
-    if (run_tail(qt) && qt >= 0) qwin_add3(qw, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
-}
-
 // Q32: every species' charge multiple is 0 or 1, so the end-position charge
 // of a diagnostic step accumulates in 32-bit LDS words (always so in the
 // single case).
@@ -767,16 +773,13 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     __shared__ int s_base;
     __shared__ unsigned long long s_jl[3 * kWin];
     __shared__ int s_cl[kWin];
-    // diagnostic steps: the end positions' charge window (32-bit words: in
-    // the walk queue's LDS once the walk is over, so that the block keeps
-    // the LDS footprint that allows 6 blocks per CU), per wave the kinetic
-    // energy and live count, the block's absorbed count
+    // diagnostic steps: the end positions' charge window (32-bit words in
+    // the single case: 30.7 KB of LDS per block, still 5 blocks per CU at the
+    // diagnostic step's 5 waves per SIMD), per wave the kinetic energy and
+    // live count, the block's absorbed count
     using QA = typename std::conditional<SINGLE || Q32, unsigned, unsigned long long>::type;
-    constexpr bool kQInQueue = sizeof(QA) * 3 * kWin <= sizeof(Mover) * kQCap;
-    __shared__ __align__(16) unsigned char s_queue[sizeof(Mover) * kQCap];
-    __shared__ QA s_qown[DIAG && !kQInQueue ? 3 * kWin : 1];
-    Mover *const s_mv = reinterpret_cast<Mover *>(s_queue);
-    QA *const s_ql = kQInQueue ? reinterpret_cast<QA *>(s_queue) : s_qown;
+    __shared__ Mover s_mv[kQCap];
+    __shared__ QA s_ql[DIAG ? 3 * kWin : 1];
     __shared__ double s_wk[kWG / 64];
     __shared__ int s_nl[kWG / 64];
     __shared__ int s_nabs;
@@ -821,6 +824,8 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     }
     Win w{s_jl, s_cl, 0};
     win_zero(w);
+    if (DIAG)
+        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
     if (DIAG) {                      // particles pushed in the step (live at its start), per wave
         int nl = 0;
 #pragma unroll
@@ -833,6 +838,7 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     // ---- phase 1: push
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
+    QA q0 = 0, q1 = 0, q2 = 0;       // diagnostic steps: the run's end-position corner charges
     int ct = -1, cc = 0;             // run-length count of the new faces (stayers only)
     bool mover[kPPT];
     float mfz[kPPT], mfr[kPPT];
@@ -870,10 +876,18 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             long long c0, c1, c2;
             piece_current(L0, L1, L2, e0, e1, e2, SINGLE ? 1 : ic.kq, c0, c1, c2);
             if (T != acc_t) {
-                if (acc_t >= 0) win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
+                if (acc_t >= 0) {
+                    win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
+                    if (DIAG) qwin_add3(qw, s.Qloc, acc_t, (long long)q0, (long long)q1, (long long)q2);
+                }
                 acc_t = T; a0 = a1 = a2 = 0;
+                q0 = q1 = q2 = 0;
             }
             a0 += c0; a1 += c1; a2 += c2;
+            if (DIAG) {              // level n+1 charge of a stayer: its end coordinates in T
+                const QA kq = SINGLE ? (QA)1 : (QA)ic.kq;
+                q0 += kq * (QA)e0; q1 += kq * (QA)e1; q2 += kq * (QA)e2;
+            }
             P[j].L0 = (uint32_t)e0;
             P[j].L1 = (uint32_t)e1;
             if (do_count) {
@@ -889,7 +903,8 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             mfr[j] = fr;
         }
     }
-    wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
+    if (DIAG) wave_deposit_q<QA>(w, s.Jloc, qw, s.Qloc, acc_t, a0, a1, a2, q0, q1, q2);
+    else wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
     if (DIAG) {
         const double v = wave_sum_d(kin);
         if ((threadIdx.x & 63) == 0) s_wk[threadIdx.x >> 6] = v;
@@ -923,14 +938,14 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
         for (int j = 0; j < kPPT; ++j)
             if (slot[j] == -2) {
                 Mover mv{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
-                walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, &s_nabs, mv);
+                walk_mover<SINGLE, DIAG, QA>(m, s, w, qw, k0, max_walk, &s_nabs, mv);
                 P[j].cell = mv.cell; P[j].L0 = (uint32_t)mv.L0; P[j].L1 = (uint32_t)mv.L1;
                 if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
             }
     }
     for (int i = threadIdx.x; i < nmv; i += kWG) {
         Mover mv = s_mv[i];
-        walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, &s_nabs, mv);
+        walk_mover<SINGLE, DIAG, QA>(m, s, w, qw, k0, max_walk, &s_nabs, mv);
         s_mv[i] = mv;
         if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
     }
@@ -943,14 +958,6 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             P[j].L0 = (uint32_t)s_mv[slot[j]].L0;
             P[j].L1 = (uint32_t)s_mv[slot[j]].L1;
         }
-    if (DIAG) {
-        // level n+1: the end positions' charge (absorbed particles, cell -1, hold none)
-        __syncthreads();             // the owners have read the queue: its LDS becomes the charge window
-        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
-        __syncthreads();
-        end_charge<SINGLE, QA>(m, k0, qw, s.Qloc, P);
-        __syncthreads();
-    }
     win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
     if (DIAG) {                      // the charge window, and the block's partials of level n and n+1
         for (int i = threadIdx.x; i < 3 * kWin; i += kWG) {
@@ -1313,6 +1320,8 @@ __global__ __launch_bounds__(kWG) void k_charge_now(DevMesh m, DevState s) {
 // was evaluated, the total charge; per edge 1/2 E^n D^n (W_E with the
 // scheme's [*eps]_a).  Each block also folds its slice of the step's
 // particle, face and edge partials (in_step).
+constexpr int kNodeCols = 8;   // list entries a node loads in one go (a mesh node has about six; longer lists loop)
+
 // Node i of an evaluation at level n = ctr->step: nodal charge (wall charge
 // plus the corners of its faces), the Gauss residual against its reference
 // and its scale, the continuity residual against the last evaluated level,
@@ -1321,43 +1330,52 @@ __device__ __forceinline__ void node_vals(const DevMesh &m, DevState &s, int i, 
                                           DiagVals &v) {
     const int inst = m.ninst ? m.ninst[i] : 0;
     long long Q = s.Qres[i];
-    // four incident corners and edges at a time: their index loads, then their
-    // value loads, are in flight together; the sums keep the list order
-    const int c0 = m.ncptr[i], c1 = m.ncptr[i + 1];
-    for (int k = c0; k < c1; k += 4) {
-        int idx[4];
+    // the node's slice of the padded lists: every index load of the first
+    // kNodeCols entries, then every value load, in flight together (the
+    // mesh's longest list is a kernel argument, so no load bounds them); the
+    // sums keep the list order
+    const size_t sl = (size_t)(i >> 6), l = (size_t)(i & 63);
+    const int32_t *cp = m.ncorner_ell + sl * (size_t)m.nwc * 64 + l;
+    const int32_t *ep = m.nedge_ell + sl * (size_t)m.nwe * 64 + l;
+    int ci[kNodeCols], ei[kNodeCols];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) idx[q] = k + q < c1 ? m.ncorner[k + q] : -1;
-        long long v[4];
+    for (int j = 0; j < kNodeCols; ++j) {
+        ci[j] = j < m.nwc ? cp[64 * j] : -1;
+        ei[j] = j < m.nwe ? ep[64 * j] : 0;
+    }
+    long long qv[kNodeCols], jv[kNodeCols];
+    double d[kNodeCols];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = idx[q] >= 0 ? (long long)s.Qloc[idx[q]] : 0ll;
+    for (int j = 0; j < kNodeCols; ++j) {
+        const int e = (ei[j] < 0 ? -ei[j] : ei[j]) - 1;
+        qv[j] = ci[j] >= 0 ? (long long)s.Qloc[ci[j]] : 0ll;
+        d[j] = ei[j] ? s.D[e] : 0.0;
+        jv[j] = ei[j] ? s.Jfx[e] : 0ll;
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Q += v[q];
+    for (int j = 0; j < kNodeCols; ++j) Q += qv[j];
+    for (int j = kNodeCols; j < m.nwc; ++j) {
+        const int c = cp[64 * j];
+        if (c >= 0) Q += (long long)s.Qloc[c];
     }
     double div = 0.0, mag = 0.0;
     long long divj = 0;
-    const int e0 = m.nptr[i], e1 = m.nptr[i + 1];
-    for (int k = e0; k < e1; k += 4) {
-        int e[4], sg[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            e[q] = k + q < e1 ? m.nedge[k + q] : -1;
-            sg[q] = k + q < e1 ? m.nsign[k + q] : 0;
+    for (int j = 0; j < kNodeCols; ++j)
+        if (ei[j]) {
+            div += ei[j] > 0 ? d[j] : -d[j];
+            mag += fabs(d[j]);
+            divj += ei[j] > 0 ? jv[j] : -jv[j];
         }
-        double d[4];
-        long long j[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            d[q] = e[q] >= 0 ? s.D[e[q]] : 0.0;
-            j[q] = e[q] >= 0 ? s.Jfx[e[q]] : 0ll;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (e[q] >= 0) {
-                div += sg[q] > 0 ? d[q] : -d[q];
-                mag += fabs(d[q]);
-                divj += sg[q] > 0 ? j[q] : -j[q];
-            }
+    for (int j = kNodeCols; j < m.nwe; ++j) {
+        const int x = ep[64 * j];
+        if (!x) continue;
+        const int e = (x < 0 ? -x : x) - 1;
+        const double dd = s.D[e];
+        const long long jj = s.Jfx[e];
+        div += x > 0 ? dd : -dd;
+        mag += fabs(dd);
+        divj += x > 0 ? jj : -jj;
     }
     const double q = (double)Q * m.inst[inst].qscale;
     if (have_prev) {
@@ -1454,37 +1472,57 @@ __device__ __forceinline__ void load_eval_state(const DevState &s, int l, unsign
 // is a double (|dQ + Ddiv J| in charge units) judged against max |Q|.
 constexpr int kFinalThreads = 64 * kDiagSlots;      // one wave per slot
 
+// Slot k of the evaluation's partials reduced by one wave (lane l) in a fixed
+// order: four independent accumulators per lane (loads in flight together),
+// combined in order, then a butterfly; with nb_we > 0 the energy of the new
+// level comes from the SpMV blocks' partials instead of the node-pass blocks'.
+__device__ __forceinline__ double reduce_slot(const DevState &s, int k, int l, int nb_node, int nb_we) {
+    const bool we = k == kSumWEnow && nb_we > 0;
+    const double *p = we ? s.part_wenow : s.part_node + (size_t)k * nb_node;
+    const int nb = we ? nb_we : nb_node;
+    if (k < kDiagSums) {
+        double x[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = l; b < nb; b += 256)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (b + 64 * q < nb) x[q] += p[b + 64 * q];
+        return wave_sum64d(((x[0] + x[1]) + x[2]) + x[3]);
+    }
+    unsigned long long x = 0;
+    for (int b = l; b < nb_node; b += 256)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (b + 64 * q < nb_node) {
+                const unsigned long long y = dbits(p[b + 64 * q]);
+                x = y > x ? y : x;
+            }
+    return __longlong_as_double((long long)wave_max64(x));
+}
+
+// k_diag_final of a diagnostic step by one block of 256 threads riding in the
+// next face pass (the same slot reductions, so the same results).
+__device__ void final_block(DevState s, int nb_node, int nb_we) {
+    __shared__ double res[kDiagSlots];
+    __shared__ unsigned long long cur[7];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (w == 0 && l < 7) load_eval_state(s, l, cur);
+    for (int k = w; k < kDiagSums + kDiagMaxes; k += 4) {      // wave-uniform
+        const double t = reduce_slot(s, k, l, nb_node, nb_we);
+        if (l == 0) res[k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) finish_eval(s, res, cur, 1, 0);
+}
+
 __global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb_node, int in_step, int plain,
                                                                int nb_we) {
     __shared__ double res[kDiagSlots];
     __shared__ unsigned long long cur[7];     // the counters and running values thread 0 updates
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;   // wave w reduces slot w over the node-pass blocks
     if (w == kDiagSlots - 1 && l < 7) load_eval_state(s, l, cur);   // in parallel with the reduction
-    // slot w of every node-pass block; with nb_we > 0 the energy of the new
-    // level comes from the SpMV blocks' partials instead
-    const bool we = w == kSumWEnow && nb_we > 0;
-    const double *p = we ? s.part_wenow : s.part_node + (size_t)w * nb_node;
-    const int nb = we ? nb_we : nb_node;
-    // four independent accumulators per lane (loads in flight together), combined in order
-    if (w < kDiagSums) {
-        double x[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = l; b < nb; b += 256)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + 64 * q < nb) x[q] += p[b + 64 * q];
-        const double t = wave_sum64d(((x[0] + x[1]) + x[2]) + x[3]);
+    if (w < kDiagSums + kDiagMaxes) {
+        const double t = reduce_slot(s, w, l, nb_node, nb_we);
         if (l == 0) res[w] = t;
-    } else if (w < kDiagSums + kDiagMaxes) {
-        unsigned long long x = 0;
-        for (int b = l; b < nb_node; b += 256)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + 64 * q < nb_node) {
-                    const unsigned long long y = dbits(p[b + 64 * q]);
-                    x = y > x ? y : x;
-                }
-        x = wave_max64(x);
-        if (l == 0) res[w] = __longlong_as_double((long long)x);
     }
     __syncthreads();
     if (threadIdx.x == 0) finish_eval(s, res, cur, in_step, plain);
@@ -1509,7 +1547,9 @@ __global__ __launch_bounds__(256) void k_spmv_we(DevMesh m, DevState s) {
 }
 
 // The node pass of a diagnostic step: one thread per node only (the energy
-// of the new level comes from the SpMV blocks).
+// of the new level comes from the SpMV blocks).  A last-block-done final
+// reduction (device-scope fences around a ticket) was measured 12 us slower
+// per step than the separate k_diag_final launch.
 __global__ __launch_bounds__(256) void k_node_step(DevMesh m, DevState s, int nb_face, int nb_edge) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long n = s.ctr->step;
@@ -1575,12 +1615,17 @@ bool emission_fits_face_pass(const InjParams &p) {
 }
 
 void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
-                     const EmitEdge *ee, const InjParams *emit, hipStream_t st) {
-    if (m.n2 == 0) return;
+                     const EmitEdge *ee, const InjParams *emit, bool final_prev, hipStream_t st) {
+    if (m.n2 == 0) {
+        if (final_prev) launch_step_final(m, s, st);
+        return;
+    }
     InjParams ip{};
     if (emit && emission_fits_face_pass(*emit)) ip = *emit;
-    const unsigned nb = (unsigned)nblk(m.n2, 256) + (ip.per_step > 0 ? 1u : 0u);
-    hipLaunchKernelGGL(k_tri_pass, dim3(nb), dim3(256), 0, st, m, s, fs, lay, diag ? 1 : 0, ee, ip);
+    const unsigned nb = (unsigned)nblk(m.n2, 256) + (final_prev ? 1u : 0u) + (ip.per_step > 0 ? 1u : 0u);
+    const int fin_nb_node = final_prev ? (int)nblk(m.n0, 256) : 0, fin_nb_we = (int)nblk(m.n1, 256);
+    hipLaunchKernelGGL(k_tri_pass, dim3(nb), dim3(256), 0, st, m, s, fs, lay, diag ? 1 : 0, ee, ip, fin_nb_node,
+                       fin_nb_we);
 }
 
 template <class T>
@@ -1754,7 +1799,11 @@ void launch_spmv_diag(const DevMesh &m, DevState &s, hipStream_t st) {
     const int nb_node = (int)nblk(m.n0, 256), nb_spmv = (int)nblk(m.n1, 256);
     hipLaunchKernelGGL(k_spmv_we, dim3(nb_spmv), dim3(256), 0, st, m, s);
     hipLaunchKernelGGL(k_node_step, dim3(nb_node), dim3(256), 0, st, m, s, (int)nblk(m.n2, 256), nb_spmv);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kFinalThreads), 0, st, s, nb_node, 1, 0, nb_spmv);
+}
+
+void launch_step_final(const DevMesh &m, DevState &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kFinalThreads), 0, st, s, (int)nblk(m.n0, 256), 1, 0,
+                       (int)nblk(m.n1, 256));
 }
 
 void launch_diag_now(const DevMesh &m, DevState &s, hipStream_t st) {
