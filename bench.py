@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import subprocess
 import sys
@@ -500,6 +501,17 @@ def main():
         nodiag["roofline_frac"] = pb / (nodiag["particle_kernel_us"] / 1e6) / 1e9 / HBM_PEAK_GBS
         nodiag["step_algorithmic_frac"] = step_bytes / (nodiag["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS
         log(f"without diagnostics: {nodiag['value']:.3e} particle-steps/s, {nodiag['ms_per_step']:.4f} ms/step")
+    diag_cost = None
+    if nodiag is not None:
+        # what the diagnostic steps add to the step, and the cadence that keeps it within 10 %
+        extra = head["ms_per_step"] / nodiag["ms_per_step"] - 1.0
+        per_eval = extra * args.diag_every
+        diag_cost = {"diag_every": args.diag_every, "ms_per_step_with": head["ms_per_step"],
+                     "ms_per_step_without": nodiag["ms_per_step"], "overhead": extra,
+                     "overhead_per_diagnostic_step": per_eval,
+                     "diag_every_for_10pct": max(1, math.ceil(per_eval / 0.10 - 1e-9))}
+        log(f"diagnostics every {args.diag_every} step(s): +{100 * extra:.1f} % per step; every "
+            f"{diag_cost['diag_every_for_10pct']} steps keeps it within 10 %")
     # field kernels alone: from the steps without diagnostics (with them, the
     # SpMV launch also carries the node pass of the evaluation)
     ft = tim0 if args.diag_every else tim
@@ -596,6 +608,7 @@ def main():
                      "bytes_model": "48 B per particle + 40 B per face", "avg_launch_us": part_s * 1e6,
                      "kernel_source_sha256_16": kernel_source_hash()},
         "no_diagnostics": nodiag,
+        "diagnostics_overhead": diag_cost,
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
         "plain_fp64": plain,

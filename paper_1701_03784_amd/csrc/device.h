@@ -224,9 +224,9 @@ struct DevPlain {
 
 // ---- launchers (kernels_mixed.hip) ----
 // the face pass; with emit (1 to 4096 per step from an emitter of at most 1024
-// edges) its last block also does the step's emission; with final_prev one
-// more block does the final reduction the last diagnostic step's node pass
-// left (launch_spmv_diag)
+// edges) one extra block does the step's emission; with final_prev another
+// does the final reduction the last diagnostic step's node pass left
+// (launch_spmv_diag)
 bool emission_fits_face_pass(const InjParams &p);
 void launch_tri_pass(const DevMesh &m, DevState &s, const FieldSrc &fs, const DevLayers &lay, bool diag,
                      const EmitEdge *ee, const InjParams *emit, bool final_prev, hipStream_t st);
@@ -248,7 +248,8 @@ void launch_sort(const DevMesh &m, DevState &s, bool counted, hipStream_t st);
 // the energy record of its start level n, launched after the field update.
 void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st);
 // E = M D of a diagnostic step (no absorbing layers) with the energy of the
-// new level per block of rows, then the node pass over the nodes alone.  Its
+// new level per block of rows, and in the same launch the node pass over the
+// nodes alone.  Its
 // final reduction is left to the next face pass (final_prev) or to
 // launch_step_final, which must run before anything reads the diagnostics.
 void launch_spmv_diag(const DevMesh &m, DevState &s, hipStream_t st);

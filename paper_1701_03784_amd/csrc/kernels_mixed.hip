@@ -171,27 +171,40 @@ __device__ __forceinline__ void inject_block(const DevState &s, const EmitEdge *
     }
 }
 
-// The face pass; with ip.per_step > 0 its last block is the step's emission
-// (independent of the faces, so it overlaps them and costs no launch).
 // final reduction of a diagnostic step's evaluation by one block (defined with the diagnostics)
 __device__ void final_block(DevState s, int nb_node, int nb_we);
 
+// The face pass.  With fin_nb_node > 0 one extra block is the final reduction
+// of the last diagnostic step, with ip.per_step > 0 one more is the step's
+// emission: both are independent of the faces, so they overlap them and cost
+// no launch.
+
 __global__ __launch_bounds__(256) void k_tri_pass(DevMesh m, DevState s, FieldSrc fs, DevLayers lay, int diag,
                                                   const EmitEdge *ee, InjParams ip, int fin_nb_node, int fin_nb_we) {
-    if (ip.per_step > 0 && (int)blockIdx.x == (int)gridDim.x - 1) {
-        __shared__ unsigned long long s_q[2 * kInjMaxEdges];
-        inject_block(s, ee, ip, s_q);
-        return;
+    // the final reduction, then the emission, take the first blocks, so that
+    // their chains of dependent loads start with the grid instead of after
+    // the face blocks
+    int bid = blockIdx.x;
+    if (fin_nb_node > 0) {
+        if (bid == 0) {
+            final_block(s, fin_nb_node, fin_nb_we);
+            return;
+        }
+        --bid;
     }
-    if (fin_nb_node > 0 && (int)blockIdx.x == (m.n2 + 255) / 256) {
-        final_block(s, fin_nb_node, fin_nb_we);
-        return;
+    if (ip.per_step > 0) {
+        if (bid == 0) {
+            __shared__ unsigned long long s_q[2 * kInjMaxEdges];
+            inject_block(s, ee, ip, s_q);
+            return;
+        }
+        --bid;
     }
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = bid * blockDim.x + threadIdx.x;
     const double wb = t < m.n2 ? tri_pass_face(m, s, fs, lay, t, diag != 0) : 0.0;
     if (!diag) return;                          // uniform across the grid
     const double tot = block_sum256(wb);
-    if (threadIdx.x == 0) s.part_face[blockIdx.x] = tot;
+    if (threadIdx.x == 0) s.part_face[bid] = tot;
 }
 
 // -------------------------------------------------------------- particles
@@ -338,34 +351,6 @@ __device__ __forceinline__ void seg_scan(int run, V (&a)[N]) {
     seg_step<0x143, 0xC>(run, a);
 }
 
-// The same over two arrays at once (one run exchange per step).
-template <int CTRL, int ROWS, class V, int N, class U, int K>
-__device__ __forceinline__ void seg_step2(int run, V (&a)[N], U (&b)[K]) {
-    const int ro = dpp_mov<CTRL, ROWS>(run);
-    V x[N];
-    U y[K];
-#pragma unroll
-    for (int k = 0; k < N; ++k) x[k] = dpp_mov<CTRL, ROWS>(a[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) y[k] = dpp_mov<CTRL, ROWS>(b[k]);
-    if (ro == run) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) a[k] += x[k];
-#pragma unroll
-        for (int k = 0; k < K; ++k) b[k] += y[k];
-    }
-}
-
-template <class V, int N, class U, int K>
-__device__ __forceinline__ void seg_scan2(int run, V (&a)[N], U (&b)[K]) {
-    seg_step2<0x111, 0xF>(run, a, b);
-    seg_step2<0x112, 0xF>(run, a, b);
-    seg_step2<0x114, 0xF>(run, a, b);
-    seg_step2<0x118, 0xF>(run, a, b);
-    seg_step2<0x142, 0xA>(run, a, b);
-    seg_step2<0x143, 0xC>(run, a, b);
-}
-
 __device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0, long long a1,
                                              long long a2) {
     long long a[3] = {a0, a1, a2};
@@ -407,22 +392,6 @@ __device__ __forceinline__ void qwin_add3(const QWinL<QA> &w, unsigned long long
         if (q0) atomicAdd(&Qloc[3 * t], (unsigned long long)q0);
         if (q1) atomicAdd(&Qloc[3 * t + 1], (unsigned long long)q1);
         if (q2) atomicAdd(&Qloc[3 * t + 2], (unsigned long long)q2);
-    }
-}
-
-// A diagnostic step's stayers: their side currents and the corner charges of
-// their end positions (eq. charge, kq Lambda_k per corner), reduced over the
-// same runs of lanes.
-template <class QA>
-__device__ __forceinline__ void wave_deposit_q(const Win &w, unsigned long long *J, const QWinL<QA> &qw,
-                                               unsigned long long *Qloc, int t, long long a0, long long a1,
-                                               long long a2, QA q0, QA q1, QA q2) {
-    long long a[3] = {a0, a1, a2};
-    QA q[3] = {q0, q1, q2};
-    seg_scan2<long long, 3, QA, 3>(lane_run(t), a, q);
-    if (run_tail(t) && t >= 0) {
-        win_add_j(w, J, t, a[0], a[1], a[2]);
-        qwin_add3(qw, Qloc, t, (long long)q[0], (long long)q[1], (long long)q[2]);
     }
 }
 
@@ -569,12 +538,10 @@ struct Mover {
 // the path ends inside a face, is absorbed by a conductor or open boundary
 // edge (its charge kept on the wall nodes), stops on the axis, or hits the
 // piece cap.  mv holds the start (face, coordinates, remaining
-// displacement) and receives the final cell word and coordinates.  In a
-// diagnostic step a particle still live at the end adds the corner charges
-// of its end position (eq. charge) to the charge window qw.
-template <bool SINGLE, bool DIAG, class QA>
-__device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const QWinL<QA> &qw,
-                                           const PushConst &k0, int max_walk, int *nabs, Mover &mv) {
+// displacement) and receives the final cell word and coordinates.
+template <bool SINGLE, bool DIAG>
+__device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, const Win &w, const PushConst &k0,
+                                           int max_walk, int *nabs, Mover &mv) {
     int t = mv.cell & kCellMask;
     const int sp = (mv.cell >> kCellBits) & 15;
     const int kq = SINGLE ? 1 : push_const<SINGLE>(m, k0, t, sp).kq;
@@ -655,8 +622,6 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
         }
         win_add_j(w, s.Jloc, tf, c0, c1, c2);
     }
-    if (DIAG && newcell >= 0)
-        qwin_add3(qw, s.Qloc, t, (long long)kq * L0, (long long)kq * L1, (long long)kq * L2);
     mv.cell = newcell;
     mv.L0 = L0;
     mv.L1 = L1;
@@ -760,6 +725,38 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v;
 }
 
+// Charge of the particles' end positions (level n+1, eq. charge) in a
+// diagnostic step: the thread folds its particles face by face, the wave
+// sums runs of lanes holding the same face, and each run's last lane adds
+// the three corner sums kq Lambda_k to the block's charge window.  Done after
+// the walk, when the push's registers are free.  With QA = 32-bit words a
+// wave's sums stay below 2^32 (256 particles of at most 2^23 each).
+template <bool SINGLE, class QA>
+__device__ __forceinline__ void end_charge(const DevMesh &m, const PushConst &k0, const QWinL<QA> &qw,
+                                           unsigned long long *Qloc, const Particle (&P)[kPPT]) {
+    int qt = -1;
+    QA q[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kPPT; ++j) {
+        if (P[j].cell < 0) continue;
+        const int T = P[j].cell & kCellMask;
+        if (T != qt) {
+            if (qt >= 0) qwin_add3(qw, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
+            qt = T;
+            q[0] = q[1] = q[2] = 0;
+        }
+        const QA L0 = (QA)P[j].L0, L1 = (QA)P[j].L1, L2 = (QA)kS - L0 - L1;
+        if (SINGLE) {
+            q[0] += L0; q[1] += L1; q[2] += L2;
+        } else {
+            const QA kq = (QA)(long long)push_const<SINGLE>(m, k0, T, (P[j].cell >> kCellBits) & 15).kq;
+            q[0] += kq * L0; q[1] += kq * L1; q[2] += kq * L2;
+        }
+    }
+    wave_run_sums<QA, 3>(qt, q);
+    if (run_tail(qt) && qt >= 0) qwin_add3(qw, Qloc, qt, (long long)q[0], (long long)q[1], (long long)q[2]);
+}
+
 // Q32: every species' charge multiple is 0 or 1, so the end-position charge
 // of a diagnostic step accumulates in 32-bit LDS words (always so in the
 // single case).
@@ -773,14 +770,18 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     __shared__ int s_base;
     __shared__ unsigned long long s_jl[3 * kWin];
     __shared__ int s_cl[kWin];
-    // diagnostic steps: the end positions' charge window (32-bit words in
-    // the single case: 30.7 KB of LDS per block, still 5 blocks per CU at the
-    // diagnostic step's 5 waves per SIMD), per wave the kinetic energy and
-    // live count, the block's absorbed count
+    // diagnostic steps: the end positions' charge window (32-bit words: in
+    // the walk queue's LDS once the walk is over, so that the block keeps
+    // the LDS footprint that allows 6 blocks per CU), per wave the kinetic
+    // energy and live count, the block's absorbed count
     using QA = typename std::conditional<SINGLE || Q32, unsigned, unsigned long long>::type;
-    __shared__ Mover s_mv[kQCap];
-    __shared__ QA s_ql[DIAG ? 3 * kWin : 1];
+    constexpr bool kQInQueue = sizeof(QA) * 3 * kWin <= sizeof(Mover) * kQCap;
+    __shared__ __align__(16) unsigned char s_queue[sizeof(Mover) * kQCap];
+    __shared__ QA s_qown[DIAG && !kQInQueue ? 3 * kWin : 1];
+    Mover *const s_mv = reinterpret_cast<Mover *>(s_queue);
+    QA *const s_ql = kQInQueue ? reinterpret_cast<QA *>(s_queue) : s_qown;
     __shared__ double s_wk[kWG / 64];
+    __shared__ double s_wk1[kWG / 64];   // single case: K^{n-1/2} in s_wk, K^{n+1/2} here
     __shared__ int s_nl[kWG / 64];
     __shared__ int s_nabs;
     // The grid covers the buffer's capacity (a graph replays one launch
@@ -824,13 +825,19 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     }
     Win w{s_jl, s_cl, 0};
     win_zero(w);
-    if (DIAG)
-        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
     if (DIAG) {                      // particles pushed in the step (live at its start), per wave
         int nl = 0;
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) nl += __popcll(__ballot(P[j].cell >= 0));
         if ((threadIdx.x & 63) == 0) s_nl[threadIdx.x >> 6] = nl;
+    }
+    if (DIAG && SINGLE) {            // K^{n-1/2} of those particles, before the push needs the registers
+        double k = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j)
+            if (P[j].cell >= 0) k += (double)gamma_m1(P[j].ur, P[j].up, P[j].uz);
+        const double v = wave_sum_d(k);
+        if ((threadIdx.x & 63) == 0) s_wk[threadIdx.x >> 6] = v;
     }
     __syncthreads();
     w.base = s_base;
@@ -838,11 +845,10 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     // ---- phase 1: push
     int acc_t = -1;
     long long a0 = 0, a1 = 0, a2 = 0;
-    QA q0 = 0, q1 = 0, q2 = 0;       // diagnostic steps: the run's end-position corner charges
     int ct = -1, cc = 0;             // run-length count of the new faces (stayers only)
     bool mover[kPPT];
     float mfz[kPPT], mfr[kPPT];
-    double kin = 0.0;                // diagnostic steps: sum of mw (gamma - 1) at n-1/2 and n+1/2
+    double kin = 0.0;                // diagnostic steps, several species: sum of mw (gamma - 1) at n-1/2 and n+1/2
     int Tc = -1;                     // face data cached across the thread's particles
     float4 cf0 = make_float4(0.f, 0.f, 0.f, 0.f), cf1 = cf0, cr4 = cf0, cg = cf0;
     int ic_key = -1;                 // cell word (face, species) the constants below belong to
@@ -864,11 +870,11 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
         }
         const int L0 = (int)P[j].L0, L1 = (int)P[j].L1, L2 = kS - L0 - L1;
         float fz, fr;
-        if (DIAG) {                  // W_K = 1/2 (K^{n-1/2} + K^{n+1/2}), absorbed particles included
+        if (DIAG && !SINGLE) {       // W_K = 1/2 (K^{n-1/2} + K^{n+1/2}), absorbed particles included
             kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
         }
         push<VAY>(s, P[j], ic, cf0, cf1, cr4, L0, L1, L2, fz, fr);
-        if (DIAG) kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
+        if (DIAG && !SINGLE) kin += (double)(ic.mw * gamma_m1(P[j].ur, P[j].up, P[j].uz));
         int d0, d1, d2;
         lam_change(cg, fz, fr, d0, d1, d2);
         const int e0 = L0 + d0, e1 = L1 + d1, e2 = L2 + d2;
@@ -876,18 +882,10 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             long long c0, c1, c2;
             piece_current(L0, L1, L2, e0, e1, e2, SINGLE ? 1 : ic.kq, c0, c1, c2);
             if (T != acc_t) {
-                if (acc_t >= 0) {
-                    win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
-                    if (DIAG) qwin_add3(qw, s.Qloc, acc_t, (long long)q0, (long long)q1, (long long)q2);
-                }
+                if (acc_t >= 0) win_add_j(w, s.Jloc, acc_t, a0, a1, a2);
                 acc_t = T; a0 = a1 = a2 = 0;
-                q0 = q1 = q2 = 0;
             }
             a0 += c0; a1 += c1; a2 += c2;
-            if (DIAG) {              // level n+1 charge of a stayer: its end coordinates in T
-                const QA kq = SINGLE ? (QA)1 : (QA)ic.kq;
-                q0 += kq * (QA)e0; q1 += kq * (QA)e1; q2 += kq * (QA)e2;
-            }
             P[j].L0 = (uint32_t)e0;
             P[j].L1 = (uint32_t)e1;
             if (do_count) {
@@ -903,13 +901,34 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             mfr[j] = fr;
         }
     }
-    if (DIAG) wave_deposit_q<QA>(w, s.Jloc, qw, s.Qloc, acc_t, a0, a1, a2, q0, q1, q2);
-    else wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
-    if (DIAG) {
+    wave_deposit(w, s.Jloc, acc_t, a0, a1, a2);
+    if (DIAG && !SINGLE) {
         const double v = wave_sum_d(kin);
         if ((threadIdx.x & 63) == 0) s_wk[threadIdx.x >> 6] = v;
     }
     if (do_count) wave_count(w, s.cnt, ct, cc);
+    // Momenta are final after the push (the walk moves particles, not
+    // momenta).  The diagnostic step of the single case sums K^{n+1/2} of the
+    // particles live at the start and stores the momenta now, which frees
+    // their registers for the walk and the charge pass.
+    constexpr bool kEarlyU = DIAG && SINGLE;
+    if (kEarlyU) {
+        double k = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPPT; ++j)
+            if (P[j].cell >= 0) k += (double)gamma_m1(P[j].ur, P[j].up, P[j].uz);
+        const double v = wave_sum_d(k);
+        if ((threadIdx.x & 63) == 0) s_wk1[threadIdx.x >> 6] = v;
+        if (full) {
+            *reinterpret_cast<float4 *>(ura + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
+            *reinterpret_cast<float4 *>(upa + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
+            *reinterpret_cast<float4 *>(uza + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPPT; ++j)
+                if (p0 + j < n) { ura[p0 + j] = P[j].ur; upa[p0 + j] = P[j].up; uza[p0 + j] = P[j].uz; }
+        }
+    }
     // queue the movers in LDS (one LDS atomic per wave and particle slot)
     const int lane = threadIdx.x & 63;
     int slot[kPPT];
@@ -938,14 +957,14 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
         for (int j = 0; j < kPPT; ++j)
             if (slot[j] == -2) {
                 Mover mv{P[j].cell, (int)P[j].L0, (int)P[j].L1, mfz[j], mfr[j]};
-                walk_mover<SINGLE, DIAG, QA>(m, s, w, qw, k0, max_walk, &s_nabs, mv);
+                walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, &s_nabs, mv);
                 P[j].cell = mv.cell; P[j].L0 = (uint32_t)mv.L0; P[j].L1 = (uint32_t)mv.L1;
                 if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
             }
     }
     for (int i = threadIdx.x; i < nmv; i += kWG) {
         Mover mv = s_mv[i];
-        walk_mover<SINGLE, DIAG, QA>(m, s, w, qw, k0, max_walk, &s_nabs, mv);
+        walk_mover<SINGLE, DIAG>(m, s, w, k0, max_walk, &s_nabs, mv);
         s_mv[i] = mv;
         if (do_count && mv.cell >= 0) win_add_c(w, s.cnt, mv.cell & kCellMask, 1);
     }
@@ -958,6 +977,14 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             P[j].L0 = (uint32_t)s_mv[slot[j]].L0;
             P[j].L1 = (uint32_t)s_mv[slot[j]].L1;
         }
+    if (DIAG) {
+        // level n+1: the end positions' charge (absorbed particles, cell -1, hold none)
+        __syncthreads();             // the owners have read the queue: its LDS becomes the charge window
+        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
+        __syncthreads();
+        end_charge<SINGLE, QA>(m, k0, qw, s.Qloc, P);
+        __syncthreads();
+    }
     win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
     if (DIAG) {                      // the charge window, and the block's partials of level n and n+1
         for (int i = threadIdx.x; i < 3 * kWin; i += kWG) {
@@ -969,7 +996,7 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
             double v = 0.0;
             int nl = 0;
 #pragma unroll
-            for (int k = 0; k < kWG / 64; ++k) { v += s_wk[k]; nl += s_nl[k]; }
+            for (int k = 0; k < kWG / 64; ++k) { v += SINGLE ? s_wk[k] + s_wk1[k] : s_wk[k]; nl += s_nl[k]; }
             v *= 0.5;                // W_K = 1/2 (K^{n-1/2} + K^{n+1/2})
             s.part_kin[3 * chunk] = SINGLE ? v * m.inst[0].mw[0] : v;
             s.part_kin[3 * chunk + 1] = (double)nl;
@@ -980,16 +1007,18 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
         *reinterpret_cast<int4 *>(cell + p0) = make_int4(P[0].cell, P[1].cell, P[2].cell, P[3].cell);
         *reinterpret_cast<uint4 *>(L0a + p0) = make_uint4(P[0].L0, P[1].L0, P[2].L0, P[3].L0);
         *reinterpret_cast<uint4 *>(L1a + p0) = make_uint4(P[0].L1, P[1].L1, P[2].L1, P[3].L1);
-        *reinterpret_cast<float4 *>(ura + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
-        *reinterpret_cast<float4 *>(upa + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
-        *reinterpret_cast<float4 *>(uza + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
+        if (!kEarlyU) {
+            *reinterpret_cast<float4 *>(ura + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
+            *reinterpret_cast<float4 *>(upa + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
+            *reinterpret_cast<float4 *>(uza + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < kPPT; ++j) {
             const long long p = p0 + j;
             if (p < n) {
                 cell[p] = P[j].cell; L0a[p] = P[j].L0; L1a[p] = P[j].L1;
-                ura[p] = P[j].ur; upa[p] = P[j].up; uza[p] = P[j].uz;
+                if (!kEarlyU) { ura[p] = P[j].ur; upa[p] = P[j].up; uza[p] = P[j].uz; }
             }
         }
     }
@@ -1472,44 +1501,74 @@ __device__ __forceinline__ void load_eval_state(const DevState &s, int l, unsign
 // is a double (|dQ + Ddiv J| in charge units) judged against max |Q|.
 constexpr int kFinalThreads = 64 * kDiagSlots;      // one wave per slot
 
-// Slot k of the evaluation's partials reduced by one wave (lane l) in a fixed
-// order: four independent accumulators per lane (loads in flight together),
-// combined in order, then a butterfly; with nb_we > 0 the energy of the new
-// level comes from the SpMV blocks' partials instead of the node-pass blocks'.
-__device__ __forceinline__ double reduce_slot(const DevState &s, int k, int l, int nb_node, int nb_we) {
+// Slots of the evaluation's partials reduced in a fixed order: lane l sums
+// (or takes the largest of) entries l, l + 64, l + 128, ... in that order,
+// then a butterfly over the wave.  A lane loads kSlotChunk entries of every
+// slot it reduces before it adds any, so they are in flight together.  Slot
+// kSumWEnow comes from the SpMV blocks' nb_we partials when nb_we > 0.
+constexpr int kSlotChunk = 8;
+
+__device__ __forceinline__ const double *slot_src(const DevState &s, int k, int nb_node, int nb_we, int &nb) {
     const bool we = k == kSumWEnow && nb_we > 0;
-    const double *p = we ? s.part_wenow : s.part_node + (size_t)k * nb_node;
-    const int nb = we ? nb_we : nb_node;
-    if (k < kDiagSums) {
-        double x[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = l; b < nb; b += 256)
+    nb = we ? nb_we : nb_node;
+    return we ? s.part_wenow : s.part_node + (size_t)k * nb_node;
+}
+
+// slots k0, k0 + 4, ..., k0 + 4 (NS - 1) by one wave (lane l)
+template <int NS>
+__device__ __forceinline__ void reduce_slots(const DevState &s, int k0, int l, int nb_node, int nb_we,
+                                             double (&out)[NS]) {
+    const double *p[NS];
+    int nb[NS];
+    double x[NS];
+    unsigned long long mx[NS];
+    int nbmax = 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (b + 64 * q < nb) x[q] += p[b + 64 * q];
-        return wave_sum64d(((x[0] + x[1]) + x[2]) + x[3]);
+    for (int i = 0; i < NS; ++i) {
+        p[i] = slot_src(s, k0 + 4 * i, nb_node, nb_we, nb[i]);
+        x[i] = 0.0;
+        mx[i] = 0ull;
+        nbmax = nb[i] > nbmax ? nb[i] : nbmax;
     }
-    unsigned long long x = 0;
-    for (int b = l; b < nb_node; b += 256)
+    for (int b = l; b < nbmax; b += 64 * kSlotChunk) {
+        double v[NS][kSlotChunk];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (b + 64 * q < nb_node) {
-                const unsigned long long y = dbits(p[b + 64 * q]);
-                x = y > x ? y : x;
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int u = 0; u < kSlotChunk; ++u) v[i][u] = b + 64 * u < nb[i] ? p[i][b + 64 * u] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (k0 + 4 * i < kDiagSums) {
+#pragma unroll
+                for (int u = 0; u < kSlotChunk; ++u) x[i] += v[i][u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < kSlotChunk; ++u) {
+                    const unsigned long long y = dbits(v[i][u]);
+                    mx[i] = y > mx[i] ? y : mx[i];
+                }
             }
-    return __longlong_as_double((long long)wave_max64(x));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+        out[i] = k0 + 4 * i < kDiagSums ? wave_sum64d(x[i]) : __longlong_as_double((long long)wave_max64(mx[i]));
 }
 
 // k_diag_final of a diagnostic step by one block of 256 threads riding in the
-// next face pass (the same slot reductions, so the same results).
+// next face pass: each wave reduces three slots together (the same per-slot
+// order, so the same results).
 __device__ void final_block(DevState s, int nb_node, int nb_we) {
+    static_assert(kDiagSums + kDiagMaxes == 12, "three slots per wave");
     __shared__ double res[kDiagSlots];
     __shared__ unsigned long long cur[7];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (w == 0 && l < 7) load_eval_state(s, l, cur);
-    for (int k = w; k < kDiagSums + kDiagMaxes; k += 4) {      // wave-uniform
-        const double t = reduce_slot(s, k, l, nb_node, nb_we);
-        if (l == 0) res[k] = t;
-    }
+    double r[3];
+    reduce_slots<3>(s, w, l, nb_node, nb_we, r);
+    if (l == 0)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) res[w + 4 * i] = r[i];
     __syncthreads();
     if (threadIdx.x == 0) finish_eval(s, res, cur, 1, 0);
 }
@@ -1521,19 +1580,20 @@ __global__ __launch_bounds__(kFinalThreads) void k_diag_final(DevState s, int nb
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;   // wave w reduces slot w over the node-pass blocks
     if (w == kDiagSlots - 1 && l < 7) load_eval_state(s, l, cur);   // in parallel with the reduction
     if (w < kDiagSums + kDiagMaxes) {
-        const double t = reduce_slot(s, w, l, nb_node, nb_we);
-        if (l == 0) res[w] = t;
+        double t[1];
+        reduce_slots<1>(s, w, l, nb_node, nb_we, t);
+        if (l == 0) res[w] = t[0];
     }
     __syncthreads();
     if (threadIdx.x == 0) finish_eval(s, res, cur, in_step, plain);
 }
 
 // E = M D of a diagnostic step, with 1/2 E D of the new level summed per
-// block of rows (the energy the evaluation reports for that level).
-__global__ __launch_bounds__(256) void k_spmv_we(DevMesh m, DevState s) {
+// block of rows b (the energy the evaluation reports for that level).
+__device__ __forceinline__ void spmv_we_block(const DevMesh &m, DevState &s, int b) {
     __shared__ double wsum[4];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
-    const int i = blockIdx.x * 256 + t;
+    const int i = b * 256 + t;
     double we = 0.0;
     if (i < m.n1) {
         const float e = spmv_row(m, s, i);
@@ -1543,23 +1603,32 @@ __global__ __launch_bounds__(256) void k_spmv_we(DevMesh m, DevState s) {
     we = wave_sum64d(we);
     if (l == 0) wsum[w] = we;
     __syncthreads();
-    if (t == 0) s.part_wenow[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    if (t == 0) s.part_wenow[b] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
-// The node pass of a diagnostic step: one thread per node only (the energy
-// of the new level comes from the SpMV blocks).  A last-block-done final
-// reduction (device-scope fences around a ticket) was measured 12 us slower
-// per step than the separate k_diag_final launch.
-__global__ __launch_bounds__(256) void k_node_step(DevMesh m, DevState s, int nb_face, int nb_edge) {
+// The node pass of a diagnostic step, block b of nb_node: one thread per
+// node only (the energy of the new level comes from the SpMV blocks).
+__device__ __forceinline__ void node_step_block(const DevMesh &m, DevState &s, int nb_node, int nb_face,
+                                                int nb_edge) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long n = s.ctr->step;
     const bool have_prev = s.ctr->diag_level1 == n && n > 0;
     const bool first = s.ctr->g0_set == 0;
     DiagVals v{};
     if (i < m.n0) node_vals(m, s, i, have_prev, first, v);
-    fold_slices(s, v, 1, nb_face, nb_edge, gridDim.x);
+    fold_slices(s, v, 1, nb_face, nb_edge, nb_node);
     const DiagVals r = block_reduce_diag(v);
-    if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, gridDim.x, r);
+    if (threadIdx.x == 0) store_partials(s.part_node, blockIdx.x, nb_node, r);
+}
+
+// Both in one launch: blocks 0 .. nb_node - 1 are the node pass (chains of
+// dependent gathers, so they start first), the rest the SpMV.  They share no
+// array (the SpMV reads D and writes E; the node pass reads D, the charges
+// and the edge currents).  A separate node-pass launch after the SpMV took
+// 12.8 us of its own.
+__global__ __launch_bounds__(256) void k_spmv_node(DevMesh m, DevState s, int nb_node, int nb_face, int nb_edge) {
+    if ((int)blockIdx.x < nb_node) node_step_block(m, s, nb_node, nb_face, nb_edge);
+    else spmv_we_block(m, s, (int)blockIdx.x - nb_node);
 }
 
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
@@ -1797,8 +1866,8 @@ void launch_diag_in_step(const DevMesh &m, DevState &s, hipStream_t st) {
 
 void launch_spmv_diag(const DevMesh &m, DevState &s, hipStream_t st) {
     const int nb_node = (int)nblk(m.n0, 256), nb_spmv = (int)nblk(m.n1, 256);
-    hipLaunchKernelGGL(k_spmv_we, dim3(nb_spmv), dim3(256), 0, st, m, s);
-    hipLaunchKernelGGL(k_node_step, dim3(nb_node), dim3(256), 0, st, m, s, (int)nblk(m.n2, 256), nb_spmv);
+    hipLaunchKernelGGL(k_spmv_node, dim3(nb_node + nb_spmv), dim3(256), 0, st, m, s, nb_node, (int)nblk(m.n2, 256),
+                       nb_spmv);
 }
 
 void launch_step_final(const DevMesh &m, DevState &s, hipStream_t st) {
