@@ -402,23 +402,36 @@ __device__ __forceinline__ void wave_count(const Win &w, int *cnt, int t, int c)
     if (run_tail(t) && t >= 0 && a[0]) win_add_c(w, cnt, t, a[0]);
 }
 
+// (blocks of kWG threads: each thread takes fixed rows of the window, and
+// reads all of its rows before the first atomic)
+static_assert((3 * kWin) % kWG == 0 && kWin % kWG == 0, "window rows per thread");
+
 __device__ __forceinline__ void win_zero(const Win &w) {
-    for (int i = threadIdx.x; i < 3 * kWin; i += blockDim.x) w.jl[i] = 0ull;
-    for (int i = threadIdx.x; i < kWin; i += blockDim.x) w.cl[i] = 0;
+#pragma unroll
+    for (int r = 0; r < 3 * kWin / kWG; ++r) w.jl[threadIdx.x + r * kWG] = 0ull;
+#pragma unroll
+    for (int r = 0; r < kWin / kWG; ++r) w.cl[threadIdx.x + r * kWG] = 0;
 }
 
-// after a barrier: add the window to the global arrays
+// after a barrier: add the window to the global arrays (3 n2 < 2^31)
 __device__ __forceinline__ void win_flush(const Win &w, unsigned long long *J, int *cnt, int n2, bool counts) {
-    for (int i = threadIdx.x; i < 3 * kWin; i += blockDim.x) {
-        const unsigned long long v = w.jl[i];
-        const long long gi = 3ll * w.base + i;
-        if (v != 0ull && gi >= 0 && gi < 3ll * n2) atomicAdd(&J[gi], v);
+    constexpr int R = 3 * kWin / kWG, RC = kWin / kWG;
+    unsigned long long v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = w.jl[threadIdx.x + r * kWG];
+    int c[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) c[r] = counts ? w.cl[threadIdx.x + r * kWG] : 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gi = 3 * w.base + (int)threadIdx.x + r * kWG;
+        if (v[r] != 0ull && gi >= 0 && gi < 3 * n2) atomicAdd(&J[gi], v[r]);
     }
-    if (counts)
-        for (int i = threadIdx.x; i < kWin; i += blockDim.x) {
-            const int v = w.cl[i], t = w.base + i;
-            if (v != 0 && t >= 0 && t < n2) atomicAdd(&cnt[t], v);
-        }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        const int t = w.base + (int)threadIdx.x + r * kWG;
+        if (c[r] != 0 && t >= 0 && t < n2) atomicAdd(&cnt[t], c[r]);
+    }
 }
 
 struct Particle {
@@ -713,10 +726,25 @@ __device__ __forceinline__ float gamma_m1(float ur, float up, float uz) {
 }
 
 // Per-wave sums in a fixed butterfly (deterministic); every lane gets the total.
+// Sum over the 64 lanes of a wave in a fixed order, returned to every lane:
+// the row shifts and broadcasts of seg_scan (every lane in one run) leave
+// the total in lane 63.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov_d(double v) {
+    return __longlong_as_double(dpp_mov<CTRL, ROWS>((long long)__double_as_longlong(v)));
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_mov_d<0x111, 0xF>(v);
+    v += dpp_mov_d<0x112, 0xF>(v);
+    v += dpp_mov_d<0x114, 0xF>(v);
+    v += dpp_mov_d<0x118, 0xF>(v);
+    v += dpp_mov_d<0x142, 0xA>(v);
+    v += dpp_mov_d<0x143, 0xC>(v);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 __device__ __forceinline__ int wave_sum_i(int v) {
@@ -980,17 +1008,22 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     if (DIAG) {
         // level n+1: the end positions' charge (absorbed particles, cell -1, hold none)
         __syncthreads();             // the owners have read the queue: its LDS becomes the charge window
-        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) s_ql[i] = 0;
+#pragma unroll
+        for (int r = 0; r < 3 * kWin / kWG; ++r) s_ql[threadIdx.x + r * kWG] = 0;
         __syncthreads();
         end_charge<SINGLE, QA>(m, k0, qw, s.Qloc, P);
         __syncthreads();
     }
     win_flush(w, s.Jloc, s.cnt, m.n2, do_count != 0);
     if (DIAG) {                      // the charge window, and the block's partials of level n and n+1
-        for (int i = threadIdx.x; i < 3 * kWin; i += kWG) {
-            const unsigned long long v = (unsigned long long)s_ql[i];
-            const long long gi = 3ll * w.base + i;
-            if (v != 0ull && gi >= 0 && gi < 3ll * m.n2) atomicAdd(&s.Qloc[gi], v);
+        constexpr int R = 3 * kWin / kWG;
+        unsigned long long q[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) q[r] = (unsigned long long)s_ql[threadIdx.x + r * kWG];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gi = 3 * w.base + (int)threadIdx.x + r * kWG;
+            if (q[r] != 0ull && gi >= 0 && gi < 3 * m.n2) atomicAdd(&s.Qloc[gi], q[r]);
         }
         if (threadIdx.x == 0) {
             double v = 0.0;
