@@ -65,58 +65,90 @@ __device__ __forceinline__ void fold_slices(const DevState &s, DiagVals &v, int 
     }
 }
 
-// Butterfly over the 64 lanes of a wave (fixed order): sum, and max of bit patterns.
+// Reductions over the 64 lanes of a wave in a fixed order, by DPP moves (no
+// LDS round trip): inclusive scans within each row of 16 lanes (row_shr by
+// 1, 2, 4, 8), then lane 15 into row 1 and lane 47 into row 3 (row_bcast:15),
+// then lane 31 into rows 2 and 3 (row_bcast:31); lane 63 ends with the
+// result, which every lane receives.  Lanes that receive nothing get 0, the
+// identity of both the sum and the max of non-negative bit patterns.  The
+// whole wave must be active.  GFX9 DPP controls: row_shr:n = 0x110 + n,
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+    return (unsigned long long)__builtin_amdgcn_update_dpp((long long)0, (long long)v, CTRL, ROWS, 0xF, true);
+}
+
+__device__ __forceinline__ unsigned long long lane63(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double x) {
+    return x + __longlong_as_double((long long)dpp64<CTRL, ROWS>(dbits(x)));
+}
+
 __device__ __forceinline__ double wave_sum64d(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x = dpp_add<0x111, 0xF>(x);
+    x = dpp_add<0x112, 0xF>(x);
+    x = dpp_add<0x114, 0xF>(x);
+    x = dpp_add<0x118, 0xF>(x);
+    x = dpp_add<0x142, 0xA>(x);
+    x = dpp_add<0x143, 0xC>(x);
+    return __longlong_as_double((long long)lane63(dbits(x)));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_max(unsigned long long x) {
+    const unsigned long long y = dpp64<CTRL, ROWS>(x);
+    return y > x ? y : x;
 }
 
 __device__ __forceinline__ unsigned long long wave_max64(unsigned long long x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(x, off, 64);
-        x = o > x ? o : x;
-    }
-    return x;
+    x = dpp_max<0x111, 0xF>(x);
+    x = dpp_max<0x112, 0xF>(x);
+    x = dpp_max<0x114, 0xF>(x);
+    x = dpp_max<0x118, 0xF>(x);
+    x = dpp_max<0x142, 0xA>(x);
+    x = dpp_max<0x143, 0xC>(x);
+    return lane63(x);
 }
 
-// Fixed-order reduction of DiagVals over a block of 256 threads: the values
-// are staged in LDS, each wave reduces whole slots (four entries per lane in
-// order, then a butterfly).  Thread 0 receives the result.
+// Fixed-order reduction of DiagVals over a block of 256 threads (four
+// waves): each wave reduces every value, then thread 0 combines the four
+// waves in order.  Thread 0 receives the result.
 __device__ __forceinline__ DiagVals block_reduce_diag(const DiagVals &v) {
     constexpr int NV = kDiagSums + kDiagMaxes;
-    __shared__ double sh[NV][256];
-    __shared__ double res[NV];
-    const int t = threadIdx.x;
+    __shared__ double sh[NV][4];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double sm[kDiagSums];
+    unsigned long long mx[kDiagMaxes];
 #pragma unroll
-    for (int k = 0; k < kDiagSums; ++k) sh[k][t] = v.sum[k];
+    for (int k = 0; k < kDiagSums; ++k) sm[k] = wave_sum64d(v.sum[k]);
 #pragma unroll
-    for (int k = 0; k < kDiagMaxes; ++k) sh[kDiagSums + k][t] = __longlong_as_double((long long)v.mx[k]);
-    __syncthreads();
-    const int w = t >> 6, l = t & 63;
-    for (int k = w; k < NV; k += 4) {                 // wave-uniform
-        if (k < kDiagSums) {
-            const double x = wave_sum64d(((sh[k][l] + sh[k][l + 64]) + sh[k][l + 128]) + sh[k][l + 192]);
-            if (l == 0) res[k] = x;
-        } else {
-            unsigned long long x = 0;
+    for (int k = 0; k < kDiagMaxes; ++k) mx[k] = wave_max64(v.mx[k]);
+    if (l == 0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const unsigned long long y = dbits(sh[k][l + 64 * q]);
-                x = y > x ? y : x;
-            }
-            x = wave_max64(x);
-            if (l == 0) res[k] = __longlong_as_double((long long)x);
-        }
+        for (int k = 0; k < kDiagSums; ++k) sh[k][w] = sm[k];
+#pragma unroll
+        for (int k = 0; k < kDiagMaxes; ++k) sh[kDiagSums + k][w] = __longlong_as_double((long long)mx[k]);
     }
     __syncthreads();
     DiagVals r{};
-    if (t == 0) {
+    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < kDiagSums; ++k) r.sum[k] = res[k];
+        for (int k = 0; k < kDiagSums; ++k) r.sum[k] = ((sh[k][0] + sh[k][1]) + sh[k][2]) + sh[k][3];
 #pragma unroll
-        for (int k = 0; k < kDiagMaxes; ++k) r.mx[k] = dbits(res[kDiagSums + k]);
+        for (int k = 0; k < kDiagMaxes; ++k) {
+            unsigned long long x = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const unsigned long long y = dbits(sh[kDiagSums + k][q]);
+                x = y > x ? y : x;
+            }
+            r.mx[k] = x;
+        }
     }
     return r;
 }

@@ -279,19 +279,17 @@ __device__ __forceinline__ void win_add_c(const Win &w, int *cnt, int t, int v) 
     else atomicAdd(&cnt[t], v);
 }
 
-// Deposit every lane's (face t, 3 side currents): a segmented inclusive scan
-// over runs of consecutive lanes holding the same face (lanes follow the
-// particle order, which is sorted by face), after which the last lane of
-// each run adds the run's total.  Cost is independent of how many faces the
-// wave holds.  Lanes with t < 0 hold nothing.  All lanes of the wave must
-// call this together.
+// Deposit every lane's (face t, 3 side currents): sums over runs of
+// consecutive lanes holding the same face (lanes follow the particle order,
+// which is sorted by face), after which the last lane of each run adds the
+// run's total.  Cost is independent of how many faces the wave holds.  Lanes
+// with t < 0 hold nothing.  All lanes of the wave must call this together.
 //
-// The scan moves values between lanes with DPP (data-parallel primitives of
-// the VALU, no LDS round trip): shifts by 1, 2, 4 and 8 lanes within each
-// row of 16, then the last lane of a row broadcast into the next row
-// (row_bcast:15, rows 1 and 3) and lane 31 into the upper half (row_bcast:31,
-// rows 2 and 3).  A lane adds what arrives only from a lane of its own run;
-// lanes outside a move's source range receive 0, which is no run.
+// Values move between lanes with DPP (data-parallel primitives of the VALU,
+// no LDS round trip): shifts by 1, 2, 4 and 8 lanes within each row of 16,
+// then the last lane of a row broadcast into the next row (row_bcast:15,
+// rows 1 and 3) and lane 31 into the upper half (row_bcast:31, rows 2 and
+// 3); lanes outside a move's source range receive 0.
 // GFX9 DPP controls: row_shr:n = 0x110 + n, wave_shl:1 = 0x130,
 // wave_shr:1 = 0x138, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
 template <int CTRL, int ROWS>
@@ -304,23 +302,16 @@ __device__ __forceinline__ unsigned dpp_mov(unsigned v) {
     return (unsigned)dpp_mov<CTRL, ROWS>((int)v);
 }
 
+// (64-bit: one move per 32-bit half; the 64-bit form of the builtin keeps the
+// halves in one register pair, so a following 64-bit add is one instruction)
 template <int CTRL, int ROWS>
 __device__ __forceinline__ long long dpp_mov(long long v) {
-    const unsigned lo = (unsigned)dpp_mov<CTRL, ROWS>((int)(unsigned)v);
-    const unsigned hi = (unsigned)dpp_mov<CTRL, ROWS>((int)(unsigned)((unsigned long long)v >> 32));
-    return (long long)(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_update_dpp((long long)0, v, CTRL, ROWS, 0xF, true);
 }
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ unsigned long long dpp_mov(unsigned long long v) {
     return (unsigned long long)dpp_mov<CTRL, ROWS>((long long)v);
-}
-
-__device__ __forceinline__ int lane_run(int t) {
-    const int lane = threadIdx.x & 63;
-    const int tp = dpp_mov<0x138, 0xF>(t);                   // lane - 1 (lane 0: head anyway)
-    const unsigned long long heads = __ballot(lane == 0 || tp != t);
-    return __popcll(heads & ((2ull << lane) - 1ull));       // 1-based index of the lane's run
 }
 
 __device__ __forceinline__ bool run_tail(int t) {
@@ -329,32 +320,56 @@ __device__ __forceinline__ bool run_tail(int t) {
     return lane == 63 || tn != t;
 }
 
-template <int CTRL, int ROWS, class V, int N>
-__device__ __forceinline__ void seg_step(int run, V (&a)[N]) {
-    const int ro = dpp_mov<CTRL, ROWS>(run);
-    V b[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) b[k] = dpp_mov<CTRL, ROWS>(a[k]);
-    if (ro == run)
-#pragma unroll
-        for (int k = 0; k < N; ++k) a[k] += b[k];
+// ds_bpermute of a lane's value from the lane at byte address addr (4 x lane)
+__device__ __forceinline__ int bperm(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+__device__ __forceinline__ unsigned bperm(int addr, unsigned v) { return (unsigned)bperm(addr, (int)v); }
+__device__ __forceinline__ long long bperm(int addr, long long v) {
+    const unsigned lo = bperm(addr, (unsigned)(unsigned long long)v);
+    const unsigned hi = bperm(addr, (unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ unsigned long long bperm(int addr, unsigned long long v) {
+    return (unsigned long long)bperm(addr, (long long)v);
 }
 
-// Inclusive sums of a[] over the lane's run (run: 1-based run index).
+template <int CTRL, int ROWS, class V, int N>
+__device__ __forceinline__ void scan_step(V (&a)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] += dpp_mov<CTRL, ROWS>(a[k]);
+}
+
+// Sums of a[] over runs of consecutive lanes holding the same key t: each
+// lane receives the sum over its run up to itself, so a run's last lane
+// holds the run's total.  Integer sums, exact in any order (modular for the
+// unsigned types, whose run totals stay below 2^32): an inclusive scan over
+// the whole wave (row shifts, then the row broadcasts), after which each
+// lane subtracts the scan value of the lane just before its run's first lane
+// (one ds_bpermute per 32-bit word).  All lanes of the wave must call this
+// together.
 template <class V, int N>
-__device__ __forceinline__ void seg_scan(int run, V (&a)[N]) {
-    seg_step<0x111, 0xF>(run, a);
-    seg_step<0x112, 0xF>(run, a);
-    seg_step<0x114, 0xF>(run, a);
-    seg_step<0x118, 0xF>(run, a);
-    seg_step<0x142, 0xA>(run, a);
-    seg_step<0x143, 0xC>(run, a);
+__device__ __forceinline__ void run_totals(int t, V (&a)[N]) {
+    const int lane = threadIdx.x & 63;
+    const int tp = dpp_mov<0x138, 0xF>(t);                   // lane - 1 (lane 0: a head anyway)
+    const unsigned long long heads = __ballot(lane == 0 || tp != t);
+    const int head = 63 - __clzll(heads & ((2ull << lane) - 1ull));   // first lane of this lane's run
+    scan_step<0x111, 0xF>(a);
+    scan_step<0x112, 0xF>(a);
+    scan_step<0x114, 0xF>(a);
+    scan_step<0x118, 0xF>(a);
+    scan_step<0x142, 0xA>(a);
+    scan_step<0x143, 0xC>(a);
+    const int src = (head > 0 ? head - 1 : 0) << 2;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const V before = bperm(src, a[k]);
+        if (head > 0) a[k] -= before;
+    }
 }
 
 __device__ __forceinline__ void wave_deposit(const Win &w, unsigned long long *J, int t, long long a0, long long a1,
                                              long long a2) {
     long long a[3] = {a0, a1, a2};
-    seg_scan<long long, 3>(lane_run(t), a);
+    run_totals<long long, 3>(t, a);
     if (run_tail(t) && t >= 0) win_add_j(w, J, t, a[0], a[1], a[2]);
 }
 
@@ -398,7 +413,7 @@ __device__ __forceinline__ void qwin_add3(const QWinL<QA> &w, unsigned long long
 // Same for a count per face (histogram of the counting sort).
 __device__ __forceinline__ void wave_count(const Win &w, int *cnt, int t, int c) {
     int a[1] = {c};
-    seg_scan<int, 1>(lane_run(t), a);
+    run_totals<int, 1>(t, a);
     if (run_tail(t) && t >= 0 && a[0]) win_add_c(w, cnt, t, a[0]);
 }
 
@@ -645,7 +660,7 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
 // lanes of the wave must call it together.
 template <class V, int N>
 __device__ __forceinline__ void wave_run_sums(int t, V (&a)[N]) {
-    seg_scan<V, N>(lane_run(t), a);
+    run_totals<V, N>(t, a);
 }
 
 __device__ __forceinline__ void corner_add(unsigned long long *Qloc, int t, long long q0, long long q1, long long q2) {
@@ -726,26 +741,8 @@ __device__ __forceinline__ float gamma_m1(float ur, float up, float uz) {
 }
 
 // Per-wave sums in a fixed butterfly (deterministic); every lane gets the total.
-// Sum over the 64 lanes of a wave in a fixed order, returned to every lane:
-// the row shifts and broadcasts of seg_scan (every lane in one run) leave
-// the total in lane 63.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_mov_d(double v) {
-    return __longlong_as_double(dpp_mov<CTRL, ROWS>((long long)__double_as_longlong(v)));
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-    v += dpp_mov_d<0x111, 0xF>(v);
-    v += dpp_mov_d<0x112, 0xF>(v);
-    v += dpp_mov_d<0x114, 0xF>(v);
-    v += dpp_mov_d<0x118, 0xF>(v);
-    v += dpp_mov_d<0x142, 0xA>(v);
-    v += dpp_mov_d<0x143, 0xC>(v);
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
+// Sum over the 64 lanes of a wave in a fixed order, returned to every lane.
+__device__ __forceinline__ double wave_sum_d(double v) { return wave_sum64d(v); }
 
 __device__ __forceinline__ int wave_sum_i(int v) {
 #pragma unroll
@@ -1382,7 +1379,7 @@ __global__ __launch_bounds__(kWG) void k_charge_now(DevMesh m, DevState s) {
 // was evaluated, the total charge; per edge 1/2 E^n D^n (W_E with the
 // scheme's [*eps]_a).  Each block also folds its slice of the step's
 // particle, face and edge partials (in_step).
-constexpr int kNodeCols = 8;   // list entries a node loads in one go (a mesh node has about six; longer lists loop)
+constexpr int kNodeCols = 4;   // list entries a node loads in one go (a mesh node has about six)
 
 // Node i of an evaluation at level n = ctr->step: nodal charge (wall charge
 // plus the corners of its faces), the Gauss residual against its reference
@@ -1392,52 +1389,41 @@ __device__ __forceinline__ void node_vals(const DevMesh &m, DevState &s, int i, 
                                           DiagVals &v) {
     const int inst = m.ninst ? m.ninst[i] : 0;
     long long Q = s.Qres[i];
-    // the node's slice of the padded lists: every index load of the first
-    // kNodeCols entries, then every value load, in flight together (the
-    // mesh's longest list is a kernel argument, so no load bounds them); the
-    // sums keep the list order
+    // the node's slice of the padded lists, kNodeCols entries at a time: the
+    // index loads of a chunk, then its value loads, are in flight together
+    // (the mesh's longest lists are kernel arguments, so no load bounds the
+    // chunks); the sums keep the list order
     const size_t sl = (size_t)(i >> 6), l = (size_t)(i & 63);
     const int32_t *cp = m.ncorner_ell + sl * (size_t)m.nwc * 64 + l;
     const int32_t *ep = m.nedge_ell + sl * (size_t)m.nwe * 64 + l;
-    int ci[kNodeCols], ei[kNodeCols];
-#pragma unroll
-    for (int j = 0; j < kNodeCols; ++j) {
-        ci[j] = j < m.nwc ? cp[64 * j] : -1;
-        ei[j] = j < m.nwe ? ep[64 * j] : 0;
-    }
-    long long qv[kNodeCols], jv[kNodeCols];
-    double d[kNodeCols];
-#pragma unroll
-    for (int j = 0; j < kNodeCols; ++j) {
-        const int e = (ei[j] < 0 ? -ei[j] : ei[j]) - 1;
-        qv[j] = ci[j] >= 0 ? (long long)s.Qloc[ci[j]] : 0ll;
-        d[j] = ei[j] ? s.D[e] : 0.0;
-        jv[j] = ei[j] ? s.Jfx[e] : 0ll;
-    }
-#pragma unroll
-    for (int j = 0; j < kNodeCols; ++j) Q += qv[j];
-    for (int j = kNodeCols; j < m.nwc; ++j) {
-        const int c = cp[64 * j];
-        if (c >= 0) Q += (long long)s.Qloc[c];
-    }
+    const int ncol = m.nwc > m.nwe ? m.nwc : m.nwe;
     double div = 0.0, mag = 0.0;
     long long divj = 0;
+    for (int j0 = 0; j0 < ncol; j0 += kNodeCols) {
+        int ci[kNodeCols], ei[kNodeCols];
 #pragma unroll
-    for (int j = 0; j < kNodeCols; ++j)
-        if (ei[j]) {
-            div += ei[j] > 0 ? d[j] : -d[j];
-            mag += fabs(d[j]);
-            divj += ei[j] > 0 ? jv[j] : -jv[j];
+        for (int j = 0; j < kNodeCols; ++j) {
+            ci[j] = j0 + j < m.nwc ? cp[64 * (j0 + j)] : -1;
+            ei[j] = j0 + j < m.nwe ? ep[64 * (j0 + j)] : 0;
         }
-    for (int j = kNodeCols; j < m.nwe; ++j) {
-        const int x = ep[64 * j];
-        if (!x) continue;
-        const int e = (x < 0 ? -x : x) - 1;
-        const double dd = s.D[e];
-        const long long jj = s.Jfx[e];
-        div += x > 0 ? dd : -dd;
-        mag += fabs(dd);
-        divj += x > 0 ? jj : -jj;
+        long long qv[kNodeCols], jv[kNodeCols];
+        double d[kNodeCols];
+#pragma unroll
+        for (int j = 0; j < kNodeCols; ++j) {
+            const int e = (ei[j] < 0 ? -ei[j] : ei[j]) - 1;
+            qv[j] = ci[j] >= 0 ? (long long)s.Qloc[ci[j]] : 0ll;
+            d[j] = ei[j] ? s.D[e] : 0.0;
+            jv[j] = ei[j] ? s.Jfx[e] : 0ll;
+        }
+#pragma unroll
+        for (int j = 0; j < kNodeCols; ++j) {
+            Q += qv[j];
+            if (ei[j]) {
+                div += ei[j] > 0 ? d[j] : -d[j];
+                mag += fabs(d[j]);
+                divj += ei[j] > 0 ? jv[j] : -jv[j];
+            }
+        }
     }
     const double q = (double)Q * m.inst[inst].qscale;
     if (have_prev) {
