@@ -1,6 +1,7 @@
 """Train and evaluate the learned-SPAI network.
 
     python -m paper_1701_03784_amd.train_spai --meshes 48 --out spai_mlp_l3.bin [--bwo-steps 20000]
+    python -m paper_1701_03784_amd.train_spai --load spai_mlp_l3.bin --eval-meshes 64 [--faces-max 200000]
 
 Training meshes are seeded rippled-wall tubes (random ripple amplitude,
 period, taper and mesh size); every mesh's plain SPAI is computed by the
@@ -135,37 +136,43 @@ def main():
     ap.add_argument("--bwo-steps", type=int, default=0)
     ap.add_argument("--bwo-particles", type=int, default=8_000_000)
     ap.add_argument("--out", default="")
+    ap.add_argument("--load", default="", help="evaluate a saved network instead of training one")
     args = ap.parse_args()
 
     import torch  # noqa: F401  (device buffers)
     from . import Mlp, load_library
     from .learned_spai import training_pairs, train
     load_library()
-    t0 = time.perf_counter()
-    meshes = (random_tube(1000 + i, args.faces_min, args.faces_max) for i in range(args.meshes))
-    X, y = training_pairs(meshes, max_pairs_per_mesh=args.pairs_per_mesh, seed=0, log=log)
-    t_data = time.perf_counter() - t0
-    n_pairs = int(len(y))
-    log(f"{n_pairs} training pairs from {args.meshes} meshes in {t_data:.1f} s")
-    net = Mlp(n_hidden=64, n_layers=2, seed=0)
-    t1 = time.perf_counter()
-    hist = train(net, X, y, epochs=args.epochs, batch=4096, lr=3e-3, lr_final=1e-4,
-                 log=lambda s: log(s) if s.endswith("9") or s.startswith("epoch 0") else None)
-    t_train = time.perf_counter() - t1
-    log(f"trained in {t_train:.1f} s: loss {hist[0]:.3e} -> {hist[-1]:.3e}")
-    if args.out:
-        net.save(args.out)
-    del X, y
+    if args.load:
+        net = Mlp.load(args.load)
+        training = {"loaded": args.load}
+        log(f"network loaded from {args.load}")
+    else:
+        t0 = time.perf_counter()
+        meshes = (random_tube(1000 + i, args.faces_min, args.faces_max) for i in range(args.meshes))
+        X, y = training_pairs(meshes, max_pairs_per_mesh=args.pairs_per_mesh, seed=0, log=log)
+        t_data = time.perf_counter() - t0
+        n_pairs = int(len(y))
+        log(f"{n_pairs} training pairs from {args.meshes} meshes in {t_data:.1f} s")
+        net = Mlp(n_hidden=64, n_layers=2, seed=0)
+        t1 = time.perf_counter()
+        hist = train(net, X, y, epochs=args.epochs, batch=4096, lr=3e-3, lr_final=1e-4,
+                     log=lambda s: log(s) if s.endswith("9") or s.startswith("epoch 0") else None)
+        t_train = time.perf_counter() - t1
+        log(f"trained in {t_train:.1f} s: loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+        if args.out:
+            net.save(args.out)
+        del X, y
+        training = {"meshes": args.meshes, "faces": [args.faces_min, args.faces_max], "pairs": n_pairs,
+                    "data_seconds": t_data, "train_seconds": t_train, "loss_first_epoch": hist[0],
+                    "loss_last_epoch": hist[-1], "epochs": args.epochs}
     evals = []
     ident = identity_network()
     for i in range(args.eval_meshes):
         res = residual_study(net, ident, random_tube(2000 + i, args.faces_min, args.faces_max))
         log(f"unseen mesh {i}: {json.dumps(res)}")
         evals.append(res)
-    summary = {"training": {"meshes": args.meshes, "pairs": n_pairs, "data_seconds": t_data,
-                            "train_seconds": t_train, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-                            "epochs": args.epochs},
-               "unseen": evals}
+    summary = {"training": training, "unseen": evals}
     if args.bwo_steps:
         summary["bwo"] = bwo_runs(net, args.bwo_steps, args.bwo_particles, max(100, args.bwo_steps // 10))
     print(json.dumps(summary), flush=True)

@@ -209,7 +209,7 @@ def test_guard_rejects_a_broken_network(axp):
 
 
 def test_shipped_network_on_the_bwo_profile(axp):
-    # the network trained by train_spai.py (seeded tubes, seeds 1000-1047) on a
+    # the network trained by train_spai.py (seeded tubes, seeds 1000-1255) on a
     # tube it was not trained on: the construction keeps most of its columns
     net = axp.default_spai_model()
     assert net.info()["spai_level"] == 3

@@ -60,10 +60,10 @@ def test_learned_vs_plain_spai_on_the_benchmarked_tube(axp):
     # the row tolerance, so ||I - A M||_F is 12 % above least squares (measured)
     assert il["spai_fro_residual"] <= 1.25 * ip["spai_fro_residual"]
     # the stage the network replaces (least squares of every column, then the
-    # shared assembly) takes half the time (measured 0.18 s against 0.34 s) ...
+    # shared assembly) takes half the time (measured 0.16 s against 0.33 s) ...
     assert il["spai_solve_seconds"] < 0.7 * ip["spai_solve_seconds"]
     # ... but the pair features and the inference cost about what that saves
-    # (measured 0.19 s against 0.16 s): no gain in total at this size
+    # (measured 0.17 s against 0.17 s): no gain in total at this size
     saved = ip["spai_solve_seconds"] - il["spai_solve_seconds"]
     spent = il["spai_feature_seconds"] + il["spai_infer_seconds"]
     print(f"[gpu] least-squares stage saved {saved:.3f} s, features and inference spent {spent:.3f} s: "
