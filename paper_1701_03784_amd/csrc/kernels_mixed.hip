@@ -655,9 +655,9 @@ __device__ __forceinline__ void walk_mover(const DevMesh &m, const DevState &s, 
     mv.L1 = L1;
 }
 
-// Inclusive sum of N values over runs of consecutive lanes holding the same
-// key t (segmented scan); the run's last lane then holds the run's sums.  All
-// lanes of the wave must call it together.
+// Sums of N values over runs of consecutive lanes holding the same key t
+// (run_totals); the run's last lane then holds the run's sums.  All lanes of
+// the wave must call it together.
 template <class V, int N>
 __device__ __forceinline__ void wave_run_sums(int t, V (&a)[N]) {
     run_totals<V, N>(t, a);
@@ -1371,14 +1371,6 @@ __global__ __launch_bounds__(kWG) void k_charge_now(DevMesh m, DevState s) {
     }
 }
 
-// Node pass of an evaluation at level n = ctr->step (in a diagnostic step,
-// after its field update: n is the step's end level): Q^n from the wall
-// charge and the corner charges, the Gauss residual res = Ddiv D^n - Q^n
-// (Sec. 3.5.2) and its drift from the reference level, the continuity
-// residual 2^23 (Q^n - Q^{n-1}) + Ddiv J^{n-1/2} (Sec. 3.5.1) when level n-1
-// was evaluated, the total charge; per edge 1/2 E^n D^n (W_E with the
-// scheme's [*eps]_a).  Each block also folds its slice of the step's
-// particle, face and edge partials (in_step).
 constexpr int kNodeCols = 4;   // list entries a node loads in one go (a mesh node has about six)
 
 // Node i of an evaluation at level n = ctr->step: nodal charge (wall charge
@@ -1442,6 +1434,14 @@ __device__ __forceinline__ void node_vals(const DevMesh &m, DevState &s, int i, 
     v.sum[0] = q;
 }
 
+// Node pass of an evaluation at level n = ctr->step, on demand or (in_step)
+// after the field update of a diagnostic step with absorbing layers: Q^n
+// from the wall charge and the corner charges, the Gauss residual
+// res = Ddiv D^n - Q^n (Sec. 3.5.2) and its drift from the reference level,
+// the continuity residual 2^23 (Q^n - Q^{n-1}) + Ddiv J^{n-1/2} (Sec. 3.5.1)
+// when level n-1 was evaluated, the total charge; per edge 1/2 E^n D^n (W_E
+// with the scheme's [*eps]_a).  Each block also folds its slice of the
+// step's particle, face and edge partials (in_step).
 __global__ __launch_bounds__(256) void k_node_diag(DevMesh m, DevState s, int in_step, int nb_face, int nb_edge) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned long long n = s.ctr->step;
