@@ -449,6 +449,16 @@ __device__ __forceinline__ void win_flush(const Win &w, unsigned long long *J, i
     }
 }
 
+// Particle streams are loaded and stored non-temporally: each word is read
+// and written once per step, and without the hint the 400 MB a step moves
+// evicts the faces' and edges' tables from L2 and the last-level cache
+// (measured: particle kernel 108.8 -> 105.7 us, SpMV 20.3 -> 16.1 us, face
+// pass 13.9 -> 12.6 us, the step 0.155 -> 0.146 ms).  Native vector types,
+// which the non-temporal builtins take.
+typedef int nt_i4 __attribute__((ext_vector_type(4)));
+typedef unsigned nt_u4 __attribute__((ext_vector_type(4)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+
 struct Particle {
     int cell;
     uint32_t L0, L1;
@@ -824,12 +834,12 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
     const bool full = p0 + kPPT <= n;
     Particle P[kPPT];
     if (full) {
-        const int4 cc = *reinterpret_cast<const int4 *>(cell + p0);
-        const uint4 a = *reinterpret_cast<const uint4 *>(L0a + p0);
-        const uint4 b = *reinterpret_cast<const uint4 *>(L1a + p0);
-        const float4 x = *reinterpret_cast<const float4 *>(ura + p0);
-        const float4 y = *reinterpret_cast<const float4 *>(upa + p0);
-        const float4 z = *reinterpret_cast<const float4 *>(uza + p0);
+        const nt_i4 cc = __builtin_nontemporal_load(reinterpret_cast<const nt_i4 *>(cell + p0));
+        const nt_u4 a = __builtin_nontemporal_load(reinterpret_cast<const nt_u4 *>(L0a + p0));
+        const nt_u4 b = __builtin_nontemporal_load(reinterpret_cast<const nt_u4 *>(L1a + p0));
+        const nt_f4 x = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(ura + p0));
+        const nt_f4 y = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(upa + p0));
+        const nt_f4 z = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(uza + p0));
         P[0] = {cc.x, a.x, b.x, x.x, y.x, z.x};
         P[1] = {cc.y, a.y, b.y, x.y, y.y, z.y};
         P[2] = {cc.z, a.z, b.z, x.z, y.z, z.z};
@@ -945,9 +955,9 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
         const double v = wave_sum_d(k);
         if ((threadIdx.x & 63) == 0) s_wk1[threadIdx.x >> 6] = v;
         if (full) {
-            *reinterpret_cast<float4 *>(ura + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
-            *reinterpret_cast<float4 *>(upa + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
-            *reinterpret_cast<float4 *>(uza + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
+            __builtin_nontemporal_store((nt_f4){P[0].ur, P[1].ur, P[2].ur, P[3].ur}, reinterpret_cast<nt_f4 *>(ura + p0));
+            __builtin_nontemporal_store((nt_f4){P[0].up, P[1].up, P[2].up, P[3].up}, reinterpret_cast<nt_f4 *>(upa + p0));
+            __builtin_nontemporal_store((nt_f4){P[0].uz, P[1].uz, P[2].uz, P[3].uz}, reinterpret_cast<nt_f4 *>(uza + p0));
         } else {
 #pragma unroll
             for (int j = 0; j < kPPT; ++j)
@@ -1034,13 +1044,13 @@ __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevS
         }
     }
     if (full) {
-        *reinterpret_cast<int4 *>(cell + p0) = make_int4(P[0].cell, P[1].cell, P[2].cell, P[3].cell);
-        *reinterpret_cast<uint4 *>(L0a + p0) = make_uint4(P[0].L0, P[1].L0, P[2].L0, P[3].L0);
-        *reinterpret_cast<uint4 *>(L1a + p0) = make_uint4(P[0].L1, P[1].L1, P[2].L1, P[3].L1);
+        __builtin_nontemporal_store((nt_i4){P[0].cell, P[1].cell, P[2].cell, P[3].cell}, reinterpret_cast<nt_i4 *>(cell + p0));
+        __builtin_nontemporal_store((nt_u4){P[0].L0, P[1].L0, P[2].L0, P[3].L0}, reinterpret_cast<nt_u4 *>(L0a + p0));
+        __builtin_nontemporal_store((nt_u4){P[0].L1, P[1].L1, P[2].L1, P[3].L1}, reinterpret_cast<nt_u4 *>(L1a + p0));
         if (!kEarlyU) {
-            *reinterpret_cast<float4 *>(ura + p0) = make_float4(P[0].ur, P[1].ur, P[2].ur, P[3].ur);
-            *reinterpret_cast<float4 *>(upa + p0) = make_float4(P[0].up, P[1].up, P[2].up, P[3].up);
-            *reinterpret_cast<float4 *>(uza + p0) = make_float4(P[0].uz, P[1].uz, P[2].uz, P[3].uz);
+            __builtin_nontemporal_store((nt_f4){P[0].ur, P[1].ur, P[2].ur, P[3].ur}, reinterpret_cast<nt_f4 *>(ura + p0));
+            __builtin_nontemporal_store((nt_f4){P[0].up, P[1].up, P[2].up, P[3].up}, reinterpret_cast<nt_f4 *>(upa + p0));
+            __builtin_nontemporal_store((nt_f4){P[0].uz, P[1].uz, P[2].uz, P[3].uz}, reinterpret_cast<nt_f4 *>(uza + p0));
         }
     } else {
 #pragma unroll
