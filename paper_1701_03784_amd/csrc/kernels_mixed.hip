@@ -1271,15 +1271,17 @@ __global__ __launch_bounds__(256) void k_scatter(DevState s, int n2, Payload<W, 
     }
     for (int i = threadIdx.x; i < kSortWin; i += 256) lcnt[i] = 0;
     // the payload is loaded up front: its latency overlaps the ranking and
-    // the slot reservations, which do not depend on it
+    // the slot reservations, which do not depend on it.  The loads are
+    // non-temporal (each word is read once); the scattered stores are not
+    // (non-temporal, they doubled the scatter's time: 50 -> 103 us)
     int cv[K];
     W v[NF][K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const long long p = pb + threadIdx.x + 256 * k;
-        cv[k] = p < n ? cell_a[p] : -1;
+        cv[k] = p < n ? __builtin_nontemporal_load(&cell_a[p]) : -1;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) v[f][k] = p < n ? pl.src[f][p] : W(0);
+        for (int f = 0; f < NF; ++f) v[f][k] = p < n ? __builtin_nontemporal_load(&pl.src[f][p]) : W(0);
     }
     __syncthreads();
     const int base = s_base;
