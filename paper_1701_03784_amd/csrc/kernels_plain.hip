@@ -399,12 +399,7 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
 #pragma unroll
     for (int j = 0; j < kPPTd; ++j) {
         const long long q = p0 + j;
-        // non-temporal, as in the mixed kernel: each word is read and written
-        // once per step, and the field tables stay cached
-        if (q < n)
-            P[j] = {__builtin_nontemporal_load(&cell[q]), __builtin_nontemporal_load(&l0a[q]),
-                    __builtin_nontemporal_load(&l1a[q]), __builtin_nontemporal_load(&ura[q]),
-                    __builtin_nontemporal_load(&upa[q]), __builtin_nontemporal_load(&uza[q])};
+        if (q < n) P[j] = {cell[q], l0a[q], l1a[q], ura[q], upa[q], uza[q]};
         else P[j] = {-1, 0.0, 0.0, 0.0, 0.0, 0.0};
     }
     // thread 0 holds the block's first particle: the window starts at its face
@@ -551,12 +546,9 @@ __global__ __launch_bounds__(kWGd) void k_particles_d(DevMesh m, DevState s, Dev
     for (int j = 0; j < kPPTd; ++j) {
         const long long q = p0 + j;
         if (q < n) {
-            __builtin_nontemporal_store(P[j].cell, &cell[q]);
-            __builtin_nontemporal_store(P[j].l0, &l0a[q]);
-            __builtin_nontemporal_store(P[j].l1, &l1a[q]);
-            __builtin_nontemporal_store(P[j].ur, &ura[q]);
-            __builtin_nontemporal_store(P[j].up, &upa[q]);
-            __builtin_nontemporal_store(P[j].uz, &uza[q]);
+            cell[q] = P[j].cell;
+            l0a[q] = P[j].l0; l1a[q] = P[j].l1;
+            ura[q] = P[j].ur; upa[q] = P[j].up; uza[q] = P[j].uz;
         }
     }
 }
