@@ -796,9 +796,11 @@ __device__ __forceinline__ void end_charge(const DevMesh &m, const PushConst &k0
 // of a diagnostic step accumulates in 32-bit LDS words (always so in the
 // single case).
 template <bool SINGLE, bool VAY, bool DIAG, bool Q32>
-// Occupancy: 6 waves per SIMD (80 VGPRs) for the plain step; the diagnostic
-// step's extra live values would spill at 80 (scratch traffic measured 1.2x
-// the kernel's bytes and 20 % slower), so it takes 5 waves (96 VGPRs).
+// Occupancy: 6 waves per SIMD (80 VGPRs) for the plain step.  The diagnostic
+// step is bounded at 5 waves (96 VGPRs) so that its extra live values never
+// spill (forced to 80, an earlier form spilled: scratch traffic 1.2x the
+// kernel's bytes, 20 % slower); with the momenta stored before its walk the
+// single-species form needs 80 and runs at 6 waves as well.
 __global__ __launch_bounds__(kWG, DIAG ? 5 : 6) void k_particles(DevMesh m, DevState s, int max_walk, int do_count,
                                                       PushConst k0, int win_lead) {
     __shared__ int s_nmv;
