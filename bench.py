@@ -56,6 +56,17 @@ def field_bytes(n_free_edges, n_faces, spai_nnz):
     return 28.0 * n_faces + 8.0 * spai_nnz + 20.0 * n_free_edges
 
 
+def diagnostics_cost(ms_with, ms_without, diag_every):
+    """What diagnostic steps every diag_every steps add to the step: per step,
+    per diagnostic step, and the smallest cadence that keeps the per-step
+    overhead within 10 %."""
+    extra = ms_with / ms_without - 1.0
+    per_eval = extra * diag_every
+    return {"diag_every": diag_every, "ms_per_step_with": ms_with, "ms_per_step_without": ms_without,
+            "overhead": extra, "overhead_per_diagnostic_step": per_eval,
+            "diag_every_for_10pct": max(1, math.ceil(per_eval / 0.10 - 1e-9))}
+
+
 def kernel_source_hash():
     import hashlib
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
@@ -503,14 +514,8 @@ def main():
         log(f"without diagnostics: {nodiag['value']:.3e} particle-steps/s, {nodiag['ms_per_step']:.4f} ms/step")
     diag_cost = None
     if nodiag is not None:
-        # what the diagnostic steps add to the step, and the cadence that keeps it within 10 %
-        extra = head["ms_per_step"] / nodiag["ms_per_step"] - 1.0
-        per_eval = extra * args.diag_every
-        diag_cost = {"diag_every": args.diag_every, "ms_per_step_with": head["ms_per_step"],
-                     "ms_per_step_without": nodiag["ms_per_step"], "overhead": extra,
-                     "overhead_per_diagnostic_step": per_eval,
-                     "diag_every_for_10pct": max(1, math.ceil(per_eval / 0.10 - 1e-9))}
-        log(f"diagnostics every {args.diag_every} step(s): +{100 * extra:.1f} % per step; every "
+        diag_cost = diagnostics_cost(head["ms_per_step"], nodiag["ms_per_step"], args.diag_every)
+        log(f"diagnostics every {args.diag_every} step(s): +{100 * diag_cost['overhead']:.1f} % per step; every "
             f"{diag_cost['diag_every_for_10pct']} steps keeps it within 10 %")
     # field kernels alone: from the steps without diagnostics (with them, the
     # SpMV launch also carries the node pass of the evaluation)
